@@ -1,0 +1,113 @@
+"""Random smooth fields on a regular longitude/latitude grid.
+
+The paper's experiments run on regular lon/lat grids of NX x NY points
+(128x64, 256x128, 512x256) with a mean depth of 8 km (Section 3).  Its test
+cases (a Rossby-Haurwitz wave and flow over Earth orography) need data that is
+not available here, so every workload is synthetic: real spherical-harmonic
+series with standard-normal coefficients, which are smooth on the sphere
+(no pole artefacts) and have a controlled spectral content.
+
+Grid convention (shared with every consumer, restated independently by each):
+longitude  lambda_i = i * 2*pi/NX,  latitude  phi_j = -pi/2 + (j + 1/2) * pi/NY,
+arrays are [NY][NX] row-major, longitude contiguous, row 0 southernmost.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.special import sph_harm_y
+
+CONFIG_SEED_BASE = 2103
+
+
+def cell_centres(nx: int, ny: int):
+    """Longitudes (nx,) and latitudes (ny,) of the cell centres, radians."""
+    lam = np.arange(nx, dtype=np.float64) * (2.0 * np.pi / nx)
+    phi = -0.5 * np.pi + (np.arange(ny, dtype=np.float64) + 0.5) * (np.pi / ny)
+    return lam, phi
+
+
+def harmonic_field(nx, ny, lmax, rng, lmin=0, amplitude=1.0, lam_shift=0.0):
+    """Real spherical-harmonic series sum_{l=lmin..lmax} sum_m (a cos + b sin),
+    coefficients N(0,1) drawn in (l up, m up, cos then sin) order, sampled at
+    the cell centres and rescaled so that max|field| == amplitude.
+
+    ``lam_shift`` evaluates the same series at longitude (lambda - lam_shift),
+    i.e. the pattern advected eastward by lam_shift radians.
+    """
+    lam, phi = cell_centres(nx, ny)
+    lam = lam - lam_shift
+    theta = 0.5 * np.pi - phi  # colatitude
+    TH, LA = np.meshgrid(theta, lam, indexing="ij")
+    field = np.zeros((ny, nx), dtype=np.float64)
+    for l in range(lmin, lmax + 1):
+        for m in range(0, l + 1):
+            y = sph_harm_y(l, m, TH, LA)
+            a = rng.standard_normal()
+            if m == 0:
+                field += a * y.real
+            else:
+                b = rng.standard_normal()
+                field += np.sqrt(2.0) * (a * y.real + b * y.imag)
+    peak = np.max(np.abs(field))
+    if peak == 0.0:
+        return field
+    return field * (amplitude / peak)
+
+
+def _seed(config: int, instance: int) -> int:
+    return CONFIG_SEED_BASE + 1000 * config + instance
+
+
+def problem(config: int, nx: int, ny: int, instance: int = 0, dt: float | None = None,
+            depth_mean=8000.0, depth_amp=500.0, depth_lmax=8, sol_lmax=12):
+    """One solve of the configuration family: depth field, time step, and the
+    field whose operator image becomes the right-hand side.
+
+    Returns dict(nx, ny, dt, depth[ny,nx], x_true[ny,nx], seed).  The depth is
+    depth_mean + depth_amp * (harmonic series of degree 1..depth_lmax with max 1);
+    x_true is a degree 0..sol_lmax series with max|x_true| = 1.
+    """
+    seed = _seed(config, instance)
+    rng = np.random.default_rng(seed)
+    depth = depth_mean + harmonic_field(nx, ny, depth_lmax, rng, lmin=1, amplitude=depth_amp)
+    x_true = harmonic_field(nx, ny, sol_lmax, rng, lmin=0, amplitude=1.0)
+    return dict(nx=nx, ny=ny, dt=600.0 if dt is None else float(dt), depth=depth,
+                x_true=x_true, seed=seed)
+
+
+def batch_problems(config: int, count: int, grids=((128, 64), (256, 128), (512, 256)),
+                   dt_range=(300.0, 1200.0), depth_range=(4000.0, 10000.0)):
+    """Independent solves of uneven sizes: grid drawn uniformly from ``grids``,
+    dt uniform in ``dt_range``, depth = mid + half-range * Psi_8 / max|Psi_8|
+    so that it spans ``depth_range``; each member has its own x_true."""
+    rng = np.random.default_rng(_seed(config, 999))
+    out = []
+    mid = 0.5 * (depth_range[0] + depth_range[1])
+    half = 0.5 * (depth_range[1] - depth_range[0])
+    for n in range(count):
+        nx, ny = grids[int(rng.integers(len(grids)))]
+        dt = float(rng.uniform(*dt_range))
+        p = problem(config, nx, ny, instance=n, dt=dt, depth_mean=mid, depth_amp=half)
+        out.append(p)
+    return out
+
+
+# Zonal jet used for the time-stepping sequence.  Earth constants are inputs of
+# the workload here (they set the jet's balanced depth), not solver arithmetic.
+_A = 6.371e6
+_G = 9.80616
+_OMEGA = 7.292e-5
+
+
+def jet_sequence_depth(nx, ny, step, dt, u0=40.0, pert_amp=200.0, pert_lmax=16,
+                       seed_instance=0, config=5):
+    """Depth field of step ``step`` of a sequence: a zonal jet u = u0 cos(lat) in
+    gradient-wind balance, h = 8000 - (a*Omega*u0 + u0^2/2) sin^2(lat) / g, plus a
+    degree <= pert_lmax perturbation of amplitude pert_amp advected eastward at
+    u0 (solid-body rotation by u0*step*dt/a radians)."""
+    lam, phi = cell_centres(nx, ny)
+    h = 8000.0 - (_A * _OMEGA * u0 + 0.5 * u0 * u0) * np.sin(phi) ** 2 / _G
+    rng = np.random.default_rng(_seed(config, seed_instance))
+    shift = u0 * step * dt / _A
+    pert = harmonic_field(nx, ny, pert_lmax, rng, lmin=1, amplitude=pert_amp, lam_shift=shift)
+    return h[:, None] + pert
