@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X GCR(k) depth solver.
+
+Workload (one "step"): a batch of B = 64 independent elliptic depth solves on
+the 512x256 lon/lat grid -- each member with its own seeded depth field
+(8000 m + 500 m x degree<=8 harmonics), dt = 600 s, and right-hand side
+L(x_true) for a seeded degree<=12 field -- assembled from the depth field
+(coefficients on the GPU) and solved to 1e-8 relative residual with GCR(3)
+and the semi-implicit Richardson preconditioner (two row solves).  The
+headline form is the mixed one (float16/float32 operator storage, float32
+Krylov vectors, float64 inner products, float64 solution and residual
+replacement at every restart); the float64 form is timed beside it.
+
+Prints one JSON line (rank 0).  Inputs are resident in HBM before the timed
+region starts.  --gpus above 1 is refused: this build measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic HBM bytes per grid point and launch of each kernel kind in the
+# mixed form (float16 coefficients: 6 face arrays of 2 B; float32 Krylov
+# vectors: 4 B; float16 preconditioner intermediate: 2 B; float64 solution).
+# The step-2 update kernel and the L/step-4 kernels depend on the window
+# position nu; the counts below are the averages over a GCR(3) cycle
+# (nu = 0, 1, 2).  Constant-size kernels are preferred for the roofline.
+ALG_BYTES_MIXED = {
+    # q_in (2) + r (4) + 6 coefficient arrays (12) -> e (4)
+    "sweep2": 22.0,
+}
+ALG_BYTES_FP64 = {
+    # q_in (8) + r (8) + 6 coefficient arrays (48) -> e (8)
+    "sweep2": 72.0,
+}
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--nx", type=int, default=512)
+    ap.add_argument("--ny", type=int, default=256)
+    ap.add_argument("--dt", type=float, default=600.0)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle timing sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison leg")
+    ap.add_argument("--no-timing", action="store_true", help="no per-kernel event timing")
+    return ap.parse_args()
+
+
+def make_inputs(args, torch, lib):
+    from workloads import problem
+    sizes = [(args.nx, args.ny)] * args.batch
+    probs = [problem(2, args.nx, args.ny, instance=m, dt=args.dt) for m in range(args.batch)]
+    depth = [torch.from_numpy(p["depth"]).cuda() for p in probs]
+    xtrue = [torch.from_numpy(p["x_true"]).cuda() for p in probs]
+    # right-hand sides R = L(x_true), computed by the library's float64 operator
+    s = lib.Solver(sizes, precision=lib.FP64)
+    for m, p in enumerate(probs):
+        s.set_operator(m, depth[m], p["dt"])
+    rhs = [s.apply_operator(m, xtrue[m]) for m in range(args.batch)]
+    torch.cuda.synchronize()
+    s.close()
+    return probs, sizes, depth, rhs
+
+
+class Leg:
+    """One precision form of the step: assemble every member, solve the batch."""
+
+    def __init__(self, lib, torch, args, sizes, probs, depth, rhs, precision):
+        self.lib, self.torch = lib, torch
+        self.solver = lib.Solver(sizes, precision=precision, rtol=args.rtol, max_iters=100)
+        self.probs, self.depth, self.rhs = probs, depth, rhs
+        self.x = [torch.zeros_like(r) for r in rhs]
+        self.reports = None
+
+    def step(self):
+        for m, p in enumerate(self.probs):
+            self.solver.set_operator(m, self.depth[m], p["dt"])
+        for x in self.x:
+            x.zero_()
+        self.reports = self.solver.solve(self.rhs, self.x)
+        return self.reports
+
+    def run(self, steps, warmup, timing):
+        torch = self.torch
+        for _ in range(warmup):
+            self.step()
+        torch.cuda.synchronize()
+        if timing:
+            self.solver.set_kernel_timing(True)
+        iters = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            reps = self.step()
+            iters.append([r.iterations for r in reps])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ktimes = self.solver.kernel_times() if timing else {}
+        if timing:
+            self.solver.set_kernel_timing(False)
+        return dt, np.array(iters), ktimes
+
+
+def roofline(ktimes, iters, reports, pts, table, name="sweep2"):
+    """Achieved algorithmic bandwidth of kernel `name`: every member is
+    processed once in the setup and once per iteration it performs."""
+    n, ms = ktimes.get(name, (0, 0.0))
+    if n == 0 or ms <= 0:
+        return None
+    member_passes = float(np.sum(1 + iters))            # over all timed steps
+    bytes_total = member_passes * pts * table[name]
+    achieved = bytes_total / (ms * 1e-3) / 1e9
+    per_launch = bytes_total / n
+    return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_us": round(ms * 1e3 / n, 2), "launches": n,
+            "alg_bytes_per_launch": int(per_launch)}
+
+
+def cpu_baseline(args, probs, budget_s):
+    """The float64 oracle, single-threaded, on members of the same workload
+    until the time budget is used (assembly + solve per member)."""
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(1)
+    except Exception:
+        limiter = None
+    from oracle.operator import EllipticOperator
+    from oracle.gcr import gcr
+    done, its = 0, []
+    t0 = time.perf_counter()
+    for p in probs:
+        op = EllipticOperator(p["nx"], p["ny"], p["depth"], p["dt"])
+        rhs = op.apply(p["x_true"])
+        res = gcr(op, rhs, rtol=args.rtol)
+        its.append(res.iterations)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    if limiter is not None:
+        limiter.unregister() if hasattr(limiter, "unregister") else None
+    return {"value": round(done / el, 4), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} of the {len(probs)} members ({p['nx']}x{p['ny']}, float64, assembly+solve, "
+                      f"rtol {args.rtol:g}), {el:.1f} s, iterations {min(its)}-{max(its)}"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(independent solves shard across GPUs without communication; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    from paper_2103_16120_amd import lib
+
+    probs, sizes, depth, rhs = make_inputs(args, torch, lib)
+    pts = args.nx * args.ny
+
+    mixed = Leg(lib, torch, args, sizes, probs, depth, rhs, lib.MIXED_FP64DOT)
+    t_mixed, it_mixed, kt_mixed = mixed.run(args.steps, args.warmup, not args.no_timing)
+    rep_m = mixed.reports
+    solves = args.batch * args.steps
+    value = solves / t_mixed
+
+    out = {
+        "metric": "elliptic solves/sec + GCR iters to 1e-8 rel resid, 512x256; mixed/learned vs FP64",
+        "value": round(value, 2),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t_mixed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.batch} independent {args.nx}x{args.ny} depth solves per step "
+                        f"(assembly + GCR(3) solve, rtol {args.rtol:g}), dt {args.dt:g} s",
+            "batch": args.batch, "nx": args.nx, "ny": args.ny, "rtol": args.rtol,
+            "precision": "mixed: f16/f32-polar operator storage, f32 Krylov, f64 dots + f64 "
+                         "solution + f64 residual replacement per restart",
+            "preconditioner": "semi-implicit Richardson, 2 row solves",
+        },
+        "gcr_iters": {"mean": float(it_mixed.mean()), "min": int(it_mixed.min()), "max": int(it_mixed.max())},
+        "rel_res_true_max": max(r.rel_res_true for r in rep_m),
+        "statuses": sorted(set(r.status for r in rep_m)),
+    }
+    if not args.no_timing:
+        out["roofline"] = roofline(kt_mixed, it_mixed, rep_m, pts, ALG_BYTES_MIXED)
+        out["kernel_ms_per_step"] = {k: round(v[1] / args.steps, 4) for k, v in kt_mixed.items() if v[0]}
+        out["kernel_launches_per_step"] = {k: v[0] / args.steps for k, v in kt_mixed.items() if v[0]}
+    mixed.solver.close()
+
+    if not args.no_fp64:
+        f64 = Leg(lib, torch, args, sizes, probs, depth, rhs, lib.FP64)
+        t64, it64, kt64 = f64.run(args.steps, args.warmup, not args.no_timing)
+        out["fp64"] = {"solves_per_s": round(solves / t64, 2), "ms_per_step": round(1e3 * t64 / args.steps, 3),
+                       "gcr_iters_mean": float(it64.mean()),
+                       "rel_res_true_max": max(r.rel_res_true for r in f64.reports)}
+        if not args.no_timing:
+            out["fp64"]["roofline"] = roofline(kt64, it64, f64.reports, pts, ALG_BYTES_FP64)
+        out["speedup_mixed_vs_fp64"] = round(t64 / t_mixed, 3)
+        f64.solver.close()
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args, probs, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,221 @@
+/*
+ * mpgcr -- preconditioned non-symmetric GCR(k) solver for the elliptic depth
+ * problem of a semi-implicit shallow-water model on a regular
+ * longitude/latitude grid, for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Ackmann, Dueben, Palmer, Smolarkiewicz, "Mixed-precision for linear
+ * solvers in global geophysical flows" (arXiv:2103.16120), Section 2.
+ *   - The problem solved is L(Phi) - R = 0 (eq. Elliptic) with the generalised
+ *     Laplacian of eq. L_Operator, whose coefficient fields come from the
+ *     linearised pressure gradient (eq. rhslin) and the pointwise 2x2
+ *     inversion of the implicit momentum equations (eq. Qexpr).
+ *   - The solver is preconditioned GCR(k) (Section 2.3) with exit test
+ *     ||r_N||_2 <= eps ||r_0||_2 (eq. exitcondition) and at least one full
+ *     GCR(k) cycle; the preconditioner is option 3, the semi-implicit
+ *     Richardson scheme of eq. P_Operator, or one of options 0-2.
+ *   - Precision forms follow Sections 4.2-4.3: double precision throughout,
+ *     or low-precision storage of the operator/preconditioner with single
+ *     precision Krylov vectors, a double precision solution accumulator and
+ *     double precision residual recomputation.
+ *
+ * Grid: NX x NY cell-centred points, longitude lambda_i = i*2*pi/NX, latitude
+ * phi_j = -pi/2 + (j+1/2)*pi/NY.  Every field is a contiguous row-major
+ * [NY][NX] float64 array, longitude fastest, row 0 southernmost.  NX must be a
+ * power of two in [8, 1024] and NY an integer in [2, 4096].
+ *
+ * Conventions for every entry point:
+ *   - Return value: GCR_OK (0) or a positive soft status, or a negative hard
+ *     error.  No exception, abort or exit crosses this interface.  After a hard
+ *     error the caller's output arrays are untouched and gcr_last_error()
+ *     describes the cause.
+ *   - Device pointers are HIP device memory of the current device; "host"
+ *     pointers are ordinary host memory.  The library never frees caller
+ *     memory and never keeps caller pointers after a call returns.
+ *   - A solver is used from one host thread at a time; its work is ordered on
+ *     the stream given at creation (NULL = the default stream).  Calls that
+ *     return results to the host synchronise that stream.
+ */
+#ifndef MPGCR_H
+#define MPGCR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gcr_solver gcr_solver; /* opaque; owned by the library */
+
+/* status codes */
+enum {
+  GCR_OK = 0,            /* converged: ||r|| <= rtol ||r_0|| after >= min_iters      */
+  GCR_NOT_CONVERGED = 1, /* max_iters reached; x holds the last iterate               */
+  GCR_STAGNATED = 2,     /* breakdown or no decrease over a whole cycle; x = last     */
+  GCR_FALLBACK_USED = 3, /* converged, but the learned preconditioner was replaced
+                            by the semi-implicit one during the solve               */
+  GCR_EINVAL = -1,       /* invalid argument                                          */
+  GCR_ENOMEM = -2,       /* device or host allocation failed                          */
+  GCR_EHIP = -3,         /* HIP runtime error (includes: no usable GPU)               */
+  GCR_ESTATE = -4        /* call out of order (e.g. solve before set_operator)        */
+};
+
+/* precision forms (paper Sections 4.1-4.3) */
+enum {
+  GCR_FP64 = 0,          /* everything in float64                                     */
+  GCR_MIXED = 1,         /* operator and preconditioner coefficients stored as
+                            float16 (float32 in the polar rows), float32 arithmetic;
+                            float32 Krylov vectors and inner products; solver
+                            increments accumulated in float32 and added to the
+                            float64 solution at exit                                 */
+  GCR_MIXED_FP64DOT = 2  /* as GCR_MIXED, plus float64 inner products, a float64
+                            solution accumulator, and the residual recomputed in
+                            float64 from the solution at every restart and before
+                            exit (residual replacement)                             */
+};
+
+/* preconditioners (paper Section 2.3, options 0-3; 4 is a learned network) */
+enum {
+  GCR_PC_NONE = 0,           /* P = I                                                 */
+  GCR_PC_DIAG = 1,           /* P = diagonal of L                                     */
+  GCR_PC_RICHARDSON = 2,     /* explicit Richardson on L, diagonally preconditioned   */
+  GCR_PC_SEMI_IMPLICIT = 3,  /* semi-implicit Richardson, eq. P_Operator (default)    */
+  GCR_PC_LEARNED = 4         /* 3x3 convolution network between the two row solves of
+                                option 3 (not from the paper); needs gcr_set_learned  */
+};
+
+/* flags */
+#define GCR_F_RECORD_HISTORY 0x1u  /* keep ||r_nu||/||r_0|| per iteration in reports  */
+#define GCR_F_USE_GRAPH 0x2u       /* replay captured HIP graphs of one GCR cycle     */
+#define GCR_F_PERSISTENT 0x4u      /* one persistent kernel per solve (batch-wide)    */
+
+typedef struct {
+  int32_t batch;          /* number of independent solves, 1..4096                    */
+  const int32_t* nx;      /* host array [batch]: longitudes per member                */
+  const int32_t* ny;      /* host array [batch]: latitudes per member                 */
+  int32_t k;              /* GCR(k) window, 1..8 (paper: 3)                           */
+  int32_t precision;      /* GCR_FP64 / GCR_MIXED / GCR_MIXED_FP64DOT                 */
+  int32_t precond;        /* GCR_PC_*                                                 */
+  int32_t richardson_iters; /* Richardson iterations in options 2-3, 1..16 (paper: 2) */
+  int32_t polar_rows;     /* rows per pole kept in float32 in the mixed forms;
+                             -1 = max(1, log2(NY/32)), i.e. 1/2/3 at NY = 64/128/256  */
+  int32_t min_iters;      /* no exit before this many iterations; -1 = k+1            */
+  int32_t max_iters;      /* 1..100000                                                */
+  double rtol;            /* exit when ||r||_2 <= rtol * ||r_0||_2; >= 0              */
+  void* stream;           /* hipStream_t all work is ordered on; NULL = default        */
+  uint32_t flags;         /* GCR_F_*                                                  */
+} gcr_params;
+
+typedef struct {
+  double dt;              /* time step, s (> 0)                                       */
+  double g;               /* gravity, m s^-2 (> 0)                                    */
+  double omega;           /* rotation rate, s^-1 (f = 2 omega sin(lat)); 0 allowed    */
+  double radius;          /* sphere radius, m (> 0)                                   */
+  double absorber;        /* polar absorber strength alpha_max, s^-1 (>= 0): alpha
+                             rises linearly from 0 at 3*pi/64 from a pole to
+                             alpha_max at the pole (paper Section 3.2)               */
+  const double* depth;    /* Phi*, explicit depth predictor [NY][NX], m, > 0          */
+  const double* orography;/* H0 [NY][NX], m, or NULL for a flat surface               */
+  int32_t b_terms;        /* 1 = the paper's operator; 0 drops the B^I terms (tests)  */
+  int32_t mem_is_device;  /* 1 if depth/orography are device pointers, 0 if host      */
+} gcr_operator;
+
+typedef struct {
+  int32_t status;             /* GCR_OK / NOT_CONVERGED / STAGNATED / FALLBACK_USED  */
+  int32_t iterations;         /* number of step-2 updates                            */
+  int32_t restarts;           /* residual recomputations (GCR_MIXED_FP64DOT)         */
+  int32_t fallback_used;      /* 1 if the learned preconditioner was abandoned       */
+  double r0_norm;             /* ||L(x_0) - R||_2                                    */
+  double rel_res_recursive;   /* ||r_N|| / ||r_0|| of the iterated residual         */
+  double rel_res_true;        /* ||L(x_N) - R||_2 / ||r_0||, recomputed in float64   */
+  double* history;            /* host buffer supplied by the caller, or NULL         */
+  int32_t history_cap;        /* entries available in history                        */
+  int32_t history_len;        /* entries written: ||r_nu||/||r_0||, nu = 0..N        */
+} gcr_report;
+
+/* Fill *p with defaults for one member of size nx x ny: k = 3, GCR_FP64,
+ * GCR_PC_SEMI_IMPLICIT, 2 Richardson iterations, polar_rows = -1,
+ * min_iters = -1, max_iters = 200, rtol = 1e-8, default stream, no flags.
+ * The nx/ny pointers are left NULL; the caller must set them.  Returns
+ * GCR_EINVAL if p is NULL. */
+int gcr_default_params(gcr_params* p);
+
+/* Create a solver for params->batch independent members.  Validates the
+ * parameters, selects the device that is current, and allocates all device
+ * workspace for the declared sizes (the solve path allocates nothing).
+ * On success *out receives the solver; on failure *out is set to NULL.
+ * Errors: GCR_EINVAL (bad sizes or options), GCR_ENOMEM, GCR_EHIP (no GPU).
+ * gcr_last_error(NULL) describes a creation failure. */
+int gcr_create(const gcr_params* params, gcr_solver** out);
+
+/* Build the coefficient fields of member `member` (0-based) from the
+ * physical inputs (paper eqs. rhslin, Qexpr, L_Operator; Section 2.2).  The
+ * inputs are copied; the caller may free them when the call returns.  All
+ * precision forms of the coefficients are built on the device, on the
+ * solver's stream.  Errors: GCR_EINVAL, GCR_EHIP. */
+int gcr_set_operator(gcr_solver* s, int32_t member, const gcr_operator* op);
+
+/* Solve L(x_m) = rhs_m for every member m (paper Section 2.3).
+ * rhs, x: host arrays [batch] of device pointers to float64 [NY][NX] fields;
+ * x[m] holds the initial guess on entry and the solution on return; x[m]
+ * must not overlap rhs[m] or another member's x.  reports: host array
+ * [batch], or NULL.  Returns the worst soft status over the members (or a
+ * hard error, with every x untouched).  Synchronises the solver's stream.
+ * Errors: GCR_EINVAL (NULL pointers), GCR_ESTATE (a member without operator),
+ * GCR_EHIP. */
+int gcr_solve(gcr_solver* s, const double* const* rhs, double* const* x, gcr_report* reports);
+
+/* y = L(x) for member `member` in float64 (eq. L_Operator), device pointers
+ * [NY][NX]; y must not overlap x.  Asynchronous on the solver's stream. */
+int gcr_apply_operator(gcr_solver* s, int32_t member, const double* x, double* y);
+
+/* e = P^{-1}(r) for member `member` with the solver's preconditioner and
+ * Richardson count, in float64 (eq. P_Operator for option 3), device
+ * pointers [NY][NX]; e must not overlap r.  Asynchronous on the stream. */
+int gcr_apply_precond(gcr_solver* s, int32_t member, const double* r, double* e);
+
+/* Release every resource of the solver.  NULL is accepted (no-op). */
+int gcr_destroy(gcr_solver* s);
+
+/* Text of a status or error code (static storage). */
+const char* gcr_status_string(int code);
+
+/* Description of the last hard error on `s` (or of the last failed
+ * gcr_create when s is NULL); static or solver-owned storage, valid until the
+ * next call on the same solver. */
+const char* gcr_last_error(const gcr_solver* s);
+
+/* Kernel kinds for per-kernel timing. */
+enum {
+  GCR_K_ASSEMBLE = 0,   /* coefficient assembly (gcr_set_operator)                  */
+  GCR_K_RESIDUAL = 1,   /* float64 residual L(x) - R                                 */
+  GCR_K_SWEEP1 = 2,     /* step-2 update fused with the first row solve              */
+  GCR_K_SWEEP2 = 3,     /* later Richardson iterations (P^M + row solve)             */
+  GCR_K_APPLY_L = 4,    /* L(e) with fused inner products                            */
+  GCR_K_ORTH = 5,       /* step-4 direction update with fused inner products         */
+  GCR_K_CONTROL = 6,    /* per-member scalar updates                                 */
+  GCR_K_COPY = 7,       /* gather/scatter of caller fields                           */
+  GCR_K_PERSISTENT = 8, /* whole-solve persistent kernel (GCR_F_PERSISTENT)          */
+  GCR_K_COUNT = 9
+};
+
+/* Enable (1) or disable (0) timing of every kernel the solver launches with
+ * HIP events recorded on its stream around each launch, and reset the
+ * accumulated times.  Timing adds two event records per launch. */
+int gcr_set_kernel_timing(gcr_solver* s, int32_t enable);
+
+/* Launch count and summed duration (milliseconds) of kernel kind `kind`
+ * (GCR_K_*) since timing was last enabled.  Synchronises the stream. */
+int gcr_kernel_time(gcr_solver* s, int32_t kind, int64_t* launches, double* total_ms);
+
+/* Name of a kernel kind (static storage). */
+const char* gcr_kernel_name(int32_t kind);
+
+/* Library version string, e.g. "mpgcr 0.1.0 gfx950". */
+const char* gcr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPGCR_H */

@@ -1,0 +1,247 @@
+// Device-side building blocks of the GCR(k) depth solver for gfx950.
+//
+// Layout of every field: one pooled allocation per field for the whole batch,
+// member m occupying [geom.off, geom.off + nx*ny), row-major [NY][NX] with
+// longitude fastest (within a row, points are interleaved by lane, see
+// below).  Work is distributed one latitude row per wave64 (four rows per
+// 256-thread workgroup, no workgroup barriers): the zonal cyclic tridiagonal
+// solves of the preconditioner couple a whole row, and the stencil needs rows
+// j-1..j+1.  Lane l of a row owns the M = max(2, NX/64) contiguous points
+// [l*M, (l+1)*M); the L = NX/M lanes of a row exchange chunk edges with
+// cross-lane shuffles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace mpgcr {
+
+constexpr int WG = 256;             // threads per workgroup
+constexpr int WPB = WG / 64;        // rows (waves) per workgroup
+constexpr int KMAX = 8;             // largest GCR(k) window
+constexpr int NXMAX = 1024;         // longest row (one wave, 16 points per lane)
+
+// Slots of the per-row partial inner-product buffer.
+constexpr int DOT_RR = 0;               // <r, r> after the step-2 update
+constexpr int DOT_LE_LP = 1;            // <L e, L p_l>, l = 0..k-1  -> slots 1..KMAX
+constexpr int DOT_R_LP = KMAX + 1;      // <r, L p_new>
+constexpr int DOT_LP_LP = KMAX + 2;     // <L p_new, L p_new>
+constexpr int NDOT = KMAX + 3;
+
+// Face-coefficient arrays, each [NY][NX], pre-divided by the grid factors of
+// the difference they multiply, so the stencil is weights x differences:
+//   AXX = A^xx_e/dlam^2, AXY = A^xy_e/(4 dlam dphi), BX = B^x_e/(2 dlam)  (east faces)
+//   AYY = A^yy_n/dphi^2, AYX = A^yx_n/(4 dlam dphi), BY = B^y_n/(2 dphi)  (north faces;
+//   row NY-1 is the pole face and holds zeros)
+enum { C_AXX = 0, C_AXY, C_BX, C_AYY, C_AYX, C_BY, NCOEF };
+
+struct MemberGeom {
+  int nx, ny, log2nx, polar;  // polar: rows per pole held in float32 (mixed forms)
+  long long off;              // first point of the member in pooled fields (multiple of 64)
+  int row0;                   // first global row of the member
+  int log2m;                  // points per lane M = 1 << log2m
+};
+
+// Per-member solver state kept on the device between kernels.
+struct MemberState {
+  double rho0;                // ||r_0||
+  double rn;                  // ||r|| after the last step-2 update
+  double rn_cycle;            // ||r|| at the start of the current cycle
+  double beta;                // next step-2 coefficient
+  double alpha[KMAX];         // step-4 coefficients of the current iteration
+  double lpsq[KMAX + 1];      // <L p_l, L p_l> per ring slot
+  double rtrue;               // ||L x - R|| recomputed in float64
+  int it, status, done, restarts;
+  int fallback, pad1, pad2, pad3;
+};
+
+// ---------------------------------------------------------------------------
+// cross-lane helpers (wave64)
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T shfl(T v, int src) {
+  return __shfl(v, src, 64);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Row-interleaved storage.  Every internal field stores row point
+// i = l*M + k (lane l's k-th point) at offset k*L + l of the row, where
+// M = max(2, NX/64) points per lane and L = NX/M lanes (64 for NX >= 128).
+// Lane l's loads of row[l + L*k], k = 0..M-1, are then fully coalesced and
+// return its contiguous chunk of points [l*M, l*M + M): stencil neighbours
+// in longitude are in registers except at chunk edges (one shuffle), and the
+// cyclic row solves work on the chunks directly.  Caller-facing fields keep
+// the natural [NY][NX] layout; the library permutes on entry and exit.
+// Idle lanes (l >= L, only for NX < 128) mirror lane l & (L-1) for loads and
+// never store.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int row_slot(int i, int log2m, int L) {   // natural column -> stored offset
+  return (i & ((1 << log2m) - 1)) * L + (i >> log2m);
+}
+
+template <int M, typename S, typename T>
+__device__ __forceinline__ void ldr(const S* row, int l, int L, T (&v)[M]) {
+#pragma unroll
+  for (int k = 0; k < M; ++k) v[k] = (T)row[l + L * k];
+}
+template <int M, typename T>
+__device__ __forceinline__ void ldr(const __half* row, int l, int L, T (&v)[M]) {
+#pragma unroll
+  for (int k = 0; k < M; ++k) v[k] = (T)__half2float(row[l + L * k]);
+}
+template <int M, typename S, typename T>
+__device__ __forceinline__ void str(S* row, int l, int L, const T (&v)[M]) {
+#pragma unroll
+  for (int k = 0; k < M; ++k) row[l + L * k] = (S)v[k];
+}
+template <int M, typename T>
+__device__ __forceinline__ void str(__half* row, int l, int L, const T (&v)[M]) {
+#pragma unroll
+  for (int k = 0; k < M; ++k) row[l + L * k] = __float2half_rn((float)v[k]);
+}
+
+// the same row seen across the pole: longitude shifted by NX/2 = (L/2)*M,
+// i.e. the chunk of lane l + L/2
+template <int M, typename T>
+__device__ __forceinline__ void across_pole(const T (&v)[M], T (&o)[M], int l, int L) {
+  const int src = (l + (L >> 1)) & (L - 1);
+#pragma unroll
+  for (int k = 0; k < M; ++k) o[k] = shfl(v[k], src);
+}
+
+// value at longitude i-1 / i+1 for every point of the lane's chunk
+template <int M, typename T>
+__device__ __forceinline__ void west_of(const T (&v)[M], T (&o)[M], int l, int L) {
+  o[0] = shfl(v[M - 1], (l - 1) & (L - 1));
+#pragma unroll
+  for (int k = 1; k < M; ++k) o[k] = v[k - 1];
+}
+template <int M, typename T>
+__device__ __forceinline__ void east_of(const T (&v)[M], T (&o)[M], int l, int L) {
+  o[M - 1] = shfl(v[0], (l + 1) & (L - 1));
+#pragma unroll
+  for (int k = 0; k < M - 1; ++k) o[k] = v[k + 1];
+}
+
+// ---------------------------------------------------------------------------
+// Row context of one wave.
+// ---------------------------------------------------------------------------
+struct RowCtx {
+  int m, j, g, nx, ny, lane, L;
+  long long rc;           // element offset of the start of row j
+  bool south, north;      // row j-1 / row j+1 exist (otherwise: across the pole)
+  bool act;               // lane owns points (lane < L)
+};
+
+__device__ __forceinline__ RowCtx make_row(const MemberGeom& G, int m, int g, int lane, int M) {
+  RowCtx R;
+  R.m = m;
+  R.g = g;
+  R.j = g - G.row0;
+  R.nx = G.nx;
+  R.ny = G.ny;
+  R.L = G.nx / M;
+  R.act = lane < R.L;
+  R.lane = lane & (R.L - 1);
+  R.rc = G.off + (long long)R.j * G.nx;
+  R.south = R.j > 0;
+  R.north = R.j < G.ny - 1;
+  return R;
+}
+
+// ---------------------------------------------------------------------------
+// Cyclic tridiagonal solve of one latitude row held by one wave.
+//   lo_i x_{i-1} + di_i x_i + up_i x_{i+1} = rh_i   (indices mod NX)
+// Partition method: lane l owns the M equations of points [lM, lM+M).
+// 1. Its first M-1 unknowns are eliminated by a Thomas sweep with the lane's
+//    last unknown y_l and the previous lane's last unknown y_{l-1} moved to
+//    the right-hand side: x_k = f_k + g_k y_{l-1} + h_k y_l.  The forward
+//    sweep runs while the equations are produced (push), so only the sweep's
+//    factors are held in registers.
+// 2. Substituting into the lane's last equation (which also needs f,g,h of
+//    the next lane's first point) leaves one equation per lane coupling
+//    y_{l-1}, y_l, y_{l+1}: a cyclic tridiagonal system of size L.
+// 3. That system is solved by parallel cyclic reduction across the lanes
+//    (shuffles); at stride L every equation reads (A+B+C) y_l = D.
+// 4. Back substitution with y_{l-1} from the previous lane.
+// The row systems of the preconditioner are strictly diagonally dominant, so
+// every elimination step is stable.
+// ---------------------------------------------------------------------------
+template <typename T, int M>
+struct RowSolver {
+  static_assert(M >= 2, "at least two points per lane");
+  T cp[M - 1], f[M - 1], g[M - 1], h[M - 1];
+  T al, bl, cl, dl;   // the lane's last equation
+
+  // equation k of the lane's chunk, in increasing k (k is a compile-time
+  // constant after unrolling)
+  __device__ __forceinline__ void push(int k, T lo, T di, T up, T rh) {
+    if (k == M - 1) {
+      al = lo;
+      bl = di;
+      cl = up;
+      dl = rh;
+      return;
+    }
+    const T hr = (k == M - 2) ? -up : (T)0;   // coupling to y_l moves to the right-hand side
+    if (k == 0) {
+      const T inv = (T)1 / di;
+      cp[0] = up * inv;
+      f[0] = rh * inv;
+      g[0] = -lo * inv;
+      h[0] = hr * inv;
+    } else {
+      const T inv = (T)1 / (di - lo * cp[k - 1]);
+      cp[k] = up * inv;
+      f[k] = (rh - lo * f[k - 1]) * inv;
+      g[k] = (-lo * g[k - 1]) * inv;
+      h[k] = (hr - lo * h[k - 1]) * inv;
+    }
+  }
+
+  __device__ __forceinline__ void solve(int lane, int L, T (&x)[M]) {
+#pragma unroll
+    for (int k = M - 3; k >= 0; --k) {
+      f[k] -= cp[k] * f[k + 1];
+      g[k] -= cp[k] * g[k + 1];
+      h[k] -= cp[k] * h[k + 1];
+    }
+    const int nxt = (lane + 1) & (L - 1), prv = (lane - 1 + L) & (L - 1);
+    const T fn = shfl(f[0], nxt), gn = shfl(g[0], nxt), hn = shfl(h[0], nxt);
+    T A = al * g[M - 2];
+    T B = al * h[M - 2] + bl + cl * gn;
+    T C = cl * hn;
+    T D = dl - al * f[M - 2] - cl * fn;
+    for (int s = 1; s < L; s <<= 1) {
+      const int im = (lane - s + L) & (L - 1), ip = (lane + s) & (L - 1);
+      const T Am = shfl(A, im), Bm = shfl(B, im), Cm = shfl(C, im), Dm = shfl(D, im);
+      const T Ap = shfl(A, ip), Bp = shfl(B, ip), Cp = shfl(C, ip), Dp = shfl(D, ip);
+      const T k1 = A / Bm, k2 = C / Bp;
+      B = B - k1 * Cm - k2 * Ap;
+      D = D - k1 * Dm - k2 * Dp;
+      A = -k1 * Am;
+      C = -k2 * Cp;
+    }
+    const T y = D / (A + B + C);
+    const T ym = shfl(y, prv);
+#pragma unroll
+    for (int k = 0; k < M - 1; ++k) x[k] = f[k] + g[k] * ym + h[k] * y;
+    x[M - 1] = y;
+  }
+};
+
+}  // namespace mpgcr

@@ -1,0 +1,922 @@
+// Kernels of the GCR(k) depth solver (gfx950).  Row kernels map one latitude
+// row to one wave64 (four rows per workgroup); a batch of independent members
+// is one flat list of rows, `rowmap[g]` giving the member of global row g.
+#pragma once
+
+#include <type_traits>
+
+#include "device.h"
+
+namespace mpgcr {
+
+// kernel kinds for the optional per-kernel timing (values match the header)
+enum {
+  KT_ASSEMBLE = 0, KT_RESIDUAL, KT_SWEEP1, KT_SWEEP2, KT_APPLY_L, KT_ORTH, KT_CONTROL, KT_COPY, KT_PERSISTENT,
+  KT_COUNT
+};
+
+// ---------------------------------------------------------------------------
+// precision-specific coefficient access (wave-uniform choice per row)
+// ---------------------------------------------------------------------------
+struct CoefF64 {
+  const double* a[NCOEF];
+  const double* c;            // Helmholtz coefficient per global row
+};
+
+// float16 storage in the interior, float32 in the polar rows, float32 maths.
+struct CoefMixed {
+  const __half* h[NCOEF];
+  const float* f[NCOEF];
+  const float* c;             // scaled Helmholtz coefficient per global row (float32)
+};
+
+template <typename T>
+struct CoefView;
+
+template <>
+struct CoefView<double> {
+  const CoefF64* cf;
+  template <int M>
+  __device__ __forceinline__ void row(int k, long long start, int l, int L, double (&v)[M]) const {
+    ldr<M>(cf->a[k] + start, l, L, v);
+  }
+  __device__ __forceinline__ double helm(int g) const { return cf->c[g]; }
+};
+
+template <>
+struct CoefView<float> {
+  const CoefMixed* cf;
+  bool polar;
+  template <int M>
+  __device__ __forceinline__ void row(int k, long long start, int l, int L, float (&v)[M]) const {
+    if (polar) ldr<M>(cf->f[k] + start, l, L, v);
+    else ldr<M>(cf->h[k] + start, l, L, v);
+  }
+  __device__ __forceinline__ float helm(int g) const { return cf->c[g]; }
+};
+
+// ---------------------------------------------------------------------------
+// precision forms
+// ---------------------------------------------------------------------------
+struct PrecF64 {              // everything float64
+  using V = double;           // Krylov vectors
+  using A = double;           // inner-product accumulation
+  using Q = double;           // preconditioner intermediate storage
+  using T = double;           // arithmetic
+  static constexpr bool mixed = false;
+};
+struct PrecMixed {            // float32 vectors and inner products, float16 coefficients
+  using V = float;
+  using A = float;
+  using Q = __half;
+  using T = float;
+  static constexpr bool mixed = true;
+};
+struct PrecMixedD {           // as PrecMixed with float64 inner products
+  using V = float;
+  using A = double;
+  using Q = __half;
+  using T = float;
+  static constexpr bool mixed = true;
+};
+
+// Everything a kernel may touch, passed by value.
+struct Fields {
+  const MemberGeom* geom;
+  const int* rowmap;
+  MemberState* state;
+  double* part;               // [rows][NDOT] per-row partial inner products
+  const double* scale;        // per member: mixed-form operator scale dt/(2 a^2)
+  CoefF64 c64;
+  CoefMixed cmx;
+  double* x;                  // solution, float64 pool
+  const double* rhs;          // right-hand side, float64 pool
+  double* r64;                // float64 residual (float64 form, restart scratch)
+  void* r;                    // residual in the Krylov type
+  void* e;                    // preconditioner output P^{-1}(r)
+  void* le;                   // L(e)
+  void* q[2];                 // preconditioner intermediates (Q type; V type for options 0-2)
+  float* qs[2];               // per-row scales of q when stored as float16
+  void* p[KMAX + 1];          // direction ring
+  void* lp[KMAX + 1];         // L(direction) ring
+  float* dx;                  // float32 solution increments (GCR_MIXED)
+  double* hist;               // [batch][hist_stride] recursive residual history, or null
+  int hist_stride;
+  int row_base;               // global row handled by wave 0 of workgroup 0
+  int row_end;                // one past the last global row of the launch
+  int ignore_done;            // process finished members too (stand-alone operator calls)
+};
+
+template <typename P>
+__device__ __forceinline__ CoefView<typename P::T> coef_view(const Fields& F, const MemberGeom& G, int j);
+template <>
+__device__ __forceinline__ CoefView<double> coef_view<PrecF64>(const Fields& F, const MemberGeom&, int) {
+  return CoefView<double>{&F.c64};
+}
+template <>
+__device__ __forceinline__ CoefView<float> coef_view<PrecMixed>(const Fields& F, const MemberGeom& G, int j) {
+  return CoefView<float>{&F.cmx, (j < G.polar) || (j >= G.ny - G.polar)};
+}
+template <>
+__device__ __forceinline__ CoefView<float> coef_view<PrecMixedD>(const Fields& F, const MemberGeom& G, int j) {
+  return CoefView<float>{&F.cmx, (j < G.polar) || (j >= G.ny - G.polar)};
+}
+
+// Wave -> row assignment.  Returns false when the wave has no row or the
+// row's member has finished.
+__device__ __forceinline__ bool wave_row(const Fields& F, int& g, int& m, MemberGeom& G, int& lane, int& w) {
+  lane = threadIdx.x & 63;
+  w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  g = F.row_base + blockIdx.x * WPB + w;
+  if (g >= F.row_end) return false;
+  m = F.rowmap[g];
+  G = F.geom[m];
+  return F.ignore_done || F.state[m].done == 0;
+}
+
+// Field row readers for the stencil (row-interleaved storage), converted to T.
+template <typename T, typename S>
+struct RowReader {
+  const S* p;
+  template <int M>
+  __device__ __forceinline__ void row(long long start, int l, int L, T (&v)[M], int /*row_g*/) const {
+    ldr<M>(p + start, l, L, v);
+  }
+};
+
+// float16 storage with one scale per row
+template <typename T>
+struct ScaledHalfReader {
+  const __half* p;
+  const float* qs;
+  template <int M>
+  __device__ __forceinline__ void row(long long start, int l, int L, T (&v)[M], int row_g) const {
+    ldr<M>(p + start, l, L, v);
+    const T s = (T)qs[row_g];
+#pragma unroll
+    for (int k = 0; k < M; ++k) v[k] *= s;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// 9-point stencil of the discrete L on one row (each lane: its chunk), split into
+//   zon  = A^xx zonal second difference          (P^Z)
+//   rest = meridional, cross and B terms         (P^M)
+//   L    = zon + rest - C x                      (P^H = C x)
+// Also returns the centre values and the A^xx / A^yy faces the row solves need.
+// Rows beyond the poles are the polar row seen across the pole.
+// ---------------------------------------------------------------------------
+template <typename T, int M, typename CV, typename XR>
+__device__ __forceinline__ void stencil_row(const RowCtx& R, const CV& cv, const XR& X, T (&zon)[M], T (&rest)[M],
+                                            T (&xc)[M], T (&axe)[M], T (&axw)[M], T (&ayn)[M], T (&ays)[M]) {
+  const int l = R.lane, L = R.L;
+  T xs[M], xn[M];
+  X.row(R.rc, l, L, xc, R.g);
+  if (R.south) X.row(R.rc - R.nx, l, L, xs, R.g - 1);
+  else across_pole(xc, xs, l, L);
+  if (R.north) X.row(R.rc + R.nx, l, L, xn, R.g + 1);
+  else across_pole(xc, xn, l, L);
+  T axy[M], bx[M], ayxn[M], byn[M], ayxs[M], bys[M];
+  cv.row(C_AXX, R.rc, l, L, axe);
+  cv.row(C_AXY, R.rc, l, L, axy);
+  cv.row(C_BX, R.rc, l, L, bx);
+  cv.row(C_AYY, R.rc, l, L, ayn);
+  cv.row(C_AYX, R.rc, l, L, ayxn);
+  cv.row(C_BY, R.rc, l, L, byn);
+  if (R.south) {
+    cv.row(C_AYY, R.rc - R.nx, l, L, ays);
+    cv.row(C_AYX, R.rc - R.nx, l, L, ayxs);
+    cv.row(C_BY, R.rc - R.nx, l, L, bys);
+  } else {           // the south pole face carries no flux
+#pragma unroll
+    for (int k = 0; k < M; ++k) ays[k] = ayxs[k] = bys[k] = (T)0;
+  }
+  T cw[M], ce[M], sw[M], se[M], nw[M], ne[M], axyw[M], bxw[M];
+  west_of(xc, cw, l, L);
+  east_of(xc, ce, l, L);
+  west_of(xs, sw, l, L);
+  east_of(xs, se, l, L);
+  west_of(xn, nw, l, L);
+  east_of(xn, ne, l, L);
+  west_of(axe, axw, l, L);
+  west_of(axy, axyw, l, L);
+  west_of(bx, bxw, l, L);
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const T c = xc[k], w = cw[k], e = ce[k];
+    const T sc = xs[k], nc = xn[k];
+    zon[k] = axe[k] * (e - c) - axw[k] * (c - w);
+    T r = axy[k] * ((nc - sc) + (ne[k] - se[k])) - axyw[k] * ((nw[k] - sw[k]) + (nc - sc));
+    r += bx[k] * (c + e) - bxw[k] * (w + c);
+    r += ayn[k] * (nc - c) + ayxn[k] * ((e - w) + (ne[k] - nw[k])) + byn[k] * (c + nc);
+    r -= ays[k] * (c - sc) + ayxs[k] * ((se[k] - sw[k]) + (e - w)) + bys[k] * (sc + c);
+    rest[k] = r;
+  }
+}
+
+// A^xx (east, west) and A^yy (north, south) faces of a row, for the row
+// systems when no stencil is evaluated.
+template <typename T, int M, typename CV>
+__device__ __forceinline__ void row_faces(const RowCtx& R, const CV& cv, T (&axe)[M], T (&axw)[M], T (&ayn)[M],
+                                          T (&ays)[M]) {
+  const int l = R.lane, L = R.L;
+  cv.row(C_AXX, R.rc, l, L, axe);
+  west_of(axe, axw, l, L);
+  cv.row(C_AYY, R.rc, l, L, ayn);
+  if (R.south) cv.row(C_AYY, R.rc - R.nx, l, L, ays);
+  else {
+#pragma unroll
+    for (int k = 0; k < M; ++k) ays[k] = (T)0;
+  }
+}
+
+// diagonal of L on a row
+template <typename T, int M, typename CV>
+__device__ __forceinline__ void diag_row(const RowCtx& R, const CV& cv, T (&d)[M]) {
+  const int l = R.lane, L = R.L;
+  T axe[M], axw[M], bx[M], bxw[M], ayn[M], byn[M], ays[M], bys[M];
+  cv.row(C_AXX, R.rc, l, L, axe);
+  cv.row(C_BX, R.rc, l, L, bx);
+  cv.row(C_AYY, R.rc, l, L, ayn);
+  cv.row(C_BY, R.rc, l, L, byn);
+  if (R.south) {
+    cv.row(C_AYY, R.rc - R.nx, l, L, ays);
+    cv.row(C_BY, R.rc - R.nx, l, L, bys);
+  } else {
+#pragma unroll
+    for (int k = 0; k < M; ++k) ays[k] = bys[k] = (T)0;
+  }
+  west_of(axe, axw, l, L);
+  west_of(bx, bxw, l, L);
+  const T helm = cv.helm(R.g);
+#pragma unroll
+  for (int k = 0; k < M; ++k)
+    d[k] = -(axe[k] + axw[k]) + (bx[k] - bxw[k]) - ayn[k] + byn[k] - (ays[k] + bys[k]) - helm;
+}
+
+// T = I - eta (P^Z - P^H) at one point
+template <typename T>
+__device__ __forceinline__ void row_system(T eta, T axe, T axw, T helm, T& lo, T& di, T& up) {
+  lo = -eta * axw;
+  up = -eta * axe;
+  di = (T)1 + eta * (axe + axw) + eta * helm;
+}
+
+// Solve the row systems (each lane holds its chunk of equations).
+template <typename T, int M>
+__device__ __forceinline__ void solve_row(const RowCtx& R, const T (&lo)[M], const T (&di)[M], const T (&up)[M],
+                                          const T (&rh)[M], T (&x)[M]) {
+  RowSolver<T, M> rs;
+#pragma unroll
+  for (int k = 0; k < M; ++k) rs.push(k, lo[k], di[k], up[k], rh[k]);
+  rs.solve(R.lane, R.L, x);
+}
+
+// store a preconditioner intermediate (Q type; float16 with a per-row scale)
+template <typename P, int M>
+__device__ __forceinline__ void store_q(const Fields& F, int qout, const RowCtx& R, const typename P::T (&v)[M]) {
+  using T = typename P::T;
+  using Q = typename P::Q;
+  Q* q = (Q*)F.q[qout] + R.rc;
+  if constexpr (P::mixed) {
+    float mx = 0.f;
+    if (R.act) {
+#pragma unroll
+      for (int k = 0; k < M; ++k) mx = fmaxf(mx, fabsf((float)v[k]));
+    }
+    mx = wave_max(mx);
+    const float sc = mx > 0.f ? mx : 1.f;
+    if (R.lane == 0 && R.act) F.qs[qout][R.g] = sc;
+    const float inv = 1.f / sc;
+    T t[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) t[k] = v[k] * inv;
+    if (R.act) str<M>(q, R.lane, R.L, t);
+  } else {
+    if (R.act) str<M>(q, R.lane, R.L, v);
+  }
+}
+
+template <typename P, int M>
+__device__ __forceinline__ void store_v(void* dst, const RowCtx& R, const typename P::T (&v)[M]) {
+  if (R.act) str<M>((typename P::V*)dst + R.rc, R.lane, R.L, v);
+}
+
+template <typename A>
+__device__ __forceinline__ void write_partial(const Fields& F, const RowCtx& R, int slot, A v) {
+  v = wave_sum(v);
+  if (R.lane == 0 && R.act) F.part[(long long)R.g * NDOT + slot] = (double)v;
+}
+
+// step 2 on one row: x += beta p_nu ; r += beta L p_nu ; returns r and <r,r>
+template <typename P, int M>
+__device__ __forceinline__ typename P::A row_update(const Fields& F, const RowCtx& R, int slot_nu,
+                                                    typename P::T (&rv)[M]) {
+  using T = typename P::T;
+  using V = typename P::V;
+  using A = typename P::A;
+  const int l = R.lane, L = R.L;
+  const double beta = F.state[R.m].beta;
+  V* r = (V*)F.r + R.rc;
+  T pv[M], lv[M];
+  ldr<M>((const V*)F.p[slot_nu] + R.rc, l, L, pv);
+  ldr<M>((const V*)F.lp[slot_nu] + R.rc, l, L, lv);
+  if (P::mixed && F.dx) {
+    float xv[M];
+    ldr<M>(F.dx + R.rc, l, L, xv);
+#pragma unroll
+    for (int k = 0; k < M; ++k) xv[k] += (float)beta * (float)pv[k];
+    if (R.act) str<M>(F.dx + R.rc, l, L, xv);
+  } else {
+    double xv[M];
+    ldr<M>(F.x + R.rc, l, L, xv);
+#pragma unroll
+    for (int k = 0; k < M; ++k) xv[k] += beta * (double)pv[k];
+    if (R.act) str<M>(F.x + R.rc, l, L, xv);
+  }
+  A acc = (A)0;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    rv[k] = (T)(V)(rv[k] + (T)beta * lv[k]);
+    acc += (A)rv[k] * (A)rv[k];
+  }
+  if (R.act) str<M>(r, l, L, rv);
+  return R.act ? acc : (A)0;
+}
+
+// ---------------------------------------------------------------------------
+// step 2 + first semi-implicit Richardson iteration (q_0 = 0, eq. P_Operator):
+//   (update)  x += beta p_nu ; r += beta L p_nu ; partial <r,r>
+//   q1 = T^{-1}(-eta r),  T = I - eta (P^Z - P^H)
+// `qout` = -1 writes the result to e (single Richardson iteration).
+// ---------------------------------------------------------------------------
+template <typename P, int M>
+__device__ __forceinline__ void row_update_sweep1(const Fields& F, const RowCtx& R, const MemberGeom& G, int do_update,
+                                                  int slot_nu, int qout) {
+  using T = typename P::T;
+  using V = typename P::V;
+  using A = typename P::A;
+  const auto cv = coef_view<P>(F, G, R.j);
+  const T helm = cv.helm(R.g);
+  T rv[M];
+  ldr<M>((const V*)F.r + R.rc, R.lane, R.L, rv);
+  if (do_update) {
+    const A acc = row_update<P, M>(F, R, slot_nu, rv);
+    write_partial<A>(F, R, DOT_RR, acc);
+  }
+  T axe[M], axw[M], ayn[M], ays[M], lo[M], di[M], up[M], rh[M], xq[M];
+  row_faces<T, M>(R, cv, axe, axw, ayn, ays);
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const T eta = (T)1 / (ayn[k] + ays[k]);
+    row_system(eta, axe[k], axw[k], helm, lo[k], di[k], up[k]);
+    rh[k] = -eta * rv[k];
+  }
+  solve_row<T, M>(R, lo, di, up, rh, xq);
+  if (qout < 0) store_v<P, M>(F.e, R, xq);
+  else store_q<P, M>(F, qout, R, xq);
+}
+
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_update_sweep1(Fields F, int do_update, int slot_nu, int qout) {
+  int g, m, lane, w;
+  MemberGeom G;
+  if (!wave_row(F, g, m, G, lane, w)) return;
+  row_update_sweep1<P, M>(F, make_row(G, m, g, lane, M), G, do_update, slot_nu, qout);
+}
+
+// ---------------------------------------------------------------------------
+// later semi-implicit Richardson iterations (eq. P_Operator):
+//   q_out = T^{-1}( q_in + eta (P^M q_in - r) )
+// `qout` = -1 writes the final iterate to e.
+// ---------------------------------------------------------------------------
+template <typename P, int M>
+__device__ __forceinline__ void row_sweep2(const Fields& F, const RowCtx& R, const MemberGeom& G, int qin,
+                                           int qout) {
+  using T = typename P::T;
+  using V = typename P::V;
+  const auto cv = coef_view<P>(F, G, R.j);
+  const T helm = cv.helm(R.g);
+  T zon[M], rest[M], xc[M], axe[M], axw[M], ayn[M], ays[M], rv[M];
+  if constexpr (P::mixed) {
+    ScaledHalfReader<T> X{(const __half*)F.q[qin], F.qs[qin]};
+    stencil_row<T, M>(R, cv, X, zon, rest, xc, axe, axw, ayn, ays);
+  } else {
+    RowReader<T, double> X{(const double*)F.q[qin]};
+    stencil_row<T, M>(R, cv, X, zon, rest, xc, axe, axw, ayn, ays);
+  }
+  ldr<M>((const V*)F.r + R.rc, R.lane, R.L, rv);
+  T lo[M], di[M], up[M], rh[M], xq[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const T eta = (T)1 / (ayn[k] + ays[k]);
+    row_system(eta, axe[k], axw[k], helm, lo[k], di[k], up[k]);
+    rh[k] = xc[k] + eta * (rest[k] - rv[k]);
+  }
+  solve_row<T, M>(R, lo, di, up, rh, xq);
+  if (qout < 0) store_v<P, M>(F.e, R, xq);
+  else store_q<P, M>(F, qout, R, xq);
+}
+
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_sweep2(Fields F, int qin, int qout) {
+  int g, m, lane, w;
+  MemberGeom G;
+  if (!wave_row(F, g, m, G, lane, w)) return;
+  row_sweep2<P, M>(F, make_row(G, m, g, lane, M), G, qin, qout);
+}
+
+// ---------------------------------------------------------------------------
+// preconditioner options 0-2 (paper Section 2.3):
+//   first pass  (update as in k_update_sweep1), then q = r or r/diag(L)
+//   Richardson  q_out = q_in - (L q_in - r) / diag(L)
+// (intermediates in the Krylov type)
+// ---------------------------------------------------------------------------
+template <typename P, int M>
+__device__ __forceinline__ void row_update_simple(const Fields& F, const RowCtx& R, const MemberGeom& G, int do_update,
+                                                  int slot_nu, int use_diag, int qout) {
+  using T = typename P::T;
+  using V = typename P::V;
+  using A = typename P::A;
+  const auto cv = coef_view<P>(F, G, R.j);
+  T rv[M];
+  ldr<M>((const V*)F.r + R.rc, R.lane, R.L, rv);
+  if (do_update) {
+    const A acc = row_update<P, M>(F, R, slot_nu, rv);
+    write_partial<A>(F, R, DOT_RR, acc);
+  }
+  if (use_diag) {
+    T d[M];
+    diag_row<T, M>(R, cv, d);
+#pragma unroll
+    for (int k = 0; k < M; ++k) rv[k] /= d[k];
+  }
+  store_v<P, M>(qout < 0 ? F.e : F.q[qout], R, rv);
+}
+
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_update_simple(Fields F, int do_update, int slot_nu, int use_diag, int qout) {
+  int g, m, lane, w;
+  MemberGeom G;
+  if (!wave_row(F, g, m, G, lane, w)) return;
+  row_update_simple<P, M>(F, make_row(G, m, g, lane, M), G, do_update, slot_nu, use_diag, qout);
+}
+
+template <typename P, int M>
+__device__ __forceinline__ void row_jacobi(const Fields& F, const RowCtx& R, const MemberGeom& G, int qin, int qout) {
+  using T = typename P::T;
+  using V = typename P::V;
+  const auto cv = coef_view<P>(F, G, R.j);
+  const T helm = cv.helm(R.g);
+  RowReader<T, V> X{(const V*)F.q[qin]};
+  T zon[M], rest[M], xc[M], axe[M], axw[M], ayn[M], ays[M], rv[M], d[M], o[M];
+  stencil_row<T, M>(R, cv, X, zon, rest, xc, axe, axw, ayn, ays);
+  diag_row<T, M>(R, cv, d);
+  ldr<M>((const V*)F.r + R.rc, R.lane, R.L, rv);
+#pragma unroll
+  for (int k = 0; k < M; ++k) o[k] = xc[k] - ((zon[k] + rest[k] - helm * xc[k]) - rv[k]) / d[k];
+  store_v<P, M>(qout < 0 ? F.e : F.q[qout], R, o);
+}
+
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_jacobi(Fields F, int qin, int qout) {
+  int g, m, lane, w;
+  MemberGeom G;
+  if (!wave_row(F, g, m, G, lane, w)) return;
+  row_jacobi<P, M>(F, make_row(G, m, g, lane, M), G, qin, qout);
+}
+
+// ---------------------------------------------------------------------------
+// out = L(in) in the Krylov precision, with fused inner products:
+//   mode 0: <out, L p_l> for the nl ring slots in `slots`  -> DOT_LE_LP + l
+//   mode 1: <r, out>, <out, out>                           -> DOT_R_LP, DOT_LP_LP
+//   mode 2: none
+// ---------------------------------------------------------------------------
+struct Slots {
+  int s[KMAX + 1];
+};
+
+template <typename P, int M>
+__device__ __forceinline__ void row_apply_L(const Fields& F, const RowCtx& R, const MemberGeom& G, const void* in,
+                                            void* out, int mode, int nl, const Slots& sl) {
+  using T = typename P::T;
+  using V = typename P::V;
+  using A = typename P::A;
+  const int l = R.lane, L = R.L;
+  const auto cv = coef_view<P>(F, G, R.j);
+  const T helm = cv.helm(R.g);
+  RowReader<T, V> X{(const V*)in};
+  T zon[M], rest[M], xc[M], axe[M], axw[M], ayn[M], ays[M], y[M];
+  stencil_row<T, M>(R, cv, X, zon, rest, xc, axe, axw, ayn, ays);
+#pragma unroll
+  for (int k = 0; k < M; ++k) y[k] = (T)(V)(zon[k] + rest[k] - helm * xc[k]);
+  store_v<P, M>(out, R, y);
+  if (mode == 0) {
+    for (int li = 0; li < nl; ++li) {
+      T lv[M];
+      ldr<M>((const V*)F.lp[sl.s[li]] + R.rc, l, L, lv);
+      A acc = (A)0;
+#pragma unroll
+      for (int k = 0; k < M; ++k) acc += (A)y[k] * (A)lv[k];
+      write_partial<A>(F, R, DOT_LE_LP + li, R.act ? acc : (A)0);
+    }
+  } else if (mode == 1) {
+    T rv[M];
+    ldr<M>((const V*)F.r + R.rc, l, L, rv);
+    A a0 = (A)0, a1 = (A)0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      a0 += (A)rv[k] * (A)y[k];
+      a1 += (A)y[k] * (A)y[k];
+    }
+    write_partial<A>(F, R, DOT_R_LP, R.act ? a0 : (A)0);
+    write_partial<A>(F, R, DOT_LP_LP, R.act ? a1 : (A)0);
+  }
+}
+
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_apply_L(Fields F, const void* in, void* out, int mode, int nl, Slots sl) {
+  int g, m, lane, w;
+  MemberGeom G;
+  if (!wave_row(F, g, m, G, lane, w)) return;
+  row_apply_L<P, M>(F, make_row(G, m, g, lane, M), G, in, out, mode, nl, sl);
+}
+
+// ---------------------------------------------------------------------------
+// residual r = L(x) - R in float64 (eq. Residual).  Writes r64 and, if asked,
+// the Krylov copy r = s*r64 (s = 1 in the float64 form).  Partials: <r,r>
+// (slot DOT_RR, in the Krylov scaling); with `lp_slot` >= 0 also <r, L p_slot>.
+// `respect_done`: skip finished members (restart) or not (final check).
+// ---------------------------------------------------------------------------
+template <typename P, int M>
+__device__ __forceinline__ void row_residual(const Fields& F, const RowCtx& R, int write_krylov, int lp_slot) {
+  using V = typename P::V;
+  const int l = R.lane, L = R.L;
+  const CoefView<double> cv{&F.c64};
+  const double helm = cv.helm(R.g);
+  const double s = P::mixed ? F.scale[R.m] : 1.0;
+  RowReader<double, double> X{F.x};
+  double zon[M], rest[M], xc[M], axe[M], axw[M], ayn[M], ays[M], rr[M], b[M];
+  stencil_row<double, M>(R, cv, X, zon, rest, xc, axe, axw, ayn, ays);
+  ldr<M>(F.rhs + R.rc, l, L, b);
+  double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    rr[k] = zon[k] + rest[k] - helm * xc[k] - b[k];
+    acc0 += rr[k] * rr[k];
+  }
+  if (R.act) str<M>(F.r64 + R.rc, l, L, rr);
+  if (write_krylov) {
+    double rk[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) rk[k] = (double)(V)(s * rr[k]);
+    if (R.act) str<M>((V*)F.r + R.rc, l, L, rk);
+    if (lp_slot >= 0) {
+      double lv[M];
+      ldr<M>((const V*)F.lp[lp_slot] + R.rc, l, L, lv);
+#pragma unroll
+      for (int k = 0; k < M; ++k) acc1 += rk[k] * lv[k];
+    }
+  }
+  // the Krylov residual lives in scaled units in the mixed forms
+  write_partial<double>(F, R, DOT_RR, R.act ? acc0 * s * s : 0.0);
+  write_partial<double>(F, R, DOT_R_LP, R.act ? acc1 : 0.0);
+}
+
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_residual(Fields F, int write_krylov, int lp_slot, int respect_done) {
+  int g, m, lane, w;
+  MemberGeom G;
+  const bool active = wave_row(F, g, m, G, lane, w);
+  if (g >= F.row_end || (respect_done && !active)) return;
+  row_residual<P, M>(F, make_row(G, m, g, lane, M), write_krylov, lp_slot);
+}
+
+// ---------------------------------------------------------------------------
+// step 4: p_{nu+1} = e + sum alpha_l p_l ; L p_{nu+1} = L e + sum alpha_l L p_l,
+// with fused <r, L p_{nu+1}> and <L p_{nu+1}, L p_{nu+1}>.
+// ---------------------------------------------------------------------------
+template <typename P, int M>
+__device__ __forceinline__ void row_orth(const Fields& F, const RowCtx& R, int nl, const Slots& sl, int out_slot) {
+  using T = typename P::T;
+  using V = typename P::V;
+  using A = typename P::A;
+  const int l = R.lane, L = R.L;
+  T pv[M], lv[M], rv[M];
+  ldr<M>((const V*)F.e + R.rc, l, L, pv);
+  ldr<M>((const V*)F.le + R.rc, l, L, lv);
+  for (int li = 0; li < nl; ++li) {
+    const T alpha = (T)F.state[R.m].alpha[li];
+    T a[M], b[M];
+    ldr<M>((const V*)F.p[sl.s[li]] + R.rc, l, L, a);
+    ldr<M>((const V*)F.lp[sl.s[li]] + R.rc, l, L, b);
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      pv[k] += alpha * a[k];
+      lv[k] += alpha * b[k];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    pv[k] = (T)(V)pv[k];
+    lv[k] = (T)(V)lv[k];
+  }
+  if (R.act) {
+    str<M>((V*)F.p[out_slot] + R.rc, l, L, pv);
+    str<M>((V*)F.lp[out_slot] + R.rc, l, L, lv);
+  }
+  ldr<M>((const V*)F.r + R.rc, l, L, rv);
+  A acc0 = (A)0, acc1 = (A)0;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    acc0 += (A)rv[k] * (A)lv[k];
+    acc1 += (A)lv[k] * (A)lv[k];
+  }
+  write_partial<A>(F, R, DOT_R_LP, R.act ? acc0 : (A)0);
+  write_partial<A>(F, R, DOT_LP_LP, R.act ? acc1 : (A)0);
+}
+
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_orth(Fields F, int nl, Slots sl, int out_slot) {
+  int g, m, lane, w;
+  MemberGeom G;
+  if (!wave_row(F, g, m, G, lane, w)) return;
+  row_orth<P, M>(F, make_row(G, m, g, lane, M), nl, sl, out_slot);
+}
+
+// ---------------------------------------------------------------------------
+// coefficient assembly (paper eqs. rhslin, Qexpr, L_Operator), one thread per
+// point, float64; also writes the scaled float16 / float32 copies.
+// ---------------------------------------------------------------------------
+struct AssembleArgs {
+  const double* depth;        // member fields (pool offset applied by the host)
+  const double* oro;          // or null
+  double dt, g, omega, radius, absorber;
+  int nx, ny, b_terms, row0;
+  long long off;
+  double* a64[NCOEF];
+  __half* a16[NCOEF];
+  float* a32[NCOEF];
+  double* c64;                // per global row
+  float* c32;
+  double* scale;              // per member: mixed-form scale dt/(2 a^2)
+  int member;
+  int log2m;                  // points per lane of the row-interleaved storage
+};
+
+__device__ __forceinline__ double absorber_at(double lat, double amax) {
+  const double kPi = 3.14159265358979323846;
+  const double dist = 0.5 * kPi - fabs(lat);
+  const double w = 1.0 - dist / (3.0 * kPi / 64.0);
+  return amax * (w > 0.0 ? w : 0.0);
+}
+
+__global__ void k_assemble(AssembleArgs A) {
+  const int nx = A.nx, ny = A.ny;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nx * ny) return;
+  const int j = idx / nx, i = idx - j * nx;
+  const double kPi = 3.14159265358979323846;
+  const double dlam = 2.0 * kPi / nx, dphi = kPi / ny;
+  const double delta = 0.5 * A.dt;
+  const int ie = (i + 1) & (nx - 1), iw = (i - 1) & (nx - 1), h = nx >> 1;
+  auto D = [&](int jj, int ii) { return A.depth[(long long)jj * nx + ii]; };
+  auto H = [&](int jj, int ii) {
+    if (jj < 0) { jj = 0; ii = (ii + h) & (nx - 1); }
+    if (jj >= ny) { jj = ny - 1; ii = (ii + h) & (nx - 1); }
+    const long long k = (long long)jj * nx + ii;
+    return A.depth[k] + (A.oro ? A.oro[k] : 0.0);
+  };
+  double out[NCOEF];
+  // east face (i+1/2, j), latitude of row j
+  {
+    const double lat = -0.5 * kPi + (j + 0.5) * dphi;
+    const double cs = cos(lat);
+    const double gam = 1.0 + delta * absorber_at(lat, A.absorber);
+    const double b = delta * 2.0 * A.omega * sin(lat);
+    const double Dn = gam * gam + b * b;
+    const double kap = delta * A.g * 0.5 * (D(j, i) + D(j, ie)) / (2.0 * Dn);
+    out[C_AXX] = kap * gam / cs / (dlam * dlam);
+    out[C_AXY] = kap * b / (4.0 * dlam * dphi);
+    double bx = 0.0;
+    if (A.b_terms) {
+      const double dhl = (H(j, ie) - H(j, i)) / dlam;
+      const double dhp = ((H(j + 1, i) - H(j - 1, i)) + (H(j + 1, ie) - H(j - 1, ie))) / (4.0 * dphi);
+      bx = delta * A.g / (2.0 * Dn) * (gam / cs * dhl + b * dhp);
+    }
+    out[C_BX] = bx / (2.0 * dlam);
+  }
+  // north face (i, j+1/2); the pole face carries no flux
+  if (j < ny - 1) {
+    const double lat = -0.5 * kPi + (j + 1.0) * dphi;
+    const double cs = cos(lat);
+    const double gam = 1.0 + delta * absorber_at(lat, A.absorber);
+    const double b = delta * 2.0 * A.omega * sin(lat);
+    const double Dn = gam * gam + b * b;
+    const double kap = delta * A.g * 0.5 * (D(j, i) + D(j + 1, i)) / (2.0 * Dn);
+    out[C_AYY] = kap * gam * cs / (dphi * dphi);
+    out[C_AYX] = -kap * b / (4.0 * dlam * dphi);
+    double by = 0.0;
+    if (A.b_terms) {
+      const double dhp = (H(j + 1, i) - H(j, i)) / dphi;
+      const double dhl = ((H(j, ie) - H(j, iw)) + (H(j + 1, ie) - H(j + 1, iw))) / (4.0 * dlam);
+      by = delta * A.g / (2.0 * Dn) * (-b * dhl + gam * cs * dhp);
+    }
+    out[C_BY] = by / (2.0 * dphi);
+  } else {
+    out[C_AYY] = out[C_AYX] = out[C_BY] = 0.0;
+  }
+  const double s = A.dt / (2.0 * A.radius * A.radius);   // mixed-form scale
+  const long long o = A.off + (long long)j * nx + row_slot(i, A.log2m, nx >> A.log2m);
+#pragma unroll
+  for (int k = 0; k < NCOEF; ++k) {
+    A.a64[k][o] = out[k];
+    A.a32[k][o] = (float)(s * out[k]);
+    A.a16[k][o] = __float2half_rn((float)(s * out[k]));
+  }
+  if (idx == 0) A.scale[A.member] = s;
+  if (i == 0) {
+    const double lat = -0.5 * kPi + (j + 0.5) * dphi;
+    const double c = 2.0 * A.radius * A.radius * cos(lat) / A.dt;
+    A.c64[A.row0 + j] = c;
+    A.c32[A.row0 + j] = (float)(s * c);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gather / scatter between caller fields (natural [NY][NX]) and the pools
+// (row-interleaved storage)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long long pool_index(const MemberGeom& G, long long k) {
+  const int j = (int)(k >> G.log2nx), i = (int)(k & (G.nx - 1));
+  return G.off + ((long long)j << G.log2nx) + row_slot(i, G.log2m, G.nx >> G.log2m);
+}
+
+__global__ void k_gather(const double* const* src, double* dst, const MemberGeom* geom) {
+  const int m = blockIdx.y;
+  const MemberGeom G = geom[m];
+  const long long n = (long long)G.nx * G.ny;
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
+    dst[pool_index(G, k)] = src[m][k];
+}
+
+__global__ void k_scatter(const double* src, double* const* dst, const MemberGeom* geom) {
+  const int m = blockIdx.y;
+  const MemberGeom G = geom[m];
+  const long long n = (long long)G.nx * G.ny;
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
+    dst[m][k] = src[pool_index(G, k)];
+}
+
+// one member, direct pointers
+__global__ void k_to_pool(const double* src, double* pool, MemberGeom G) {
+  const long long n = (long long)G.nx * G.ny;
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
+    pool[pool_index(G, k)] = src[k];
+}
+
+__global__ void k_from_pool(const double* pool, double* dst, MemberGeom G) {
+  const long long n = (long long)G.nx * G.ny;
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
+    dst[k] = pool[pool_index(G, k)];
+}
+
+// mixed form without float64 accumulator: x += dx at exit, dx = 0
+__global__ void k_apply_increments(Fields F, long long total) {
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < total;
+       k += (long long)gridDim.x * blockDim.x) {
+    F.x[k] += (double)F.dx[k];
+    F.dx[k] = 0.f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// control: one wave per member; sums the member's per-row partials in a
+// fixed order (deterministic) and updates the device-resident scalars.
+// ---------------------------------------------------------------------------
+template <typename A>
+__device__ __forceinline__ double member_sum(const Fields& F, const MemberGeom& G, int slot) {
+  A s = (A)0;
+  for (int jj = threadIdx.x; jj < G.ny; jj += 64) s += (A)F.part[(long long)(G.row0 + jj) * NDOT + slot];
+  return (double)wave_sum(s);
+}
+
+enum { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_STAGNATED = 2 };
+
+template <typename A>
+__global__ void k_ctrl_init(Fields F) {
+  const int m = blockIdx.x;
+  const MemberGeom G = F.geom[m];
+  const double rr = member_sum<double>(F, G, DOT_RR);
+  if (threadIdx.x == 0) {
+    MemberState& S = F.state[m];
+    S.rho0 = sqrt(rr);
+    S.rn = S.rho0;
+    S.rn_cycle = S.rho0;
+    S.it = 0;
+    S.restarts = 0;
+    S.fallback = 0;
+    S.beta = 0.0;
+    S.rtrue = -1.0;
+    S.status = ST_NOT_CONVERGED;
+    S.done = 0;
+    if (!(S.rho0 > 0.0)) {   // zero residual: x_0 solves the problem (NaN: stop too)
+      S.status = S.rho0 == 0.0 ? ST_OK : ST_STAGNATED;
+      S.done = 1;
+    }
+    if (F.hist) F.hist[(long long)m * F.hist_stride] = 1.0;
+  }
+}
+
+template <typename A>
+__global__ void k_ctrl_beta(Fields F, int slot) {
+  const int m = blockIdx.x;
+  MemberState& S = F.state[m];
+  if (S.done) return;
+  const MemberGeom G = F.geom[m];
+  const double lpsq = member_sum<A>(F, G, DOT_LP_LP);
+  const double num = member_sum<A>(F, G, DOT_R_LP);
+  if (threadIdx.x == 0) {
+    S.lpsq[slot] = lpsq;
+    const double beta = -num / lpsq;
+    if (!(lpsq > 0.0) || !isfinite(beta)) {
+      S.status = ST_STAGNATED;
+      S.done = 1;
+    }
+    S.beta = beta;
+  }
+}
+
+// after step 3: exit test on the updated residual, then step-4 coefficients
+template <typename A>
+__global__ void k_ctrl_alpha(Fields F, int nl, Slots sl, int cycle_end, int min_iters, int max_iters, double rtol) {
+  const int m = blockIdx.x;
+  MemberState& S = F.state[m];
+  if (S.done) return;
+  const MemberGeom G = F.geom[m];
+  const double rr = member_sum<A>(F, G, DOT_RR);
+  double dots[KMAX];
+  for (int l = 0; l < KMAX; ++l) dots[l] = l < nl ? member_sum<A>(F, G, DOT_LE_LP + l) : 0.0;
+  if (threadIdx.x == 0) {
+    S.it += 1;
+    const double rn = sqrt(rr);
+    S.rn = rn;
+    if (F.hist && S.it < F.hist_stride) F.hist[(long long)m * F.hist_stride + S.it] = rn / S.rho0;
+    if (!isfinite(rn)) {
+      S.status = ST_STAGNATED;
+      S.done = 1;
+      return;
+    }
+    if (S.it >= min_iters && rn <= rtol * S.rho0) {
+      S.status = ST_OK;
+      S.done = 1;
+      return;
+    }
+    if (S.it >= max_iters) {
+      S.status = ST_NOT_CONVERGED;
+      S.done = 1;
+      return;
+    }
+    for (int l = 0; l < nl; ++l) S.alpha[l] = -dots[l] / S.lpsq[sl.s[l]];
+    if (cycle_end) {
+      if (rn >= S.rn_cycle) {
+        S.status = ST_STAGNATED;
+        S.done = 1;
+        return;
+      }
+      S.rn_cycle = rn;
+    }
+  }
+}
+
+// after a float64 residual recomputation at a restart: replace ||r|| and beta
+template <typename A>
+__global__ void k_ctrl_restart(Fields F, int slot0) {
+  const int m = blockIdx.x;
+  MemberState& S = F.state[m];
+  if (S.done) return;
+  const MemberGeom G = F.geom[m];
+  const double rr = member_sum<double>(F, G, DOT_RR);
+  const double num = member_sum<double>(F, G, DOT_R_LP);
+  if (threadIdx.x == 0) {
+    S.restarts += 1;
+    S.rn = sqrt(rr);
+    S.rn_cycle = S.rn;
+    const double beta = -num / S.lpsq[slot0];
+    if (!isfinite(beta)) {
+      S.status = ST_STAGNATED;
+      S.done = 1;
+    }
+    S.beta = beta;
+  }
+}
+
+// final float64 true residual of every member
+__global__ void k_ctrl_true(Fields F) {
+  const int m = blockIdx.x;
+  const MemberGeom G = F.geom[m];
+  const double rr = member_sum<double>(F, G, DOT_RR);
+  if (threadIdx.x == 0) F.state[m].rtrue = sqrt(rr);
+}
+
+}  // namespace mpgcr

@@ -1,0 +1,720 @@
+// Host runtime and C-ABI of the GCR(k) depth solver (see include/mpgcr.h).
+//
+// The solve is driven from the host one GCR cycle at a time: every kernel of
+// an iteration is enqueued on the solver's stream, the per-member scalars
+// (beta, alpha, ||r||, exit decisions) stay on the device, and the host reads
+// the members' "done" flags once per cycle.  Finished members make every
+// later kernel return at once, so a batch runs until its slowest member.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <type_traits>
+#include <string>
+#include <vector>
+
+#include "../../include/mpgcr.h"
+#include "kernels.h"
+
+using namespace mpgcr;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+// Rows of members with the same points-per-lane M form one contiguous range
+// and are processed by one kernel specialisation.
+struct RowClass {
+  int log2m, row_begin, row_end;
+};
+
+namespace {
+
+template <typename T>
+T* dalloc(size_t n, hipError_t& err) {
+  void* p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess && err == hipSuccess) err = e;
+  return (T*)p;
+}
+
+}  // namespace
+
+struct gcr_solver {
+  gcr_params prm{};
+  std::vector<int> nx, ny;
+  std::vector<MemberGeom> geom_h;
+  std::vector<int> have_op;
+  std::vector<double> scale_h;
+  int rows = 0;
+  long long npts = 0;
+  int nxmax = 0;
+  std::vector<RowClass> classes;     // contiguous row ranges of equal points-per-lane
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+
+  // device memory
+  std::vector<void*> allocs;
+  MemberGeom* geom = nullptr;
+  int* rowmap = nullptr;
+  MemberState* state = nullptr;
+  double* part = nullptr;
+  double* scale = nullptr;
+  double* a64[NCOEF] = {};
+  float* a32[NCOEF] = {};
+  __half* a16[NCOEF] = {};
+  double* c64 = nullptr;
+  float* c32 = nullptr;
+  double* x = nullptr;
+  double* rhs = nullptr;
+  double* r64 = nullptr;
+  void* r = nullptr;
+  void* e = nullptr;
+  void* le = nullptr;
+  void* q[2] = {};
+  float* qs[2] = {};
+  void* p[KMAX + 1] = {};
+  void* lp[KMAX + 1] = {};
+  float* dx = nullptr;
+  double* hist = nullptr;
+  int hist_stride = 0;
+  // float64 scratch for stand-alone preconditioner calls in the mixed forms
+  double* aux_r = nullptr;
+  double* aux_e = nullptr;
+  double* aux_q[2] = {};
+  const double** ptr_rhs = nullptr;  // device tables of caller pointers
+  double** ptr_x = nullptr;
+  const void** ptr_stage = nullptr;  // pinned host staging for the tables
+  MemberState* state_h = nullptr;    // pinned host copy
+
+  // optional per-kernel timing with HIP events on the solver's stream
+  bool timing = false;
+  std::vector<hipEvent_t> ev;        // pool, pairs (start, stop)
+  std::vector<int> ev_kind;          // kind of each recorded pair
+  size_t ev_used = 0;
+  int64_t kt_count[KT_COUNT] = {};
+  double kt_ms[KT_COUNT] = {};
+  void tm_begin(int kind) {
+    if (!timing) return;
+    if (ev_used + 2 > ev.size()) {
+      for (int i = 0; i < 256; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) { timing = false; return; }
+        ev.push_back(e);
+      }
+    }
+    if (ev_kind.size() < ev.size() / 2) ev_kind.resize(ev.size() / 2);
+    ev_kind[ev_used / 2] = kind;
+    (void)hipEventRecord(ev[ev_used], stream);
+  }
+  void tm_end() {
+    if (!timing) return;
+    (void)hipEventRecord(ev[ev_used + 1], stream);
+    ev_used += 2;
+  }
+  void tm_collect() {  // after a stream synchronisation
+    for (size_t i = 0; i + 1 < ev_used; i += 2) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) {
+        kt_count[ev_kind[i / 2]] += 1;
+        kt_ms[ev_kind[i / 2]] += ms;
+      }
+    }
+    ev_used = 0;
+  }
+};
+
+static int fail(gcr_solver* s, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (s) s->err = buf;
+  else g_create_error = buf;
+  return code;
+}
+
+#define HIPCHK(s, call)                                                                        \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) return fail((s), GCR_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define KLAUNCH(s, kind, ...)   \
+  do {                          \
+    (s)->tm_begin(kind);        \
+    hipLaunchKernelGGL(__VA_ARGS__); \
+    (s)->tm_end();              \
+  } while (0)
+
+// Launch a kernel through a pointer to its specialisation, timed if enabled.
+template <typename... KArgs, typename... Args>
+static void launch(gcr_solver* s, int kind, void (*kern)(KArgs...), dim3 grid, dim3 block, Args... args) {
+  s->tm_begin(kind);
+  hipLaunchKernelGGL(kern, grid, block, 0, s->stream, args...);
+  s->tm_end();
+}
+
+// One launch of row kernel KNAME<P, M> per row class, each covering that
+// class's rows (one wave per row).
+#define ROWS_LAUNCH(s, CLASSES, F, KIND, KNAME, P, ...)                                     \
+  for (const RowClass& c_ : (CLASSES)) {                                                 \
+    Fields f_ = (F);                                                                     \
+    f_.row_base = c_.row_begin;                                                          \
+    f_.row_end = c_.row_end;                                                             \
+    const dim3 g_((c_.row_end - c_.row_begin + WPB - 1) / WPB), b_(WG);                  \
+    switch (c_.log2m) {                                                                  \
+      case 1: launch(s, KIND, &KNAME<P, 2>, g_, b_, f_, ##__VA_ARGS__); break;            \
+      case 2: launch(s, KIND, &KNAME<P, 4>, g_, b_, f_, ##__VA_ARGS__); break;            \
+      case 3: launch(s, KIND, &KNAME<P, 8>, g_, b_, f_, ##__VA_ARGS__); break;            \
+      default: launch(s, KIND, &KNAME<P, 16>, g_, b_, f_, ##__VA_ARGS__); break;          \
+    }                                                                                    \
+  }
+
+static std::vector<RowClass> member_class(const gcr_solver* s, int member) {
+  const MemberGeom& G = s->geom_h[member];
+  return {RowClass{G.log2m, G.row0, G.row0 + G.ny}};
+}
+
+static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+static int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+static Fields make_fields(gcr_solver* s) {
+  Fields F{};
+  F.geom = s->geom;
+  F.rowmap = s->rowmap;
+  F.state = s->state;
+  F.part = s->part;
+  F.scale = s->scale;
+  for (int k = 0; k < NCOEF; ++k) {
+    F.c64.a[k] = s->a64[k];
+    F.cmx.h[k] = s->a16[k];
+    F.cmx.f[k] = s->a32[k];
+  }
+  F.c64.c = s->c64;
+  F.cmx.c = s->c32;
+  F.x = s->x;
+  F.rhs = s->rhs;
+  F.r64 = s->r64;
+  F.r = s->r;
+  F.e = s->e;
+  F.le = s->le;
+  for (int i = 0; i < 2; ++i) {
+    F.q[i] = s->q[i];
+    F.qs[i] = s->qs[i];
+  }
+  for (int i = 0; i <= s->prm.k; ++i) {
+    F.p[i] = s->p[i];
+    F.lp[i] = s->lp[i];
+  }
+  F.dx = s->prm.precision == GCR_MIXED ? s->dx : nullptr;
+  F.hist = s->hist;
+  F.hist_stride = s->hist_stride;
+  F.row_base = 0;
+  F.row_end = s->rows;
+  F.ignore_done = 0;
+  return F;
+}
+
+extern "C" int gcr_default_params(gcr_params* p) {
+  if (!p) return GCR_EINVAL;
+  std::memset(p, 0, sizeof *p);
+  p->batch = 1;
+  p->k = 3;
+  p->precision = GCR_FP64;
+  p->precond = GCR_PC_SEMI_IMPLICIT;
+  p->richardson_iters = 2;
+  p->polar_rows = -1;
+  p->min_iters = -1;
+  p->max_iters = 200;
+  p->rtol = 1e-8;
+  return GCR_OK;
+}
+
+static void free_all(gcr_solver* s) {
+  for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+  s->ev.clear();
+  for (void* a : s->allocs)
+    if (a) (void)hipFree(a);
+  s->allocs.clear();
+  if (s->ptr_stage) (void)hipHostFree(s->ptr_stage);
+  if (s->state_h) (void)hipHostFree(s->state_h);
+  s->ptr_stage = nullptr;
+  s->state_h = nullptr;
+}
+
+extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
+  if (out) *out = nullptr;
+  if (!prm || !out) return fail(nullptr, GCR_EINVAL, "gcr_create: NULL argument");
+  const gcr_params& P = *prm;
+  if (P.batch < 1 || P.batch > 4096) return fail(nullptr, GCR_EINVAL, "batch must be in [1, 4096], got %d", P.batch);
+  if (!P.nx || !P.ny) return fail(nullptr, GCR_EINVAL, "nx/ny arrays must not be NULL");
+  if (P.k < 1 || P.k > KMAX) return fail(nullptr, GCR_EINVAL, "k must be in [1, %d], got %d", KMAX, P.k);
+  if (P.precision < GCR_FP64 || P.precision > GCR_MIXED_FP64DOT)
+    return fail(nullptr, GCR_EINVAL, "unknown precision form %d", P.precision);
+  if (P.precond < GCR_PC_NONE || P.precond > GCR_PC_SEMI_IMPLICIT)
+    return fail(nullptr, GCR_EINVAL, "unsupported preconditioner %d", P.precond);
+  if (P.richardson_iters < 1 || P.richardson_iters > 16)
+    return fail(nullptr, GCR_EINVAL, "richardson_iters must be in [1, 16], got %d", P.richardson_iters);
+  if (P.max_iters < 1 || P.max_iters > 100000) return fail(nullptr, GCR_EINVAL, "max_iters must be in [1, 100000]");
+  if (P.min_iters < -1 || P.min_iters > P.max_iters) return fail(nullptr, GCR_EINVAL, "min_iters out of range");
+  if (!(P.rtol >= 0.0) || !std::isfinite(P.rtol)) return fail(nullptr, GCR_EINVAL, "rtol must be finite and >= 0");
+  if (P.polar_rows < -1) return fail(nullptr, GCR_EINVAL, "polar_rows must be >= -1");
+  for (int m = 0; m < P.batch; ++m) {
+    const int nx = P.nx[m], ny = P.ny[m];
+    if (!is_pow2(nx) || nx < 8 || nx > NXMAX)
+      return fail(nullptr, GCR_EINVAL, "member %d: nx must be a power of two in [8, %d], got %d", m, NXMAX, nx);
+    if (ny < 2 || ny > 4096) return fail(nullptr, GCR_EINVAL, "member %d: ny must be in [2, 4096], got %d", m, ny);
+  }
+
+  gcr_solver* s = new (std::nothrow) gcr_solver();
+  if (!s) return fail(nullptr, GCR_ENOMEM, "host allocation failed");
+  s->prm = P;
+  if (s->prm.min_iters < 0) s->prm.min_iters = std::min(P.k + 1, P.max_iters);
+  s->stream = (hipStream_t)P.stream;
+  s->prm.nx = nullptr;
+  s->prm.ny = nullptr;
+  s->nx.assign(P.nx, P.nx + P.batch);
+  s->ny.assign(P.ny, P.ny + P.batch);
+  s->have_op.assign(P.batch, 0);
+  s->scale_h.assign(P.batch, 1.0);
+  for (int m = 0; m < P.batch; ++m) {
+    MemberGeom G{};
+    G.nx = s->nx[m];
+    G.ny = s->ny[m];
+    G.log2nx = ilog2(G.nx);
+    G.log2m = std::max(1, G.log2nx - 6);  // M = max(2, NX/64) points per lane
+    int polar = P.polar_rows;
+    if (polar < 0) polar = std::max(1, ilog2(std::max(G.ny / 32, 1)));
+    G.polar = std::min(polar, G.ny);
+    G.off = s->npts;
+    s->geom_h.push_back(G);
+    s->npts += ((long long)G.nx * G.ny + 63) / 64 * 64;  // member offsets stay 64-element aligned
+    s->nxmax = std::max(s->nxmax, G.nx);
+  }
+  std::vector<int> rowmap_h;
+  for (int lm = 1; lm <= 4; ++lm) {
+    RowClass c{lm, s->rows, s->rows};
+    for (int m = 0; m < P.batch; ++m) {
+      MemberGeom& G = s->geom_h[m];
+      if (G.log2m != lm) continue;
+      G.row0 = s->rows;
+      for (int j = 0; j < G.ny; ++j) rowmap_h.push_back(m);
+      s->rows += G.ny;
+    }
+    c.row_end = s->rows;
+    if (c.row_end > c.row_begin) s->classes.push_back(c);
+  }
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    delete s;
+    return fail(nullptr, GCR_EHIP, "no HIP device available");
+  }
+  (void)hipGetDevice(&s->device);
+
+  hipError_t herr = hipSuccess;
+  auto track = [&](void* a) { s->allocs.push_back(a); return a; };
+  const long long N = s->npts;
+  const int R = s->rows;
+  const bool mixed = P.precision != GCR_FP64;
+  const size_t vsz = mixed ? sizeof(float) : sizeof(double);
+  const size_t qsz = vsz;  // float16 intermediates (option 3) or Krylov-type ones (options 0-2)
+  s->geom = (MemberGeom*)track(dalloc<MemberGeom>(P.batch, herr));
+  s->rowmap = (int*)track(dalloc<int>(R, herr));
+  s->state = (MemberState*)track(dalloc<MemberState>(P.batch, herr));
+  s->part = (double*)track(dalloc<double>((size_t)R * NDOT, herr));
+  s->scale = (double*)track(dalloc<double>(P.batch, herr));
+  for (int k = 0; k < NCOEF; ++k) {
+    s->a64[k] = (double*)track(dalloc<double>(N, herr));
+    s->a32[k] = (float*)track(dalloc<float>(N, herr));
+    s->a16[k] = (__half*)track(dalloc<__half>(N, herr));
+  }
+  s->c64 = (double*)track(dalloc<double>(R, herr));
+  s->c32 = (float*)track(dalloc<float>(R, herr));
+  s->x = (double*)track(dalloc<double>(N, herr));
+  s->rhs = (double*)track(dalloc<double>(N, herr));
+  s->r64 = (double*)track(dalloc<double>(N, herr));
+  s->r = track(dalloc<char>(N * vsz, herr));
+  s->e = track(dalloc<char>(N * vsz, herr));
+  s->le = track(dalloc<char>(N * vsz, herr));
+  for (int i = 0; i < 2; ++i) {
+    s->q[i] = track(dalloc<char>(N * qsz, herr));
+    s->qs[i] = (float*)track(dalloc<float>(R, herr));
+  }
+  for (int i = 0; i <= P.k; ++i) {
+    s->p[i] = track(dalloc<char>(N * vsz, herr));
+    s->lp[i] = track(dalloc<char>(N * vsz, herr));
+  }
+  if (P.precision == GCR_MIXED) s->dx = (float*)track(dalloc<float>(N, herr));
+  if (mixed) {
+    s->aux_r = (double*)track(dalloc<double>(N, herr));
+    s->aux_e = (double*)track(dalloc<double>(N, herr));
+    s->aux_q[0] = (double*)track(dalloc<double>(N, herr));
+    s->aux_q[1] = (double*)track(dalloc<double>(N, herr));
+  }
+  s->hist_stride = P.max_iters + 1;
+  if (P.flags & GCR_F_RECORD_HISTORY)
+    s->hist = (double*)track(dalloc<double>((size_t)P.batch * s->hist_stride, herr));
+  s->ptr_rhs = (const double**)track(dalloc<const double*>(P.batch, herr));
+  s->ptr_x = (double**)track(dalloc<double*>(P.batch, herr));
+  if (herr == hipSuccess) herr = hipHostMalloc((void**)&s->ptr_stage, 2 * P.batch * sizeof(void*), 0);
+  if (herr == hipSuccess) herr = hipHostMalloc((void**)&s->state_h, P.batch * sizeof(MemberState), 0);
+  if (herr != hipSuccess) {
+    const bool oom = herr == hipErrorOutOfMemory;
+    free_all(s);
+    delete s;
+    return fail(nullptr, oom ? GCR_ENOMEM : GCR_EHIP, "device allocation failed: %s", hipGetErrorString(herr));
+  }
+  herr = hipMemcpyAsync(s->geom, s->geom_h.data(), P.batch * sizeof(MemberGeom), hipMemcpyHostToDevice, s->stream);
+  if (herr == hipSuccess)
+    herr = hipMemcpyAsync(s->rowmap, rowmap_h.data(), R * sizeof(int), hipMemcpyHostToDevice, s->stream);
+  if (herr == hipSuccess) herr = hipMemsetAsync(s->state, 0, P.batch * sizeof(MemberState), s->stream);
+  if (herr == hipSuccess) herr = hipMemsetAsync(s->part, 0, (size_t)R * NDOT * sizeof(double), s->stream);
+  if (herr == hipSuccess) herr = hipStreamSynchronize(s->stream);
+  if (herr != hipSuccess) {
+    free_all(s);
+    delete s;
+    return fail(nullptr, GCR_EHIP, "initialisation failed: %s", hipGetErrorString(herr));
+  }
+  *out = s;
+  return GCR_OK;
+}
+
+extern "C" int gcr_destroy(gcr_solver* s) {
+  if (!s) return GCR_OK;
+  (void)hipStreamSynchronize(s->stream);
+  free_all(s);
+  delete s;
+  return GCR_OK;
+}
+
+extern "C" int gcr_set_operator(gcr_solver* s, int32_t member, const gcr_operator* op) {
+  if (!s) return GCR_EINVAL;
+  if (!op) return fail(s, GCR_EINVAL, "gcr_set_operator: NULL operator");
+  if (member < 0 || member >= s->prm.batch) return fail(s, GCR_EINVAL, "member %d out of range", member);
+  if (!op->depth) return fail(s, GCR_EINVAL, "depth must not be NULL");
+  if (!(op->dt > 0.0) || !(op->g > 0.0) || !(op->radius > 0.0) || !std::isfinite(op->omega) ||
+      !(op->absorber >= 0.0) || !std::isfinite(op->dt * op->g * op->radius * op->absorber))
+    return fail(s, GCR_EINVAL, "dt, g, radius must be > 0, absorber >= 0, all finite");
+  const MemberGeom& G = s->geom_h[member];
+  const long long n = (long long)G.nx * G.ny;
+  // stage inputs into the pools (x and r64 serve as staging for depth/orography)
+  const hipMemcpyKind kind = op->mem_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (!op->mem_is_device) {
+    // host inputs: check positivity of the depth on the host
+    for (long long k = 0; k < n; ++k)
+      if (!(op->depth[k] > 0.0) || !std::isfinite(op->depth[k]))
+        return fail(s, GCR_EINVAL, "depth must be finite and > 0 (point %lld)", k);
+  }
+  HIPCHK(s, hipMemcpyAsync(s->x + G.off, op->depth, n * sizeof(double), kind, s->stream));
+  if (op->orography)
+    HIPCHK(s, hipMemcpyAsync(s->r64 + G.off, op->orography, n * sizeof(double), kind, s->stream));
+  AssembleArgs A{};
+  A.depth = s->x + G.off;
+  A.oro = op->orography ? s->r64 + G.off : nullptr;
+  A.dt = op->dt;
+  A.g = op->g;
+  A.omega = op->omega;
+  A.radius = op->radius;
+  A.absorber = op->absorber;
+  A.nx = G.nx;
+  A.ny = G.ny;
+  A.b_terms = op->b_terms ? 1 : 0;
+  A.row0 = G.row0;
+  A.off = G.off;
+  for (int k = 0; k < NCOEF; ++k) {
+    A.a64[k] = s->a64[k];
+    A.a32[k] = s->a32[k];
+    A.a16[k] = s->a16[k];
+  }
+  A.c64 = s->c64;
+  A.c32 = s->c32;
+  A.scale = s->scale;
+  A.member = member;
+  A.log2m = G.log2m;
+  const int blocks = (int)((n + 255) / 256);
+  KLAUNCH(s, KT_ASSEMBLE, k_assemble, dim3(blocks), dim3(256), 0, s->stream, A);
+  HIPCHK(s, hipGetLastError());
+  s->scale_h[member] = op->dt / (2.0 * op->radius * op->radius);
+  if (!op->mem_is_device) HIPCHK(s, hipStreamSynchronize(s->stream));  // host inputs are read asynchronously
+  s->have_op[member] = 1;
+  return GCR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernel sequences
+// ---------------------------------------------------------------------------
+// e = P^{-1}(r) on the rows of `cls`, optionally fused with the step-2
+// update along ring slot `slot_nu`.
+template <typename P>
+static void launch_precond(gcr_solver* s, const std::vector<RowClass>& cls, const Fields& F, int do_update,
+                           int slot_nu) {
+  const int ri = s->prm.richardson_iters;
+  switch (s->prm.precond) {
+    case GCR_PC_NONE:
+    case GCR_PC_DIAG:
+      ROWS_LAUNCH(s, cls, F, KT_SWEEP1, k_update_simple, P, do_update, slot_nu,
+                  s->prm.precond == GCR_PC_DIAG ? 1 : 0, -1);
+      break;
+    case GCR_PC_RICHARDSON: {
+      // q_1 = r / diag(L); q_{mu+1} = q_mu - (L q_mu - r) / diag(L)
+      ROWS_LAUNCH(s, cls, F, KT_SWEEP1, k_update_simple, P, do_update, slot_nu, 1, ri == 1 ? -1 : 0);
+      int cur = 0;
+      for (int mu = 1; mu < ri; ++mu) {
+        const int nxt = mu + 1 == ri ? -1 : cur ^ 1;
+        ROWS_LAUNCH(s, cls, F, KT_SWEEP2, k_jacobi, P, cur, nxt);
+        cur ^= 1;
+      }
+      break;
+    }
+    default: {
+      ROWS_LAUNCH(s, cls, F, KT_SWEEP1, k_update_sweep1, P, do_update, slot_nu, ri == 1 ? -1 : 0);
+      int cur = 0;
+      for (int mu = 1; mu < ri; ++mu) {
+        const int nxt = mu + 1 == ri ? -1 : cur ^ 1;
+        ROWS_LAUNCH(s, cls, F, KT_SWEEP2, k_sweep2, P, cur, nxt);
+        cur ^= 1;
+      }
+    }
+  }
+}
+
+template <typename P>
+static int run_solve(gcr_solver* s) {
+  using A = typename P::A;
+  const int k = s->prm.k, B = s->prm.batch;
+  Fields F = make_fields(s);
+  const bool mixed = P::mixed;
+  const bool replace = s->prm.precision == GCR_MIXED_FP64DOT;
+  const dim3 ctl(B), wave(64);
+
+  // step 1: r_0 = L(x_0) - R (float64), p_0 = P^{-1}(r_0), L(p_0)
+  ROWS_LAUNCH(s, s->classes, F, KT_RESIDUAL, k_residual, P, 1, -1, 0);
+  KLAUNCH(s, KT_CONTROL, k_ctrl_init<double>, ctl, wave, 0, s->stream, F);
+  launch_precond<P>(s, s->classes, F, 0, 0);
+  Slots sl{};
+  int base = 0;  // ring slot of p_0 in the current cycle
+  // p_0 = e  (the preconditioner wrote e); L(p_0) with <r, L p_0>, <L p_0, L p_0>
+  HIPCHK(s, hipMemcpyAsync(s->p[0], s->e, s->npts * (mixed ? sizeof(float) : sizeof(double)),
+                           hipMemcpyDeviceToDevice, s->stream));
+  ROWS_LAUNCH(s, s->classes, F, KT_APPLY_L, k_apply_L, P, (const void*)s->p[0], s->lp[0], 1, 0, sl);
+  KLAUNCH(s, KT_CONTROL, k_ctrl_beta<A>, ctl, wave, 0, s->stream, F, 0);
+  HIPCHK(s, hipGetLastError());
+
+  int it = 0;
+  bool all_done = false;
+  while (!all_done && it < s->prm.max_iters) {
+    for (int nu = 0; nu < k && it < s->prm.max_iters; ++nu) {
+      ++it;
+      for (int l = 0; l <= k; ++l) sl.s[l] = (base + l) % (k + 1);
+      // step 2 (+ first row solve of step 3)
+      launch_precond<P>(s, s->classes, F, 1, sl.s[nu]);
+      // step 3: L(e) with <L e, L p_l>, l = 0..nu
+      ROWS_LAUNCH(s, s->classes, F, KT_APPLY_L, k_apply_L, P, (const void*)s->e, s->le, 0, nu + 1, sl);
+      KLAUNCH(s, KT_CONTROL, k_ctrl_alpha<A>, ctl, wave, 0, s->stream, F, nu + 1, sl, nu == k - 1 ? 1 : 0,
+                         s->prm.min_iters, s->prm.max_iters, s->prm.rtol);
+      // step 4
+      ROWS_LAUNCH(s, s->classes, F, KT_ORTH, k_orth, P, nu + 1, sl, sl.s[nu + 1]);
+      KLAUNCH(s, KT_CONTROL, k_ctrl_beta<A>, ctl, wave, 0, s->stream, F, sl.s[nu + 1]);
+    }
+    HIPCHK(s, hipGetLastError());
+    base = (base + k) % (k + 1);  // (p_0, L p_0) := (p_k, L p_k)
+    if (replace) {
+      // residual replacement: r = L(x) - R in float64, beta re-derived
+      ROWS_LAUNCH(s, s->classes, F, KT_RESIDUAL, k_residual, P, 1, base, 1);
+      KLAUNCH(s, KT_CONTROL, k_ctrl_restart<double>, ctl, wave, 0, s->stream, F, base);
+    }
+    HIPCHK(s, hipMemcpyAsync(s->state_h, s->state, B * sizeof(MemberState), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    all_done = true;
+    for (int m = 0; m < B; ++m) all_done = all_done && s->state_h[m].done;
+  }
+  if (s->prm.precision == GCR_MIXED) {
+    const dim3 g((unsigned)std::min<long long>((s->npts + 255) / 256, 65535));
+    KLAUNCH(s, KT_COPY, k_apply_increments, g, dim3(256), 0, s->stream, F, s->npts);
+  }
+  // true residual of every member in float64
+  ROWS_LAUNCH(s, s->classes, F, KT_RESIDUAL, k_residual, P, 0, -1, 0);
+  KLAUNCH(s, KT_CONTROL, k_ctrl_true, ctl, wave, 0, s->stream, F);
+  HIPCHK(s, hipGetLastError());
+  return GCR_OK;
+}
+
+extern "C" int gcr_solve(gcr_solver* s, const double* const* rhs, double* const* x, gcr_report* reports) {
+  if (!s) return GCR_EINVAL;
+  if (!rhs || !x) return fail(s, GCR_EINVAL, "gcr_solve: NULL rhs or x table");
+  const int B = s->prm.batch;
+  for (int m = 0; m < B; ++m) {
+    if (!rhs[m] || !x[m]) return fail(s, GCR_EINVAL, "member %d: NULL field pointer", m);
+    if (!s->have_op[m]) return fail(s, GCR_ESTATE, "member %d has no operator (call gcr_set_operator)", m);
+  }
+  HIPCHK(s, hipStreamSynchronize(s->stream));  // staging buffer reuse
+  for (int m = 0; m < B; ++m) {
+    s->ptr_stage[m] = rhs[m];
+    s->ptr_stage[B + m] = x[m];
+  }
+  HIPCHK(s, hipMemcpyAsync(s->ptr_rhs, s->ptr_stage, B * sizeof(void*), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipMemcpyAsync(s->ptr_x, s->ptr_stage + B, B * sizeof(void*), hipMemcpyHostToDevice, s->stream));
+  const dim3 gg(64, B);
+  KLAUNCH(s, KT_COPY, k_gather, gg, dim3(256), 0, s->stream, s->ptr_rhs, s->rhs, s->geom);
+  KLAUNCH(s, KT_COPY, k_gather, gg, dim3(256), 0, s->stream, (const double* const*)s->ptr_x, s->x, s->geom);
+  if (s->dx) HIPCHK(s, hipMemsetAsync(s->dx, 0, s->npts * sizeof(float), s->stream));
+  HIPCHK(s, hipGetLastError());
+  int rc;
+  switch (s->prm.precision) {
+    case GCR_FP64: rc = run_solve<PrecF64>(s); break;
+    case GCR_MIXED: rc = run_solve<PrecMixed>(s); break;
+    default: rc = run_solve<PrecMixedD>(s); break;
+  }
+  if (rc != GCR_OK) return rc;
+  KLAUNCH(s, KT_COPY, k_scatter, gg, dim3(256), 0, s->stream, s->x, s->ptr_x, s->geom);
+  HIPCHK(s, hipGetLastError());
+  HIPCHK(s, hipMemcpyAsync(s->state_h, s->state, B * sizeof(MemberState), hipMemcpyDeviceToHost, s->stream));
+  std::vector<double> hist_h;
+  if (s->hist && reports) {
+    hist_h.resize((size_t)B * s->hist_stride);
+    HIPCHK(s, hipMemcpyAsync(hist_h.data(), s->hist, hist_h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                             s->stream));
+  }
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  s->tm_collect();
+  int worst = GCR_OK;
+  for (int m = 0; m < B; ++m) {
+    const MemberState& S = s->state_h[m];
+    const int st = S.status;
+    if (st > worst) worst = st;
+    if (!reports) continue;
+    gcr_report& rp = reports[m];
+    rp.status = st;
+    rp.iterations = S.it;
+    rp.restarts = S.restarts;
+    rp.fallback_used = S.fallback;
+    const double sc = s->prm.precision == GCR_FP64 ? 1.0 : s->scale_h[m];
+    rp.r0_norm = S.rho0 / sc;
+    rp.rel_res_recursive = S.rho0 > 0 ? S.rn / S.rho0 : 0.0;
+    rp.rel_res_true = S.rho0 > 0 ? S.rtrue / S.rho0 : 0.0;
+    rp.history_len = 0;
+    if (rp.history && rp.history_cap > 0 && s->hist) {
+      const int n = std::min(rp.history_cap, std::min(S.it + 1, s->hist_stride));
+      std::memcpy(rp.history, hist_h.data() + (size_t)m * s->hist_stride, n * sizeof(double));
+      rp.history_len = n;
+    }
+  }
+  return worst;
+}
+
+// ---------------------------------------------------------------------------
+// stand-alone operator and preconditioner (float64)
+// ---------------------------------------------------------------------------
+static int check_member(gcr_solver* s, int32_t member, const void* a, const void* b) {
+  if (!s) return GCR_EINVAL;
+  if (member < 0 || member >= s->prm.batch) return fail(s, GCR_EINVAL, "member %d out of range", member);
+  if (!a || !b) return fail(s, GCR_EINVAL, "NULL field pointer");
+  if (a == b) return fail(s, GCR_EINVAL, "input and output must not alias");
+  if (!s->have_op[member]) return fail(s, GCR_ESTATE, "member %d has no operator", member);
+  return GCR_OK;
+}
+
+extern "C" int gcr_apply_operator(gcr_solver* s, int32_t member, const double* x, double* y) {
+  int rc = check_member(s, member, x, y);
+  if (rc != GCR_OK) return rc;
+  const MemberGeom& G = s->geom_h[member];
+  const long long n = (long long)G.nx * G.ny;
+  const dim3 cg((unsigned)std::min<long long>((n + 255) / 256, 1024));
+  KLAUNCH(s, KT_COPY, k_to_pool, cg, dim3(256), 0, s->stream, x, s->x, G);
+  Fields F = make_fields(s);
+  F.row_base = G.row0;
+  F.row_end = G.row0 + G.ny;
+  F.ignore_done = 1;
+  Slots sl{};
+  ROWS_LAUNCH(s, member_class(s, member), F, KT_APPLY_L, k_apply_L, PrecF64, (const void*)(s->x), (void*)s->r64, 2,
+              0, sl);
+  KLAUNCH(s, KT_COPY, k_from_pool, cg, dim3(256), 0, s->stream, (const double*)s->r64, y, G);
+  HIPCHK(s, hipGetLastError());
+  return GCR_OK;
+}
+
+extern "C" int gcr_apply_precond(gcr_solver* s, int32_t member, const double* r, double* e) {
+  int rc = check_member(s, member, r, e);
+  if (rc != GCR_OK) return rc;
+  const MemberGeom& G = s->geom_h[member];
+  const long long n = (long long)G.nx * G.ny;
+  Fields F = make_fields(s);
+  if (s->prm.precision != GCR_FP64) {
+    F.r = s->aux_r;
+    F.e = s->aux_e;
+    F.q[0] = s->aux_q[0];
+    F.q[1] = s->aux_q[1];
+  }
+  F.row_base = G.row0;
+  F.row_end = G.row0 + G.ny;
+  F.ignore_done = 1;
+  const dim3 cg((unsigned)std::min<long long>((n + 255) / 256, 1024));
+  KLAUNCH(s, KT_COPY, k_to_pool, cg, dim3(256), 0, s->stream, r, (double*)F.r, G);
+  launch_precond<PrecF64>(s, member_class(s, member), F, 0, 0);
+  KLAUNCH(s, KT_COPY, k_from_pool, cg, dim3(256), 0, s->stream, (const double*)F.e, e, G);
+  HIPCHK(s, hipGetLastError());
+  return GCR_OK;
+}
+
+extern "C" const char* gcr_status_string(int code) {
+  switch (code) {
+    case GCR_OK: return "converged";
+    case GCR_NOT_CONVERGED: return "not converged (max_iters reached)";
+    case GCR_STAGNATED: return "stagnated (breakdown or no decrease over a cycle)";
+    case GCR_FALLBACK_USED: return "converged after falling back to the semi-implicit preconditioner";
+    case GCR_EINVAL: return "invalid argument";
+    case GCR_ENOMEM: return "out of memory";
+    case GCR_EHIP: return "HIP runtime error";
+    case GCR_ESTATE: return "call out of order";
+    default: return "unknown status";
+  }
+}
+
+extern "C" const char* gcr_last_error(const gcr_solver* s) {
+  if (!s) return g_create_error.c_str();
+  return s->err.c_str();
+}
+
+extern "C" const char* gcr_version(void) { return "mpgcr 0.1.0 gfx950"; }
+
+extern "C" int gcr_set_kernel_timing(gcr_solver* s, int32_t enable) {
+  if (!s) return GCR_EINVAL;
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  s->tm_collect();
+  s->timing = enable != 0;
+  for (int k = 0; k < KT_COUNT; ++k) {
+    s->kt_count[k] = 0;
+    s->kt_ms[k] = 0.0;
+  }
+  return GCR_OK;
+}
+
+extern "C" int gcr_kernel_time(gcr_solver* s, int32_t kind, int64_t* launches, double* total_ms) {
+  if (!s || !launches || !total_ms || kind < 0 || kind >= KT_COUNT) return GCR_EINVAL;
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  s->tm_collect();
+  *launches = s->kt_count[kind];
+  *total_ms = s->kt_ms[kind];
+  return GCR_OK;
+}
+
+extern "C" const char* gcr_kernel_name(int32_t kind) {
+  static const char* names[KT_COUNT] = {"assemble", "residual",  "update_sweep1", "sweep2",    "apply_L",
+                                        "orth",     "control",   "copy",          "persistent"};
+  return (kind >= 0 && kind < KT_COUNT) ? names[kind] : "unknown";
+}

@@ -1,0 +1,259 @@
+"""ctypes binding of the mpgcr C-ABI (include/mpgcr.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+torch supplies device memory and the stream; fields are float64 CUDA tensors
+of shape (ny, nx), contiguous.  When the library has not been built this
+module raises at import time instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+from .build import lib_path
+
+# status codes / enums (mirroring include/mpgcr.h)
+OK, NOT_CONVERGED, STAGNATED, FALLBACK_USED = 0, 1, 2, 3
+EINVAL, ENOMEM, EHIP, ESTATE = -1, -2, -3, -4
+FP64, MIXED, MIXED_FP64DOT = 0, 1, 2
+PC_NONE, PC_DIAG, PC_RICHARDSON, PC_SEMI_IMPLICIT, PC_LEARNED = 0, 1, 2, 3, 4
+F_RECORD_HISTORY, F_USE_GRAPH, F_PERSISTENT = 0x1, 0x2, 0x4
+
+RADIUS = 6.371e6
+GRAVITY = 9.80616
+OMEGA = 7.292e-5
+
+
+class GcrParams(C.Structure):
+    _fields_ = [
+        ("batch", C.c_int32), ("nx", C.POINTER(C.c_int32)), ("ny", C.POINTER(C.c_int32)),
+        ("k", C.c_int32), ("precision", C.c_int32), ("precond", C.c_int32),
+        ("richardson_iters", C.c_int32), ("polar_rows", C.c_int32), ("min_iters", C.c_int32),
+        ("max_iters", C.c_int32), ("rtol", C.c_double), ("stream", C.c_void_p), ("flags", C.c_uint32),
+    ]
+
+
+class GcrOperator(C.Structure):
+    _fields_ = [
+        ("dt", C.c_double), ("g", C.c_double), ("omega", C.c_double), ("radius", C.c_double),
+        ("absorber", C.c_double), ("depth", C.c_void_p), ("orography", C.c_void_p),
+        ("b_terms", C.c_int32), ("mem_is_device", C.c_int32),
+    ]
+
+
+class GcrReport(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32), ("iterations", C.c_int32), ("restarts", C.c_int32),
+        ("fallback_used", C.c_int32), ("r0_norm", C.c_double), ("rel_res_recursive", C.c_double),
+        ("rel_res_true", C.c_double), ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int32),
+        ("history_len", C.c_int32),
+    ]
+
+
+# every symbol the header declares, with its ctypes signature
+_SIGNATURES = {
+    "gcr_default_params": (C.c_int, [C.POINTER(GcrParams)]),
+    "gcr_create": (C.c_int, [C.POINTER(GcrParams), C.POINTER(C.c_void_p)]),
+    "gcr_set_operator": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(GcrOperator)]),
+    "gcr_solve": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(GcrReport)]),
+    "gcr_apply_operator": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "gcr_apply_precond": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "gcr_destroy": (C.c_int, [C.c_void_p]),
+    "gcr_status_string": (C.c_char_p, [C.c_int]),
+    "gcr_last_error": (C.c_char_p, [C.c_void_p]),
+    "gcr_version": (C.c_char_p, []),
+    "gcr_set_kernel_timing": (C.c_int, [C.c_void_p, C.c_int32]),
+    "gcr_kernel_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    "gcr_kernel_name": (C.c_char_p, [C.c_int32]),
+}
+
+K_ASSEMBLE, K_RESIDUAL, K_SWEEP1, K_SWEEP2, K_APPLY_L, K_ORTH, K_CONTROL, K_COPY, K_PERSISTENT = range(9)
+K_COUNT = 9
+
+
+def _load():
+    path = lib_path()
+    if not os.path.exists(path):
+        raise ImportError(f"mpgcr HIP library not built ({path}); run python -m paper_2103_16120_amd.build")
+    lib = C.CDLL(path)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+class GcrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_lib.gcr_status_string(code).decode()} ({code}): {msg}")
+        self.code = code
+
+
+def version() -> str:
+    return _lib.gcr_version().decode()
+
+
+def status_string(code: int) -> str:
+    return _lib.gcr_status_string(code).decode()
+
+
+@dataclass
+class Report:
+    status: int
+    iterations: int
+    restarts: int
+    fallback_used: int
+    r0_norm: float
+    rel_res_recursive: float
+    rel_res_true: float
+    history: list
+
+
+def _check_field(t: torch.Tensor, ny: int, nx: int, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != (ny, nx):
+        raise ValueError(f"{name} must be a contiguous float64 tensor of shape ({ny}, {nx})")
+
+
+class Solver:
+    """A batch of independent GCR(k) depth solves sharing one configuration."""
+
+    def __init__(self, sizes, k=3, precision=FP64, precond=PC_SEMI_IMPLICIT, richardson_iters=2,
+                 polar_rows=-1, min_iters=-1, max_iters=200, rtol=1e-8, stream=None, flags=0):
+        self.sizes = [(int(nx), int(ny)) for nx, ny in sizes]
+        b = len(self.sizes)
+        self._nx = (C.c_int32 * b)(*[s[0] for s in self.sizes])
+        self._ny = (C.c_int32 * b)(*[s[1] for s in self.sizes])
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        p = GcrParams()
+        _lib.gcr_default_params(C.byref(p))
+        p.batch, p.nx, p.ny = b, self._nx, self._ny
+        p.k, p.precision, p.precond = k, precision, precond
+        p.richardson_iters, p.polar_rows = richardson_iters, polar_rows
+        p.min_iters, p.max_iters, p.rtol = min_iters, max_iters, rtol
+        p.stream = C.c_void_p(stream.cuda_stream)
+        p.flags = flags
+        self.params = p
+        h = C.c_void_p()
+        rc = _lib.gcr_create(C.byref(p), C.byref(h))
+        if rc < 0:
+            raise GcrError(rc, _lib.gcr_last_error(None).decode())
+        self._h = h
+        self.max_iters = max_iters
+
+    def _err(self, rc):
+        return GcrError(rc, _lib.gcr_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.gcr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_operator(self, member, depth, dt, orography=None, absorber=0.0, g=GRAVITY, omega=OMEGA,
+                     radius=RADIUS, b_terms=True):
+        """depth / orography: float64 CUDA tensors (ny, nx) or numpy arrays."""
+        nx, ny = self.sizes[member]
+        keep = []
+
+        def ptr(a):
+            if a is None:
+                return None, None
+            if isinstance(a, torch.Tensor):
+                _check_field(a, ny, nx, "field")
+                return a.data_ptr(), 1
+            import numpy as np
+            arr = np.ascontiguousarray(a, dtype=np.float64)
+            if arr.shape != (ny, nx):
+                raise ValueError(f"field must have shape ({ny}, {nx})")
+            keep.append(arr)
+            return arr.ctypes.data, 0
+
+        dptr, dev = ptr(depth)
+        optr, odev = ptr(orography)
+        if optr is not None and odev != dev:
+            raise ValueError("depth and orography must both be on the host or both on the device")
+        op = GcrOperator(dt=dt, g=g, omega=omega, radius=radius, absorber=absorber, depth=dptr,
+                         orography=optr, b_terms=1 if b_terms else 0, mem_is_device=dev)
+        rc = _lib.gcr_set_operator(self._h, member, C.byref(op))
+        if rc < 0:
+            raise self._err(rc)
+
+    def solve(self, rhs, x, record_history=False):
+        """rhs, x: lists (one per member) of float64 CUDA tensors; x is updated
+        in place.  Returns a list of Report."""
+        b = len(self.sizes)
+        if len(rhs) != b or len(x) != b:
+            raise ValueError("one rhs and one x per member")
+        for m, (nx, ny) in enumerate(self.sizes):
+            _check_field(rhs[m], ny, nx, f"rhs[{m}]")
+            _check_field(x[m], ny, nx, f"x[{m}]")
+        rp = (C.c_void_p * b)(*[t.data_ptr() for t in rhs])
+        xp = (C.c_void_p * b)(*[t.data_ptr() for t in x])
+        reps = (GcrReport * b)()
+        bufs = []
+        if record_history:
+            for m in range(b):
+                buf = (C.c_double * (self.max_iters + 1))()
+                bufs.append(buf)
+                reps[m].history = C.cast(buf, C.POINTER(C.c_double))
+                reps[m].history_cap = self.max_iters + 1
+        rc = _lib.gcr_solve(self._h, rp, xp, reps)
+        if rc < 0:
+            raise self._err(rc)
+        out = []
+        for m in range(b):
+            r = reps[m]
+            hist = list(bufs[m][:r.history_len]) if record_history else []
+            out.append(Report(r.status, r.iterations, r.restarts, r.fallback_used, r.r0_norm,
+                              r.rel_res_recursive, r.rel_res_true, hist))
+        return out
+
+    def set_kernel_timing(self, enable=True):
+        rc = _lib.gcr_set_kernel_timing(self._h, 1 if enable else 0)
+        if rc < 0:
+            raise self._err(rc)
+
+    def kernel_times(self):
+        """{kernel name: (launches, total milliseconds)} since timing was enabled."""
+        out = {}
+        for k in range(K_COUNT):
+            n = C.c_int64()
+            ms = C.c_double()
+            rc = _lib.gcr_kernel_time(self._h, k, C.byref(n), C.byref(ms))
+            if rc < 0:
+                raise self._err(rc)
+            out[_lib.gcr_kernel_name(k).decode()] = (n.value, ms.value)
+        return out
+
+    def apply_operator(self, member, x, out=None):
+        nx, ny = self.sizes[member]
+        _check_field(x, ny, nx, "x")
+        y = torch.empty_like(x) if out is None else out
+        rc = _lib.gcr_apply_operator(self._h, member, x.data_ptr(), y.data_ptr())
+        if rc < 0:
+            raise self._err(rc)
+        return y
+
+    def apply_precond(self, member, r, out=None):
+        nx, ny = self.sizes[member]
+        _check_field(r, ny, nx, "r")
+        e = torch.empty_like(r) if out is None else out
+        rc = _lib.gcr_apply_precond(self._h, member, r.data_ptr(), e.data_ptr())
+        if rc < 0:
+            raise self._err(rc)
+        return e

@@ -1,0 +1,117 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+the header declares, and rejects invalid arguments before touching a device."""
+import ctypes as C
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b((?:gcr|cnn)_\w+)\s*\(", text, re.M):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2103_16120_amd import lib as L
+    return L
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ["gcr_create", "gcr_set_operator", "gcr_solve", "gcr_destroy"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    cdll = lib._lib
+    missing = [n for n in sorted(_declared()) if not hasattr(cdll, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol(lib):
+    assert _declared() <= set(lib._SIGNATURES)
+
+
+def test_version_and_status_strings(lib):
+    assert "gfx950" in lib.version()
+    assert "converged" in lib.status_string(lib.OK)
+    assert "invalid" in lib.status_string(lib.EINVAL)
+
+
+def _params(lib, nx=(64,), ny=(32,), **kw):
+    p = lib.GcrParams()
+    assert lib._lib.gcr_default_params(C.byref(p)) == lib.OK
+    b = len(nx)
+    p.batch = b
+    p._nxa = (C.c_int32 * b)(*nx)
+    p._nya = (C.c_int32 * b)(*ny)
+    p.nx, p.ny = p._nxa, p._nya
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_defaults(lib):
+    p = lib.GcrParams()
+    lib._lib.gcr_default_params(C.byref(p))
+    assert (p.k, p.precision, p.precond, p.richardson_iters, p.max_iters) == (3, lib.FP64, lib.PC_SEMI_IMPLICIT, 2, 200)
+    assert p.rtol == 1e-8 and p.min_iters == -1 and p.polar_rows == -1
+    assert lib._lib.gcr_default_params(None) == lib.EINVAL
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=(63,)), dict(nx=(2048,)), dict(nx=(4,)), dict(ny=(1,)), dict(k=0), dict(k=9),
+    dict(precision=7), dict(precond=9), dict(richardson_iters=0), dict(max_iters=0),
+    dict(rtol=-1.0), dict(rtol=float("nan")), dict(min_iters=500), dict(polar_rows=-2),
+])
+def test_create_rejects_invalid_params(lib, bad):
+    kw = dict(bad)
+    nx = kw.pop("nx", (64,))
+    ny = kw.pop("ny", (32,))
+    p = _params(lib, nx, ny, **kw)
+    h = C.c_void_p(123)
+    assert lib._lib.gcr_create(C.byref(p), C.byref(h)) == lib.EINVAL
+    assert h.value is None
+    assert len(lib._lib.gcr_last_error(None)) > 0
+
+
+def test_create_null_and_batch_limits(lib):
+    h = C.c_void_p()
+    assert lib._lib.gcr_create(None, C.byref(h)) == lib.EINVAL
+    p = _params(lib)
+    p.batch = 0
+    assert lib._lib.gcr_create(C.byref(p), C.byref(h)) == lib.EINVAL
+    p = _params(lib)
+    p.nx = None
+    assert lib._lib.gcr_create(C.byref(p), C.byref(h)) == lib.EINVAL
+
+
+def test_destroy_null_is_noop(lib):
+    assert lib._lib.gcr_destroy(None) == lib.OK
+
+
+def test_entry_points_reject_null_solver(lib):
+    assert lib._lib.gcr_set_operator(None, 0, None) == lib.EINVAL
+    assert lib._lib.gcr_solve(None, None, None, None) == lib.EINVAL
+    assert lib._lib.gcr_apply_operator(None, 0, None, None) == lib.EINVAL
+    assert lib._lib.gcr_apply_precond(None, 0, None, None) == lib.EINVAL
+
+
+def test_create_without_gpu_reports_hip_error(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    p = _params(lib)
+    h = C.c_void_p()
+    rc = lib._lib.gcr_create(C.byref(p), C.byref(h))
+    assert rc == lib.EHIP and h.value is None

@@ -1,0 +1,262 @@
+"""Parity of the HIP path with the float64 oracle, through the C-ABI.
+
+Operator and preconditioner: element by element, within a bound derived from
+float64 rounding of the stencil's summands (operator) or from the row
+systems' conditioning (preconditioner).  Full solves: the tolerances of the
+solver's contract -- float64 form: true relative residual at the requested
+tolerance, the oracle's iteration count +-1, solution within 1e-9 of the
+oracle's; mixed forms: relative L2 distance to the oracle's solution <= 1e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.operator import EllipticOperator
+from oracle.precond import Preconditioner
+from oracle.gcr import gcr, CONVERGED
+from workloads import problem, batch_problems
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def stencil_magnitude(op, x):
+    """Pointwise sum of |summands| of L(x), inflated by the conditioning of the
+    latitude-dependent factors: a latitude computed with or without a fused
+    multiply-add differs by ~1 ulp of pi/2, which changes cos(lat) by a
+    relative ~ulp/cos(lat) -- large next to the poles, where A^xx ~ 1/cos.
+    A small multiple of eps times this bounds the float64 rounding of any
+    evaluation order."""
+    g = op.grid
+    ax = np.abs(x)
+    m = ax
+    mx = np.maximum.reduce([ax, np.roll(ax, 1, 1), np.roll(ax, -1, 1)])
+    ext = np.vstack([np.roll(mx[0], g.nx // 2)[None], mx, np.roll(mx[-1], g.nx // 2)[None]])
+    m3 = np.maximum.reduce([ext[:-2], ext[1:-1], ext[2:]])
+    aw = np.roll(op.axx_e, 1, 1)
+    north, south = op.ayy_north_south()
+    zero = np.zeros((1, g.nx))
+    cross = (np.abs(op.axy_e) + np.abs(np.roll(op.axy_e, 1, 1))) / (4 * g.dlam * g.dphi) * 4
+    cross += (np.abs(np.vstack([op.ayx_n, zero])) + np.abs(np.vstack([zero, op.ayx_n]))) / (4 * g.dlam * g.dphi) * 4
+    bterm = (np.abs(op.bx_e) + np.abs(np.roll(op.bx_e, 1, 1))) / g.dlam
+    bterm += (np.abs(np.vstack([op.by_n, zero])) + np.abs(np.vstack([zero, op.by_n]))) / g.dphi
+    cond = 1.0 + 1.0 / np.cos(g.lat)[:, None]
+    return ((2 * (np.abs(op.axx_e) + np.abs(aw)) / g.dlam ** 2 + 2 * (north + south) / g.dphi ** 2
+             + cross + bterm) * m3 + op.c[:, None] * m) * cond
+
+
+def make_solver(lib, sizes, **kw):
+    return lib.Solver(sizes, **kw)
+
+
+OPS = [
+    # nx, ny, dt, extras
+    (64, 32, 600.0, {}),
+    (128, 64, 400.0, dict(absorber=1.0 / (2 * 400.0), orography=True)),
+    (256, 128, 600.0, dict(b_terms=False)),
+    (512, 256, 600.0, {}),
+    (1024, 512, 100.0, dict(orography=True)),
+    (8, 2, 600.0, {}),
+    (16, 7, 900.0, dict(absorber=1e-3)),
+]
+
+
+def _build(nx, ny, dt, extras, seed=0):
+    pr = problem(2, nx, ny, instance=seed, dt=dt)
+    oro = None
+    if extras.get("orography"):
+        rng = np.random.default_rng(77 + seed)
+        oro = 1500.0 * rng.random((ny, nx))
+    kw = dict(absorber=extras.get("absorber", 0.0), b_terms=extras.get("b_terms", True))
+    op = EllipticOperator(nx, ny, pr["depth"], dt, orography=oro, **kw)
+    return pr, oro, kw, op
+
+
+@pytest.mark.parametrize("nx,ny,dt,extras", OPS)
+def test_operator_parity(gpu_lib, nx, ny, dt, extras):
+    pr, oro, kw, op = _build(nx, ny, dt, extras)
+    s = make_solver(gpu_lib, [(nx, ny)])
+    s.set_operator(0, pr["depth"], dt, orography=oro, **kw)
+    x = np.random.default_rng(5).standard_normal((ny, nx))
+    y = host(s.apply_operator(0, dev(x)))
+    ref = op.apply(x)
+    bound = 32 * EPS * stencil_magnitude(op, x)
+    err = np.abs(y - ref)
+    assert np.all(err <= bound), (err.max(), (err / bound).max())
+
+
+@pytest.mark.parametrize("nx,ny,dt,extras", OPS)
+def test_operator_parity_device_inputs(gpu_lib, nx, ny, dt, extras):
+    # same operator built from device-resident depth/orography
+    pr, oro, kw, op = _build(nx, ny, dt, extras, seed=1)
+    s = make_solver(gpu_lib, [(nx, ny)])
+    s.set_operator(0, dev(pr["depth"]), dt, orography=None if oro is None else dev(oro), **kw)
+    x = pr["x_true"]
+    y = host(s.apply_operator(0, dev(x)))
+    ref = op.apply(x)
+    assert np.all(np.abs(y - ref) <= 32 * EPS * stencil_magnitude(op, x))
+
+
+@pytest.mark.parametrize("nx,ny,dt,extras", OPS)
+@pytest.mark.parametrize("option,iters", [(3, 2), (3, 1), (3, 4), (0, 1), (1, 1), (2, 2), (2, 3)])
+def test_preconditioner_parity(gpu_lib, nx, ny, dt, extras, option, iters):
+    pr, oro, kw, op = _build(nx, ny, dt, extras)
+    s = make_solver(gpu_lib, [(nx, ny)], precond=option, richardson_iters=iters)
+    s.set_operator(0, pr["depth"], dt, orography=oro, **kw)
+    r = np.random.default_rng(9).standard_normal((ny, nx))
+    e = host(s.apply_precond(0, dev(r)))
+    ref = Preconditioner(op, option, iters)(r)
+    # row systems are strictly diagonally dominant; their condition number
+    # bounds the amplification of rounding in either solver
+    from oracle.precond import row_systems
+    lo, di, up = row_systems(op)
+    cond = np.max(di / (di - np.abs(lo) - np.abs(up)))
+    tol = 64 * EPS * cond * iters * max(1.0, np.max(np.abs(ref)))
+    err = np.max(np.abs(e - ref))
+    assert err <= tol * 10, (err, tol)
+
+
+def _solve_pair(lib, pr, op, nx, ny, rtol, precision=0, **kw):
+    rhs = op.apply(pr["x_true"])
+    ores = gcr(op, rhs, rtol=rtol, max_iters=kw.get("max_iters", 200))
+    s = make_solver(lib, [(nx, ny)], precision=precision, rtol=rtol, **kw)
+    s.set_operator(0, pr["depth"], pr["dt"])
+    x = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    rep = s.solve([dev(rhs)], [x], record_history=True)[0]
+    return ores, rep, host(x), rhs
+
+
+def test_config1_fp64_parity(gpu_lib):
+    # 64x32, dt = 600 s, rtol 1e-10, GCR(3), option 3 with two Richardson iterations
+    pr = problem(1, 64, 32, dt=600.0)
+    op = EllipticOperator(64, 32, pr["depth"], 600.0)
+    ores, rep, x, rhs = _solve_pair(gpu_lib, pr, op, 64, 32, 1e-10)
+    assert ores.status == CONVERGED and rep.status == gpu_lib.OK
+    assert abs(rep.iterations - ores.iterations) <= 1
+    assert rep.rel_res_true <= 1e-10
+    true_res = np.linalg.norm(op.apply(x) - rhs) / ores.r0_norm
+    assert true_res <= 1e-10
+    assert np.linalg.norm(x - ores.x) / np.linalg.norm(ores.x) <= 1e-9
+    assert rep.r0_norm == pytest.approx(ores.r0_norm, rel=1e-12)
+    n = min(len(rep.history), len(ores.history))
+    assert np.allclose(rep.history[:n], ores.history[:n], rtol=1e-6, atol=1e-14)
+
+
+@pytest.mark.parametrize("nx,ny", [(256, 128), (512, 256)])
+def test_fp64_parity(gpu_lib, nx, ny):
+    pr = problem(2, nx, ny, dt=600.0)
+    op = EllipticOperator(nx, ny, pr["depth"], 600.0)
+    ores, rep, x, rhs = _solve_pair(gpu_lib, pr, op, nx, ny, 1e-8)
+    assert rep.status == gpu_lib.OK
+    assert abs(rep.iterations - ores.iterations) <= 1
+    assert rep.rel_res_true <= 1e-8
+    assert np.linalg.norm(op.apply(x) - rhs) / ores.r0_norm <= 1e-8
+    assert np.linalg.norm(x - ores.x) / np.linalg.norm(ores.x) <= 1e-9
+
+
+@pytest.mark.parametrize("nx,ny", [(256, 128), (512, 256)])
+@pytest.mark.parametrize("precision", [1, 2])
+def test_mixed_forms_vs_oracle(gpu_lib, nx, ny, precision):
+    pr = problem(2, nx, ny, dt=600.0)
+    op = EllipticOperator(nx, ny, pr["depth"], 600.0)
+    ores, rep, x, rhs = _solve_pair(gpu_lib, pr, op, nx, ny, 1e-8, precision=precision, max_iters=60)
+    err = np.linalg.norm(x - ores.x) / np.linalg.norm(ores.x)
+    true_res = np.linalg.norm(op.apply(x) - rhs) / ores.r0_norm
+    print(f"\nprecision={precision} {nx}x{ny}: status={rep.status} it={rep.iterations} "
+          f"restarts={rep.restarts} rec={rep.rel_res_recursive:.3e} true={rep.rel_res_true:.3e} "
+          f"(host {true_res:.3e}) err_vs_oracle={err:.3e} oracle_it={ores.iterations}")
+    assert rep.rel_res_true == pytest.approx(true_res, rel=1e-6, abs=1e-14)
+    if precision == 2:
+        assert rep.status == gpu_lib.OK and true_res <= 1e-8
+    assert err <= 1e-5
+
+
+def test_zero_rhs_and_exact_guess(gpu_lib):
+    pr = problem(1, 64, 32)
+    s = make_solver(gpu_lib, [(64, 32)])
+    s.set_operator(0, pr["depth"], 600.0)
+    x = torch.zeros((32, 64), dtype=torch.float64, device="cuda")
+    rep = s.solve([torch.zeros_like(x)], [x])[0]
+    assert rep.status == gpu_lib.OK and rep.iterations == 0 and torch.all(x == 0)
+    # exact initial guess: r_0 == 0 up to rounding -> at most one cycle
+    op = EllipticOperator(64, 32, pr["depth"], 600.0)
+    xt = dev(pr["x_true"])
+    rhs = s.apply_operator(0, xt)
+    x2 = xt.clone()
+    rep = s.solve([rhs], [x2])[0]
+    assert rep.status in (gpu_lib.OK, gpu_lib.STAGNATED)
+    assert torch.allclose(x2, xt, rtol=0, atol=1e-12)
+
+
+def test_max_iters_reached(gpu_lib):
+    pr = problem(1, 64, 32)
+    op = EllipticOperator(64, 32, pr["depth"], 600.0)
+    rhs = op.apply(pr["x_true"])
+    s = make_solver(gpu_lib, [(64, 32)], precond=0, rtol=0.0, max_iters=7)
+    s.set_operator(0, pr["depth"], 600.0)
+    x = torch.zeros((32, 64), dtype=torch.float64, device="cuda")
+    rep = s.solve([dev(rhs)], [x])[0]
+    assert rep.status == gpu_lib.NOT_CONVERGED and rep.iterations == 7
+    ores = gcr(op, rhs, rtol=0.0, max_iters=7, precond=0)
+    assert np.linalg.norm(host(x) - ores.x) <= 1e-9 * np.linalg.norm(ores.x)
+
+
+@pytest.mark.parametrize("option", [0, 1, 2])
+def test_other_preconditioners_solve(gpu_lib, option):
+    pr = problem(1, 64, 32)
+    op = EllipticOperator(64, 32, pr["depth"], 600.0)
+    rhs = op.apply(pr["x_true"])
+    ores = gcr(op, rhs, rtol=1e-10, precond=option, max_iters=500)
+    s = make_solver(gpu_lib, [(64, 32)], precond=option, rtol=1e-10, max_iters=500)
+    s.set_operator(0, pr["depth"], 600.0)
+    x = torch.zeros((32, 64), dtype=torch.float64, device="cuda")
+    rep = s.solve([dev(rhs)], [x])[0]
+    assert rep.status == gpu_lib.OK
+    assert abs(rep.iterations - ores.iterations) <= max(1, ores.iterations // 20)
+    assert np.linalg.norm(host(x) - ores.x) / np.linalg.norm(ores.x) <= 1e-8
+
+
+@pytest.mark.parametrize("precision", [0, 2])
+def test_batch_members_equal_solo_solves(gpu_lib, precision):
+    probs = batch_problems(3, 5, grids=((64, 32), (128, 64), (256, 128)))
+    sizes = [(p["nx"], p["ny"]) for p in probs]
+    ops = [EllipticOperator(p["nx"], p["ny"], p["depth"], p["dt"]) for p in probs]
+    rhs = [dev(op.apply(p["x_true"])) for op, p in zip(ops, probs)]
+    sb = make_solver(gpu_lib, sizes, precision=precision)
+    for m, p in enumerate(probs):
+        sb.set_operator(m, p["depth"], p["dt"])
+    xb = [torch.zeros((ny, nx), dtype=torch.float64, device="cuda") for nx, ny in sizes]
+    reps = sb.solve(rhs, xb)
+    for m, p in enumerate(probs):
+        s1 = make_solver(gpu_lib, [sizes[m]], precision=precision)
+        s1.set_operator(0, p["depth"], p["dt"])
+        x1 = torch.zeros_like(xb[m])
+        r1 = s1.solve([rhs[m]], [x1])[0]
+        assert r1.iterations == reps[m].iterations
+        assert torch.equal(x1, xb[m]), m
+        ores = gcr(ops[m], host(rhs[m]), rtol=1e-8)
+        assert np.linalg.norm(host(x1) - ores.x) / np.linalg.norm(ores.x) <= (1e-9 if precision == 0 else 1e-5)
+
+
+def test_solve_is_deterministic(gpu_lib):
+    pr = problem(2, 256, 128)
+    op = EllipticOperator(256, 128, pr["depth"], 600.0)
+    rhs = dev(op.apply(pr["x_true"]))
+    s = make_solver(gpu_lib, [(256, 128)], precision=2)
+    s.set_operator(0, pr["depth"], 600.0)
+    outs = []
+    for _ in range(2):
+        x = torch.zeros((128, 256), dtype=torch.float64, device="cuda")
+        s.solve([rhs], [x])
+        outs.append(x)
+    assert torch.equal(outs[0], outs[1])

@@ -26,28 +26,51 @@ def cell_centres(nx: int, ny: int):
     return lam, phi
 
 
+_LEGENDRE_CACHE = {}
+
+
+def _legendre_table(ny, lmax):
+    """Y_lm(colatitude, lambda = 0) for l <= lmax, m <= l at the row latitudes:
+    the fully normalised associated Legendre functions (real for lambda = 0)."""
+    key = (ny, lmax)
+    tab = _LEGENDRE_CACHE.get(key)
+    if tab is None:
+        _, phi = cell_centres(2, ny)
+        theta = 0.5 * np.pi - phi
+        tab = np.zeros((lmax + 1, lmax + 1, ny))
+        for l in range(lmax + 1):
+            for m in range(l + 1):
+                tab[l, m] = sph_harm_y(l, m, theta, 0.0).real
+        _LEGENDRE_CACHE[key] = tab
+    return tab
+
+
 def harmonic_field(nx, ny, lmax, rng, lmin=0, amplitude=1.0, lam_shift=0.0):
     """Real spherical-harmonic series sum_{l=lmin..lmax} sum_m (a cos + b sin),
     coefficients N(0,1) drawn in (l up, m up, cos then sin) order, sampled at
-    the cell centres and rescaled so that max|field| == amplitude.
+    the cell centres and rescaled so that max|field| == amplitude.  The m > 0
+    terms carry the factor sqrt(2) of the orthonormal real harmonics.
 
     ``lam_shift`` evaluates the same series at longitude (lambda - lam_shift),
     i.e. the pattern advected eastward by lam_shift radians.
     """
-    lam, phi = cell_centres(nx, ny)
+    lam, _ = cell_centres(nx, ny)
     lam = lam - lam_shift
-    theta = 0.5 * np.pi - phi  # colatitude
-    TH, LA = np.meshgrid(theta, lam, indexing="ij")
-    field = np.zeros((ny, nx), dtype=np.float64)
+    tab = _legendre_table(ny, lmax)
+    # field = sum_m [ A_m(lat) cos(m lam) + B_m(lat) sin(m lam) ]
+    A = np.zeros((lmax + 1, ny))
+    Bc = np.zeros((lmax + 1, ny))
     for l in range(lmin, lmax + 1):
         for m in range(0, l + 1):
-            y = sph_harm_y(l, m, TH, LA)
             a = rng.standard_normal()
             if m == 0:
-                field += a * y.real
+                A[0] += a * tab[l, 0]
             else:
                 b = rng.standard_normal()
-                field += np.sqrt(2.0) * (a * y.real + b * y.imag)
+                A[m] += np.sqrt(2.0) * a * tab[l, m]
+                Bc[m] += np.sqrt(2.0) * b * tab[l, m]
+    ms = np.arange(lmax + 1)[:, None]
+    field = A.T @ np.cos(ms * lam[None, :]) + Bc.T @ np.sin(ms * lam[None, :])
     peak = np.max(np.abs(field))
     if peak == 0.0:
         return field
