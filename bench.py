@@ -88,8 +88,7 @@ class Leg:
         self.reports = None
 
     def step(self):
-        for m, p in enumerate(self.probs):
-            self.solver.set_operator(m, self.depth[m], p["dt"])
+        self.solver.set_operators(list(range(len(self.probs))), self.depth, [p["dt"] for p in self.probs])
         for x in self.x:
             x.zero_()
         self.reports = self.solver.solve(self.rhs, self.x)
@@ -175,7 +174,7 @@ def main():
     probs, sizes, depth, rhs = make_inputs(args, torch, lib)
     pts = args.nx * args.ny
 
-    mixed = Leg(lib, torch, args, sizes, probs, depth, rhs, lib.MIXED_FP64DOT)
+    mixed = Leg(lib, torch, args, sizes, probs, depth, rhs, lib.MIXED_HALF_PC)
     t_mixed, it_mixed, kt_mixed = mixed.run(args.steps, args.warmup, not args.no_timing)
     rep_m = mixed.reports
     solves = args.batch * args.steps
@@ -198,8 +197,8 @@ def main():
             "workload": f"{args.batch} independent {args.nx}x{args.ny} depth solves per step "
                         f"(assembly + GCR(3) solve, rtol {args.rtol:g}), dt {args.dt:g} s",
             "batch": args.batch, "nx": args.nx, "ny": args.ny, "rtol": args.rtol,
-            "precision": "mixed: f16/f32-polar operator storage, f32 Krylov, f64 dots + f64 "
-                         "solution + f64 residual replacement per restart",
+            "precision": "mixed: f16 (f32 polar rows) preconditioner storage, f32 operator and Krylov "
+                         "vectors, f64 dots + f64 solution + f64 residual replacement per restart",
             "preconditioner": "semi-implicit Richardson, 2 row solves",
         },
         "gcr_iters": {"mean": float(it_mixed.mean()), "min": int(it_mixed.min()), "max": int(it_mixed.max())},

@@ -68,10 +68,14 @@ enum {
                             float32 Krylov vectors and inner products; solver
                             increments accumulated in float32 and added to the
                             float64 solution at exit                                 */
-  GCR_MIXED_FP64DOT = 2  /* as GCR_MIXED, plus float64 inner products, a float64
+  GCR_MIXED_FP64DOT = 2, /* as GCR_MIXED, plus float64 inner products, a float64
                             solution accumulator, and the residual recomputed in
-                            float64 from the solution at every restart and before
-                            exit (residual replacement)                             */
+                            float64 from the solution at every restart
+                            (residual replacement)                                 */
+  GCR_MIXED_HALF_PC = 3  /* as GCR_MIXED_FP64DOT, but the operator applied inside
+                            the Krylov iteration keeps float32 coefficients: half
+                            precision only in the preconditioner, the step the
+                            paper finds most robust to reduced precision          */
 };
 
 /* preconditioners (paper Section 2.3, options 0-3; 4 is a learned network) */
@@ -94,7 +98,7 @@ typedef struct {
   const int32_t* nx;      /* host array [batch]: longitudes per member                */
   const int32_t* ny;      /* host array [batch]: latitudes per member                 */
   int32_t k;              /* GCR(k) window, 1..8 (paper: 3)                           */
-  int32_t precision;      /* GCR_FP64 / GCR_MIXED / GCR_MIXED_FP64DOT                 */
+  int32_t precision;      /* GCR_FP64 / GCR_MIXED / GCR_MIXED_FP64DOT / _HALF_PC      */
   int32_t precond;        /* GCR_PC_*                                                 */
   int32_t richardson_iters; /* Richardson iterations in options 2-3, 1..16 (paper: 2) */
   int32_t polar_rows;     /* rows per pole kept in float32 in the mixed forms;
@@ -123,7 +127,7 @@ typedef struct {
 typedef struct {
   int32_t status;             /* GCR_OK / NOT_CONVERGED / STAGNATED / FALLBACK_USED  */
   int32_t iterations;         /* number of step-2 updates                            */
-  int32_t restarts;           /* residual recomputations (GCR_MIXED_FP64DOT)         */
+  int32_t restarts;           /* residual recomputations (FP64DOT / HALF_PC forms)   */
   int32_t fallback_used;      /* 1 if the learned preconditioner was abandoned       */
   double r0_norm;             /* ||L(x_0) - R||_2                                    */
   double rel_res_recursive;   /* ||r_N|| / ||r_0|| of the iterated residual         */
@@ -149,11 +153,21 @@ int gcr_default_params(gcr_params* p);
 int gcr_create(const gcr_params* params, gcr_solver** out);
 
 /* Build the coefficient fields of member `member` (0-based) from the
- * physical inputs (paper eqs. rhslin, Qexpr, L_Operator; Section 2.2).  The
- * inputs are copied; the caller may free them when the call returns.  All
+ * physical inputs (paper eqs. rhslin, Qexpr, L_Operator; Section 2.2).  All
  * precision forms of the coefficients are built on the device, on the
- * solver's stream.  Errors: GCR_EINVAL, GCR_EHIP. */
+ * solver's stream.  Host inputs are copied before the call returns; device
+ * inputs are read in place by the assembly kernel, so they must stay valid
+ * until that kernel has run (see gcr_set_operators).
+ * Errors: GCR_EINVAL, GCR_EHIP. */
 int gcr_set_operator(gcr_solver* s, int32_t member, const gcr_operator* op);
+
+/* Batched form of gcr_set_operator: members[t] (distinct, 0-based) gets
+ * operator ops[t], t = 0..count-1, all assembled by one kernel launch.  Device
+ * inputs (mem_is_device = 1) are read in place and must stay valid until the
+ * work on the solver's stream has run (any later call that synchronises the
+ * stream, e.g. gcr_solve, guarantees that); host inputs are copied before the
+ * call returns.  Errors: GCR_EINVAL, GCR_EHIP. */
+int gcr_set_operators(gcr_solver* s, int32_t count, const int32_t* members, const gcr_operator* ops);
 
 /* Solve L(x_m) = rhs_m for every member m (paper Section 2.3).
  * rhs, x: host arrays [batch] of device pointers to float64 [NY][NX] fields;

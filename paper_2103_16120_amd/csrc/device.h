@@ -114,6 +114,11 @@ __device__ __forceinline__ void str(__half* row, int l, int L, const T (&v)[M]) 
   for (int k = 0; k < M; ++k) row[l + L * k] = __float2half_rn((float)v[k]);
 }
 
+template <typename T, typename S>
+__device__ __forceinline__ T ld1(const S* p) { return (T)*p; }
+template <typename T>
+__device__ __forceinline__ T ld1(const __half* p) { return (T)__half2float(*p); }
+
 // the same row seen across the pole: longitude shifted by NX/2 = (L/2)*M,
 // i.e. the chunk of lane l + L/2
 template <int M, typename T>

@@ -30,29 +30,17 @@ struct CoefMixed {
   const float* c;             // scaled Helmholtz coefficient per global row (float32)
 };
 
-template <typename T>
-struct CoefView;
-
-template <>
-struct CoefView<double> {
-  const CoefF64* cf;
+// Coefficient rows of one storage precision (chosen once per row).
+template <typename S, typename T>
+struct CoefRow {
+  const S* const* a;          // NCOEF arrays
+  const T* c;                 // Helmholtz coefficient per global row
   template <int M>
-  __device__ __forceinline__ void row(int k, long long start, int l, int L, double (&v)[M]) const {
-    ldr<M>(cf->a[k] + start, l, L, v);
+  __device__ __forceinline__ void row(int k, long long start, int l, int L, T (&v)[M]) const {
+    ldr<M>(a[k] + start, l, L, v);
   }
-  __device__ __forceinline__ double helm(int g) const { return cf->c[g]; }
-};
-
-template <>
-struct CoefView<float> {
-  const CoefMixed* cf;
-  bool polar;
-  template <int M>
-  __device__ __forceinline__ void row(int k, long long start, int l, int L, float (&v)[M]) const {
-    if (polar) ldr<M>(cf->f[k] + start, l, L, v);
-    else ldr<M>(cf->h[k] + start, l, L, v);
-  }
-  __device__ __forceinline__ float helm(int g) const { return cf->c[g]; }
+  __device__ __forceinline__ T one(int k, long long off) const { return ld1<T>(a[k] + off); }
+  __device__ __forceinline__ T helm(int g) const { return c[g]; }
 };
 
 // ---------------------------------------------------------------------------
@@ -64,6 +52,7 @@ struct PrecF64 {              // everything float64
   using Q = double;           // preconditioner intermediate storage
   using T = double;           // arithmetic
   static constexpr bool mixed = false;
+  static constexpr bool op_f32 = false;   // operator coefficients in float32 (not float16)
 };
 struct PrecMixed {            // float32 vectors and inner products, float16 coefficients
   using V = float;
@@ -71,6 +60,7 @@ struct PrecMixed {            // float32 vectors and inner products, float16 coe
   using Q = __half;
   using T = float;
   static constexpr bool mixed = true;
+  static constexpr bool op_f32 = false;
 };
 struct PrecMixedD {           // as PrecMixed with float64 inner products
   using V = float;
@@ -78,6 +68,15 @@ struct PrecMixedD {           // as PrecMixed with float64 inner products
   using Q = __half;
   using T = float;
   static constexpr bool mixed = true;
+  static constexpr bool op_f32 = false;
+};
+struct PrecMixedP {           // as PrecMixedD, float16 only in the preconditioner
+  using V = float;
+  using A = double;
+  using Q = __half;
+  using T = float;
+  static constexpr bool mixed = true;
+  static constexpr bool op_f32 = true;
 };
 
 // Everything a kernel may touch, passed by value.
@@ -107,19 +106,19 @@ struct Fields {
   int ignore_done;            // process finished members too (stand-alone operator calls)
 };
 
-template <typename P>
-__device__ __forceinline__ CoefView<typename P::T> coef_view(const Fields& F, const MemberGeom& G, int j);
-template <>
-__device__ __forceinline__ CoefView<double> coef_view<PrecF64>(const Fields& F, const MemberGeom&, int) {
-  return CoefView<double>{&F.c64};
-}
-template <>
-__device__ __forceinline__ CoefView<float> coef_view<PrecMixed>(const Fields& F, const MemberGeom& G, int j) {
-  return CoefView<float>{&F.cmx, (j < G.polar) || (j >= G.ny - G.polar)};
-}
-template <>
-__device__ __forceinline__ CoefView<float> coef_view<PrecMixedD>(const Fields& F, const MemberGeom& G, int j) {
-  return CoefView<float>{&F.cmx, (j < G.polar) || (j >= G.ny - G.polar)};
+// Run fn(coefficient rows) for row j with the storage precision of the
+// operator applied inside the Krylov iteration (`op`) or of the
+// preconditioner; polar rows always use float32 in the mixed forms.  The
+// choice is wave-uniform and made once per row.
+template <typename P, typename Fn>
+__device__ __forceinline__ void with_coef(const Fields& F, const MemberGeom& G, int j, bool op, Fn&& fn) {
+  if constexpr (!P::mixed) {
+    fn(CoefRow<double, double>{F.c64.a, F.c64.c});
+  } else {
+    const bool f32 = (op && P::op_f32) || (j < G.polar) || (j >= G.ny - G.polar);
+    if (f32) fn(CoefRow<float, float>{F.cmx.f, F.cmx.c});
+    else fn(CoefRow<__half, float>{F.cmx.h, F.cmx.c});
+  }
 }
 
 // Wave -> row assignment.  Returns false when the wave has no row or the
@@ -159,24 +158,25 @@ struct ScaledHalfReader {
 };
 
 // ---------------------------------------------------------------------------
-// 9-point stencil of the discrete L on one row (each lane: its chunk), split into
+// 9-point stencil of the discrete L on one row (each lane: its chunk), split
+// into
 //   zon  = A^xx zonal second difference          (P^Z)
 //   rest = meridional, cross and B terms         (P^M)
 //   L    = zon + rest - C x                      (P^H = C x)
-// Also returns the centre values and the A^xx / A^yy faces the row solves need.
-// Rows beyond the poles are the polar row seen across the pole.
+// delivered point by point, in chunk order, to emit(k, zon, rest, x, axe,
+// axw, ayn, ays) together with the A^xx / A^yy faces the row solves need.
+// Rows beyond the poles are the polar row seen across the pole.  The field
+// rows are held whole; the coefficients stream through per point.
 // ---------------------------------------------------------------------------
-template <typename T, int M, typename CV, typename XR>
-__device__ __forceinline__ void stencil_row(const RowCtx& R, const CV& cv, const XR& X, T (&zon)[M], T (&rest)[M],
-                                            T (&xc)[M], T (&axe)[M], T (&axw)[M], T (&ayn)[M], T (&ays)[M]) {
+template <typename T, int M, typename CV, typename XR, typename Emit>
+__device__ __forceinline__ void stencil_row(const RowCtx& R, const CV& cv, const XR& X, Emit&& emit) {
   const int l = R.lane, L = R.L;
-  T xs[M], xn[M];
+  const int wl = (l - 1) & (L - 1), el = (l + 1) & (L - 1);
+  T xc[M], xs[M], xn[M];
   X.row(R.rc, l, L, xc, R.g);
   if (R.south) X.row(R.rc - R.nx, l, L, xs, R.g - 1);
-  else across_pole(xc, xs, l, L);
   if (R.north) X.row(R.rc + R.nx, l, L, xn, R.g + 1);
-  else across_pole(xc, xn, l, L);
-  T axy[M], bx[M], ayxn[M], byn[M], ayxs[M], bys[M];
+  T axe[M], axy[M], bx[M], ayn[M], ayxn[M], byn[M], ays[M], ayxs[M], bys[M];
   cv.row(C_AXX, R.rc, l, L, axe);
   cv.row(C_AXY, R.rc, l, L, axy);
   cv.row(C_BX, R.rc, l, L, bx);
@@ -191,26 +191,27 @@ __device__ __forceinline__ void stencil_row(const RowCtx& R, const CV& cv, const
 #pragma unroll
     for (int k = 0; k < M; ++k) ays[k] = ayxs[k] = bys[k] = (T)0;
   }
-  T cw[M], ce[M], sw[M], se[M], nw[M], ne[M], axyw[M], bxw[M];
-  west_of(xc, cw, l, L);
-  east_of(xc, ce, l, L);
-  west_of(xs, sw, l, L);
-  east_of(xs, se, l, L);
-  west_of(xn, nw, l, L);
-  east_of(xn, ne, l, L);
-  west_of(axe, axw, l, L);
-  west_of(axy, axyw, l, L);
-  west_of(bx, bxw, l, L);
+  if (!R.south) across_pole(xc, xs, l, L);
+  if (!R.north) across_pole(xc, xn, l, L);
+  // chunk-edge neighbours from the adjacent lanes
+  const T cw0 = shfl(xc[M - 1], wl), ceM = shfl(xc[0], el);
+  const T sw0 = shfl(xs[M - 1], wl), seM = shfl(xs[0], el);
+  const T nw0 = shfl(xn[M - 1], wl), neM = shfl(xn[0], el);
+  T axe_p = shfl(axe[M - 1], wl), axy_p = shfl(axy[M - 1], wl), bx_p = shfl(bx[M - 1], wl);
 #pragma unroll
   for (int k = 0; k < M; ++k) {
-    const T c = xc[k], w = cw[k], e = ce[k];
-    const T sc = xs[k], nc = xn[k];
-    zon[k] = axe[k] * (e - c) - axw[k] * (c - w);
-    T r = axy[k] * ((nc - sc) + (ne[k] - se[k])) - axyw[k] * ((nw[k] - sw[k]) + (nc - sc));
-    r += bx[k] * (c + e) - bxw[k] * (w + c);
-    r += ayn[k] * (nc - c) + ayxn[k] * ((e - w) + (ne[k] - nw[k])) + byn[k] * (c + nc);
-    r -= ays[k] * (c - sc) + ayxs[k] * ((se[k] - sw[k]) + (e - w)) + bys[k] * (sc + c);
-    rest[k] = r;
+    const T c = xc[k], w = k > 0 ? xc[k - 1] : cw0, e = k < M - 1 ? xc[k + 1] : ceM;
+    const T sc = xs[k], sw = k > 0 ? xs[k - 1] : sw0, se = k < M - 1 ? xs[k + 1] : seM;
+    const T nc = xn[k], nw = k > 0 ? xn[k - 1] : nw0, ne = k < M - 1 ? xn[k + 1] : neM;
+    const T zon = axe[k] * (e - c) - axe_p * (c - w);
+    T r = axy[k] * ((nc - sc) + (ne - se)) - axy_p * ((nw - sw) + (nc - sc));
+    r += bx[k] * (c + e) - bx_p * (w + c);
+    r += ayn[k] * (nc - c) + ayxn[k] * ((e - w) + (ne - nw)) + byn[k] * (c + nc);
+    r -= ays[k] * (c - sc) + ayxs[k] * ((se - sw) + (e - w)) + bys[k] * (sc + c);
+    emit(k, zon, r, c, axe[k], axe_p, ayn[k], ays[k]);
+    axe_p = axe[k];
+    axy_p = axy[k];
+    bx_p = bx[k];
   }
 }
 
@@ -356,25 +357,26 @@ __device__ __forceinline__ void row_update_sweep1(const Fields& F, const RowCtx&
   using T = typename P::T;
   using V = typename P::V;
   using A = typename P::A;
-  const auto cv = coef_view<P>(F, G, R.j);
-  const T helm = cv.helm(R.g);
-  T rv[M];
-  ldr<M>((const V*)F.r + R.rc, R.lane, R.L, rv);
-  if (do_update) {
-    const A acc = row_update<P, M>(F, R, slot_nu, rv);
-    write_partial<A>(F, R, DOT_RR, acc);
-  }
-  T axe[M], axw[M], ayn[M], ays[M], lo[M], di[M], up[M], rh[M], xq[M];
-  row_faces<T, M>(R, cv, axe, axw, ayn, ays);
-#pragma unroll
-  for (int k = 0; k < M; ++k) {
-    const T eta = (T)1 / (ayn[k] + ays[k]);
-    row_system(eta, axe[k], axw[k], helm, lo[k], di[k], up[k]);
-    rh[k] = -eta * rv[k];
-  }
-  solve_row<T, M>(R, lo, di, up, rh, xq);
-  if (qout < 0) store_v<P, M>(F.e, R, xq);
-  else store_q<P, M>(F, qout, R, xq);
+  with_coef<P>(F, G, R.j, false, [&](const auto& cv) {
+    const T helm = cv.helm(R.g);
+    T rv[M];
+    ldr<M>((const V*)F.r + R.rc, R.lane, R.L, rv);
+    if (do_update) {
+      const A acc = row_update<P, M>(F, R, slot_nu, rv);
+      write_partial<A>(F, R, DOT_RR, acc);
+    }
+    T axe[M], axw[M], ayn[M], ays[M], lo[M], di[M], up[M], rh[M], xq[M];
+    row_faces<T, M>(R, cv, axe, axw, ayn, ays);
+  #pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const T eta = (T)1 / (ayn[k] + ays[k]);
+      row_system(eta, axe[k], axw[k], helm, lo[k], di[k], up[k]);
+      rh[k] = -eta * rv[k];
+    }
+    solve_row<T, M>(R, lo, di, up, rh, xq);
+    if (qout < 0) store_v<P, M>(F.e, R, xq);
+    else store_q<P, M>(F, qout, R, xq);
+  });
 }
 
 template <typename P, int M>
@@ -395,27 +397,29 @@ __device__ __forceinline__ void row_sweep2(const Fields& F, const RowCtx& R, con
                                            int qout) {
   using T = typename P::T;
   using V = typename P::V;
-  const auto cv = coef_view<P>(F, G, R.j);
-  const T helm = cv.helm(R.g);
-  T zon[M], rest[M], xc[M], axe[M], axw[M], ayn[M], ays[M], rv[M];
-  if constexpr (P::mixed) {
-    ScaledHalfReader<T> X{(const __half*)F.q[qin], F.qs[qin]};
-    stencil_row<T, M>(R, cv, X, zon, rest, xc, axe, axw, ayn, ays);
-  } else {
-    RowReader<T, double> X{(const double*)F.q[qin]};
-    stencil_row<T, M>(R, cv, X, zon, rest, xc, axe, axw, ayn, ays);
-  }
-  ldr<M>((const V*)F.r + R.rc, R.lane, R.L, rv);
-  T lo[M], di[M], up[M], rh[M], xq[M];
-#pragma unroll
-  for (int k = 0; k < M; ++k) {
-    const T eta = (T)1 / (ayn[k] + ays[k]);
-    row_system(eta, axe[k], axw[k], helm, lo[k], di[k], up[k]);
-    rh[k] = xc[k] + eta * (rest[k] - rv[k]);
-  }
-  solve_row<T, M>(R, lo, di, up, rh, xq);
-  if (qout < 0) store_v<P, M>(F.e, R, xq);
-  else store_q<P, M>(F, qout, R, xq);
+  with_coef<P>(F, G, R.j, false, [&](const auto& cv) {
+    const T helm = cv.helm(R.g);
+    T rv[M];
+    ldr<M>((const V*)F.r + R.rc, R.lane, R.L, rv);
+    RowSolver<T, M> rs;
+    auto emit = [&](int k, T, T rest, T xc, T axe, T axw, T ayn, T ays) {
+      const T eta = (T)1 / (ayn + ays);
+      T lo, di, up;
+      row_system(eta, axe, axw, helm, lo, di, up);
+      rs.push(k, lo, di, up, xc + eta * (rest - rv[k]));
+    };
+    if constexpr (P::mixed) {
+      ScaledHalfReader<T> X{(const __half*)F.q[qin], F.qs[qin]};
+      stencil_row<T, M>(R, cv, X, emit);
+    } else {
+      RowReader<T, double> X{(const double*)F.q[qin]};
+      stencil_row<T, M>(R, cv, X, emit);
+    }
+    T xq[M];
+    rs.solve(R.lane, R.L, xq);
+    if (qout < 0) store_v<P, M>(F.e, R, xq);
+    else store_q<P, M>(F, qout, R, xq);
+  });
 }
 
 template <typename P, int M>
@@ -438,20 +442,21 @@ __device__ __forceinline__ void row_update_simple(const Fields& F, const RowCtx&
   using T = typename P::T;
   using V = typename P::V;
   using A = typename P::A;
-  const auto cv = coef_view<P>(F, G, R.j);
-  T rv[M];
-  ldr<M>((const V*)F.r + R.rc, R.lane, R.L, rv);
-  if (do_update) {
-    const A acc = row_update<P, M>(F, R, slot_nu, rv);
-    write_partial<A>(F, R, DOT_RR, acc);
-  }
-  if (use_diag) {
-    T d[M];
-    diag_row<T, M>(R, cv, d);
-#pragma unroll
-    for (int k = 0; k < M; ++k) rv[k] /= d[k];
-  }
-  store_v<P, M>(qout < 0 ? F.e : F.q[qout], R, rv);
+  with_coef<P>(F, G, R.j, false, [&](const auto& cv) {
+    T rv[M];
+    ldr<M>((const V*)F.r + R.rc, R.lane, R.L, rv);
+    if (do_update) {
+      const A acc = row_update<P, M>(F, R, slot_nu, rv);
+      write_partial<A>(F, R, DOT_RR, acc);
+    }
+    if (use_diag) {
+      T d[M];
+      diag_row<T, M>(R, cv, d);
+  #pragma unroll
+      for (int k = 0; k < M; ++k) rv[k] /= d[k];
+    }
+    store_v<P, M>(qout < 0 ? F.e : F.q[qout], R, rv);
+  });
 }
 
 template <typename P, int M>
@@ -466,16 +471,17 @@ template <typename P, int M>
 __device__ __forceinline__ void row_jacobi(const Fields& F, const RowCtx& R, const MemberGeom& G, int qin, int qout) {
   using T = typename P::T;
   using V = typename P::V;
-  const auto cv = coef_view<P>(F, G, R.j);
-  const T helm = cv.helm(R.g);
-  RowReader<T, V> X{(const V*)F.q[qin]};
-  T zon[M], rest[M], xc[M], axe[M], axw[M], ayn[M], ays[M], rv[M], d[M], o[M];
-  stencil_row<T, M>(R, cv, X, zon, rest, xc, axe, axw, ayn, ays);
-  diag_row<T, M>(R, cv, d);
-  ldr<M>((const V*)F.r + R.rc, R.lane, R.L, rv);
-#pragma unroll
-  for (int k = 0; k < M; ++k) o[k] = xc[k] - ((zon[k] + rest[k] - helm * xc[k]) - rv[k]) / d[k];
-  store_v<P, M>(qout < 0 ? F.e : F.q[qout], R, o);
+  with_coef<P>(F, G, R.j, false, [&](const auto& cv) {
+    const T helm = cv.helm(R.g);
+    RowReader<T, V> X{(const V*)F.q[qin]};
+    T rv[M], d[M], o[M];
+    diag_row<T, M>(R, cv, d);
+    ldr<M>((const V*)F.r + R.rc, R.lane, R.L, rv);
+    stencil_row<T, M>(R, cv, X, [&](int k, T zon, T rest, T xc, T, T, T, T) {
+      o[k] = xc - ((zon + rest - helm * xc) - rv[k]) / d[k];
+    });
+    store_v<P, M>(qout < 0 ? F.e : F.q[qout], R, o);
+  });
 }
 
 template <typename P, int M>
@@ -503,35 +509,36 @@ __device__ __forceinline__ void row_apply_L(const Fields& F, const RowCtx& R, co
   using V = typename P::V;
   using A = typename P::A;
   const int l = R.lane, L = R.L;
-  const auto cv = coef_view<P>(F, G, R.j);
-  const T helm = cv.helm(R.g);
-  RowReader<T, V> X{(const V*)in};
-  T zon[M], rest[M], xc[M], axe[M], axw[M], ayn[M], ays[M], y[M];
-  stencil_row<T, M>(R, cv, X, zon, rest, xc, axe, axw, ayn, ays);
-#pragma unroll
-  for (int k = 0; k < M; ++k) y[k] = (T)(V)(zon[k] + rest[k] - helm * xc[k]);
-  store_v<P, M>(out, R, y);
-  if (mode == 0) {
-    for (int li = 0; li < nl; ++li) {
-      T lv[M];
-      ldr<M>((const V*)F.lp[sl.s[li]] + R.rc, l, L, lv);
-      A acc = (A)0;
-#pragma unroll
-      for (int k = 0; k < M; ++k) acc += (A)y[k] * (A)lv[k];
-      write_partial<A>(F, R, DOT_LE_LP + li, R.act ? acc : (A)0);
+  with_coef<P>(F, G, R.j, true, [&](const auto& cv) {
+    const T helm = cv.helm(R.g);
+    RowReader<T, V> X{(const V*)in};
+    T y[M];
+    stencil_row<T, M>(R, cv, X, [&](int k, T zon, T rest, T xc, T, T, T, T) {
+      y[k] = (T)(V)(zon + rest - helm * xc);
+    });
+    store_v<P, M>(out, R, y);
+    if (mode == 0) {
+      for (int li = 0; li < nl; ++li) {
+        T lv[M];
+        ldr<M>((const V*)F.lp[sl.s[li]] + R.rc, l, L, lv);
+        A acc = (A)0;
+  #pragma unroll
+        for (int k = 0; k < M; ++k) acc += (A)y[k] * (A)lv[k];
+        write_partial<A>(F, R, DOT_LE_LP + li, R.act ? acc : (A)0);
+      }
+    } else if (mode == 1) {
+      T rv[M];
+      ldr<M>((const V*)F.r + R.rc, l, L, rv);
+      A a0 = (A)0, a1 = (A)0;
+  #pragma unroll
+      for (int k = 0; k < M; ++k) {
+        a0 += (A)rv[k] * (A)y[k];
+        a1 += (A)y[k] * (A)y[k];
+      }
+      write_partial<A>(F, R, DOT_R_LP, R.act ? a0 : (A)0);
+      write_partial<A>(F, R, DOT_LP_LP, R.act ? a1 : (A)0);
     }
-  } else if (mode == 1) {
-    T rv[M];
-    ldr<M>((const V*)F.r + R.rc, l, L, rv);
-    A a0 = (A)0, a1 = (A)0;
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-      a0 += (A)rv[k] * (A)y[k];
-      a1 += (A)y[k] * (A)y[k];
-    }
-    write_partial<A>(F, R, DOT_R_LP, R.act ? a0 : (A)0);
-    write_partial<A>(F, R, DOT_LP_LP, R.act ? a1 : (A)0);
-  }
+  });
 }
 
 template <typename P, int M>
@@ -552,19 +559,17 @@ template <typename P, int M>
 __device__ __forceinline__ void row_residual(const Fields& F, const RowCtx& R, int write_krylov, int lp_slot) {
   using V = typename P::V;
   const int l = R.lane, L = R.L;
-  const CoefView<double> cv{&F.c64};
+  const CoefRow<double, double> cv{F.c64.a, F.c64.c};
   const double helm = cv.helm(R.g);
   const double s = P::mixed ? F.scale[R.m] : 1.0;
   RowReader<double, double> X{F.x};
-  double zon[M], rest[M], xc[M], axe[M], axw[M], ayn[M], ays[M], rr[M], b[M];
-  stencil_row<double, M>(R, cv, X, zon, rest, xc, axe, axw, ayn, ays);
+  double rr[M], b[M];
   ldr<M>(F.rhs + R.rc, l, L, b);
   double acc0 = 0.0, acc1 = 0.0;
-#pragma unroll
-  for (int k = 0; k < M; ++k) {
-    rr[k] = zon[k] + rest[k] - helm * xc[k] - b[k];
+  stencil_row<double, M>(R, cv, X, [&](int k, double zon, double rest, double xc, double, double, double, double) {
+    rr[k] = zon + rest - helm * xc - b[k];
     acc0 += rr[k] * rr[k];
-  }
+  });
   if (R.act) str<M>(F.r64 + R.rc, l, L, rr);
   if (write_krylov) {
     double rk[M];
@@ -648,20 +653,22 @@ __global__ __launch_bounds__(WG) void k_orth(Fields F, int nl, Slots sl, int out
 // coefficient assembly (paper eqs. rhslin, Qexpr, L_Operator), one thread per
 // point, float64; also writes the scaled float16 / float32 copies.
 // ---------------------------------------------------------------------------
-struct AssembleArgs {
-  const double* depth;        // member fields (pool offset applied by the host)
-  const double* oro;          // or null
+struct AsmMember {             // one member of a batched assembly
+  const double* depth;        // Phi*, natural [NY][NX] layout (device)
+  const double* oro;          // H0 or null
   double dt, g, omega, radius, absorber;
-  int nx, ny, b_terms, row0;
-  long long off;
+  int member, b_terms;
+};
+
+struct AssembleArgs {
+  const AsmMember* tab;       // [count]
+  const MemberGeom* geom;
   double* a64[NCOEF];
   __half* a16[NCOEF];
   float* a32[NCOEF];
   double* c64;                // per global row
   float* c32;
   double* scale;              // per member: mixed-form scale dt/(2 a^2)
-  int member;
-  int log2m;                  // points per lane of the row-interleaved storage
 };
 
 __device__ __forceinline__ double absorber_at(double lat, double amax) {
@@ -671,38 +678,41 @@ __device__ __forceinline__ double absorber_at(double lat, double amax) {
   return amax * (w > 0.0 ? w : 0.0);
 }
 
+// grid: x over the points of the largest member, y over the table entries
 __global__ void k_assemble(AssembleArgs A) {
-  const int nx = A.nx, ny = A.ny;
+  const AsmMember P = A.tab[blockIdx.y];
+  const MemberGeom G = A.geom[P.member];
+  const int nx = G.nx, ny = G.ny;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nx * ny) return;
-  const int j = idx / nx, i = idx - j * nx;
+  const int j = idx >> G.log2nx, i = idx & (nx - 1);
   const double kPi = 3.14159265358979323846;
   const double dlam = 2.0 * kPi / nx, dphi = kPi / ny;
-  const double delta = 0.5 * A.dt;
+  const double delta = 0.5 * P.dt;
   const int ie = (i + 1) & (nx - 1), iw = (i - 1) & (nx - 1), h = nx >> 1;
-  auto D = [&](int jj, int ii) { return A.depth[(long long)jj * nx + ii]; };
+  auto D = [&](int jj, int ii) { return P.depth[(long long)jj * nx + ii]; };
   auto H = [&](int jj, int ii) {
     if (jj < 0) { jj = 0; ii = (ii + h) & (nx - 1); }
     if (jj >= ny) { jj = ny - 1; ii = (ii + h) & (nx - 1); }
     const long long k = (long long)jj * nx + ii;
-    return A.depth[k] + (A.oro ? A.oro[k] : 0.0);
+    return P.depth[k] + (P.oro ? P.oro[k] : 0.0);
   };
   double out[NCOEF];
   // east face (i+1/2, j), latitude of row j
   {
     const double lat = -0.5 * kPi + (j + 0.5) * dphi;
     const double cs = cos(lat);
-    const double gam = 1.0 + delta * absorber_at(lat, A.absorber);
-    const double b = delta * 2.0 * A.omega * sin(lat);
+    const double gam = 1.0 + delta * absorber_at(lat, P.absorber);
+    const double b = delta * 2.0 * P.omega * sin(lat);
     const double Dn = gam * gam + b * b;
-    const double kap = delta * A.g * 0.5 * (D(j, i) + D(j, ie)) / (2.0 * Dn);
+    const double kap = delta * P.g * 0.5 * (D(j, i) + D(j, ie)) / (2.0 * Dn);
     out[C_AXX] = kap * gam / cs / (dlam * dlam);
     out[C_AXY] = kap * b / (4.0 * dlam * dphi);
     double bx = 0.0;
-    if (A.b_terms) {
+    if (P.b_terms) {
       const double dhl = (H(j, ie) - H(j, i)) / dlam;
       const double dhp = ((H(j + 1, i) - H(j - 1, i)) + (H(j + 1, ie) - H(j - 1, ie))) / (4.0 * dphi);
-      bx = delta * A.g / (2.0 * Dn) * (gam / cs * dhl + b * dhp);
+      bx = delta * P.g / (2.0 * Dn) * (gam / cs * dhl + b * dhp);
     }
     out[C_BX] = bx / (2.0 * dlam);
   }
@@ -710,36 +720,36 @@ __global__ void k_assemble(AssembleArgs A) {
   if (j < ny - 1) {
     const double lat = -0.5 * kPi + (j + 1.0) * dphi;
     const double cs = cos(lat);
-    const double gam = 1.0 + delta * absorber_at(lat, A.absorber);
-    const double b = delta * 2.0 * A.omega * sin(lat);
+    const double gam = 1.0 + delta * absorber_at(lat, P.absorber);
+    const double b = delta * 2.0 * P.omega * sin(lat);
     const double Dn = gam * gam + b * b;
-    const double kap = delta * A.g * 0.5 * (D(j, i) + D(j + 1, i)) / (2.0 * Dn);
+    const double kap = delta * P.g * 0.5 * (D(j, i) + D(j + 1, i)) / (2.0 * Dn);
     out[C_AYY] = kap * gam * cs / (dphi * dphi);
     out[C_AYX] = -kap * b / (4.0 * dlam * dphi);
     double by = 0.0;
-    if (A.b_terms) {
+    if (P.b_terms) {
       const double dhp = (H(j + 1, i) - H(j, i)) / dphi;
       const double dhl = ((H(j, ie) - H(j, iw)) + (H(j + 1, ie) - H(j + 1, iw))) / (4.0 * dlam);
-      by = delta * A.g / (2.0 * Dn) * (-b * dhl + gam * cs * dhp);
+      by = delta * P.g / (2.0 * Dn) * (-b * dhl + gam * cs * dhp);
     }
     out[C_BY] = by / (2.0 * dphi);
   } else {
     out[C_AYY] = out[C_AYX] = out[C_BY] = 0.0;
   }
-  const double s = A.dt / (2.0 * A.radius * A.radius);   // mixed-form scale
-  const long long o = A.off + (long long)j * nx + row_slot(i, A.log2m, nx >> A.log2m);
+  const double s = P.dt / (2.0 * P.radius * P.radius);   // mixed-form scale
+  const long long o = G.off + (long long)j * nx + row_slot(i, G.log2m, nx >> G.log2m);
 #pragma unroll
   for (int k = 0; k < NCOEF; ++k) {
     A.a64[k][o] = out[k];
     A.a32[k][o] = (float)(s * out[k]);
     A.a16[k][o] = __float2half_rn((float)(s * out[k]));
   }
-  if (idx == 0) A.scale[A.member] = s;
+  if (idx == 0) A.scale[P.member] = s;
   if (i == 0) {
     const double lat = -0.5 * kPi + (j + 0.5) * dphi;
-    const double c = 2.0 * A.radius * A.radius * cos(lat) / A.dt;
-    A.c64[A.row0 + j] = c;
-    A.c32[A.row0 + j] = (float)(s * c);
+    const double c = 2.0 * P.radius * P.radius * cos(lat) / P.dt;
+    A.c64[G.row0 + j] = c;
+    A.c32[G.row0 + j] = (float)(s * c);
   }
 }
 

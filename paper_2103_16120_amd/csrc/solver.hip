@@ -94,6 +94,8 @@ struct gcr_solver {
   double** ptr_x = nullptr;
   const void** ptr_stage = nullptr;  // pinned host staging for the tables
   MemberState* state_h = nullptr;    // pinned host copy
+  AsmMember* asm_stage = nullptr;    // pinned staging of the assembly table
+  AsmMember* asm_tab = nullptr;      // device assembly table [batch]
 
   // optional per-kernel timing with HIP events on the solver's stream
   bool timing = false;
@@ -252,8 +254,10 @@ static void free_all(gcr_solver* s) {
   s->allocs.clear();
   if (s->ptr_stage) (void)hipHostFree(s->ptr_stage);
   if (s->state_h) (void)hipHostFree(s->state_h);
+  if (s->asm_stage) (void)hipHostFree(s->asm_stage);
   s->ptr_stage = nullptr;
   s->state_h = nullptr;
+  s->asm_stage = nullptr;
 }
 
 extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
@@ -263,7 +267,7 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   if (P.batch < 1 || P.batch > 4096) return fail(nullptr, GCR_EINVAL, "batch must be in [1, 4096], got %d", P.batch);
   if (!P.nx || !P.ny) return fail(nullptr, GCR_EINVAL, "nx/ny arrays must not be NULL");
   if (P.k < 1 || P.k > KMAX) return fail(nullptr, GCR_EINVAL, "k must be in [1, %d], got %d", KMAX, P.k);
-  if (P.precision < GCR_FP64 || P.precision > GCR_MIXED_FP64DOT)
+  if (P.precision < GCR_FP64 || P.precision > GCR_MIXED_HALF_PC)
     return fail(nullptr, GCR_EINVAL, "unknown precision form %d", P.precision);
   if (P.precond < GCR_PC_NONE || P.precond > GCR_PC_SEMI_IMPLICIT)
     return fail(nullptr, GCR_EINVAL, "unsupported preconditioner %d", P.precond);
@@ -372,7 +376,9 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   s->ptr_rhs = (const double**)track(dalloc<const double*>(P.batch, herr));
   s->ptr_x = (double**)track(dalloc<double*>(P.batch, herr));
   if (herr == hipSuccess) herr = hipHostMalloc((void**)&s->ptr_stage, 2 * P.batch * sizeof(void*), 0);
+  s->asm_tab = (AsmMember*)track(dalloc<AsmMember>(P.batch, herr));
   if (herr == hipSuccess) herr = hipHostMalloc((void**)&s->state_h, P.batch * sizeof(MemberState), 0);
+  if (herr == hipSuccess) herr = hipHostMalloc((void**)&s->asm_stage, P.batch * sizeof(AsmMember), 0);
   if (herr != hipSuccess) {
     const bool oom = herr == hipErrorOutOfMemory;
     free_all(s);
@@ -402,40 +408,64 @@ extern "C" int gcr_destroy(gcr_solver* s) {
   return GCR_OK;
 }
 
-extern "C" int gcr_set_operator(gcr_solver* s, int32_t member, const gcr_operator* op) {
+extern "C" int gcr_set_operators(gcr_solver* s, int32_t count, const int32_t* members, const gcr_operator* ops) {
   if (!s) return GCR_EINVAL;
-  if (!op) return fail(s, GCR_EINVAL, "gcr_set_operator: NULL operator");
-  if (member < 0 || member >= s->prm.batch) return fail(s, GCR_EINVAL, "member %d out of range", member);
-  if (!op->depth) return fail(s, GCR_EINVAL, "depth must not be NULL");
-  if (!(op->dt > 0.0) || !(op->g > 0.0) || !(op->radius > 0.0) || !std::isfinite(op->omega) ||
-      !(op->absorber >= 0.0) || !std::isfinite(op->dt * op->g * op->radius * op->absorber))
-    return fail(s, GCR_EINVAL, "dt, g, radius must be > 0, absorber >= 0, all finite");
-  const MemberGeom& G = s->geom_h[member];
-  const long long n = (long long)G.nx * G.ny;
-  // stage inputs into the pools (x and r64 serve as staging for depth/orography)
-  const hipMemcpyKind kind = op->mem_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  if (!op->mem_is_device) {
-    // host inputs: check positivity of the depth on the host
-    for (long long k = 0; k < n; ++k)
-      if (!(op->depth[k] > 0.0) || !std::isfinite(op->depth[k]))
-        return fail(s, GCR_EINVAL, "depth must be finite and > 0 (point %lld)", k);
+  if (count < 1 || count > s->prm.batch || !members || !ops)
+    return fail(s, GCR_EINVAL, "gcr_set_operators: need 1..batch members and non-NULL tables");
+  std::vector<int> seen(s->prm.batch, 0);
+  int maxpts = 0;
+  for (int t = 0; t < count; ++t) {
+    const int member = members[t];
+    const gcr_operator* op = &ops[t];
+    if (member < 0 || member >= s->prm.batch) return fail(s, GCR_EINVAL, "member %d out of range", member);
+    if (seen[member]++) return fail(s, GCR_EINVAL, "member %d listed twice", member);
+    if (!op->depth) return fail(s, GCR_EINVAL, "member %d: depth must not be NULL", member);
+    if (!(op->dt > 0.0) || !(op->g > 0.0) || !(op->radius > 0.0) || !std::isfinite(op->omega) ||
+        !(op->absorber >= 0.0) || !std::isfinite(op->dt * op->g * op->radius * op->absorber))
+      return fail(s, GCR_EINVAL, "member %d: dt, g, radius must be > 0, absorber >= 0, all finite", member);
+    const MemberGeom& G = s->geom_h[member];
+    const long long n = (long long)G.nx * G.ny;
+    maxpts = std::max<int>(maxpts, (int)n);
+    if (!op->mem_is_device) {
+      for (long long k = 0; k < n; ++k)
+        if (!(op->depth[k] > 0.0) || !std::isfinite(op->depth[k]))
+          return fail(s, GCR_EINVAL, "member %d: depth must be finite and > 0 (point %lld)", member, k);
+    }
   }
-  HIPCHK(s, hipMemcpyAsync(s->x + G.off, op->depth, n * sizeof(double), kind, s->stream));
-  if (op->orography)
-    HIPCHK(s, hipMemcpyAsync(s->r64 + G.off, op->orography, n * sizeof(double), kind, s->stream));
+  // the staging table (pinned) may still feed an earlier upload
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  for (int t = 0; t < count; ++t) {
+    const int member = members[t];
+    const gcr_operator* op = &ops[t];
+    const MemberGeom& G = s->geom_h[member];
+    const long long n = (long long)G.nx * G.ny;
+    AsmMember& a = s->asm_stage[t];
+    a.member = member;
+    a.dt = op->dt;
+    a.g = op->g;
+    a.omega = op->omega;
+    a.radius = op->radius;
+    a.absorber = op->absorber;
+    a.b_terms = op->b_terms ? 1 : 0;
+    if (op->mem_is_device) {
+      a.depth = op->depth;
+      a.oro = op->orography;
+    } else {  // host inputs are staged in the member's x / r64 pool regions
+      HIPCHK(s, hipMemcpyAsync(s->x + G.off, op->depth, n * sizeof(double), hipMemcpyHostToDevice, s->stream));
+      a.depth = s->x + G.off;
+      a.oro = nullptr;
+      if (op->orography) {
+        HIPCHK(s, hipMemcpyAsync(s->r64 + G.off, op->orography, n * sizeof(double), hipMemcpyHostToDevice,
+                                 s->stream));
+        a.oro = s->r64 + G.off;
+      }
+    }
+    s->scale_h[member] = op->dt / (2.0 * op->radius * op->radius);
+  }
+  HIPCHK(s, hipMemcpyAsync(s->asm_tab, s->asm_stage, count * sizeof(AsmMember), hipMemcpyHostToDevice, s->stream));
   AssembleArgs A{};
-  A.depth = s->x + G.off;
-  A.oro = op->orography ? s->r64 + G.off : nullptr;
-  A.dt = op->dt;
-  A.g = op->g;
-  A.omega = op->omega;
-  A.radius = op->radius;
-  A.absorber = op->absorber;
-  A.nx = G.nx;
-  A.ny = G.ny;
-  A.b_terms = op->b_terms ? 1 : 0;
-  A.row0 = G.row0;
-  A.off = G.off;
+  A.tab = s->asm_tab;
+  A.geom = s->geom;
   for (int k = 0; k < NCOEF; ++k) {
     A.a64[k] = s->a64[k];
     A.a32[k] = s->a32[k];
@@ -444,15 +474,19 @@ extern "C" int gcr_set_operator(gcr_solver* s, int32_t member, const gcr_operato
   A.c64 = s->c64;
   A.c32 = s->c32;
   A.scale = s->scale;
-  A.member = member;
-  A.log2m = G.log2m;
-  const int blocks = (int)((n + 255) / 256);
-  KLAUNCH(s, KT_ASSEMBLE, k_assemble, dim3(blocks), dim3(256), 0, s->stream, A);
+  KLAUNCH(s, KT_ASSEMBLE, k_assemble, dim3((maxpts + 255) / 256, count), dim3(256), 0, s->stream, A);
   HIPCHK(s, hipGetLastError());
-  s->scale_h[member] = op->dt / (2.0 * op->radius * op->radius);
-  if (!op->mem_is_device) HIPCHK(s, hipStreamSynchronize(s->stream));  // host inputs are read asynchronously
-  s->have_op[member] = 1;
+  bool host_inputs = false;
+  for (int t = 0; t < count; ++t) host_inputs = host_inputs || !ops[t].mem_is_device;
+  if (host_inputs) HIPCHK(s, hipStreamSynchronize(s->stream));  // host arrays are read asynchronously
+  for (int t = 0; t < count; ++t) s->have_op[members[t]] = 1;
   return GCR_OK;
+}
+
+extern "C" int gcr_set_operator(gcr_solver* s, int32_t member, const gcr_operator* op) {
+  if (!s) return GCR_EINVAL;
+  if (!op) return fail(s, GCR_EINVAL, "gcr_set_operator: NULL operator");
+  return gcr_set_operators(s, 1, &member, op);
 }
 
 // ---------------------------------------------------------------------------
@@ -499,7 +533,7 @@ static int run_solve(gcr_solver* s) {
   const int k = s->prm.k, B = s->prm.batch;
   Fields F = make_fields(s);
   const bool mixed = P::mixed;
-  const bool replace = s->prm.precision == GCR_MIXED_FP64DOT;
+  const bool replace = s->prm.precision == GCR_MIXED_FP64DOT || s->prm.precision == GCR_MIXED_HALF_PC;
   const dim3 ctl(B), wave(64);
 
   // step 1: r_0 = L(x_0) - R (float64), p_0 = P^{-1}(r_0), L(p_0)
@@ -578,7 +612,8 @@ extern "C" int gcr_solve(gcr_solver* s, const double* const* rhs, double* const*
   switch (s->prm.precision) {
     case GCR_FP64: rc = run_solve<PrecF64>(s); break;
     case GCR_MIXED: rc = run_solve<PrecMixed>(s); break;
-    default: rc = run_solve<PrecMixedD>(s); break;
+    case GCR_MIXED_FP64DOT: rc = run_solve<PrecMixedD>(s); break;
+    default: rc = run_solve<PrecMixedP>(s); break;
   }
   if (rc != GCR_OK) return rc;
   KLAUNCH(s, KT_COPY, k_scatter, gg, dim3(256), 0, s->stream, s->x, s->ptr_x, s->geom);

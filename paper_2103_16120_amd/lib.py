@@ -18,7 +18,7 @@ from .build import lib_path
 # status codes / enums (mirroring include/mpgcr.h)
 OK, NOT_CONVERGED, STAGNATED, FALLBACK_USED = 0, 1, 2, 3
 EINVAL, ENOMEM, EHIP, ESTATE = -1, -2, -3, -4
-FP64, MIXED, MIXED_FP64DOT = 0, 1, 2
+FP64, MIXED, MIXED_FP64DOT, MIXED_HALF_PC = 0, 1, 2, 3
 PC_NONE, PC_DIAG, PC_RICHARDSON, PC_SEMI_IMPLICIT, PC_LEARNED = 0, 1, 2, 3, 4
 F_RECORD_HISTORY, F_USE_GRAPH, F_PERSISTENT = 0x1, 0x2, 0x4
 
@@ -58,6 +58,7 @@ _SIGNATURES = {
     "gcr_default_params": (C.c_int, [C.POINTER(GcrParams)]),
     "gcr_create": (C.c_int, [C.POINTER(GcrParams), C.POINTER(C.c_void_p)]),
     "gcr_set_operator": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(GcrOperator)]),
+    "gcr_set_operators": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(GcrOperator)]),
     "gcr_solve": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(GcrReport)]),
     "gcr_apply_operator": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "gcr_apply_precond": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
@@ -190,6 +191,29 @@ class Solver:
         op = GcrOperator(dt=dt, g=g, omega=omega, radius=radius, absorber=absorber, depth=dptr,
                          orography=optr, b_terms=1 if b_terms else 0, mem_is_device=dev)
         rc = _lib.gcr_set_operator(self._h, member, C.byref(op))
+        if rc < 0:
+            raise self._err(rc)
+
+    def set_operators(self, members, depths, dts, orographies=None, absorber=0.0, g=GRAVITY, omega=OMEGA,
+                      radius=RADIUS, b_terms=True):
+        """Assemble several members in one launch.  depths / orographies:
+        float64 CUDA tensors (ny, nx), kept alive by the caller until the
+        stream has run the assembly (the next solve synchronises)."""
+        n = len(members)
+        if len(depths) != n or len(dts) != n:
+            raise ValueError("one depth and one dt per member")
+        ops = (GcrOperator * n)()
+        for t, m in enumerate(members):
+            nx, ny = self.sizes[m]
+            _check_field(depths[t], ny, nx, f"depth[{t}]")
+            oro = None if orographies is None else orographies[t]
+            if oro is not None:
+                _check_field(oro, ny, nx, f"orography[{t}]")
+            ops[t] = GcrOperator(dt=float(dts[t]), g=g, omega=omega, radius=radius, absorber=absorber,
+                                 depth=depths[t].data_ptr(), orography=None if oro is None else oro.data_ptr(),
+                                 b_terms=1 if b_terms else 0, mem_is_device=1)
+        mem = (C.c_int32 * n)(*members)
+        rc = _lib.gcr_set_operators(self._h, n, mem, ops)
         if rc < 0:
             raise self._err(rc)
 

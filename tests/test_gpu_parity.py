@@ -165,7 +165,7 @@ def test_fp64_parity(gpu_lib, nx, ny):
 
 
 @pytest.mark.parametrize("nx,ny", [(256, 128), (512, 256)])
-@pytest.mark.parametrize("precision", [1, 2])
+@pytest.mark.parametrize("precision", [1, 2, 3])
 def test_mixed_forms_vs_oracle(gpu_lib, nx, ny, precision):
     pr = problem(2, nx, ny, dt=600.0)
     op = EllipticOperator(nx, ny, pr["depth"], 600.0)
@@ -176,8 +176,12 @@ def test_mixed_forms_vs_oracle(gpu_lib, nx, ny, precision):
           f"restarts={rep.restarts} rec={rep.rel_res_recursive:.3e} true={rep.rel_res_true:.3e} "
           f"(host {true_res:.3e}) err_vs_oracle={err:.3e} oracle_it={ores.iterations}")
     assert rep.rel_res_true == pytest.approx(true_res, rel=1e-6, abs=1e-14)
-    if precision == 2:
+    if precision >= 2:
+        # residual replacement: converged on the float64 true residual
         assert rep.status == gpu_lib.OK and true_res <= 1e-8
+    if precision == 3:
+        # float32 operator inside the iteration: the float64 iteration count +-1
+        assert abs(rep.iterations - ores.iterations) <= 1
     assert err <= 1e-5
 
 
@@ -226,7 +230,7 @@ def test_other_preconditioners_solve(gpu_lib, option):
     assert np.linalg.norm(host(x) - ores.x) / np.linalg.norm(ores.x) <= 1e-8
 
 
-@pytest.mark.parametrize("precision", [0, 2])
+@pytest.mark.parametrize("precision", [0, 2, 3])
 def test_batch_members_equal_solo_solves(gpu_lib, precision):
     probs = batch_problems(3, 5, grids=((64, 32), (128, 64), (256, 128)))
     sizes = [(p["nx"], p["ny"]) for p in probs]
@@ -260,3 +264,17 @@ def test_solve_is_deterministic(gpu_lib):
         s.solve([rhs], [x])
         outs.append(x)
     assert torch.equal(outs[0], outs[1])
+
+
+def test_batched_assembly_matches_single(gpu_lib):
+    probs = batch_problems(3, 4, grids=((64, 32), (128, 64)))
+    sizes = [(p["nx"], p["ny"]) for p in probs]
+    a = make_solver(gpu_lib, sizes)
+    b = make_solver(gpu_lib, sizes)
+    depths = [dev(p["depth"]) for p in probs]
+    a.set_operators([3, 1, 0, 2], [depths[3], depths[1], depths[0], depths[2]], [probs[m]["dt"] for m in (3, 1, 0, 2)])
+    for m, p in enumerate(probs):
+        b.set_operator(m, p["depth"], p["dt"])
+    for m, p in enumerate(probs):
+        x = dev(np.random.default_rng(m).standard_normal((p["ny"], p["nx"])))
+        assert torch.equal(a.apply_operator(m, x), b.apply_operator(m, x))
