@@ -678,76 +678,92 @@ __device__ __forceinline__ double absorber_at(double lat, double amax) {
   return amax * (w > 0.0 ? w : 0.0);
 }
 
-// grid: x over the points of the largest member, y over the table entries
-__global__ void k_assemble(AssembleArgs A) {
+// One workgroup per (row, table entry).  Rows j-1, j, j+1 of Phi* and of
+// H* = Phi* + H0 are staged in LDS with coalesced loads (rows beyond a pole
+// are the polar row seen across the pole); the coefficients are then written
+// in stored (row-interleaved) order, i.e. coalesced.
+constexpr int ASM_WG = 256;
+
+__global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
+  // dynamic LDS: Phi* rows j-1, j, j+1, then (with orography) H* rows
+  extern __shared__ double asm_lds[];
   const AsmMember P = A.tab[blockIdx.y];
   const MemberGeom G = A.geom[P.member];
-  const int nx = G.nx, ny = G.ny;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nx * ny) return;
-  const int j = idx >> G.log2nx, i = idx & (nx - 1);
+  const int nx = G.nx, ny = G.ny, j = blockIdx.x;
+  if (j >= ny) return;
+  const int half = nx >> 1;
+  double* sd0 = asm_lds;
+  double* sh0 = P.oro ? asm_lds + 3 * nx : asm_lds;
+  for (int r = 0; r < 3; ++r) {
+    int jj = j - 1 + r, sh_ = 0;
+    if (jj < 0) { jj = 0; sh_ = half; }
+    if (jj >= ny) { jj = ny - 1; sh_ = half; }
+    const double* drow = P.depth + (long long)jj * nx;
+    const double* orow = P.oro ? P.oro + (long long)jj * nx : nullptr;
+    for (int i = threadIdx.x; i < nx; i += ASM_WG) {
+      const int src = (i + sh_) & (nx - 1);
+      const double d = drow[src];
+      sd0[r * nx + i] = d;
+      if (orow) sh0[r * nx + i] = d + orow[src];
+    }
+  }
+  __syncthreads();
+  auto sd = [&](int r, int i) { return sd0[r * nx + i]; };
+  auto sh = [&](int r, int i) { return sh0[r * nx + i]; };
   const double kPi = 3.14159265358979323846;
   const double dlam = 2.0 * kPi / nx, dphi = kPi / ny;
   const double delta = 0.5 * P.dt;
-  const int ie = (i + 1) & (nx - 1), iw = (i - 1) & (nx - 1), h = nx >> 1;
-  auto D = [&](int jj, int ii) { return P.depth[(long long)jj * nx + ii]; };
-  auto H = [&](int jj, int ii) {
-    if (jj < 0) { jj = 0; ii = (ii + h) & (nx - 1); }
-    if (jj >= ny) { jj = ny - 1; ii = (ii + h) & (nx - 1); }
-    const long long k = (long long)jj * nx + ii;
-    return P.depth[k] + (P.oro ? P.oro[k] : 0.0);
-  };
-  double out[NCOEF];
-  // east face (i+1/2, j), latitude of row j
-  {
-    const double lat = -0.5 * kPi + (j + 0.5) * dphi;
-    const double cs = cos(lat);
-    const double gam = 1.0 + delta * absorber_at(lat, P.absorber);
-    const double b = delta * 2.0 * P.omega * sin(lat);
-    const double Dn = gam * gam + b * b;
-    const double kap = delta * P.g * 0.5 * (D(j, i) + D(j, ie)) / (2.0 * Dn);
-    out[C_AXX] = kap * gam / cs / (dlam * dlam);
-    out[C_AXY] = kap * b / (4.0 * dlam * dphi);
-    double bx = 0.0;
-    if (P.b_terms) {
-      const double dhl = (H(j, ie) - H(j, i)) / dlam;
-      const double dhp = ((H(j + 1, i) - H(j - 1, i)) + (H(j + 1, ie) - H(j - 1, ie))) / (4.0 * dphi);
-      bx = delta * P.g / (2.0 * Dn) * (gam / cs * dhl + b * dhp);
-    }
-    out[C_BX] = bx / (2.0 * dlam);
-  }
-  // north face (i, j+1/2); the pole face carries no flux
-  if (j < ny - 1) {
-    const double lat = -0.5 * kPi + (j + 1.0) * dphi;
-    const double cs = cos(lat);
-    const double gam = 1.0 + delta * absorber_at(lat, P.absorber);
-    const double b = delta * 2.0 * P.omega * sin(lat);
-    const double Dn = gam * gam + b * b;
-    const double kap = delta * P.g * 0.5 * (D(j, i) + D(j + 1, i)) / (2.0 * Dn);
-    out[C_AYY] = kap * gam * cs / (dphi * dphi);
-    out[C_AYX] = -kap * b / (4.0 * dlam * dphi);
-    double by = 0.0;
-    if (P.b_terms) {
-      const double dhp = (H(j + 1, i) - H(j, i)) / dphi;
-      const double dhl = ((H(j, ie) - H(j, iw)) + (H(j + 1, ie) - H(j + 1, iw))) / (4.0 * dlam);
-      by = delta * P.g / (2.0 * Dn) * (-b * dhl + gam * cs * dhp);
-    }
-    out[C_BY] = by / (2.0 * dphi);
-  } else {
-    out[C_AYY] = out[C_AYX] = out[C_BY] = 0.0;
-  }
+  // latitude factors of the row (east faces) and of its north face
+  const double lat_c = -0.5 * kPi + (j + 0.5) * dphi, lat_n = -0.5 * kPi + (j + 1.0) * dphi;
+  const double cs_c = cos(lat_c), cs_n = cos(lat_n);
+  const double gam_c = 1.0 + delta * absorber_at(lat_c, P.absorber);
+  const double gam_n = 1.0 + delta * absorber_at(lat_n, P.absorber);
+  const double b_c = delta * 2.0 * P.omega * sin(lat_c), b_n = delta * 2.0 * P.omega * sin(lat_n);
+  const double D_c = gam_c * gam_c + b_c * b_c, D_n = gam_n * gam_n + b_n * b_n;
   const double s = P.dt / (2.0 * P.radius * P.radius);   // mixed-form scale
-  const long long o = G.off + (long long)j * nx + row_slot(i, G.log2m, nx >> G.log2m);
+  const int Lr = nx >> G.log2m, Mr = 1 << G.log2m;
+  const long long rowoff = G.off + (long long)j * nx;
+  for (int slot = threadIdx.x; slot < nx; slot += ASM_WG) {
+    const int i = (slot % Lr) * Mr + slot / Lr;   // natural column stored at this slot
+    const int ie = (i + 1) & (nx - 1), iw = (i - 1) & (nx - 1);
+    double out[NCOEF];
+    {  // east face (i+1/2, j)
+      const double kap = delta * P.g * 0.5 * (sd(1, i) + sd(1, ie)) / (2.0 * D_c);
+      out[C_AXX] = kap * gam_c / cs_c / (dlam * dlam);
+      out[C_AXY] = kap * b_c / (4.0 * dlam * dphi);
+      double bx = 0.0;
+      if (P.b_terms) {
+        const double dhl = (sh(1, ie) - sh(1, i)) / dlam;
+        const double dhp = ((sh(2, i) - sh(0, i)) + (sh(2, ie) - sh(0, ie))) / (4.0 * dphi);
+        bx = delta * P.g / (2.0 * D_c) * (gam_c / cs_c * dhl + b_c * dhp);
+      }
+      out[C_BX] = bx / (2.0 * dlam);
+    }
+    if (j < ny - 1) {  // north face (i, j+1/2); the pole face carries no flux
+      const double kap = delta * P.g * 0.5 * (sd(1, i) + sd(2, i)) / (2.0 * D_n);
+      out[C_AYY] = kap * gam_n * cs_n / (dphi * dphi);
+      out[C_AYX] = -kap * b_n / (4.0 * dlam * dphi);
+      double by = 0.0;
+      if (P.b_terms) {
+        const double dhp = (sh(2, i) - sh(1, i)) / dphi;
+        const double dhl = ((sh(1, ie) - sh(1, iw)) + (sh(2, ie) - sh(2, iw))) / (4.0 * dlam);
+        by = delta * P.g / (2.0 * D_n) * (-b_n * dhl + gam_n * cs_n * dhp);
+      }
+      out[C_BY] = by / (2.0 * dphi);
+    } else {
+      out[C_AYY] = out[C_AYX] = out[C_BY] = 0.0;
+    }
+    const long long o = rowoff + slot;
 #pragma unroll
-  for (int k = 0; k < NCOEF; ++k) {
-    A.a64[k][o] = out[k];
-    A.a32[k][o] = (float)(s * out[k]);
-    A.a16[k][o] = __float2half_rn((float)(s * out[k]));
+    for (int k = 0; k < NCOEF; ++k) {
+      A.a64[k][o] = out[k];
+      A.a32[k][o] = (float)(s * out[k]);
+      A.a16[k][o] = __float2half_rn((float)(s * out[k]));
+    }
   }
-  if (idx == 0) A.scale[P.member] = s;
-  if (i == 0) {
-    const double lat = -0.5 * kPi + (j + 0.5) * dphi;
-    const double c = 2.0 * P.radius * P.radius * cos(lat) / P.dt;
+  if (threadIdx.x == 0) {
+    if (j == 0) A.scale[P.member] = s;
+    const double c = 2.0 * P.radius * P.radius * cs_c / P.dt;
     A.c64[G.row0 + j] = c;
     A.c32[G.row0 + j] = (float)(s * c);
   }

@@ -94,6 +94,8 @@ struct gcr_solver {
   double** ptr_x = nullptr;
   const void** ptr_stage = nullptr;  // pinned host staging for the tables
   MemberState* state_h = nullptr;    // pinned host copy
+  MemberState* state_ring[2] = {};   // pinned copies of the scalars after a cycle
+  hipEvent_t cycle_ev[2] = {};       // recorded after each copy
   AsmMember* asm_stage = nullptr;    // pinned staging of the assembly table
   AsmMember* asm_tab = nullptr;      // device assembly table [batch]
 
@@ -255,6 +257,12 @@ static void free_all(gcr_solver* s) {
   if (s->ptr_stage) (void)hipHostFree(s->ptr_stage);
   if (s->state_h) (void)hipHostFree(s->state_h);
   if (s->asm_stage) (void)hipHostFree(s->asm_stage);
+  for (int i = 0; i < 2; ++i) {
+    if (s->state_ring[i]) (void)hipHostFree(s->state_ring[i]);
+    if (s->cycle_ev[i]) (void)hipEventDestroy(s->cycle_ev[i]);
+    s->state_ring[i] = nullptr;
+    s->cycle_ev[i] = nullptr;
+  }
   s->ptr_stage = nullptr;
   s->state_h = nullptr;
   s->asm_stage = nullptr;
@@ -379,6 +387,10 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   s->asm_tab = (AsmMember*)track(dalloc<AsmMember>(P.batch, herr));
   if (herr == hipSuccess) herr = hipHostMalloc((void**)&s->state_h, P.batch * sizeof(MemberState), 0);
   if (herr == hipSuccess) herr = hipHostMalloc((void**)&s->asm_stage, P.batch * sizeof(AsmMember), 0);
+  for (int i = 0; i < 2 && herr == hipSuccess; ++i) {
+    herr = hipHostMalloc((void**)&s->state_ring[i], P.batch * sizeof(MemberState), 0);
+    if (herr == hipSuccess) herr = hipEventCreateWithFlags(&s->cycle_ev[i], hipEventDisableTiming);
+  }
   if (herr != hipSuccess) {
     const bool oom = herr == hipErrorOutOfMemory;
     free_all(s);
@@ -413,7 +425,7 @@ extern "C" int gcr_set_operators(gcr_solver* s, int32_t count, const int32_t* me
   if (count < 1 || count > s->prm.batch || !members || !ops)
     return fail(s, GCR_EINVAL, "gcr_set_operators: need 1..batch members and non-NULL tables");
   std::vector<int> seen(s->prm.batch, 0);
-  int maxpts = 0;
+  int maxrows = 0;
   for (int t = 0; t < count; ++t) {
     const int member = members[t];
     const gcr_operator* op = &ops[t];
@@ -425,7 +437,7 @@ extern "C" int gcr_set_operators(gcr_solver* s, int32_t count, const int32_t* me
       return fail(s, GCR_EINVAL, "member %d: dt, g, radius must be > 0, absorber >= 0, all finite", member);
     const MemberGeom& G = s->geom_h[member];
     const long long n = (long long)G.nx * G.ny;
-    maxpts = std::max<int>(maxpts, (int)n);
+    maxrows = std::max(maxrows, G.ny);
     if (!op->mem_is_device) {
       for (long long k = 0; k < n; ++k)
         if (!(op->depth[k] > 0.0) || !std::isfinite(op->depth[k]))
@@ -474,7 +486,10 @@ extern "C" int gcr_set_operators(gcr_solver* s, int32_t count, const int32_t* me
   A.c64 = s->c64;
   A.c32 = s->c32;
   A.scale = s->scale;
-  KLAUNCH(s, KT_ASSEMBLE, k_assemble, dim3((maxpts + 255) / 256, count), dim3(256), 0, s->stream, A);
+  bool any_oro = false;
+  for (int t = 0; t < count; ++t) any_oro = any_oro || ops[t].orography;
+  const size_t lds = (any_oro ? 6 : 3) * (size_t)s->nxmax * sizeof(double);
+  KLAUNCH(s, KT_ASSEMBLE, k_assemble, dim3(maxrows, count), dim3(ASM_WG), lds, s->stream, A);
   HIPCHK(s, hipGetLastError());
   bool host_inputs = false;
   for (int t = 0; t < count; ++t) host_inputs = host_inputs || !ops[t].mem_is_device;
@@ -527,55 +542,81 @@ static void launch_precond(gcr_solver* s, const std::vector<RowClass>& cls, cons
   }
 }
 
+// The solve is enqueued one GCR cycle at a time.  After the k iterations of a
+// cycle (and, in the residual-replacement forms, the float64 restart) the
+// members' scalars are copied to pinned host memory and an event is
+// recorded.  Before waiting for that event the host already enqueues the
+// first iteration of the next cycle, so the GPU keeps working while the host
+// decides; members that have finished make every later kernel return at
+// once, so speculative work on converged members costs only empty launches.
 template <typename P>
 static int run_solve(gcr_solver* s) {
   using A = typename P::A;
-  const int k = s->prm.k, B = s->prm.batch;
+  const int k = s->prm.k, B = s->prm.batch, maxit = s->prm.max_iters;
   Fields F = make_fields(s);
-  const bool mixed = P::mixed;
   const bool replace = s->prm.precision == GCR_MIXED_FP64DOT || s->prm.precision == GCR_MIXED_HALF_PC;
   const dim3 ctl(B), wave(64);
 
   // step 1: r_0 = L(x_0) - R (float64), p_0 = P^{-1}(r_0), L(p_0)
   ROWS_LAUNCH(s, s->classes, F, KT_RESIDUAL, k_residual, P, 1, -1, 0);
   KLAUNCH(s, KT_CONTROL, k_ctrl_init<double>, ctl, wave, 0, s->stream, F);
-  launch_precond<P>(s, s->classes, F, 0, 0);
-  Slots sl{};
-  int base = 0;  // ring slot of p_0 in the current cycle
-  // p_0 = e  (the preconditioner wrote e); L(p_0) with <r, L p_0>, <L p_0, L p_0>
-  HIPCHK(s, hipMemcpyAsync(s->p[0], s->e, s->npts * (mixed ? sizeof(float) : sizeof(double)),
-                           hipMemcpyDeviceToDevice, s->stream));
-  ROWS_LAUNCH(s, s->classes, F, KT_APPLY_L, k_apply_L, P, (const void*)s->p[0], s->lp[0], 1, 0, sl);
+  {
+    Fields F0 = F;
+    F0.e = s->p[0];   // p_0 = P^{-1}(r_0) written in place
+    launch_precond<P>(s, s->classes, F0, 0, 0);
+  }
+  Slots sl0{};
+  ROWS_LAUNCH(s, s->classes, F, KT_APPLY_L, k_apply_L, P, (const void*)s->p[0], s->lp[0], 1, 0, sl0);
   KLAUNCH(s, KT_CONTROL, k_ctrl_beta<A>, ctl, wave, 0, s->stream, F, 0);
   HIPCHK(s, hipGetLastError());
 
-  int it = 0;
-  bool all_done = false;
-  while (!all_done && it < s->prm.max_iters) {
-    for (int nu = 0; nu < k && it < s->prm.max_iters; ++nu) {
-      ++it;
-      for (int l = 0; l <= k; ++l) sl.s[l] = (base + l) % (k + 1);
-      // step 2 (+ first row solve of step 3)
-      launch_precond<P>(s, s->classes, F, 1, sl.s[nu]);
-      // step 3: L(e) with <L e, L p_l>, l = 0..nu
-      ROWS_LAUNCH(s, s->classes, F, KT_APPLY_L, k_apply_L, P, (const void*)s->e, s->le, 0, nu + 1, sl);
-      KLAUNCH(s, KT_CONTROL, k_ctrl_alpha<A>, ctl, wave, 0, s->stream, F, nu + 1, sl, nu == k - 1 ? 1 : 0,
-                         s->prm.min_iters, s->prm.max_iters, s->prm.rtol);
-      // step 4
-      ROWS_LAUNCH(s, s->classes, F, KT_ORTH, k_orth, P, nu + 1, sl, sl.s[nu + 1]);
-      KLAUNCH(s, KT_CONTROL, k_ctrl_beta<A>, ctl, wave, 0, s->stream, F, sl.s[nu + 1]);
-    }
-    HIPCHK(s, hipGetLastError());
-    base = (base + k) % (k + 1);  // (p_0, L p_0) := (p_k, L p_k)
+  // iteration `it` (1-based) at window position nu of a cycle whose p_0 sits
+  // in ring slot `base`
+  auto iteration = [&](int it, int nu, int base) {
+    Slots sl{};
+    for (int l = 0; l <= k; ++l) sl.s[l] = (base + l) % (k + 1);
+    (void)it;
+    // step 2 (+ first row solve of step 3)
+    launch_precond<P>(s, s->classes, F, 1, sl.s[nu]);
+    // step 3: L(e) with <L e, L p_l>, l = 0..nu
+    ROWS_LAUNCH(s, s->classes, F, KT_APPLY_L, k_apply_L, P, (const void*)s->e, s->le, 0, nu + 1, sl);
+    KLAUNCH(s, KT_CONTROL, k_ctrl_alpha<A>, ctl, wave, 0, s->stream, F, nu + 1, sl, nu == k - 1 ? 1 : 0,
+            s->prm.min_iters, maxit, s->prm.rtol);
+    // step 4
+    ROWS_LAUNCH(s, s->classes, F, KT_ORTH, k_orth, P, nu + 1, sl, sl.s[nu + 1]);
+    KLAUNCH(s, KT_CONTROL, k_ctrl_beta<A>, ctl, wave, 0, s->stream, F, sl.s[nu + 1]);
+  };
+  // end of a cycle: (p_0, L p_0) := (p_k, L p_k); residual replacement; flags
+  auto cycle_end = [&](int base_next, int ring) -> int {
     if (replace) {
-      // residual replacement: r = L(x) - R in float64, beta re-derived
-      ROWS_LAUNCH(s, s->classes, F, KT_RESIDUAL, k_residual, P, 1, base, 1);
-      KLAUNCH(s, KT_CONTROL, k_ctrl_restart<double>, ctl, wave, 0, s->stream, F, base);
+      ROWS_LAUNCH(s, s->classes, F, KT_RESIDUAL, k_residual, P, 1, base_next, 1);
+      KLAUNCH(s, KT_CONTROL, k_ctrl_restart<double>, ctl, wave, 0, s->stream, F, base_next);
     }
-    HIPCHK(s, hipMemcpyAsync(s->state_h, s->state, B * sizeof(MemberState), hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(s, hipStreamSynchronize(s->stream));
-    all_done = true;
-    for (int m = 0; m < B; ++m) all_done = all_done && s->state_h[m].done;
+    HIPCHK(s, hipMemcpyAsync(s->state_ring[ring], s->state, B * sizeof(MemberState), hipMemcpyDeviceToHost,
+                             s->stream));
+    HIPCHK(s, hipEventRecord(s->cycle_ev[ring], s->stream));
+    return GCR_OK;
+  };
+
+  int it = 0, base = 0, cycle = 0, rc;
+  // cycle 0, complete
+  for (int nu = 0; nu < k && it < maxit; ++nu) iteration(++it, nu, base);
+  base = (base + k) % (k + 1);
+  if ((rc = cycle_end(base, 0)) != GCR_OK) return rc;
+  HIPCHK(s, hipGetLastError());
+  for (;;) {
+    // speculative first iteration of the next cycle
+    const bool more = it < maxit;
+    if (more) iteration(++it, 0, base);
+    HIPCHK(s, hipEventSynchronize(s->cycle_ev[cycle & 1]));
+    bool all_done = true;
+    for (int m = 0; m < B; ++m) all_done = all_done && s->state_ring[cycle & 1][m].done;
+    if (all_done || !more) break;
+    for (int nu = 1; nu < k && it < maxit; ++nu) iteration(++it, nu, base);
+    base = (base + k) % (k + 1);
+    ++cycle;
+    if ((rc = cycle_end(base, cycle & 1)) != GCR_OK) return rc;
+    HIPCHK(s, hipGetLastError());
   }
   if (s->prm.precision == GCR_MIXED) {
     const dim3 g((unsigned)std::min<long long>((s->npts + 255) / 256, 65535));
