@@ -84,8 +84,8 @@ enum {
   GCR_PC_DIAG = 1,           /* P = diagonal of L                                     */
   GCR_PC_RICHARDSON = 2,     /* explicit Richardson on L, diagonally preconditioned   */
   GCR_PC_SEMI_IMPLICIT = 3,  /* semi-implicit Richardson, eq. P_Operator (default)    */
-  GCR_PC_LEARNED = 4         /* 3x3 convolution network between the two row solves of
-                                option 3 (not from the paper); needs gcr_set_learned  */
+  GCR_PC_LEARNED = 4         /* option 3 plus a 3x3 convolution network correction
+                                (not from the paper); needs gcr_set_learned           */
 };
 
 /* flags */
@@ -210,7 +210,8 @@ enum {
   GCR_K_CONTROL = 6,    /* per-member scalar updates                                 */
   GCR_K_COPY = 7,       /* gather/scatter of caller fields                           */
   GCR_K_PERSISTENT = 8, /* whole-solve persistent kernel (GCR_F_PERSISTENT)          */
-  GCR_K_COUNT = 9
+  GCR_K_LEARNED = 9,    /* learned correction: features, five convolutions, update   */
+  GCR_K_COUNT = 10
 };
 
 /* Enable (1) or disable (0) timing of every kernel the solver launches with
@@ -227,6 +228,91 @@ const char* gcr_kernel_name(int32_t kind);
 
 /* Library version string, e.g. "mpgcr 0.1.0 gfx950". */
 const char* gcr_version(void);
+
+/* ------------------------------------------------------------------------
+ * Learned preconditioner (GCR_PC_LEARNED; not from the paper).
+ *
+ * After the semi-implicit Richardson output e_2 = P^{-1}(r) (option 3 with
+ * the solver's Richardson count) a convolution network N adds a correction:
+ *     e = e_2 + (sigma / s) * N(r / sigma, e_2 * s / sigma, cos(lat)),
+ * with s = dt / (2 a^2) and sigma = ||r||_2 / sqrt(NX*NY) in physical units,
+ * so the result is independent of the scale of r.  GCR minimises the
+ * residual over whatever directions it is given, so a preconditioner that
+ * changes between iterations is allowed.  N: 3x3 convolutions 3 -> 32 -> 32
+ * -> 32 -> 32 -> 1, ReLU between layers, periodic in longitude, the row
+ * beyond a pole is the polar row shifted by NX/2 (the operator's closure).
+ * Weights and activations bf16, float32 accumulation.
+ * ------------------------------------------------------------------------ */
+#define GCR_LEARNED_CHANNELS 3
+
+typedef struct cnn_net cnn_net; /* opaque; owned by the library */
+
+/* Parameters of a network with c_in input channels, float32, in the order
+ * w_1 [32][c_in][3][3], b_1 [32], w_2..w_4 [32][32][3][3], b_2..b_4 [32],
+ * w_5 [1][32][3][3], b_5 [1]; w[co][ci][dy+1][dx+1] multiplies the input at
+ * (lat + dy, lon + dx). */
+int64_t cnn_param_count(int c_in);
+
+/* Create a network for batches of up to max_batch images of ny x nx pixels
+ * (nx a power of two in [64, 1024], 2 <= ny <= 4096) with c_in (1..32)
+ * input channels.  Parameters start at zero (N = 0).  All device memory is
+ * allocated here; work is ordered on `stream` (hipStream_t, NULL = default).
+ * Errors: GCR_EINVAL, GCR_ENOMEM, GCR_EHIP (no GPU); *out = NULL then. */
+int cnn_create(int32_t nx, int32_t ny, int32_t max_batch, int32_t c_in, void* stream, cnn_net** out);
+
+/* Copy `count` (= cnn_param_count(c_in)) float32 parameters from / to host
+ * memory; setting them also resets the Adam moments.  Synchronous.
+ * Errors: GCR_EINVAL (NULL or wrong count), GCR_EHIP. */
+int cnn_set_params(cnn_net* n, const float* host, int64_t count);
+int cnn_get_params(cnn_net* n, float* host, int64_t count);
+
+/* out[b][y][x] = N(in[b][.][y][x]); in: device float32 [batch][c_in][ny][nx],
+ * out: device float32 [batch][ny][nx].  Asynchronous on the network's stream.
+ * Errors: GCR_EINVAL (batch outside 1..max_batch, NULL), GCR_EHIP. */
+int cnn_forward(cnn_net* n, int32_t batch, const float* in, float* out);
+
+/* Gradient of sum(dy * N(in)) with respect to every parameter, written to
+ * host memory in the parameter order (cnn_param_count floats); in and dy are
+ * device float32 [batch][c_in][ny][nx] and [batch][ny][nx].  Synchronous.
+ * Errors: as cnn_forward. */
+int cnn_gradients(cnn_net* n, int32_t batch, const float* in, const float* dy, float* grads_host);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
+ * mean squared error mean((N(in) - target)^2) over the batch; in and target
+ * as in cnn_gradients.  *loss (may be NULL) receives the loss before the
+ * step, which makes the call synchronous.  Errors: as cnn_forward, and
+ * GCR_EINVAL for lr not finite and positive. */
+int cnn_train_step(cnn_net* n, int32_t batch, const float* in, const float* target, float lr, double* loss);
+
+/* Release the network.  NULL is accepted. */
+int cnn_destroy(cnn_net* n);
+
+/* Description of the last error on n (or of the last failed cnn_create when
+ * n is NULL). */
+const char* cnn_last_error(const cnn_net* n);
+
+/* Give solver s (created with precond = GCR_PC_LEARNED, every member of one
+ * size) the network parameters `params` (cnn_param_count(3) floats, host).
+ * The solver keeps its own copy and inference buffers.  fallback_ratio in
+ * (0, 1]: a member whose residual shrinks by less than this factor over a GCR
+ * cycle drops the learned correction for the rest of the solve (reported as
+ * fallback_used / GCR_FALLBACK_USED); a cycle without any decrease also
+ * triggers it instead of GCR_STAGNATED.  Synchronous.
+ * Errors: GCR_EINVAL (wrong precond, uneven sizes, count, ratio), GCR_ENOMEM,
+ * GCR_EHIP. */
+int gcr_set_learned(gcr_solver* s, const float* params, int64_t count, double fallback_ratio);
+
+/* Training data for member `member`: with r = L(x) - rhs (float64),
+ * e_lo = P^{-1}(r) with the solver's Richardson count and, if hi_iters > 0,
+ * e_hi = P^{-1}(r) with hi_iters Richardson iterations, write
+ *   feat [3][NY][NX] = (r / sigma, e_lo * s / sigma, cos(lat))   (float32)
+ *   target [NY][NX]  = (e_hi - e_lo) * s / sigma                 (float32)
+ * (target only if hi_iters > 0 and target != NULL).  x, rhs: device float64
+ * [NY][NX]; feat, target: device float32.  *sigma (may be NULL) receives
+ * sigma; a zero residual gives sigma = 0 and zero features.  Synchronous.
+ * Errors: GCR_EINVAL, GCR_ESTATE (no operator), GCR_EHIP. */
+int gcr_learned_features(gcr_solver* s, int32_t member, const double* x, const double* rhs, int32_t hi_iters,
+                         float* feat, float* target, double* sigma);
 
 #ifdef __cplusplus
 }

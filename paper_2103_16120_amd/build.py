@@ -18,8 +18,8 @@ LIBDIR = os.path.join(HERE, "_lib")
 LIBNAME = "libmpgcr.so"
 ARCH = "gfx950"
 
-SOURCES = ["solver.hip"]
-HEADERS = ["device.h", "kernels.h"]
+SOURCES = ["solver.hip", "cnn.hip"]
+HEADERS = ["device.h", "kernels.h", "cnn.h", "cnn_internal.h", "learned.h"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",

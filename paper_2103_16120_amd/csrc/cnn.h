@@ -1,0 +1,256 @@
+// Learned preconditioner network: 3x3 convolutions C_in -> 32 -> 32 -> 32 ->
+// 32 -> 1 with ReLU between layers, BF16 weights and activations, float32
+// accumulation on the gfx950 matrix cores (v_mfma_f32_16x16x32_bf16).
+//
+// Tensors are NHWC with 32 channels per pixel (64 B; unused channels are
+// zero), natural [NY][NX] pixel order.  Padding on the sphere matches the
+// elliptic operator: longitude periodic, the row beyond a pole is the polar
+// row seen across the pole (shifted by NX/2).
+//
+// MFMA 16x16x32 operand layout (checked on the device): lane l holds
+//   A[m = l%16][k = 8*(l/16) .. +7],  B[k = 8*(l/16) .. +7][n = l%16],
+//   C[m = 4*(l/16) .. +3][n = l%16].
+// A convolution is an implicit GEMM per tap: M = 16 output pixels, K = 32
+// input channels, N = 16 output channels.
+#pragma once
+
+#include "device.h"
+
+namespace mpgcr {
+
+constexpr int CNN_LAYERS = 5;
+constexpr int TAPS = 9;             // tap t = (dy+1)*3 + (dx+1)
+constexpr int CONV_MT = 4;          // 16-pixel M tiles per wave (64 pixels)
+constexpr int WG_WAVES = 4;
+
+struct ConvArgs {
+  const __bf16* in;        // [B][ny][nx][CH]
+  const __bf16* w;         // [TAPS][CH out][CH in]
+  const __bf16* wpole;     // same layout: weights for taps that read across a pole
+  const float* bias;       // [CH] or null
+  __bf16* out;             // [B][ny][nx][CH] (bf16 output modes)
+  float* out32;            // [B][ny][nx] channel 0 (float32 output mode)
+  const __bf16* mask;      // multiply by (mask > 0), [B][ny][nx][CH], or null
+  int nx, ny, log2nx, batch;
+  int relu;
+};
+
+// source pixel (row, column) read by output pixel (j, i) through tap (dy, dx)
+__device__ __forceinline__ void sphere_src(int j, int i, int dy, int dx, int nx, int ny, int& jj, int& ii,
+                                           bool& ghost) {
+  jj = j + dy;
+  ii = (i + dx) & (nx - 1);
+  ghost = false;
+  if (jj < 0) {
+    jj = 0;
+    ii = (ii + (nx >> 1)) & (nx - 1);
+    ghost = true;
+  } else if (jj >= ny) {
+    jj = ny - 1;
+    ii = (ii + (nx >> 1)) & (nx - 1);
+    ghost = true;
+  }
+}
+
+// orders the LDS accesses of one wave (the wave's lanes run in lockstep; the
+// fences keep the compiler and the memory pipeline from reordering them)
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ bf16x8 ld8(const __bf16* p) {
+  bf16x8 v;
+  __builtin_memcpy(&v, __builtin_assume_aligned(p, 16), 16);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution, 32 input channels, NT*16 output channels.
+// OUT: 0 = bf16 NHWC (32 channels written, the upper 16 zero when NT == 1),
+//      1 = float32 channel 0 only.
+// One wave computes 64 consecutive pixels of one row; the workgroup's four
+// waves share the weight fragments staged in LDS.
+// ---------------------------------------------------------------------------
+template <int NT, int OUT>
+__global__ __launch_bounds__(256) void k_conv(ConvArgs A) {
+  __shared__ __attribute__((aligned(16))) __bf16 sw[2][TAPS * CH * CH];
+  const int tid = threadIdx.x;
+  // stage both weight sets (regular and across-pole taps)
+  for (int k = tid * 8; k < TAPS * CH * CH; k += 256 * 8) {
+    *(bf16x8*)&sw[0][k] = ld8(A.w + k);
+    *(bf16x8*)&sw[1][k] = ld8(A.wpole + k);
+  }
+  __syncthreads();
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int npix = A.nx * A.ny;
+  const long long strip = (long long)blockIdx.x * WG_WAVES + wave;   // 64-pixel strip of image blockIdx.y
+  if (strip * 64 >= npix) return;
+  const int b = blockIdx.y;
+  const int p0 = (int)(strip * 64);
+  const int j = p0 >> A.log2nx, i0 = p0 & (A.nx - 1);
+  const __bf16* img = A.in + (long long)b * npix * CH;
+  const int kq = 8 * (lane >> 4);          // channel block of this lane (A and B operands)
+  const int ml = lane & 15;
+#pragma unroll 1
+  for (int mt = 0; mt < CONV_MT; ++mt) {
+    f32x4 acc[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int i = i0 + 16 * mt + ml;
+#pragma unroll
+    for (int t = 0; t < TAPS; ++t) {
+      const int dy = t / 3 - 1, dx = t % 3 - 1;
+      int jj, ii;
+      bool ghost;
+      sphere_src(j, i, dy, dx, A.nx, A.ny, jj, ii, ghost);   // ghost is uniform over the wave
+      const bf16x8 a = ld8(img + ((long long)jj * A.nx + ii) * CH + kq);
+      const __bf16* wt = &sw[ghost ? 1 : 0][t * CH * CH];
+#pragma unroll
+      for (int n = 0; n < NT; ++n) {
+        const bf16x8 bw = *(const bf16x8*)&wt[(16 * n + ml) * CH + kq];
+        acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[n], 0, 0, 0);
+      }
+    }
+    // epilogue: lane holds output channel co = 16n + ml for 4 pixels
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+      const int co = 16 * n + ml;
+      const float bias = A.bias ? A.bias[co] : 0.f;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long long pix = (long long)b * npix + p0 + 16 * mt + 4 * (lane >> 4) + r;
+        float v = acc[n][r] + bias;
+        if (A.relu) v = fmaxf(v, 0.f);
+        if (A.mask && !((float)A.mask[pix * CH + co] > 0.f)) v = 0.f;
+        if (OUT == 1) {
+          if (co == 0) A.out32[pix] = v;
+        } else {
+          A.out[pix * CH + co] = (__bf16)v;
+          if (NT == 1) A.out[pix * CH + co + 16] = (__bf16)0.f;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight and bias gradients of a 3x3 convolution:
+//   dW[t][co][ci] = sum_q dpre[q][co] * in[src_t(q)][ci],  db[co] = sum_q dpre[q][co]
+// an implicit GEMM with M = co, N = ci and K = pixels.  Each wave walks
+// `chunks` chunks of 32 pixels of one row, transposing the dpre and input
+// blocks through wave-private LDS so the MFMA operands are 16-byte reads, and
+// writes its partial sums; k_wgrad_reduce adds the partials in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int WG_Q = 32;                 // pixels per K chunk
+constexpr int WG_LD = WG_Q + 8;          // padded LDS row (16-byte aligned)
+constexpr int WG_PART = TAPS * CH * CH + CH;
+
+struct WgradArgs {
+  const __bf16* in;        // layer input [B][ny][nx][CH]
+  const __bf16* dpre;      // gradient at the layer output before activation [B][ny][nx][CH]
+  float* part;             // [nwaves][WG_PART]
+  int nx, ny, log2nx, batch;
+  int chunks;              // 32-pixel chunks per wave
+  long long total_chunks;
+};
+
+__global__ __launch_bounds__(256) void k_wgrad(WgradArgs A) {
+  __shared__ __attribute__((aligned(16))) __bf16 sd[WG_WAVES][CH][WG_LD];
+  __shared__ __attribute__((aligned(16))) __bf16 sa[WG_WAVES][CH][WG_LD];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const long long gw = (long long)blockIdx.x * WG_WAVES + wave;
+  const long long c0 = gw * A.chunks;
+  float* part = A.part + gw * WG_PART;
+  f32x4 acc[TAPS][2][2];
+#pragma unroll
+  for (int t = 0; t < TAPS; ++t)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) acc[t][a][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float dbias = 0.f;
+  const int npix = A.nx * A.ny;
+  const int chunks_per_image = npix / WG_Q;
+  const int ql = lane >> 1, ch0 = 16 * (lane & 1);   // staging: pixel ql, channels ch0..ch0+15
+  const int kq = 8 * (lane >> 4), ml = lane & 15;
+  for (int c = 0; c < A.chunks; ++c) {
+    const long long chunk = c0 + c;
+    if (chunk >= A.total_chunks) break;      // uniform over the wave
+    const int b = (int)(chunk / chunks_per_image);
+    const int p0 = (int)(chunk % chunks_per_image) * WG_Q;
+    const int j = p0 >> A.log2nx, i0 = p0 & (A.nx - 1);
+    // dpre block, transposed to [co][q]
+    {
+      const __bf16* src = A.dpre + ((long long)b * npix + p0 + ql) * CH + ch0;
+      const bf16x8 v0 = ld8(src), v1 = ld8(src + 8);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        sd[wave][ch0 + k][ql] = v0[k];
+        sd[wave][ch0 + 8 + k][ql] = v1[k];
+      }
+    }
+    wave_sync_lds();
+    if (lane < CH) {
+      float s = 0.f;
+#pragma unroll 8
+      for (int q = 0; q < WG_Q; ++q) s += (float)sd[wave][lane][q];
+      dbias += s;
+    }
+    bf16x8 afr[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) afr[mt] = *(const bf16x8*)&sd[wave][16 * mt + ml][kq];
+#pragma unroll
+    for (int t = 0; t < TAPS; ++t) {
+      const int dy = t / 3 - 1, dx = t % 3 - 1;
+      int jj, ii;
+      bool ghost;
+      sphere_src(j, i0 + ql, dy, dx, A.nx, A.ny, jj, ii, ghost);
+      const __bf16* src = A.in + ((long long)b * npix + (long long)jj * A.nx + ii) * CH + ch0;
+      const bf16x8 v0 = ld8(src), v1 = ld8(src + 8);
+      wave_sync_lds();   // previous tap's reads of sa are complete
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        sa[wave][ch0 + k][ql] = v0[k];
+        sa[wave][ch0 + 8 + k][ql] = v1[k];
+      }
+      wave_sync_lds();
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt) {
+        const bf16x8 bfr = *(const bf16x8*)&sa[wave][16 * nt + ml][kq];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+          acc[t][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[mt], bfr, acc[t][mt][nt], 0, 0, 0);
+      }
+    }
+    wave_sync_lds();   // sd is rewritten by the next chunk
+  }
+  // partial sums: C lane layout co = 16 mt + 4*(lane/16) + r, ci = 16 nt + lane%16
+#pragma unroll
+  for (int t = 0; t < TAPS; ++t)
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int co = 16 * mt + 4 * (lane >> 4) + r, ci = 16 * nt + ml;
+          part[(t * CH + co) * CH + ci] = acc[t][mt][nt][r];
+        }
+  if (lane < CH) part[TAPS * CH * CH + lane] = dbias;
+}
+
+// grad[k] = sum over waves of part[w][k], fixed order
+__global__ void k_wgrad_reduce(const float* part, int nwaves, float* grad) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= WG_PART) return;
+  float s = 0.f;
+  for (int w = 0; w < nwaves; ++w) s += part[(long long)w * WG_PART + k];
+  grad[k] = s;
+}
+
+}  // namespace mpgcr

@@ -21,6 +21,10 @@ constexpr int WG = 256;             // threads per workgroup
 constexpr int WPB = WG / 64;        // rows (waves) per workgroup
 constexpr int KMAX = 8;             // largest GCR(k) window
 constexpr int NXMAX = 1024;         // longest row (one wave, 16 points per lane)
+constexpr int CH = 32;              // channels per pixel of the learned network's tensors
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Slots of the per-row partial inner-product buffer.
 constexpr int DOT_RR = 0;               // <r, r> after the step-2 update
@@ -52,6 +56,7 @@ struct MemberState {
   double alpha[KMAX];         // step-4 coefficients of the current iteration
   double lpsq[KMAX + 1];      // <L p_l, L p_l> per ring slot
   double rtrue;               // ||L x - R|| recomputed in float64
+  double sigma;               // RMS of r (learned preconditioner scaling)
   int it, status, done, restarts;
   int fallback, pad1, pad2, pad3;
 };

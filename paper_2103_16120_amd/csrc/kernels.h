@@ -12,7 +12,7 @@ namespace mpgcr {
 // kernel kinds for the optional per-kernel timing (values match the header)
 enum {
   KT_ASSEMBLE = 0, KT_RESIDUAL, KT_SWEEP1, KT_SWEEP2, KT_APPLY_L, KT_ORTH, KT_CONTROL, KT_COPY, KT_PERSISTENT,
-  KT_COUNT
+  KT_LEARNED, KT_COUNT
 };
 
 // ---------------------------------------------------------------------------
@@ -104,6 +104,8 @@ struct Fields {
   int row_base;               // global row handled by wave 0 of workgroup 0
   int row_end;                // one past the last global row of the launch
   int ignore_done;            // process finished members too (stand-alone operator calls)
+  int learned;                // learned preconditioner active (fallback test at cycle ends)
+  double fallback_ratio;      // required residual reduction per cycle with it
 };
 
 // Run fn(coefficient rows) for row j with the storage precision of the
@@ -827,7 +829,7 @@ __device__ __forceinline__ double member_sum(const Fields& F, const MemberGeom& 
   return (double)wave_sum(s);
 }
 
-enum { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_STAGNATED = 2 };
+enum { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_STAGNATED = 2, ST_FALLBACK = 3 };
 
 template <typename A>
 __global__ void k_ctrl_init(Fields F) {
@@ -894,7 +896,7 @@ __global__ void k_ctrl_alpha(Fields F, int nl, Slots sl, int cycle_end, int min_
       return;
     }
     if (S.it >= min_iters && rn <= rtol * S.rho0) {
-      S.status = ST_OK;
+      S.status = S.fallback ? ST_FALLBACK : ST_OK;
       S.done = 1;
       return;
     }
@@ -905,6 +907,12 @@ __global__ void k_ctrl_alpha(Fields F, int nl, Slots sl, int cycle_end, int min_
     }
     for (int l = 0; l < nl; ++l) S.alpha[l] = -dots[l] / S.lpsq[sl.s[l]];
     if (cycle_end) {
+      // learned correction not reducing the residual enough: drop it
+      if (F.learned && !S.fallback && !(rn <= F.fallback_ratio * S.rn_cycle)) {
+        S.fallback = 1;
+        S.rn_cycle = rn;
+        return;
+      }
       if (rn >= S.rn_cycle) {
         S.status = ST_STAGNATED;
         S.done = 1;

@@ -1,0 +1,153 @@
+// Solver-side kernels of the learned preconditioner: scale of the residual,
+// feature packing into the network's input tensor, and the correction
+//   e <- e + (sigma / s) N(r / sigma, e s / sigma, cos(lat))
+// in physical units (s = dt / (2 a^2)).  In the mixed forms r is held scaled
+// by s, so sigma_held = s sigma and the factors below carry one more s.
+#pragma once
+
+#include "kernels.h"
+
+namespace mpgcr {
+
+constexpr int LEARN_CIN = 3;
+
+struct LearnArgs {
+  const void* r;         // residual in the form's vector type (pooled, row-interleaved)
+  void* e;               // preconditioner output to correct (same type and layout)
+  __bf16* feat;          // network input [batch][ny][nx][32] (bf16, NHWC)
+  const float* y;        // network output [batch][ny][nx]
+  int use_part;          // sigma from the per-row <r,r> partials (1) or from r (0)
+};
+
+// cosine of the cell-centre latitude of row j (rows from the south pole)
+__device__ __forceinline__ double learn_cos(int j, int ny) { return sin(M_PI * (j + 0.5) / ny); }
+
+__device__ __forceinline__ bool learn_skip(const Fields& F, const MemberState& S) {
+  return !F.ignore_done && (S.done || S.fallback);
+}
+
+// sigma of each member: RMS of its residual in the form's units
+template <typename P>
+__global__ void k_learn_sigma(Fields F, LearnArgs A, int member0) {
+  using V = typename P::V;
+  const int m = member0 + blockIdx.x;
+  MemberState& S = F.state[m];
+  if (learn_skip(F, S)) return;
+  const MemberGeom G = F.geom[m];
+  double rr;
+  if (A.use_part) {
+    rr = member_sum<double>(F, G, DOT_RR);
+  } else {
+    const V* r = (const V*)A.r + G.off;
+    const long long n = (long long)G.nx * G.ny;
+    double acc = 0.0;
+    for (long long k = threadIdx.x; k < n; k += 64) {
+      const double v = (double)r[k];
+      acc += v * v;
+    }
+    rr = wave_sum(acc);
+  }
+  if (threadIdx.x == 0) S.sigma = sqrt(rr / ((double)G.nx * G.ny));
+}
+
+// per-member factors: features (r * fr, e * fe); correction y * fc
+template <typename P>
+__device__ __forceinline__ void learn_factors(const Fields& F, int m, double sigma, double& fr, double& fe,
+                                              double& fc) {
+  const double s = F.scale[m];
+  const double u = P::mixed ? s : 1.0;    // r held as u * r_physical
+  if (sigma > 0.0) {
+    fr = 1.0 / sigma;
+    fe = s * u / sigma;
+    fc = sigma / (u * s);
+  } else {
+    fr = fe = fc = 0.0;
+  }
+}
+
+// one wave per row: write the row's pixels of the network input
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_learn_pack(Fields F, LearnArgs A) {
+  using V = typename P::V;
+  int g, m, lane, w;
+  MemberGeom G;
+  if (!wave_row(F, g, m, G, lane, w)) return;
+  const MemberState& S = F.state[m];
+  if (learn_skip(F, S)) return;
+  const RowCtx R = make_row(G, m, g, lane, M);
+  double fr, fe, fc;
+  learn_factors<P>(F, m, S.sigma, fr, fe, fc);
+  double rv[M], ev[M];
+  ldr<M>((const V*)A.r + R.rc, R.lane, R.L, rv);
+  ldr<M>((const V*)A.e + R.rc, R.lane, R.L, ev);
+  if (!R.act) return;
+  const __bf16 cz = (__bf16)(float)learn_cos(R.j, G.ny);
+  const long long row_pix = ((long long)m * G.ny + R.j) * G.nx;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const int i = R.lane * M + k;
+    bf16x8 v0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v0[c] = (__bf16)0.f;
+    v0[0] = (__bf16)(float)(rv[k] * fr);
+    v0[1] = (__bf16)(float)(ev[k] * fe);
+    v0[2] = cz;
+    bf16x8 zero;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) zero[c] = (__bf16)0.f;
+    bf16x8* dst = (bf16x8*)(A.feat + (row_pix + i) * CH);
+    dst[0] = v0;
+    dst[1] = zero;
+    dst[2] = zero;
+    dst[3] = zero;
+  }
+}
+
+// one wave per row: e += fc * y
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_learn_apply(Fields F, LearnArgs A) {
+  using V = typename P::V;
+  int g, m, lane, w;
+  MemberGeom G;
+  if (!wave_row(F, g, m, G, lane, w)) return;
+  const MemberState& S = F.state[m];
+  if (learn_skip(F, S)) return;
+  const RowCtx R = make_row(G, m, g, lane, M);
+  if (!R.act) return;
+  double fr, fe, fc;
+  learn_factors<P>(F, m, S.sigma, fr, fe, fc);
+  const float* yrow = A.y + ((long long)m * G.ny + R.j) * G.nx + R.lane * M;
+  V* e = (V*)A.e + R.rc;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    V& d = e[k * R.L + R.lane];
+    d = (V)((double)d + fc * (double)yrow[k]);
+  }
+}
+
+// training data, natural [NY][NX] order: features and target of one member
+// from float64 pooled r, e_lo and (optionally) e_hi
+template <int M>
+__global__ __launch_bounds__(WG) void k_learn_features(Fields F, const double* r, const double* elo,
+                                                       const double* ehi, float* feat, float* target) {
+  int g, m, lane, w;
+  MemberGeom G;
+  if (!wave_row(F, g, m, G, lane, w)) return;
+  const RowCtx R = make_row(G, m, g, lane, M);
+  if (!R.act) return;
+  double fr, fe, fc;
+  learn_factors<PrecF64>(F, m, F.state[m].sigma, fr, fe, fc);
+  const long long np = (long long)G.nx * G.ny;
+  const float cz = (float)learn_cos(R.j, G.ny);
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const long long src = R.rc + k * R.L + R.lane;
+    const long long dst = (long long)R.j * G.nx + R.lane * M + k;
+    feat[dst] = (float)(r[src] * fr);
+    feat[np + dst] = (float)(elo[src] * fe);
+    feat[2 * np + dst] = cz;
+    if (target) target[dst] = (float)((ehi[src] - elo[src]) * fe);
+  }
+}
+
+}  // namespace mpgcr

@@ -18,7 +18,9 @@
 #include <vector>
 
 #include "../../include/mpgcr.h"
+#include "cnn_internal.h"
 #include "kernels.h"
+#include "learned.h"
 
 using namespace mpgcr;
 
@@ -98,6 +100,8 @@ struct gcr_solver {
   hipEvent_t cycle_ev[2] = {};       // recorded after each copy
   AsmMember* asm_stage = nullptr;    // pinned staging of the assembly table
   AsmMember* asm_tab = nullptr;      // device assembly table [batch]
+  cnn_net* net = nullptr;            // learned preconditioner (GCR_PC_LEARNED), owned
+  double fallback_ratio = 0.5;
 
   // optional per-kernel timing with HIP events on the solver's stream
   bool timing = false;
@@ -230,6 +234,8 @@ static Fields make_fields(gcr_solver* s) {
   F.row_base = 0;
   F.row_end = s->rows;
   F.ignore_done = 0;
+  F.learned = s->prm.precond == GCR_PC_LEARNED ? 1 : 0;
+  F.fallback_ratio = s->fallback_ratio;
   return F;
 }
 
@@ -249,6 +255,8 @@ extern "C" int gcr_default_params(gcr_params* p) {
 }
 
 static void free_all(gcr_solver* s) {
+  if (s->net) (void)cnn_destroy(s->net);
+  s->net = nullptr;
   for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
   s->ev.clear();
   for (void* a : s->allocs)
@@ -277,7 +285,7 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   if (P.k < 1 || P.k > KMAX) return fail(nullptr, GCR_EINVAL, "k must be in [1, %d], got %d", KMAX, P.k);
   if (P.precision < GCR_FP64 || P.precision > GCR_MIXED_HALF_PC)
     return fail(nullptr, GCR_EINVAL, "unknown precision form %d", P.precision);
-  if (P.precond < GCR_PC_NONE || P.precond > GCR_PC_SEMI_IMPLICIT)
+  if (P.precond < GCR_PC_NONE || P.precond > GCR_PC_LEARNED)
     return fail(nullptr, GCR_EINVAL, "unsupported preconditioner %d", P.precond);
   if (P.richardson_iters < 1 || P.richardson_iters > 16)
     return fail(nullptr, GCR_EINVAL, "richardson_iters must be in [1, 16], got %d", P.richardson_iters);
@@ -290,6 +298,8 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
     if (!is_pow2(nx) || nx < 8 || nx > NXMAX)
       return fail(nullptr, GCR_EINVAL, "member %d: nx must be a power of two in [8, %d], got %d", m, NXMAX, nx);
     if (ny < 2 || ny > 4096) return fail(nullptr, GCR_EINVAL, "member %d: ny must be in [2, 4096], got %d", m, ny);
+    if (P.precond == GCR_PC_LEARNED && (nx != P.nx[0] || ny != P.ny[0] || nx < 64))
+      return fail(nullptr, GCR_EINVAL, "the learned preconditioner needs members of one size with nx >= 64");
   }
 
   gcr_solver* s = new (std::nothrow) gcr_solver();
@@ -507,11 +517,34 @@ extern "C" int gcr_set_operator(gcr_solver* s, int32_t member, const gcr_operato
 // ---------------------------------------------------------------------------
 // kernel sequences
 // ---------------------------------------------------------------------------
+// Learned correction of the preconditioner output F.e (members
+// [member0, member0 + count)): residual scale, network input, five
+// convolutions over the whole batch of images, update of e.  `use_part`: the
+// per-row <r,r> partials of F.r are current (inside a solve).
+template <typename P>
+static void learned_correction(gcr_solver* s, const std::vector<RowClass>& cls, const Fields& F, int use_part,
+                               int member0, int count) {
+  LearnArgs A{};
+  A.r = F.r;
+  A.e = F.e;
+  A.feat = s->net->act[0];
+  A.y = s->net->y;
+  A.use_part = use_part;
+  KLAUNCH(s, KT_LEARNED, k_learn_sigma<P>, dim3(count), dim3(64), 0, s->stream, F, A, member0);
+  ROWS_LAUNCH(s, cls, F, KT_LEARNED, k_learn_pack, P, A);
+  s->tm_begin(KT_LEARNED);
+  (void)cnn_forward_packed(s->net, s->prm.batch, s->net->y, s->stream);
+  s->tm_end();
+  ROWS_LAUNCH(s, cls, F, KT_LEARNED, k_learn_apply, P, A);
+}
+
 // e = P^{-1}(r) on the rows of `cls`, optionally fused with the step-2
-// update along ring slot `slot_nu`.
+// update along ring slot `slot_nu`.  With the learned preconditioner and
+// `learned` >= 0 the network correction follows (learned = 1: partials of
+// <r,r> current); members [member0, member0 + count) are corrected.
 template <typename P>
 static void launch_precond(gcr_solver* s, const std::vector<RowClass>& cls, const Fields& F, int do_update,
-                           int slot_nu) {
+                           int slot_nu, int learned = 1, int member0 = 0, int count = -1) {
   const int ri = s->prm.richardson_iters;
   switch (s->prm.precond) {
     case GCR_PC_NONE:
@@ -538,6 +571,8 @@ static void launch_precond(gcr_solver* s, const std::vector<RowClass>& cls, cons
         ROWS_LAUNCH(s, cls, F, KT_SWEEP2, k_sweep2, P, cur, nxt);
         cur ^= 1;
       }
+      if (s->prm.precond == GCR_PC_LEARNED && learned >= 0 && s->net)
+        learned_correction<P>(s, cls, F, learned, member0, count < 0 ? s->prm.batch : count);
     }
   }
 }
@@ -637,6 +672,8 @@ extern "C" int gcr_solve(gcr_solver* s, const double* const* rhs, double* const*
     if (!rhs[m] || !x[m]) return fail(s, GCR_EINVAL, "member %d: NULL field pointer", m);
     if (!s->have_op[m]) return fail(s, GCR_ESTATE, "member %d has no operator (call gcr_set_operator)", m);
   }
+  if (s->prm.precond == GCR_PC_LEARNED && !s->net)
+    return fail(s, GCR_ESTATE, "learned preconditioner without parameters (call gcr_set_learned)");
   HIPCHK(s, hipStreamSynchronize(s->stream));  // staging buffer reuse
   for (int m = 0; m < B; ++m) {
     s->ptr_stage[m] = rhs[m];
@@ -668,11 +705,13 @@ extern "C" int gcr_solve(gcr_solver* s, const double* const* rhs, double* const*
   }
   HIPCHK(s, hipStreamSynchronize(s->stream));
   s->tm_collect();
+  // worst soft status: OK < FALLBACK_USED < NOT_CONVERGED < STAGNATED
+  auto severity = [](int st) { return st == GCR_FALLBACK_USED ? 1 : st == GCR_OK ? 0 : st + 1; };
   int worst = GCR_OK;
   for (int m = 0; m < B; ++m) {
     const MemberState& S = s->state_h[m];
     const int st = S.status;
-    if (st > worst) worst = st;
+    if (severity(st) > severity(worst)) worst = st;
     if (!reports) continue;
     gcr_report& rp = reports[m];
     rp.status = st;
@@ -727,6 +766,8 @@ extern "C" int gcr_apply_operator(gcr_solver* s, int32_t member, const double* x
 extern "C" int gcr_apply_precond(gcr_solver* s, int32_t member, const double* r, double* e) {
   int rc = check_member(s, member, r, e);
   if (rc != GCR_OK) return rc;
+  if (s->prm.precond == GCR_PC_LEARNED && !s->net)
+    return fail(s, GCR_ESTATE, "learned preconditioner without parameters (call gcr_set_learned)");
   const MemberGeom& G = s->geom_h[member];
   const long long n = (long long)G.nx * G.ny;
   Fields F = make_fields(s);
@@ -741,9 +782,96 @@ extern "C" int gcr_apply_precond(gcr_solver* s, int32_t member, const double* r,
   F.ignore_done = 1;
   const dim3 cg((unsigned)std::min<long long>((n + 255) / 256, 1024));
   KLAUNCH(s, KT_COPY, k_to_pool, cg, dim3(256), 0, s->stream, r, (double*)F.r, G);
-  launch_precond<PrecF64>(s, member_class(s, member), F, 0, 0);
+  launch_precond<PrecF64>(s, member_class(s, member), F, 0, 0, 0, member, 1);
   KLAUNCH(s, KT_COPY, k_from_pool, cg, dim3(256), 0, s->stream, (const double*)F.e, e, G);
   HIPCHK(s, hipGetLastError());
+  return GCR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned preconditioner
+// ---------------------------------------------------------------------------
+extern "C" int gcr_set_learned(gcr_solver* s, const float* params, int64_t count, double fallback_ratio) {
+  if (!s) return GCR_EINVAL;
+  if (s->prm.precond != GCR_PC_LEARNED)
+    return fail(s, GCR_EINVAL, "gcr_set_learned needs a solver created with GCR_PC_LEARNED");
+  if (!params) return fail(s, GCR_EINVAL, "gcr_set_learned: NULL parameters");
+  if (count != cnn_param_count(GCR_LEARNED_CHANNELS))
+    return fail(s, GCR_EINVAL, "expected %lld parameters, got %lld",
+                (long long)cnn_param_count(GCR_LEARNED_CHANNELS), (long long)count);
+  if (!(fallback_ratio > 0.0 && fallback_ratio <= 1.0))
+    return fail(s, GCR_EINVAL, "fallback_ratio must be in (0, 1]");
+  if (!s->net) {
+    const int rc = cnn_create(s->nx[0], s->ny[0], s->prm.batch, GCR_LEARNED_CHANNELS, s->stream, &s->net);
+    if (rc != GCR_OK) return fail(s, rc, "network: %s", cnn_last_error(nullptr));
+  }
+  const int rc = cnn_set_params(s->net, params, count);
+  if (rc != GCR_OK) return fail(s, rc, "network: %s", cnn_last_error(s->net));
+  s->fallback_ratio = fallback_ratio;
+  return GCR_OK;
+}
+
+extern "C" int gcr_learned_features(gcr_solver* s, int32_t member, const double* x, const double* rhs,
+                                    int32_t hi_iters, float* feat, float* target, double* sigma) {
+  int rc = check_member(s, member, x, rhs);
+  if (rc != GCR_OK) return rc;
+  if (!feat) return fail(s, GCR_EINVAL, "gcr_learned_features: NULL feat");
+  if (s->prm.precond != GCR_PC_SEMI_IMPLICIT && s->prm.precond != GCR_PC_LEARNED)
+    return fail(s, GCR_EINVAL, "features need the semi-implicit preconditioner (option 3)");
+  if (hi_iters < 0 || hi_iters > 16) return fail(s, GCR_EINVAL, "hi_iters must be in [0, 16]");
+  const MemberGeom& G = s->geom_h[member];
+  if (G.nx < 64) return fail(s, GCR_EINVAL, "features need nx >= 64");
+  const long long n = (long long)G.nx * G.ny;
+  const std::vector<RowClass> cls = member_class(s, member);
+  const dim3 cg((unsigned)std::min<long long>((n + 255) / 256, 1024));
+  Fields F = make_fields(s);
+  F.row_base = G.row0;
+  F.row_end = G.row0 + G.ny;
+  F.ignore_done = 1;
+  // float64 work buffers: e_lo, e_hi and the two intermediates
+  double* elo = s->prm.precision == GCR_FP64 ? (double*)s->e : s->aux_e;
+  double* ehi = s->prm.precision == GCR_FP64 ? (double*)s->le : s->aux_r;
+  if (s->prm.precision != GCR_FP64) {
+    F.q[0] = s->aux_q[0];
+    F.q[1] = s->aux_q[1];
+  }
+  // r = L(x) - rhs and its <r,r> partials
+  KLAUNCH(s, KT_COPY, k_to_pool, cg, dim3(256), 0, s->stream, x, s->x, G);
+  KLAUNCH(s, KT_COPY, k_to_pool, cg, dim3(256), 0, s->stream, rhs, s->rhs, G);
+  ROWS_LAUNCH(s, cls, F, KT_RESIDUAL, k_residual, PrecF64, 0, -1, 0);
+  F.r = s->r64;
+  LearnArgs A{};
+  A.r = s->r64;
+  A.use_part = 1;
+  KLAUNCH(s, KT_LEARNED, k_learn_sigma<PrecF64>, dim3(1), dim3(64), 0, s->stream, F, A, member);
+  F.e = elo;
+  launch_precond<PrecF64>(s, cls, F, 0, 0, -1);
+  if (hi_iters > 0) {
+    const int keep = s->prm.richardson_iters;
+    s->prm.richardson_iters = hi_iters;
+    F.e = ehi;
+    launch_precond<PrecF64>(s, cls, F, 0, 0, -1);
+    s->prm.richardson_iters = keep;
+  }
+  for (const RowClass& c : cls) {
+    Fields f = F;
+    f.row_base = c.row_begin;
+    f.row_end = c.row_end;
+    const dim3 g((c.row_end - c.row_begin + WPB - 1) / WPB), b(WG);
+    float* tg = hi_iters > 0 ? target : nullptr;
+    const double* eh = hi_iters > 0 ? ehi : nullptr;
+    switch (c.log2m) {
+      case 1: launch(s, KT_LEARNED, &k_learn_features<2>, g, b, f, (const double*)s->r64, (const double*)elo, eh, feat, tg); break;
+      case 2: launch(s, KT_LEARNED, &k_learn_features<4>, g, b, f, (const double*)s->r64, (const double*)elo, eh, feat, tg); break;
+      case 3: launch(s, KT_LEARNED, &k_learn_features<8>, g, b, f, (const double*)s->r64, (const double*)elo, eh, feat, tg); break;
+      default: launch(s, KT_LEARNED, &k_learn_features<16>, g, b, f, (const double*)s->r64, (const double*)elo, eh, feat, tg); break;
+    }
+  }
+  HIPCHK(s, hipGetLastError());
+  HIPCHK(s, hipMemcpyAsync(s->state_h, s->state, s->prm.batch * sizeof(MemberState), hipMemcpyDeviceToHost,
+                           s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  if (sigma) *sigma = s->state_h[member].sigma;
   return GCR_OK;
 }
 
@@ -790,7 +918,7 @@ extern "C" int gcr_kernel_time(gcr_solver* s, int32_t kind, int64_t* launches, d
 }
 
 extern "C" const char* gcr_kernel_name(int32_t kind) {
-  static const char* names[KT_COUNT] = {"assemble", "residual",  "update_sweep1", "sweep2",    "apply_L",
-                                        "orth",     "control",   "copy",          "persistent"};
+  static const char* names[KT_COUNT] = {"assemble", "residual", "update_sweep1", "sweep2",     "apply_L",
+                                        "orth",     "control",  "copy",          "persistent", "learned"};
   return (kind >= 0 && kind < KT_COUNT) ? names[kind] : "unknown";
 }

@@ -69,10 +69,25 @@ _SIGNATURES = {
     "gcr_set_kernel_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "gcr_kernel_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "gcr_kernel_name": (C.c_char_p, [C.c_int32]),
+    "gcr_set_learned": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double]),
+    "gcr_learned_features": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                       C.c_void_p, C.POINTER(C.c_double)]),
+    "cnn_param_count": (C.c_int64, [C.c_int]),
+    "cnn_create": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "cnn_set_params": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
+    "cnn_get_params": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
+    "cnn_forward": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "cnn_gradients": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cnn_train_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_float,
+                                 C.POINTER(C.c_double)]),
+    "cnn_destroy": (C.c_int, [C.c_void_p]),
+    "cnn_last_error": (C.c_char_p, [C.c_void_p]),
 }
 
-K_ASSEMBLE, K_RESIDUAL, K_SWEEP1, K_SWEEP2, K_APPLY_L, K_ORTH, K_CONTROL, K_COPY, K_PERSISTENT = range(9)
-K_COUNT = 9
+(K_ASSEMBLE, K_RESIDUAL, K_SWEEP1, K_SWEEP2, K_APPLY_L, K_ORTH, K_CONTROL, K_COPY, K_PERSISTENT,
+ K_LEARNED) = range(10)
+K_COUNT = 10
+LEARNED_CHANNELS = 3
 
 
 def _load():
@@ -273,6 +288,38 @@ class Solver:
             raise self._err(rc)
         return y
 
+    def set_learned(self, params, fallback_ratio=0.5):
+        """params: float32 numpy array of cnn_param_count(3) network parameters."""
+        import numpy as np
+        arr = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        rc = _lib.gcr_set_learned(self._h, arr.ctypes.data, arr.size, float(fallback_ratio))
+        if rc < 0:
+            raise self._err(rc)
+
+    def learned_features(self, member, x, rhs, hi_iters=0, feat=None, target=None):
+        """Features (3, ny, nx) and, with hi_iters > 0, the target (ny, nx)
+        of the residual L(x) - rhs, float32 CUDA tensors; returns
+        (feat, target or None, sigma)."""
+        nx, ny = self.sizes[member]
+        _check_field(x, ny, nx, "x")
+        _check_field(rhs, ny, nx, "rhs")
+        if feat is None:
+            feat = torch.empty((LEARNED_CHANNELS, ny, nx), dtype=torch.float32, device=x.device)
+        _check_f32(feat, (LEARNED_CHANNELS, ny, nx), "feat")
+        if hi_iters > 0:
+            if target is None:
+                target = torch.empty((ny, nx), dtype=torch.float32, device=x.device)
+            _check_f32(target, (ny, nx), "target")
+        else:
+            target = None
+        sig = C.c_double()
+        rc = _lib.gcr_learned_features(self._h, member, x.data_ptr(), rhs.data_ptr(), int(hi_iters),
+                                       feat.data_ptr(), None if target is None else target.data_ptr(),
+                                       C.byref(sig))
+        if rc < 0:
+            raise self._err(rc)
+        return feat, target, sig.value
+
     def apply_precond(self, member, r, out=None):
         nx, ny = self.sizes[member]
         _check_field(r, ny, nx, "r")
@@ -281,3 +328,94 @@ class Solver:
         if rc < 0:
             raise self._err(rc)
         return e
+
+
+def _check_f32(t, shape, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must be a contiguous float32 tensor of shape {tuple(shape)}")
+
+
+def cnn_param_count(c_in=LEARNED_CHANNELS) -> int:
+    return int(_lib.cnn_param_count(int(c_in)))
+
+
+class Network:
+    """The learned preconditioner's convolution network on the GPU (forward,
+    gradients, Adam training); tensors are float32 CUDA tensors."""
+
+    def __init__(self, nx, ny, max_batch, c_in=LEARNED_CHANNELS, stream=None):
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.nx, self.ny, self.max_batch, self.c_in = int(nx), int(ny), int(max_batch), int(c_in)
+        h = C.c_void_p()
+        rc = _lib.cnn_create(self.nx, self.ny, self.max_batch, self.c_in, C.c_void_p(stream.cuda_stream),
+                             C.byref(h))
+        if rc < 0:
+            raise GcrError(rc, _lib.cnn_last_error(None).decode())
+        self._h = h
+        self.nparams = cnn_param_count(self.c_in)
+
+    def _err(self, rc):
+        return GcrError(rc, _lib.cnn_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        import numpy as np
+        arr = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        rc = _lib.cnn_set_params(self._h, arr.ctypes.data, arr.size)
+        if rc < 0:
+            raise self._err(rc)
+
+    def get_params(self):
+        import numpy as np
+        arr = np.empty(self.nparams, dtype=np.float32)
+        rc = _lib.cnn_get_params(self._h, arr.ctypes.data, arr.size)
+        if rc < 0:
+            raise self._err(rc)
+        return arr
+
+    def _batch(self, inp):
+        _check_f32(inp, (inp.shape[0], self.c_in, self.ny, self.nx), "input")
+        return int(inp.shape[0])
+
+    def forward(self, inp, out=None):
+        b = self._batch(inp)
+        if out is None:
+            out = torch.empty((b, self.ny, self.nx), dtype=torch.float32, device=inp.device)
+        _check_f32(out, (b, self.ny, self.nx), "out")
+        rc = _lib.cnn_forward(self._h, b, inp.data_ptr(), out.data_ptr())
+        if rc < 0:
+            raise self._err(rc)
+        return out
+
+    def gradients(self, inp, dy):
+        import numpy as np
+        b = self._batch(inp)
+        _check_f32(dy, (b, self.ny, self.nx), "dy")
+        g = np.empty(self.nparams, dtype=np.float32)
+        rc = _lib.cnn_gradients(self._h, b, inp.data_ptr(), dy.data_ptr(), g.ctypes.data)
+        if rc < 0:
+            raise self._err(rc)
+        return g
+
+    def train_step(self, inp, target, lr=1e-3):
+        b = self._batch(inp)
+        _check_f32(target, (b, self.ny, self.nx), "target")
+        loss = C.c_double()
+        rc = _lib.cnn_train_step(self._h, b, inp.data_ptr(), target.data_ptr(), float(lr), C.byref(loss))
+        if rc < 0:
+            raise self._err(rc)
+        return loss.value

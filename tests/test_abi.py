@@ -115,3 +115,33 @@ def test_create_without_gpu_reports_hip_error(lib):
     h = C.c_void_p()
     rc = lib._lib.gcr_create(C.byref(p), C.byref(h))
     assert rc == lib.EHIP and h.value is None
+
+
+def test_network_entry_points_without_gpu(lib):
+    # parameter count: 3 -> 32 -> 32 -> 32 -> 32 -> 1 with 3x3 kernels and biases
+    assert lib._lib.cnn_param_count(3) == (32 * 3 * 9 + 32) + 3 * (32 * 32 * 9 + 32) + (32 * 9 + 1)
+    assert lib._lib.cnn_param_count(0) == -1 and lib._lib.cnn_param_count(33) == -1
+    assert lib._lib.cnn_destroy(None) == lib.OK
+    h = C.c_void_p()
+    for nx, ny, b, c in ((48, 16, 1, 3), (2048, 16, 1, 3), (64, 1, 1, 3), (64, 16, 0, 3), (64, 16, 1, 0)):
+        assert lib._lib.cnn_create(nx, ny, b, c, None, C.byref(h)) == lib.EINVAL
+        assert h.value is None
+        assert lib._lib.cnn_last_error(None)
+    assert lib._lib.cnn_set_params(None, None, 0) == lib.EINVAL
+    assert lib._lib.cnn_get_params(None, None, 0) == lib.EINVAL
+    assert lib._lib.cnn_forward(None, 1, None, None) == lib.EINVAL
+    assert lib._lib.cnn_gradients(None, 1, None, None, None) == lib.EINVAL
+    assert lib._lib.cnn_train_step(None, 1, None, None, 1e-3, None) == lib.EINVAL
+    assert lib._lib.gcr_set_learned(None, None, 0, 0.5) == lib.EINVAL
+    assert lib._lib.gcr_learned_features(None, 0, None, None, 0, None, None, None) == lib.EINVAL
+
+
+def test_learned_create_needs_one_size(lib):
+    p = _params(lib)
+    nx = (C.c_int32 * 2)(64, 128)
+    ny = (C.c_int32 * 2)(16, 16)
+    p.batch, p.nx, p.ny = 2, nx, ny
+    p.precond = lib.PC_LEARNED
+    h = C.c_void_p()
+    assert lib._lib.gcr_create(C.byref(p), C.byref(h)) == lib.EINVAL
+    assert b"one size" in lib._lib.gcr_last_error(None)
