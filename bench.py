@@ -7,9 +7,14 @@ the 512x256 lon/lat grid -- each member with its own seeded depth field
 L(x_true) for a seeded degree<=12 field -- assembled from the depth field
 (coefficients on the GPU) and solved to 1e-8 relative residual with GCR(3)
 and the semi-implicit Richardson preconditioner (two row solves).  The
-headline form is the mixed one (float16/float32 operator storage, float32
-Krylov vectors, float64 inner products, float64 solution and residual
-replacement at every restart); the float64 form is timed beside it.
+headline form is the mixed one with half precision confined to the
+preconditioner (float16 preconditioner coefficients and intermediates,
+float32 polar rows; float32 operator and Krylov vectors; float64 inner
+products, float64 solution and float64 residual replacement at every
+restart).  Timed beside it: the float64 form, and the mixed form with the
+learned preconditioner (semi-implicit Richardson plus a trained bf16
+convolution network correction, weights from
+paper_2103_16120_amd/weights/learned_512x256.bin).
 
 Prints one JSON line (rank 0).  Inputs are resident in HBM before the timed
 region starts.  --gpus above 1 is refused: this build measures one GPU.
@@ -58,6 +63,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison leg")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel event timing")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner leg")
     return ap.parse_args()
 
 
@@ -80,17 +86,21 @@ def make_inputs(args, torch, lib):
 class Leg:
     """One precision form of the step: assemble every member, solve the batch."""
 
-    def __init__(self, lib, torch, args, sizes, probs, depth, rhs, precision):
+    def __init__(self, lib, torch, args, sizes, probs, depth, rhs, precision, precond=None, learned=None):
         self.lib, self.torch = lib, torch
-        self.solver = lib.Solver(sizes, precision=precision, rtol=args.rtol, max_iters=100)
+        precond = lib.PC_SEMI_IMPLICIT if precond is None else precond
+        self.solver = lib.Solver(sizes, precision=precision, precond=precond, rtol=args.rtol, max_iters=100)
+        if learned is not None:
+            self.solver.set_learned(learned)
         self.probs, self.depth, self.rhs = probs, depth, rhs
-        self.x = [torch.zeros_like(r) for r in rhs]
+        # one buffer for all solutions: the zero initial guess is one fill
+        self.X = torch.zeros((len(rhs),) + tuple(rhs[0].shape), dtype=torch.float64, device=rhs[0].device)
+        self.x = [self.X[m] for m in range(len(rhs))]
         self.reports = None
 
     def step(self):
         self.solver.set_operators(list(range(len(self.probs))), self.depth, [p["dt"] for p in self.probs])
-        for x in self.x:
-            x.zero_()
+        self.X.zero_()
         self.reports = self.solver.solve(self.rhs, self.x)
         return self.reports
 
@@ -221,6 +231,22 @@ def main():
             out["fp64"]["roofline"] = roofline(kt64, it64, f64.reports, pts, ALG_BYTES_FP64)
         out["speedup_mixed_vs_fp64"] = round(t64 / t_mixed, 3)
         f64.solver.close()
+
+    if not args.no_learned:
+        from paper_2103_16120_amd.learned import load_weights, DEFAULT_WEIGHTS
+        params, head = load_weights(DEFAULT_WEIGHTS)
+        lrn = Leg(lib, torch, args, sizes, probs, depth, rhs, lib.MIXED_HALF_PC, lib.PC_LEARNED, params)
+        tl, itl, ktl = lrn.run(args.steps, args.warmup, not args.no_timing)
+        out["learned"] = {"solves_per_s": round(solves / tl, 2), "ms_per_step": round(1e3 * tl / args.steps, 3),
+                          "gcr_iters_mean": float(itl.mean()),
+                          "fallbacks": int(sum(r.fallback_used for r in lrn.reports)),
+                          "rel_res_true_max": max(r.rel_res_true for r in lrn.reports),
+                          "weights": os.path.relpath(DEFAULT_WEIGHTS, ROOT),
+                          "training": {k: head.get(k) for k in ("problems", "hi_iters", "steps", "loss_last",
+                                                                 "target_mean_square")}}
+        if not args.no_timing:
+            out["learned"]["kernel_ms_per_step"] = {k: round(v[1] / args.steps, 4) for k, v in ktl.items() if v[0]}
+        lrn.solver.close()
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, probs, args.cpu_seconds)

@@ -233,15 +233,18 @@ const char* gcr_version(void);
  * Learned preconditioner (GCR_PC_LEARNED; not from the paper).
  *
  * After the semi-implicit Richardson output e_2 = P^{-1}(r) (option 3 with
- * the solver's Richardson count) a convolution network N adds a correction:
- *     e = e_2 + (sigma / s) * N(r / sigma, e_2 * s / sigma, cos(lat)),
- * with s = dt / (2 a^2) and sigma = ||r||_2 / sqrt(NX*NY) in physical units,
- * so the result is independent of the scale of r.  GCR minimises the
- * residual over whatever directions it is given, so a preconditioner that
- * changes between iterations is allowed.  N: 3x3 convolutions 3 -> 32 -> 32
- * -> 32 -> 32 -> 1, ReLU between layers, periodic in longitude, the row
- * beyond a pole is the polar row shifted by NX/2 (the operator's closure).
- * Weights and activations bf16, float32 accumulation.
+ * the solver's Richardson count) a convolution network N adds a correction
+ * that passes through the preconditioner's row operator T = I - eta (P^Z -
+ * P^H) (eq. P_Operator):
+ *     e = e_2 + T^{-1}( s * sigma * N(r / sigma, e_2 / (s * sigma), cos(lat)) ),
+ * with s = dt / (2 a^2) and sigma = ||r||_2 / sqrt(NX*NY) in physical units
+ * (L is of size 1/s, so both inputs are of order one), so the result is
+ * independent of the scale of r.  GCR minimises the residual over whatever
+ * directions it is given, so a preconditioner that changes between
+ * iterations is allowed.  N: 3x3 convolutions 3 -> 32 -> 32 -> 32 -> 32 -> 1,
+ * ReLU between layers, periodic in longitude, the row beyond a pole is the
+ * polar row shifted by NX/2 (the operator's closure).  Weights and
+ * activations bf16, float32 accumulation.
  * ------------------------------------------------------------------------ */
 #define GCR_LEARNED_CHANNELS 3
 
@@ -305,8 +308,8 @@ int gcr_set_learned(gcr_solver* s, const float* params, int64_t count, double fa
 /* Training data for member `member`: with r = L(x) - rhs (float64),
  * e_lo = P^{-1}(r) with the solver's Richardson count and, if hi_iters > 0,
  * e_hi = P^{-1}(r) with hi_iters Richardson iterations, write
- *   feat [3][NY][NX] = (r / sigma, e_lo * s / sigma, cos(lat))   (float32)
- *   target [NY][NX]  = (e_hi - e_lo) * s / sigma                 (float32)
+ *   feat [3][NY][NX] = (r / sigma, e_lo / (s sigma), cos(lat))   (float32)
+ *   target [NY][NX]  = T(e_hi - e_lo) / (s sigma)                (float32)
  * (target only if hi_iters > 0 and target != NULL).  x, rhs: device float64
  * [NY][NX]; feat, target: device float32.  *sigma (may be NULL) receives
  * sigma; a zero residual gives sigma = 0 and zero features.  Synchronous.

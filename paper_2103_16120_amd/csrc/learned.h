@@ -1,8 +1,13 @@
 // Solver-side kernels of the learned preconditioner: scale of the residual,
 // feature packing into the network's input tensor, and the correction
-//   e <- e + (sigma / s) N(r / sigma, e s / sigma, cos(lat))
-// in physical units (s = dt / (2 a^2)).  In the mixed forms r is held scaled
-// by s, so sigma_held = s sigma and the factors below carry one more s.
+//   e <- e + T^{-1}( s sigma N(r / sigma, e / (s sigma), cos(lat)) )
+// in physical units (s = dt / (2 a^2); L is of size 1/s, so e = P^{-1} r is of
+// size s r and both network inputs are of order one).  T = I - eta (P^Z - P^H)
+// is the row operator of the semi-implicit preconditioner: the network's
+// output passes through the same implicit zonal solve as the Richardson
+// iterates, which keeps its pixel-scale errors out of the stiff zonal part of
+// L near the poles.  In the mixed forms r is held scaled by s, so there
+// sigma_held = s sigma.
 #pragma once
 
 #include "kernels.h"
@@ -50,7 +55,8 @@ __global__ void k_learn_sigma(Fields F, LearnArgs A, int member0) {
   if (threadIdx.x == 0) S.sigma = sqrt(rr / ((double)G.nx * G.ny));
 }
 
-// per-member factors: features (r * fr, e * fe); correction y * fc
+// per-member factors: features (r * fr, e * fe); correction y * fc.  `sigma`
+// is the RMS of r as held, u * sigma_physical.
 template <typename P>
 __device__ __forceinline__ void learn_factors(const Fields& F, int m, double sigma, double& fr, double& fe,
                                               double& fc) {
@@ -58,8 +64,8 @@ __device__ __forceinline__ void learn_factors(const Fields& F, int m, double sig
   const double u = P::mixed ? s : 1.0;    // r held as u * r_physical
   if (sigma > 0.0) {
     fr = 1.0 / sigma;
-    fe = s * u / sigma;
-    fc = sigma / (u * s);
+    fe = u / (s * sigma);
+    fc = s * sigma / u;
   } else {
     fr = fe = fc = 0.0;
   }
@@ -103,9 +109,24 @@ __global__ __launch_bounds__(WG) void k_learn_pack(Fields F, LearnArgs A) {
   }
 }
 
-// one wave per row: e += fc * y
+// T = I - eta (P^Z - P^H) of the lane's points of one row
+template <typename T, int M, typename CV>
+__device__ __forceinline__ void learn_row_system(const RowCtx& R, const CV& cv, T (&lo)[M], T (&di)[M],
+                                                 T (&up)[M]) {
+  const T helm = cv.helm(R.g);
+  T axe[M], axw[M], ayn[M], ays[M];
+  row_faces<T, M>(R, cv, axe, axw, ayn, ays);
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const T eta = (T)1 / (ayn[k] + ays[k]);
+    row_system(eta, axe[k], axw[k], helm, lo[k], di[k], up[k]);
+  }
+}
+
+// one wave per row: e += T^{-1}(fc * y)
 template <typename P, int M>
 __global__ __launch_bounds__(WG) void k_learn_apply(Fields F, LearnArgs A) {
+  using T = typename P::T;
   using V = typename P::V;
   int g, m, lane, w;
   MemberGeom G;
@@ -113,20 +134,24 @@ __global__ __launch_bounds__(WG) void k_learn_apply(Fields F, LearnArgs A) {
   const MemberState& S = F.state[m];
   if (learn_skip(F, S)) return;
   const RowCtx R = make_row(G, m, g, lane, M);
-  if (!R.act) return;
   double fr, fe, fc;
   learn_factors<P>(F, m, S.sigma, fr, fe, fc);
   const float* yrow = A.y + ((long long)m * G.ny + R.j) * G.nx + R.lane * M;
-  V* e = (V*)A.e + R.rc;
+  with_coef<P>(F, G, R.j, false, [&](const auto& cv) {
+    T lo[M], di[M], up[M], rh[M], z[M], ev[M];
+    learn_row_system<T, M>(R, cv, lo, di, up);
 #pragma unroll
-  for (int k = 0; k < M; ++k) {
-    V& d = e[k * R.L + R.lane];
-    d = (V)((double)d + fc * (double)yrow[k]);
-  }
+    for (int k = 0; k < M; ++k) rh[k] = (T)(fc * (double)yrow[k]);
+    solve_row<T, M>(R, lo, di, up, rh, z);
+    ldr<M>((const V*)A.e + R.rc, R.lane, R.L, ev);
+#pragma unroll
+    for (int k = 0; k < M; ++k) ev[k] += z[k];
+    if (R.act) str<M>((V*)A.e + R.rc, R.lane, R.L, ev);
+  });
 }
 
-// training data, natural [NY][NX] order: features and target of one member
-// from float64 pooled r, e_lo and (optionally) e_hi
+// training data, natural [NY][NX] order: features and target T(e_hi - e_lo)
+// (scaled) of one member from float64 pooled r, e_lo and (optionally) e_hi
 template <int M>
 __global__ __launch_bounds__(WG) void k_learn_features(Fields F, const double* r, const double* elo,
                                                        const double* ehi, float* feat, float* target) {
@@ -134,19 +159,31 @@ __global__ __launch_bounds__(WG) void k_learn_features(Fields F, const double* r
   MemberGeom G;
   if (!wave_row(F, g, m, G, lane, w)) return;
   const RowCtx R = make_row(G, m, g, lane, M);
-  if (!R.act) return;
   double fr, fe, fc;
   learn_factors<PrecF64>(F, m, F.state[m].sigma, fr, fe, fc);
   const long long np = (long long)G.nx * G.ny;
   const float cz = (float)learn_cos(R.j, G.ny);
+  double lo[M], di[M], up[M];
+  learn_row_system<double, M>(R, CoefRow<double, double>{F.c64.a, F.c64.c}, lo, di, up);
+  if (!R.act) return;
+  // stored position of natural point i of the row: (i mod M) * L + i / M
+  auto at = [&](const double* v, int i) {
+    i &= G.nx - 1;
+    return v[R.rc + (long long)(i & (M - 1)) * R.L + (i / M)];
+  };
 #pragma unroll
   for (int k = 0; k < M; ++k) {
-    const long long src = R.rc + k * R.L + R.lane;
-    const long long dst = (long long)R.j * G.nx + R.lane * M + k;
-    feat[dst] = (float)(r[src] * fr);
-    feat[np + dst] = (float)(elo[src] * fe);
+    const int i = R.lane * M + k;
+    const long long dst = (long long)R.j * G.nx + i;
+    feat[dst] = (float)(at(r, i) * fr);
+    feat[np + dst] = (float)(at(elo, i) * fe);
     feat[2 * np + dst] = cz;
-    if (target) target[dst] = (float)((ehi[src] - elo[src]) * fe);
+    if (target) {
+      const double dc = at(ehi, i) - at(elo, i);
+      const double dw = at(ehi, i - 1) - at(elo, i - 1);
+      const double de = at(ehi, i + 1) - at(elo, i + 1);
+      target[dst] = (float)((lo[k] * dw + di[k] * dc + up[k] * de) * fe);
+    }
   }
 }
 

@@ -99,6 +99,7 @@ struct gcr_solver {
   MemberState* state_ring[2] = {};   // pinned copies of the scalars after a cycle
   hipEvent_t cycle_ev[2] = {};       // recorded after each copy
   AsmMember* asm_stage = nullptr;    // pinned staging of the assembly table
+  hipEvent_t stage_ev[2] = {};       // recorded after the uploads from ptr_stage / asm_stage
   AsmMember* asm_tab = nullptr;      // device assembly table [batch]
   cnn_net* net = nullptr;            // learned preconditioner (GCR_PC_LEARNED), owned
   double fallback_ratio = 0.5;
@@ -271,6 +272,10 @@ static void free_all(gcr_solver* s) {
     s->state_ring[i] = nullptr;
     s->cycle_ev[i] = nullptr;
   }
+  for (int i = 0; i < 2; ++i) {
+    if (s->stage_ev[i]) (void)hipEventDestroy(s->stage_ev[i]);
+    s->stage_ev[i] = nullptr;
+  }
   s->ptr_stage = nullptr;
   s->state_h = nullptr;
   s->asm_stage = nullptr;
@@ -400,6 +405,7 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   for (int i = 0; i < 2 && herr == hipSuccess; ++i) {
     herr = hipHostMalloc((void**)&s->state_ring[i], P.batch * sizeof(MemberState), 0);
     if (herr == hipSuccess) herr = hipEventCreateWithFlags(&s->cycle_ev[i], hipEventDisableTiming);
+    if (herr == hipSuccess) herr = hipEventCreateWithFlags(&s->stage_ev[i], hipEventDisableTiming);
   }
   if (herr != hipSuccess) {
     const bool oom = herr == hipErrorOutOfMemory;
@@ -412,6 +418,7 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
     herr = hipMemcpyAsync(s->rowmap, rowmap_h.data(), R * sizeof(int), hipMemcpyHostToDevice, s->stream);
   if (herr == hipSuccess) herr = hipMemsetAsync(s->state, 0, P.batch * sizeof(MemberState), s->stream);
   if (herr == hipSuccess) herr = hipMemsetAsync(s->part, 0, (size_t)R * NDOT * sizeof(double), s->stream);
+  for (int i = 0; i < 2 && herr == hipSuccess; ++i) herr = hipEventRecord(s->stage_ev[i], s->stream);
   if (herr == hipSuccess) herr = hipStreamSynchronize(s->stream);
   if (herr != hipSuccess) {
     free_all(s);
@@ -454,8 +461,9 @@ extern "C" int gcr_set_operators(gcr_solver* s, int32_t count, const int32_t* me
           return fail(s, GCR_EINVAL, "member %d: depth must be finite and > 0 (point %lld)", member, k);
     }
   }
-  // the staging table (pinned) may still feed an earlier upload
-  HIPCHK(s, hipStreamSynchronize(s->stream));
+  // the staging table (pinned) may still feed the previous upload: wait for
+  // that copy only, not for the whole stream
+  HIPCHK(s, hipEventSynchronize(s->stage_ev[1]));
   for (int t = 0; t < count; ++t) {
     const int member = members[t];
     const gcr_operator* op = &ops[t];
@@ -485,6 +493,7 @@ extern "C" int gcr_set_operators(gcr_solver* s, int32_t count, const int32_t* me
     s->scale_h[member] = op->dt / (2.0 * op->radius * op->radius);
   }
   HIPCHK(s, hipMemcpyAsync(s->asm_tab, s->asm_stage, count * sizeof(AsmMember), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipEventRecord(s->stage_ev[1], s->stream));
   AssembleArgs A{};
   A.tab = s->asm_tab;
   A.geom = s->geom;
@@ -674,13 +683,14 @@ extern "C" int gcr_solve(gcr_solver* s, const double* const* rhs, double* const*
   }
   if (s->prm.precond == GCR_PC_LEARNED && !s->net)
     return fail(s, GCR_ESTATE, "learned preconditioner without parameters (call gcr_set_learned)");
-  HIPCHK(s, hipStreamSynchronize(s->stream));  // staging buffer reuse
+  HIPCHK(s, hipEventSynchronize(s->stage_ev[0]));  // staging buffer reuse
   for (int m = 0; m < B; ++m) {
     s->ptr_stage[m] = rhs[m];
     s->ptr_stage[B + m] = x[m];
   }
   HIPCHK(s, hipMemcpyAsync(s->ptr_rhs, s->ptr_stage, B * sizeof(void*), hipMemcpyHostToDevice, s->stream));
   HIPCHK(s, hipMemcpyAsync(s->ptr_x, s->ptr_stage + B, B * sizeof(void*), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipEventRecord(s->stage_ev[0], s->stream));
   const dim3 gg(64, B);
   KLAUNCH(s, KT_COPY, k_gather, gg, dim3(256), 0, s->stream, s->ptr_rhs, s->rhs, s->geom);
   KLAUNCH(s, KT_COPY, k_gather, gg, dim3(256), 0, s->stream, (const double* const*)s->ptr_x, s->x, s->geom);
