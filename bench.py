@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison leg")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel event timing")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner leg")
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -104,13 +106,13 @@ class Leg:
         self.reports = self.solver.solve(self.rhs, self.x)
         return self.reports
 
-    def run(self, steps, warmup, timing):
+    def run(self, steps, warmup, timing, timing_steps=3):
+        """Time `steps` steps (no per-kernel events), then, if `timing`, run
+        `timing_steps` more with per-kernel HIP events for the breakdown."""
         torch = self.torch
         for _ in range(warmup):
             self.step()
         torch.cuda.synchronize()
-        if timing:
-            self.solver.set_kernel_timing(True)
         iters = []
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -118,10 +120,17 @@ class Leg:
             iters.append([r.iterations for r in reps])
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        ktimes = self.solver.kernel_times() if timing else {}
+        ktimes, kiters = {}, None
         if timing:
+            self.solver.set_kernel_timing(True)
+            kiters = []
+            for _ in range(timing_steps):
+                reps = self.step()
+                kiters.append([r.iterations for r in reps])
+            ktimes = self.solver.kernel_times()
             self.solver.set_kernel_timing(False)
-        return dt, np.array(iters), ktimes
+            kiters = np.array(kiters)
+        return dt, np.array(iters), ktimes, kiters
 
 
 def roofline(ktimes, iters, reports, pts, table, name="sweep2"):
@@ -181,11 +190,18 @@ def main():
         sys.exit(2)
     from paper_2103_16120_amd import lib
 
+    if args.copy_ref_mib > 0:
+        n = args.copy_ref_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     probs, sizes, depth, rhs = make_inputs(args, torch, lib)
     pts = args.nx * args.ny
 
     mixed = Leg(lib, torch, args, sizes, probs, depth, rhs, lib.MIXED_HALF_PC)
-    t_mixed, it_mixed, kt_mixed = mixed.run(args.steps, args.warmup, not args.no_timing)
+    t_mixed, it_mixed, kt_mixed, kit_mixed = mixed.run(args.steps, args.warmup, not args.no_timing)
     rep_m = mixed.reports
     solves = args.batch * args.steps
     value = solves / t_mixed
@@ -216,19 +232,20 @@ def main():
         "statuses": sorted(set(r.status for r in rep_m)),
     }
     if not args.no_timing:
-        out["roofline"] = roofline(kt_mixed, it_mixed, rep_m, pts, ALG_BYTES_MIXED)
-        out["kernel_ms_per_step"] = {k: round(v[1] / args.steps, 4) for k, v in kt_mixed.items() if v[0]}
-        out["kernel_launches_per_step"] = {k: v[0] / args.steps for k, v in kt_mixed.items() if v[0]}
+        ts = len(kit_mixed)
+        out["roofline"] = roofline(kt_mixed, kit_mixed, rep_m, pts, ALG_BYTES_MIXED)
+        out["kernel_ms_per_step"] = {k: round(v[1] / ts, 4) for k, v in kt_mixed.items() if v[0]}
+        out["kernel_launches_per_step"] = {k: v[0] / ts for k, v in kt_mixed.items() if v[0]}
     mixed.solver.close()
 
     if not args.no_fp64:
         f64 = Leg(lib, torch, args, sizes, probs, depth, rhs, lib.FP64)
-        t64, it64, kt64 = f64.run(args.steps, args.warmup, not args.no_timing)
+        t64, it64, kt64, kit64 = f64.run(args.steps, args.warmup, not args.no_timing)
         out["fp64"] = {"solves_per_s": round(solves / t64, 2), "ms_per_step": round(1e3 * t64 / args.steps, 3),
                        "gcr_iters_mean": float(it64.mean()),
                        "rel_res_true_max": max(r.rel_res_true for r in f64.reports)}
         if not args.no_timing:
-            out["fp64"]["roofline"] = roofline(kt64, it64, f64.reports, pts, ALG_BYTES_FP64)
+            out["fp64"]["roofline"] = roofline(kt64, kit64, f64.reports, pts, ALG_BYTES_FP64)
         out["speedup_mixed_vs_fp64"] = round(t64 / t_mixed, 3)
         f64.solver.close()
 
@@ -236,7 +253,7 @@ def main():
         from paper_2103_16120_amd.learned import load_weights, DEFAULT_WEIGHTS
         params, head = load_weights(DEFAULT_WEIGHTS)
         lrn = Leg(lib, torch, args, sizes, probs, depth, rhs, lib.MIXED_HALF_PC, lib.PC_LEARNED, params)
-        tl, itl, ktl = lrn.run(args.steps, args.warmup, not args.no_timing)
+        tl, itl, ktl, kitl = lrn.run(args.steps, args.warmup, not args.no_timing)
         out["learned"] = {"solves_per_s": round(solves / tl, 2), "ms_per_step": round(1e3 * tl / args.steps, 3),
                           "gcr_iters_mean": float(itl.mean()),
                           "fallbacks": int(sum(r.fallback_used for r in lrn.reports)),
@@ -245,7 +262,7 @@ def main():
                           "training": {k: head.get(k) for k in ("problems", "hi_iters", "steps", "loss_last",
                                                                  "target_mean_square")}}
         if not args.no_timing:
-            out["learned"]["kernel_ms_per_step"] = {k: round(v[1] / args.steps, 4) for k, v in ktl.items() if v[0]}
+            out["learned"]["kernel_ms_per_step"] = {k: round(v[1] / len(kitl), 4) for k, v in ktl.items() if v[0]}
         lrn.solver.close()
 
     if not args.no_cpu_baseline:

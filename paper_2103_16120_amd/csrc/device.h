@@ -61,6 +61,12 @@ struct MemberState {
   int fallback, pad1, pad2, pad3;
 };
 
+// Quotient a / b: exact in float64; in float32 (the mixed forms' row solves,
+// whose inputs are stored in float16) the hardware reciprocal, which is
+// within 1 ulp, times a.
+__device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
 // ---------------------------------------------------------------------------
 // cross-lane helpers (wave64)
 // ---------------------------------------------------------------------------
@@ -209,13 +215,13 @@ struct RowSolver {
     }
     const T hr = (k == M - 2) ? -up : (T)0;   // coupling to y_l moves to the right-hand side
     if (k == 0) {
-      const T inv = (T)1 / di;
+      const T inv = qdiv((T)1, di);
       cp[0] = up * inv;
       f[0] = rh * inv;
       g[0] = -lo * inv;
       h[0] = hr * inv;
     } else {
-      const T inv = (T)1 / (di - lo * cp[k - 1]);
+      const T inv = qdiv((T)1, di - lo * cp[k - 1]);
       cp[k] = up * inv;
       f[k] = (rh - lo * f[k - 1]) * inv;
       g[k] = (-lo * g[k - 1]) * inv;
@@ -240,13 +246,13 @@ struct RowSolver {
       const int im = (lane - s + L) & (L - 1), ip = (lane + s) & (L - 1);
       const T Am = shfl(A, im), Bm = shfl(B, im), Cm = shfl(C, im), Dm = shfl(D, im);
       const T Ap = shfl(A, ip), Bp = shfl(B, ip), Cp = shfl(C, ip), Dp = shfl(D, ip);
-      const T k1 = A / Bm, k2 = C / Bp;
+      const T k1 = qdiv(A, Bm), k2 = qdiv(C, Bp);
       B = B - k1 * Cm - k2 * Ap;
       D = D - k1 * Dm - k2 * Dp;
       A = -k1 * Am;
       C = -k2 * Cp;
     }
-    const T y = D / (A + B + C);
+    const T y = qdiv(D, A + B + C);
     const T ym = shfl(y, prv);
 #pragma unroll
     for (int k = 0; k < M - 1; ++k) x[k] = f[k] + g[k] * ym + h[k] * y;

@@ -371,7 +371,7 @@ __device__ __forceinline__ void row_update_sweep1(const Fields& F, const RowCtx&
     row_faces<T, M>(R, cv, axe, axw, ayn, ays);
   #pragma unroll
     for (int k = 0; k < M; ++k) {
-      const T eta = (T)1 / (ayn[k] + ays[k]);
+      const T eta = qdiv((T)1, ayn[k] + ays[k]);
       row_system(eta, axe[k], axw[k], helm, lo[k], di[k], up[k]);
       rh[k] = -eta * rv[k];
     }
@@ -405,7 +405,7 @@ __device__ __forceinline__ void row_sweep2(const Fields& F, const RowCtx& R, con
     ldr<M>((const V*)F.r + R.rc, R.lane, R.L, rv);
     RowSolver<T, M> rs;
     auto emit = [&](int k, T, T rest, T xc, T axe, T axw, T ayn, T ays) {
-      const T eta = (T)1 / (ayn + ays);
+      const T eta = qdiv((T)1, ayn + ays);
       T lo, di, up;
       row_system(eta, axe, axw, helm, lo, di, up);
       rs.push(k, lo, di, up, xc + eta * (rest - rv[k]));
@@ -683,8 +683,14 @@ __device__ __forceinline__ double absorber_at(double lat, double amax) {
 // One workgroup per (row, table entry).  Rows j-1, j, j+1 of Phi* and of
 // H* = Phi* + H0 are staged in LDS with coalesced loads (rows beyond a pole
 // are the polar row seen across the pole); the coefficients are then written
-// in stored (row-interleaved) order, i.e. coalesced.
+// in stored (row-interleaved) order, i.e. coalesced.  The LDS copy of a row is
+// itself kept in padded interleaved order, lds(i) = (i mod M)(L+1) + i/M, so
+// that the stored-order reads of consecutive threads hit distinct banks.
+// Everything that depends on the latitude only is folded into per-row
+// factors, leaving no division in the per-point work.
 constexpr int ASM_WG = 256;
+
+__host__ __device__ constexpr int asm_row_lds(int nx) { return nx + 16; }   // doubles per staged row (M <= 16)
 
 __global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
   // dynamic LDS: Phi* rows j-1, j, j+1, then (with orography) H* rows
@@ -694,8 +700,11 @@ __global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
   const int nx = G.nx, ny = G.ny, j = blockIdx.x;
   if (j >= ny) return;
   const int half = nx >> 1;
+  const int lm = G.log2m, Mr = 1 << lm, Lr = nx >> lm;
+  const int rs = asm_row_lds(nx);
+  auto lidx = [&](int i) { return (i & (Mr - 1)) * (Lr + 1) + (i >> lm); };
   double* sd0 = asm_lds;
-  double* sh0 = P.oro ? asm_lds + 3 * nx : asm_lds;
+  double* sh0 = P.oro ? asm_lds + 3 * rs : asm_lds;
   for (int r = 0; r < 3; ++r) {
     int jj = j - 1 + r, sh_ = 0;
     if (jj < 0) { jj = 0; sh_ = half; }
@@ -705,13 +714,11 @@ __global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
     for (int i = threadIdx.x; i < nx; i += ASM_WG) {
       const int src = (i + sh_) & (nx - 1);
       const double d = drow[src];
-      sd0[r * nx + i] = d;
-      if (orow) sh0[r * nx + i] = d + orow[src];
+      sd0[r * rs + lidx(i)] = d;
+      if (orow) sh0[r * rs + lidx(i)] = d + orow[src];
     }
   }
   __syncthreads();
-  auto sd = [&](int r, int i) { return sd0[r * nx + i]; };
-  auto sh = [&](int r, int i) { return sh0[r * nx + i]; };
   const double kPi = 3.14159265358979323846;
   const double dlam = 2.0 * kPi / nx, dphi = kPi / ny;
   const double delta = 0.5 * P.dt;
@@ -723,35 +730,49 @@ __global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
   const double b_c = delta * 2.0 * P.omega * sin(lat_c), b_n = delta * 2.0 * P.omega * sin(lat_n);
   const double D_c = gam_c * gam_c + b_c * b_c, D_n = gam_n * gam_n + b_n * b_n;
   const double s = P.dt / (2.0 * P.radius * P.radius);   // mixed-form scale
-  const int Lr = nx >> G.log2m, Mr = 1 << G.log2m;
+  // east faces: kappa = ke * (Phi*_i + Phi*_{i+1}); the differences of H*
+  // enter B^x through bl (zonal) and bp (meridional, 4-point average)
+  const double ke = delta * P.g * 0.5 / (2.0 * D_c);
+  const double fxx = gam_c / cs_c / (dlam * dlam);
+  const double fxy = b_c / (4.0 * dlam * dphi);
+  const double gbx = delta * P.g / (2.0 * D_c) / (2.0 * dlam);
+  const double bl_e = gam_c / cs_c / dlam, bp_e = b_c / (4.0 * dphi);
+  // north face
+  const double kn = delta * P.g * 0.5 / (2.0 * D_n);
+  const double fyy = gam_n * cs_n / (dphi * dphi);
+  const double fyx = -b_n / (4.0 * dlam * dphi);
+  const double gby = delta * P.g / (2.0 * D_n) / (2.0 * dphi);
+  const double bl_n = -b_n / (4.0 * dlam), bp_n = gam_n * cs_n / dphi;
+  const bool north = j < ny - 1;   // the pole face carries no flux
   const long long rowoff = G.off + (long long)j * nx;
   for (int slot = threadIdx.x; slot < nx; slot += ASM_WG) {
     const int i = (slot % Lr) * Mr + slot / Lr;   // natural column stored at this slot
-    const int ie = (i + 1) & (nx - 1), iw = (i - 1) & (nx - 1);
+    const int c = lidx(i), ce = lidx((i + 1) & (nx - 1)), cw = lidx((i - 1) & (nx - 1));
+    const double d1 = sd0[rs + c];
     double out[NCOEF];
     {  // east face (i+1/2, j)
-      const double kap = delta * P.g * 0.5 * (sd(1, i) + sd(1, ie)) / (2.0 * D_c);
-      out[C_AXX] = kap * gam_c / cs_c / (dlam * dlam);
-      out[C_AXY] = kap * b_c / (4.0 * dlam * dphi);
+      const double kap = ke * (d1 + sd0[rs + ce]);
+      out[C_AXX] = kap * fxx;
+      out[C_AXY] = kap * fxy;
       double bx = 0.0;
       if (P.b_terms) {
-        const double dhl = (sh(1, ie) - sh(1, i)) / dlam;
-        const double dhp = ((sh(2, i) - sh(0, i)) + (sh(2, ie) - sh(0, ie))) / (4.0 * dphi);
-        bx = delta * P.g / (2.0 * D_c) * (gam_c / cs_c * dhl + b_c * dhp);
+        const double dhl = sh0[rs + ce] - sh0[rs + c];
+        const double dhp = (sh0[2 * rs + c] - sh0[c]) + (sh0[2 * rs + ce] - sh0[ce]);
+        bx = gbx * (bl_e * dhl + bp_e * dhp);
       }
-      out[C_BX] = bx / (2.0 * dlam);
+      out[C_BX] = bx;
     }
-    if (j < ny - 1) {  // north face (i, j+1/2); the pole face carries no flux
-      const double kap = delta * P.g * 0.5 * (sd(1, i) + sd(2, i)) / (2.0 * D_n);
-      out[C_AYY] = kap * gam_n * cs_n / (dphi * dphi);
-      out[C_AYX] = -kap * b_n / (4.0 * dlam * dphi);
+    if (north) {  // north face (i, j+1/2)
+      const double kap = kn * (d1 + sd0[2 * rs + c]);
+      out[C_AYY] = kap * fyy;
+      out[C_AYX] = kap * fyx;
       double by = 0.0;
       if (P.b_terms) {
-        const double dhp = (sh(2, i) - sh(1, i)) / dphi;
-        const double dhl = ((sh(1, ie) - sh(1, iw)) + (sh(2, ie) - sh(2, iw))) / (4.0 * dlam);
-        by = delta * P.g / (2.0 * D_n) * (-b_n * dhl + gam_n * cs_n * dhp);
+        const double dhp = sh0[2 * rs + c] - sh0[rs + c];
+        const double dhl = (sh0[rs + ce] - sh0[rs + cw]) + (sh0[2 * rs + ce] - sh0[2 * rs + cw]);
+        by = gby * (bl_n * dhl + bp_n * dhp);
       }
-      out[C_BY] = by / (2.0 * dphi);
+      out[C_BY] = by;
     } else {
       out[C_AYY] = out[C_AYX] = out[C_BY] = 0.0;
     }

@@ -118,7 +118,7 @@ __device__ __forceinline__ void learn_row_system(const RowCtx& R, const CV& cv, 
   row_faces<T, M>(R, cv, axe, axw, ayn, ays);
 #pragma unroll
   for (int k = 0; k < M; ++k) {
-    const T eta = (T)1 / (ayn[k] + ays[k]);
+    const T eta = qdiv((T)1, ayn[k] + ays[k]);
     row_system(eta, axe[k], axw[k], helm, lo[k], di[k], up[k]);
   }
 }

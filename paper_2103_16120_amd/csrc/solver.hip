@@ -507,7 +507,7 @@ extern "C" int gcr_set_operators(gcr_solver* s, int32_t count, const int32_t* me
   A.scale = s->scale;
   bool any_oro = false;
   for (int t = 0; t < count; ++t) any_oro = any_oro || ops[t].orography;
-  const size_t lds = (any_oro ? 6 : 3) * (size_t)s->nxmax * sizeof(double);
+  const size_t lds = (any_oro ? 6 : 3) * (size_t)asm_row_lds(s->nxmax) * sizeof(double);
   KLAUNCH(s, KT_ASSEMBLE, k_assemble, dim3(maxrows, count), dim3(ASM_WG), lds, s->stream, A);
   HIPCHK(s, hipGetLastError());
   bool host_inputs = false;
