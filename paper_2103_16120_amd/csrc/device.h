@@ -104,31 +104,104 @@ __device__ __forceinline__ int row_slot(int i, int log2m, int L) {   // natural 
   return (i & ((1 << log2m) - 1)) * L + (i >> log2m);
 }
 
+// Element k of lane l sits at row + k*L + l.  Rows are read and written with
+// raw buffer instructions: the (wave-uniform) row start goes into a scalar
+// buffer descriptor, the per-k part k*L into the scalar offset, and the lane
+// part is one unsigned vector offset shared by every k -- no per-access
+// address arithmetic on the vector ALUs.  The descriptor's extent is the row
+// (NX elements), so the hardware drops any access outside it.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* row, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(row), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename S>
+struct RowIO;
+template <>
+struct RowIO<float> {
+  static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+  }
+  static __device__ __forceinline__ void st(float v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
+  }
+};
+template <>
+struct RowIO<double> {
+  typedef unsigned B __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+  }
+  static __device__ __forceinline__ void st(double v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B, v), r, vo, so, 0);
+  }
+};
+template <>
+struct RowIO<__half> {
+  static __device__ __forceinline__ __half ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    return __builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0));
+  }
+  static __device__ __forceinline__ void st(__half v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, vo, so, 0);
+  }
+};
+
+template <typename S, typename T>
+__device__ __forceinline__ T from_store(S v) { return (T)v; }
+template <typename S, typename T>
+__device__ __forceinline__ S to_store(T v) { return (S)v; }
+template <>
+__device__ __forceinline__ float from_store<__half, float>(__half v) { return __half2float(v); }
+template <>
+__device__ __forceinline__ double from_store<__half, double>(__half v) { return (double)__half2float(v); }
+template <>
+__device__ __forceinline__ __half to_store<__half, float>(float v) { return __float2half_rn(v); }
+template <>
+__device__ __forceinline__ __half to_store<__half, double>(double v) { return __float2half_rn((float)v); }
+
 template <int M, typename S, typename T>
 __device__ __forceinline__ void ldr(const S* row, int l, int L, T (&v)[M]) {
+  const __amdgpu_buffer_rsrc_t r = row_rsrc(row, (unsigned)(M * L) * sizeof(S));
+  const unsigned vo = (unsigned)l * sizeof(S);
 #pragma unroll
-  for (int k = 0; k < M; ++k) v[k] = (T)row[l + L * k];
-}
-template <int M, typename T>
-__device__ __forceinline__ void ldr(const __half* row, int l, int L, T (&v)[M]) {
-#pragma unroll
-  for (int k = 0; k < M; ++k) v[k] = (T)__half2float(row[l + L * k]);
+  for (int k = 0; k < M; ++k) v[k] = from_store<S, T>(RowIO<S>::ld(r, vo, (unsigned)(k * L) * sizeof(S)));
 }
 template <int M, typename S, typename T>
 __device__ __forceinline__ void str(S* row, int l, int L, const T (&v)[M]) {
+  const __amdgpu_buffer_rsrc_t r = row_rsrc(row, (unsigned)(M * L) * sizeof(S));
+  const unsigned vo = (unsigned)l * sizeof(S);
 #pragma unroll
-  for (int k = 0; k < M; ++k) row[l + L * k] = (S)v[k];
+  for (int k = 0; k < M; ++k) RowIO<S>::st(to_store<S, T>(v[k]), r, vo, (unsigned)(k * L) * sizeof(S));
+}
+
+// float16 rows pair their elements: (k, k+1) of lane l (k even) share the
+// 32-bit word at half offset (k/2)*2L + 2l, so one load or store moves two
+// values of a lane and the wave still touches one contiguous 256-byte span.
+__device__ __forceinline__ int half_slot(int l, int k, int L) { return (k >> 1) * 2 * L + 2 * l + (k & 1); }
+
+template <int M, typename T>
+__device__ __forceinline__ void ldr(const __half* row, int l, int L, T (&v)[M]) {
+  static_assert(M % 2 == 0, "float16 rows hold element pairs");
+  const __amdgpu_buffer_rsrc_t r = row_rsrc(row, (unsigned)(M * L) * 2u);
+  const unsigned vo = (unsigned)l * 4u;
+#pragma unroll
+  for (int j = 0; j < M / 2; ++j) {
+    const unsigned w = __builtin_amdgcn_raw_buffer_load_b32(r, vo, (unsigned)(j * L) * 4u, 0);
+    v[2 * j] = (T)__half2float(__builtin_bit_cast(__half, (unsigned short)(w & 0xffffu)));
+    v[2 * j + 1] = (T)__half2float(__builtin_bit_cast(__half, (unsigned short)(w >> 16)));
+  }
 }
 template <int M, typename T>
 __device__ __forceinline__ void str(__half* row, int l, int L, const T (&v)[M]) {
+  static_assert(M % 2 == 0, "float16 rows hold element pairs");
+  const __amdgpu_buffer_rsrc_t r = row_rsrc(row, (unsigned)(M * L) * 2u);
+  const unsigned vo = (unsigned)l * 4u;
 #pragma unroll
-  for (int k = 0; k < M; ++k) row[l + L * k] = __float2half_rn((float)v[k]);
+  for (int j = 0; j < M / 2; ++j) {
+    const unsigned lo16 = __builtin_bit_cast(unsigned short, __float2half_rn((float)v[2 * j]));
+    const unsigned hi16 = __builtin_bit_cast(unsigned short, __float2half_rn((float)v[2 * j + 1]));
+    __builtin_amdgcn_raw_buffer_store_b32(lo16 | (hi16 << 16), r, vo, (unsigned)(j * L) * 4u, 0);
+  }
 }
-
-template <typename T, typename S>
-__device__ __forceinline__ T ld1(const S* p) { return (T)*p; }
-template <typename T>
-__device__ __forceinline__ T ld1(const __half* p) { return (T)__half2float(*p); }
 
 // the same row seen across the pole: longitude shifted by NX/2 = (L/2)*M,
 // i.e. the chunk of lane l + L/2

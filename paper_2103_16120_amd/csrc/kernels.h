@@ -39,7 +39,6 @@ struct CoefRow {
   __device__ __forceinline__ void row(int k, long long start, int l, int L, T (&v)[M]) const {
     ldr<M>(a[k] + start, l, L, v);
   }
-  __device__ __forceinline__ T one(int k, long long off) const { return ld1<T>(a[k] + off); }
   __device__ __forceinline__ T helm(int g) const { return c[g]; }
 };
 
@@ -777,11 +776,12 @@ __global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
       out[C_AYY] = out[C_AYX] = out[C_BY] = 0.0;
     }
     const long long o = rowoff + slot;
+    const long long o16 = rowoff + half_slot(slot % Lr, slot / Lr, Lr);   // float16 rows pair elements
 #pragma unroll
     for (int k = 0; k < NCOEF; ++k) {
       A.a64[k][o] = out[k];
       A.a32[k][o] = (float)(s * out[k]);
-      A.a16[k][o] = __float2half_rn((float)(s * out[k]));
+      A.a16[k][o16] = __float2half_rn((float)(s * out[k]));
     }
   }
   if (threadIdx.x == 0) {

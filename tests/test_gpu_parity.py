@@ -278,3 +278,52 @@ def test_batched_assembly_matches_single(gpu_lib):
     for m, p in enumerate(probs):
         x = dev(np.random.default_rng(m).standard_normal((p["ny"], p["nx"])))
         assert torch.equal(a.apply_operator(m, x), b.apply_operator(m, x))
+
+
+# ---------------------------------------------------------------------------
+# full sizes, in the launch configuration the benchmark times
+# ---------------------------------------------------------------------------
+def _sampled_members_check(gpu_lib, probs, precision, sample, err_tol):
+    """Batch solve of `probs` (one launch sequence, batched assembly from
+    device depth fields, zero initial guesses in one buffer); every member
+    must reach the tolerance by its float64 true residual, and the sampled
+    members must match the oracle's solution."""
+    sizes = [(p["nx"], p["ny"]) for p in probs]
+    s = make_solver(gpu_lib, sizes, precision=precision, max_iters=100)
+    f = make_solver(gpu_lib, sizes)
+    depth = [dev(p["depth"]) for p in probs]
+    for m, p in enumerate(probs):
+        f.set_operator(m, depth[m], p["dt"])
+    rhs = [f.apply_operator(m, dev(p["x_true"])) for m, p in enumerate(probs)]
+    s.set_operators(list(range(len(probs))), depth, [p["dt"] for p in probs])
+    x = [torch.zeros_like(r) for r in rhs]
+    reps = s.solve(rhs, x)
+    for m, rp in enumerate(reps):
+        assert rp.status == gpu_lib.OK, (m, rp)
+        assert rp.rel_res_true <= 1.05e-8, (m, rp)
+    for m in sample:
+        p = probs[m]
+        op = EllipticOperator(p["nx"], p["ny"], p["depth"], p["dt"])
+        ores = gcr(op, host(rhs[m]), rtol=1e-8)
+        err = np.linalg.norm(host(x[m]) - ores.x) / np.linalg.norm(ores.x)
+        assert err <= err_tol, (m, err)
+    return reps
+
+
+@pytest.mark.parametrize("precision,tol", [(3, 1e-5), (0, 1e-9)])
+def test_benchmark_batch_sampled_against_oracle(gpu_lib, precision, tol):
+    """64 members of 512x256 as in the benchmark; members 0, 21, 42, 63 are
+    compared with the oracle point by point."""
+    probs = [problem(2, 512, 256, instance=m, dt=600.0) for m in range(64)]
+    _sampled_members_check(gpu_lib, probs, precision, (0, 21, 42, 63), tol)
+
+
+def test_uneven_batch_sampled_against_oracle(gpu_lib):
+    """64 members with grids drawn from {128x64, 256x128, 512x256}, their
+    own depth range and time step, mixed precision; one member of each grid
+    size is compared with the oracle."""
+    probs = batch_problems(3, 64)
+    sample = []
+    for size in ((128, 64), (256, 128), (512, 256)):
+        sample.append(next(m for m, p in enumerate(probs) if (p["nx"], p["ny"]) == size))
+    _sampled_members_check(gpu_lib, probs, 3, sample, 1e-5)
