@@ -47,6 +47,11 @@ ALG_BYTES_FP64 = {
     "sweep2": 72.0,
 }
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of the roofline kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# counter runs (scaled by a plain copy of known size), valid only for the
+# kernel sources it was taken with
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep2_traffic_512x256_b64.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2103_16120_amd", "csrc", f) for f in ("device.h", "kernels.h")]
 
 
 def parse():
@@ -149,6 +154,30 @@ def roofline(ktimes, iters, reports, pts, table, name="sweep2"):
             "alg_bytes_per_launch": int(per_launch)}
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """Bytes per launch from the committed counter summary, or None when it
+    is missing, for another kernel/workload, or older than the sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.loads([l for l in fh if l.startswith("{")][-1])
+    except (OSError, ValueError, IndexError):
+        return None
+    if rec.get("kernel") != kernel or rec.get("workload") != workload:
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
 def cpu_baseline(args, probs, budget_s):
     """The float64 oracle, single-threaded, on members of the same workload
     until the time budget is used (assembly + solve per member)."""
@@ -234,6 +263,8 @@ def main():
     if not args.no_timing:
         ts = len(kit_mixed)
         out["roofline"] = roofline(kt_mixed, kit_mixed, rep_m, pts, ALG_BYTES_MIXED)
+        if out["roofline"] is not None and args.batch == 64 and (args.nx, args.ny) == (512, 256):
+            out["roofline"]["traffic"] = measured_traffic("sweep2", "mixed_half_pc 64x512x256")
         out["kernel_ms_per_step"] = {k: round(v[1] / ts, 4) for k, v in kt_mixed.items() if v[0]}
         out["kernel_launches_per_step"] = {k: v[0] / ts for k, v in kt_mixed.items() if v[0]}
     mixed.solver.close()

@@ -90,8 +90,6 @@ enum {
 
 /* flags */
 #define GCR_F_RECORD_HISTORY 0x1u  /* keep ||r_nu||/||r_0|| per iteration in reports  */
-#define GCR_F_USE_GRAPH 0x2u       /* replay captured HIP graphs of one GCR cycle     */
-#define GCR_F_PERSISTENT 0x4u      /* one persistent kernel per solve (batch-wide)    */
 
 typedef struct {
   int32_t batch;          /* number of independent solves, 1..4096                    */
@@ -107,7 +105,7 @@ typedef struct {
   int32_t max_iters;      /* 1..100000                                                */
   double rtol;            /* exit when ||r||_2 <= rtol * ||r_0||_2; >= 0              */
   void* stream;           /* hipStream_t all work is ordered on; NULL = default        */
-  uint32_t flags;         /* GCR_F_*                                                  */
+  uint32_t flags;         /* GCR_F_* (other bits: GCR_EINVAL)                         */
 } gcr_params;
 
 typedef struct {
@@ -209,9 +207,8 @@ enum {
   GCR_K_ORTH = 5,       /* step-4 direction update with fused inner products         */
   GCR_K_CONTROL = 6,    /* per-member scalar updates                                 */
   GCR_K_COPY = 7,       /* gather/scatter of caller fields                           */
-  GCR_K_PERSISTENT = 8, /* whole-solve persistent kernel (GCR_F_PERSISTENT)          */
-  GCR_K_LEARNED = 9,    /* learned correction: features, five convolutions, update   */
-  GCR_K_COUNT = 10
+  GCR_K_LEARNED = 8,    /* learned correction: features, five convolutions, update   */
+  GCR_K_COUNT = 9
 };
 
 /* Enable (1) or disable (0) timing of every kernel the solver launches with

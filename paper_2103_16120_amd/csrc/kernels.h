@@ -11,8 +11,8 @@ namespace mpgcr {
 
 // kernel kinds for the optional per-kernel timing (values match the header)
 enum {
-  KT_ASSEMBLE = 0, KT_RESIDUAL, KT_SWEEP1, KT_SWEEP2, KT_APPLY_L, KT_ORTH, KT_CONTROL, KT_COPY, KT_PERSISTENT,
-  KT_LEARNED, KT_COUNT
+  KT_ASSEMBLE = 0, KT_RESIDUAL, KT_SWEEP1, KT_SWEEP2, KT_APPLY_L, KT_ORTH, KT_CONTROL, KT_COPY, KT_LEARNED,
+  KT_COUNT
 };
 
 // ---------------------------------------------------------------------------

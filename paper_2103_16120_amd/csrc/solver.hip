@@ -298,6 +298,7 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   if (P.min_iters < -1 || P.min_iters > P.max_iters) return fail(nullptr, GCR_EINVAL, "min_iters out of range");
   if (!(P.rtol >= 0.0) || !std::isfinite(P.rtol)) return fail(nullptr, GCR_EINVAL, "rtol must be finite and >= 0");
   if (P.polar_rows < -1) return fail(nullptr, GCR_EINVAL, "polar_rows must be >= -1");
+  if (P.flags & ~GCR_F_RECORD_HISTORY) return fail(nullptr, GCR_EINVAL, "unknown flags 0x%x", P.flags);
   for (int m = 0; m < P.batch; ++m) {
     const int nx = P.nx[m], ny = P.ny[m];
     if (!is_pow2(nx) || nx < 8 || nx > NXMAX)
@@ -928,7 +929,7 @@ extern "C" int gcr_kernel_time(gcr_solver* s, int32_t kind, int64_t* launches, d
 }
 
 extern "C" const char* gcr_kernel_name(int32_t kind) {
-  static const char* names[KT_COUNT] = {"assemble", "residual", "update_sweep1", "sweep2",     "apply_L",
-                                        "orth",     "control",  "copy",          "persistent", "learned"};
+  static const char* names[KT_COUNT] = {"assemble", "residual", "update_sweep1", "sweep2", "apply_L",
+                                        "orth",     "control",  "copy",          "learned"};
   return (kind >= 0 && kind < KT_COUNT) ? names[kind] : "unknown";
 }

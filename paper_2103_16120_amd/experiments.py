@@ -1,0 +1,170 @@
+"""Measurements of the batched and time-sequence workloads (one JSON line each).
+
+    python -m paper_2103_16120_amd.experiments batch      # 64 members of uneven grids
+    python -m paper_2103_16120_amd.experiments sequence   # 200 warm-started solves at 1024x512
+
+batch: 64 independent solves, grids drawn from {128x64, 256x128, 512x256},
+depth 4000-10000 m, dt in [300, 1200] s, solved in one batch in every
+precision form; a step is the batched assembly plus the solve.  Each form's
+error is its solution's relative L2 distance to the float64 solution (the
+float64 solution itself is checked against the CPU oracle by the GPU tests).
+
+sequence: depth of a zonal jet in gradient-wind balance plus advected
+degree-16 perturbations, dt = 100 s; step n solves L_n(x) = L_n(Phi*_{n+1})
+warm-started from the previous solution.  Plain float64, the mixed
+half-precision-preconditioner form, and the mixed form with the learned
+preconditioner; total wall time (assembly + solve) and the iteration
+histogram.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _lib():
+    sys.path.insert(0, os.path.dirname(HERE))
+    import torch
+    from paper_2103_16120_amd import lib
+    return torch, lib
+
+
+def batch(args):
+    torch, lib = _lib()
+    from workloads import batch_problems
+    probs = batch_problems(3, args.count)
+    sizes = [(p["nx"], p["ny"]) for p in probs]
+    depth = [torch.from_numpy(p["depth"]).cuda() for p in probs]
+    dts = [p["dt"] for p in probs]
+    f = lib.Solver(sizes, precision=lib.FP64)
+    f.set_operators(list(range(len(probs))), depth, dts)
+    rhs = [f.apply_operator(m, torch.from_numpy(p["x_true"]).cuda()) for m, p in enumerate(probs)]
+    f.close()
+    pts = sum(nx * ny for nx, ny in sizes)
+    out = {"workload": f"{len(probs)} members, grids {dict(collections.Counter(f'{a}x{b}' for a, b in sizes))}, "
+                       f"dt {min(dts):.0f}-{max(dts):.0f} s, rtol {args.rtol:g}",
+           "points": pts, "forms": {}}
+    ref = None
+    for name, prec in (("fp64", lib.FP64), ("mixed_half_pc", lib.MIXED_HALF_PC),
+                       ("mixed_fp64dot", lib.MIXED_FP64DOT), ("mixed", lib.MIXED)):
+        s = lib.Solver(sizes, precision=prec, rtol=args.rtol, max_iters=100)
+        xs = [torch.zeros_like(r) for r in rhs]
+
+        def step():
+            s.set_operators(list(range(len(probs))), depth, dts)
+            for x in xs:
+                x.zero_()
+            return s.solve(rhs, xs)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            reps = step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        sol = [x.cpu().numpy() for x in xs]
+        if ref is None:
+            ref = sol
+        err = [float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(sol, ref)]
+        its = [r.iterations for r in reps]
+        out["forms"][name] = {"solves_per_s": round(len(probs) / dt, 1), "ms_per_step": round(1e3 * dt, 3),
+                              "iters_mean": float(np.mean(its)), "iters_min": int(min(its)),
+                              "iters_max": int(max(its)), "statuses": sorted(set(r.status for r in reps)),
+                              "rel_res_true_max": float(max(r.rel_res_true for r in reps)),
+                              "rel_l2_vs_fp64_max": max(err)}
+        s.close()
+        print(f"# {name}: {json.dumps(out['forms'][name])}", flush=True)
+    print(json.dumps(out), flush=True)
+
+
+def sequence(args):
+    torch, lib = _lib()
+    from workloads import jet_sequence_depth
+    nx, ny, dt, n = args.nx, args.ny, args.dt, args.steps
+    t0 = time.perf_counter()
+    depth = [torch.from_numpy(jet_sequence_depth(nx, ny, k, dt)).cuda() for k in range(n + 1)]
+    f = lib.Solver([(nx, ny)], precision=lib.FP64)
+    rhs = []
+    for k in range(n):
+        f.set_operators([0], [depth[k]], [dt])
+        rhs.append(f.apply_operator(0, depth[k + 1]).clone())
+    torch.cuda.synchronize()
+    f.close()
+    print(f"# inputs ready in {time.perf_counter() - t0:.1f} s", flush=True)
+    out = {"workload": f"{n} consecutive {nx}x{ny} solves, dt {dt:g} s, warm start, rtol {args.rtol:g}",
+           "legs": {}}
+    legs = [("plain_fp64", lib.FP64, lib.PC_SEMI_IMPLICIT), ("plain_mixed_half_pc", lib.MIXED_HALF_PC,
+                                                              lib.PC_SEMI_IMPLICIT)]
+    params = None
+    if not args.no_learned:
+        from paper_2103_16120_amd.learned import load_weights, DEFAULT_WEIGHTS
+        params, _ = load_weights(DEFAULT_WEIGHTS)
+        legs.append(("learned_mixed_half_pc", lib.MIXED_HALF_PC, lib.PC_LEARNED))
+    sols = {}
+    for name, prec, pc in legs:
+        s = lib.Solver([(nx, ny)], precision=prec, precond=pc, rtol=args.rtol, max_iters=200)
+        if pc == lib.PC_LEARNED:
+            s.set_learned(params, 0.5)
+        x = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+        # one untimed solve warms the kernels up; the sequence then starts from zero
+        s.set_operators([0], [depth[0]], [dt])
+        s.solve([rhs[0]], [x])
+        x.zero_()
+        torch.cuda.synchronize()
+        its, stats, fb = [], [], 0
+        t0 = time.perf_counter()
+        for k in range(n):
+            s.set_operators([0], [depth[k]], [dt])
+            rep = s.solve([rhs[k]], [x])[0]
+            its.append(rep.iterations)
+            stats.append(rep.status)
+            fb += rep.fallback_used
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        sols[name] = x.cpu().numpy()
+        out["legs"][name] = {"wall_s": round(wall, 4), "ms_per_solve": round(1e3 * wall / n, 3),
+                             "iters_total": int(sum(its)),
+                             "iters_histogram": dict(sorted(collections.Counter(its).items())),
+                             "statuses": dict(collections.Counter(stats)), "fallbacks": fb}
+        s.close()
+        print(f"# {name}: {json.dumps(out['legs'][name])}", flush=True)
+    ref = sols["plain_fp64"]
+    for name, v in sols.items():
+        out["legs"][name]["final_rel_l2_vs_fp64"] = float(np.linalg.norm(v - ref) / np.linalg.norm(ref))
+    print(json.dumps(out), flush=True)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    b = sub.add_parser("batch")
+    b.add_argument("--count", type=int, default=64)
+    b.add_argument("--steps", type=int, default=5)
+    b.add_argument("--warmup", type=int, default=1)
+    b.add_argument("--rtol", type=float, default=1e-8)
+    q = sub.add_parser("sequence")
+    q.add_argument("--nx", type=int, default=1024)
+    q.add_argument("--ny", type=int, default=512)
+    q.add_argument("--dt", type=float, default=100.0)
+    q.add_argument("--steps", type=int, default=200)
+    q.add_argument("--rtol", type=float, default=1e-8)
+    q.add_argument("--no-learned", action="store_true")
+    args = ap.parse_args(argv)
+    if args.cmd == "batch":
+        batch(args)
+    else:
+        sequence(args)
+
+
+if __name__ == "__main__":
+    main()

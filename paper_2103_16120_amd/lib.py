@@ -20,7 +20,7 @@ OK, NOT_CONVERGED, STAGNATED, FALLBACK_USED = 0, 1, 2, 3
 EINVAL, ENOMEM, EHIP, ESTATE = -1, -2, -3, -4
 FP64, MIXED, MIXED_FP64DOT, MIXED_HALF_PC = 0, 1, 2, 3
 PC_NONE, PC_DIAG, PC_RICHARDSON, PC_SEMI_IMPLICIT, PC_LEARNED = 0, 1, 2, 3, 4
-F_RECORD_HISTORY, F_USE_GRAPH, F_PERSISTENT = 0x1, 0x2, 0x4
+F_RECORD_HISTORY = 0x1
 
 RADIUS = 6.371e6
 GRAVITY = 9.80616
@@ -84,9 +84,8 @@ _SIGNATURES = {
     "cnn_last_error": (C.c_char_p, [C.c_void_p]),
 }
 
-(K_ASSEMBLE, K_RESIDUAL, K_SWEEP1, K_SWEEP2, K_APPLY_L, K_ORTH, K_CONTROL, K_COPY, K_PERSISTENT,
- K_LEARNED) = range(10)
-K_COUNT = 10
+K_ASSEMBLE, K_RESIDUAL, K_SWEEP1, K_SWEEP2, K_APPLY_L, K_ORTH, K_CONTROL, K_COPY, K_LEARNED = range(9)
+K_COUNT = 9
 LEARNED_CHANNELS = 3
 
 
