@@ -40,6 +40,105 @@ struct CoefRow {
     ldr<M>(a[k] + start, l, L, v);
   }
   __device__ __forceinline__ T helm(int g) const { return c[g]; }
+  // the nine face-coefficient rows the stencil of row R needs
+  template <int M>
+  __device__ __forceinline__ void load9(const RowCtx& R, T (&axe)[M], T (&axy)[M], T (&bx)[M], T (&ayn)[M],
+                                        T (&ayxn)[M], T (&byn)[M], T (&ays)[M], T (&ayxs)[M], T (&bys)[M]) const {
+    const int l = R.lane, L = R.L;
+    row(C_AXX, R.rc, l, L, axe);
+    row(C_AXY, R.rc, l, L, axy);
+    row(C_BX, R.rc, l, L, bx);
+    row(C_AYY, R.rc, l, L, ayn);
+    row(C_AYX, R.rc, l, L, ayxn);
+    row(C_BY, R.rc, l, L, byn);
+    if (R.south) {
+      row(C_AYY, R.rc - R.nx, l, L, ays);
+      row(C_AYX, R.rc - R.nx, l, L, ayxs);
+      row(C_BY, R.rc - R.nx, l, L, bys);
+    } else {           // the south pole face carries no flux
+#pragma unroll
+      for (int k = 0; k < M; ++k) ays[k] = ayxs[k] = bys[k] = (T)0;
+    }
+  }
+};
+
+// Coefficients computed on the fly from the depth fields: Phi* and H* =
+// Phi* + H0 in the pooled row layout, and per global row the factors that
+// depend on latitude only (written by k_assemble; the expressions below are
+// the same as there).  East faces of row j use (FA_KE..FA_BPE), the north face
+// j+1/2 uses (FA_KN..FA_BPN), all zero for the last row (no flux through the
+// pole face).  Reading two fields instead of six coefficient arrays cuts the
+// operator's bytes per point.
+enum { FA_KE = 0, FA_FXX, FA_FXY, FA_GBX, FA_BLE, FA_BPE, FA_KN, FA_FYY, FA_FYX, FA_GBY, FA_BLN, FA_BPN, NFAC };
+
+template <typename T>
+struct FlyPools {
+  const T* phi;               // Phi*, pooled
+  const T* hs;                // H* = Phi* + H0, pooled
+  const T* fac;               // [rows][NFAC]
+  const T* c;                 // Helmholtz coefficient per global row
+};
+
+template <typename T>
+struct CoefFly {
+  FlyPools<T> P;
+  __device__ __forceinline__ T helm(int g) const { return P.c[g]; }
+  // the nine face-coefficient rows the stencil of row R needs
+  template <int M>
+  __device__ __forceinline__ void load9(const RowCtx& R, T (&axe)[M], T (&axy)[M], T (&bx)[M], T (&ayn)[M],
+                                        T (&ayxn)[M], T (&byn)[M], T (&ays)[M], T (&ayxs)[M], T (&bys)[M]) const {
+    const int l = R.lane, L = R.L;
+    T pc[M], ps[M], pn[M], hc[M], hsr[M], hn[M];
+    ldr<M>(P.phi + R.rc, l, L, pc);
+    ldr<M>(P.hs + R.rc, l, L, hc);
+    if (R.south) {
+      ldr<M>(P.phi + R.rc - R.nx, l, L, ps);
+      ldr<M>(P.hs + R.rc - R.nx, l, L, hsr);
+    } else {
+      across_pole(pc, ps, l, L);
+      across_pole(hc, hsr, l, L);
+    }
+    if (R.north) {
+      ldr<M>(P.phi + R.rc + R.nx, l, L, pn);
+      ldr<M>(P.hs + R.rc + R.nx, l, L, hn);
+    } else {
+      across_pole(pc, pn, l, L);
+      across_pole(hc, hn, l, L);
+    }
+    T pce[M], hce[M], hcw[M], hne[M], hnw[M], hse[M], hsw[M];
+    east_of(pc, pce, l, L);
+    east_of(hc, hce, l, L);
+    west_of(hc, hcw, l, L);
+    east_of(hn, hne, l, L);
+    west_of(hn, hnw, l, L);
+    east_of(hsr, hse, l, L);
+    west_of(hsr, hsw, l, L);
+    const T* f = P.fac + (long long)R.g * NFAC;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const T kap_e = f[FA_KE] * (pc[k] + pce[k]);
+      axe[k] = kap_e * f[FA_FXX];
+      axy[k] = kap_e * f[FA_FXY];
+      bx[k] = f[FA_GBX] * (f[FA_BLE] * (hce[k] - hc[k]) + f[FA_BPE] * ((hn[k] - hsr[k]) + (hne[k] - hse[k])));
+      const T kap_n = f[FA_KN] * (pc[k] + pn[k]);
+      ayn[k] = kap_n * f[FA_FYY];
+      ayxn[k] = kap_n * f[FA_FYX];
+      byn[k] = f[FA_GBY] * (f[FA_BLN] * ((hce[k] - hcw[k]) + (hne[k] - hnw[k])) + f[FA_BPN] * (hn[k] - hc[k]));
+    }
+    if (R.south) {   // the south face is the north face of row j-1
+      const T* fs = P.fac + (long long)(R.g - 1) * NFAC;
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const T kap = fs[FA_KN] * (ps[k] + pc[k]);
+        ays[k] = kap * fs[FA_FYY];
+        ayxs[k] = kap * fs[FA_FYX];
+        bys[k] = fs[FA_GBY] * (fs[FA_BLN] * ((hse[k] - hsw[k]) + (hce[k] - hcw[k])) + fs[FA_BPN] * (hc[k] - hsr[k]));
+      }
+    } else {         // the south pole face carries no flux
+#pragma unroll
+      for (int k = 0; k < M; ++k) ays[k] = ayxs[k] = bys[k] = (T)0;
+    }
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -87,6 +186,8 @@ struct Fields {
   const double* scale;        // per member: mixed-form operator scale dt/(2 a^2)
   CoefF64 c64;
   CoefMixed cmx;
+  FlyPools<double> fly64;     // on-the-fly coefficients (float64 operator)
+  FlyPools<float> fly32;      // on-the-fly coefficients, scaled (float32 operator)
   double* x;                  // solution, float64 pool
   const double* rhs;          // right-hand side, float64 pool
   double* r64;                // float64 residual (float64 form, restart scratch)
@@ -178,20 +279,7 @@ __device__ __forceinline__ void stencil_row(const RowCtx& R, const CV& cv, const
   if (R.south) X.row(R.rc - R.nx, l, L, xs, R.g - 1);
   if (R.north) X.row(R.rc + R.nx, l, L, xn, R.g + 1);
   T axe[M], axy[M], bx[M], ayn[M], ayxn[M], byn[M], ays[M], ayxs[M], bys[M];
-  cv.row(C_AXX, R.rc, l, L, axe);
-  cv.row(C_AXY, R.rc, l, L, axy);
-  cv.row(C_BX, R.rc, l, L, bx);
-  cv.row(C_AYY, R.rc, l, L, ayn);
-  cv.row(C_AYX, R.rc, l, L, ayxn);
-  cv.row(C_BY, R.rc, l, L, byn);
-  if (R.south) {
-    cv.row(C_AYY, R.rc - R.nx, l, L, ays);
-    cv.row(C_AYX, R.rc - R.nx, l, L, ayxs);
-    cv.row(C_BY, R.rc - R.nx, l, L, bys);
-  } else {           // the south pole face carries no flux
-#pragma unroll
-    for (int k = 0; k < M; ++k) ays[k] = ayxs[k] = bys[k] = (T)0;
-  }
+  cv.template load9<M>(R, axe, axy, bx, ayn, ayxn, byn, ays, ayxs, bys);
   if (!R.south) across_pole(xc, xs, l, L);
   if (!R.north) across_pole(xc, xn, l, L);
   // chunk-edge neighbours from the adjacent lanes
@@ -510,7 +598,7 @@ __device__ __forceinline__ void row_apply_L(const Fields& F, const RowCtx& R, co
   using V = typename P::V;
   using A = typename P::A;
   const int l = R.lane, L = R.L;
-  with_coef<P>(F, G, R.j, true, [&](const auto& cv) {
+  auto body = [&](const auto& cv) {
     const T helm = cv.helm(R.g);
     RowReader<T, V> X{(const V*)in};
     T y[M];
@@ -539,7 +627,12 @@ __device__ __forceinline__ void row_apply_L(const Fields& F, const RowCtx& R, co
       write_partial<A>(F, R, DOT_R_LP, R.act ? a0 : (A)0);
       write_partial<A>(F, R, DOT_LP_LP, R.act ? a1 : (A)0);
     }
-  });
+  };
+  // float64 and float32 operators: coefficients from the depth fields;
+  // float16 operator storage (the paper's mixed form): the stored arrays
+  if constexpr (!P::mixed) body(CoefFly<double>{F.fly64});
+  else if constexpr (P::op_f32) body(CoefFly<float>{F.fly32});
+  else with_coef<P>(F, G, R.j, true, body);
 }
 
 template <typename P, int M>
@@ -560,7 +653,7 @@ template <typename P, int M>
 __device__ __forceinline__ void row_residual(const Fields& F, const RowCtx& R, int write_krylov, int lp_slot) {
   using V = typename P::V;
   const int l = R.lane, L = R.L;
-  const CoefRow<double, double> cv{F.c64.a, F.c64.c};
+  const CoefFly<double> cv{F.fly64};
   const double helm = cv.helm(R.g);
   const double s = P::mixed ? F.scale[R.m] : 1.0;
   RowReader<double, double> X{F.x};
@@ -670,6 +763,12 @@ struct AssembleArgs {
   double* c64;                // per global row
   float* c32;
   double* scale;              // per member: mixed-form scale dt/(2 a^2)
+  double* phi64;              // Phi* and H* pools (float64, and float32 for the float32 operator)
+  double* hs64;
+  float* phi32;
+  float* hs32;
+  double* fac64;              // per global row: NFAC factors (float32: scaled by s)
+  float* fac32;
 };
 
 __device__ __forceinline__ double absorber_at(double lat, double amax) {
@@ -743,6 +842,9 @@ __global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
   const double gby = delta * P.g / (2.0 * D_n) / (2.0 * dphi);
   const double bl_n = -b_n / (4.0 * dlam), bp_n = gam_n * cs_n / dphi;
   const bool north = j < ny - 1;   // the pole face carries no flux
+  // float32 copies are read by the polar rows (and, as their south face, by
+  // the row just below the northern polar rows)
+  const bool polar = j < G.polar || j >= ny - G.polar - 1;
   const long long rowoff = G.off + (long long)j * nx;
   for (int slot = threadIdx.x; slot < nx; slot += ASM_WG) {
     const int i = (slot % Lr) * Mr + slot / Lr;   // natural column stored at this slot
@@ -780,9 +882,35 @@ __global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
 #pragma unroll
     for (int k = 0; k < NCOEF; ++k) {
       A.a64[k][o] = out[k];
-      A.a32[k][o] = (float)(s * out[k]);
+      if (polar) A.a32[k][o] = (float)(s * out[k]);
       A.a16[k][o16] = __float2half_rn((float)(s * out[k]));
     }
+    const double h1 = sh0[rs + c];
+    A.phi64[o] = d1;
+    A.hs64[o] = h1;
+    A.phi32[o] = (float)d1;
+    A.hs32[o] = (float)h1;
+  }
+  if (threadIdx.x < NFAC) {   // latitude factors of the on-the-fly coefficients
+    const double gb = P.b_terms ? 1.0 : 0.0, nf = north ? 1.0 : 0.0;
+    double v;
+    switch (threadIdx.x) {
+      case FA_KE: v = ke; break;
+      case FA_FXX: v = fxx; break;
+      case FA_FXY: v = fxy; break;
+      case FA_GBX: v = gb * gbx; break;
+      case FA_BLE: v = bl_e; break;
+      case FA_BPE: v = bp_e; break;
+      case FA_KN: v = nf * kn; break;
+      case FA_FYY: v = fyy; break;
+      case FA_FYX: v = fyx; break;
+      case FA_GBY: v = nf * gb * gby; break;
+      case FA_BLN: v = bl_n; break;
+      default: v = bp_n; break;
+    }
+    const bool scaled = threadIdx.x == FA_KE || threadIdx.x == FA_GBX || threadIdx.x == FA_KN || threadIdx.x == FA_GBY;
+    A.fac64[(long long)(G.row0 + j) * NFAC + threadIdx.x] = v;
+    A.fac32[(long long)(G.row0 + j) * NFAC + threadIdx.x] = (float)(scaled ? s * v : v);
   }
   if (threadIdx.x == 0) {
     if (j == 0) A.scale[P.member] = s;

@@ -75,6 +75,12 @@ struct gcr_solver {
   __half* a16[NCOEF] = {};
   double* c64 = nullptr;
   float* c32 = nullptr;
+  double* phi64 = nullptr;           // depth fields for the on-the-fly coefficients
+  double* hs64 = nullptr;
+  float* phi32 = nullptr;
+  float* hs32 = nullptr;
+  double* fac64 = nullptr;           // [rows][NFAC] latitude factors
+  float* fac32 = nullptr;
   double* x = nullptr;
   double* rhs = nullptr;
   double* r64 = nullptr;
@@ -215,6 +221,8 @@ static Fields make_fields(gcr_solver* s) {
   }
   F.c64.c = s->c64;
   F.cmx.c = s->c32;
+  F.fly64 = FlyPools<double>{s->phi64, s->hs64, s->fac64, s->c64};
+  F.fly32 = FlyPools<float>{s->phi32, s->hs32, s->fac32, s->c32};
   F.x = s->x;
   F.rhs = s->rhs;
   F.r64 = s->r64;
@@ -373,6 +381,12 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   }
   s->c64 = (double*)track(dalloc<double>(R, herr));
   s->c32 = (float*)track(dalloc<float>(R, herr));
+  s->phi64 = (double*)track(dalloc<double>(N, herr));
+  s->hs64 = (double*)track(dalloc<double>(N, herr));
+  s->phi32 = (float*)track(dalloc<float>(N, herr));
+  s->hs32 = (float*)track(dalloc<float>(N, herr));
+  s->fac64 = (double*)track(dalloc<double>((size_t)R * NFAC, herr));
+  s->fac32 = (float*)track(dalloc<float>((size_t)R * NFAC, herr));
   s->x = (double*)track(dalloc<double>(N, herr));
   s->rhs = (double*)track(dalloc<double>(N, herr));
   s->r64 = (double*)track(dalloc<double>(N, herr));
@@ -506,6 +520,12 @@ extern "C" int gcr_set_operators(gcr_solver* s, int32_t count, const int32_t* me
   A.c64 = s->c64;
   A.c32 = s->c32;
   A.scale = s->scale;
+  A.phi64 = s->phi64;
+  A.hs64 = s->hs64;
+  A.phi32 = s->phi32;
+  A.hs32 = s->hs32;
+  A.fac64 = s->fac64;
+  A.fac32 = s->fac32;
   bool any_oro = false;
   for (int t = 0; t < count; ++t) any_oro = any_oro || ops[t].orography;
   const size_t lds = (any_oro ? 6 : 3) * (size_t)asm_row_lds(s->nxmax) * sizeof(double);
