@@ -33,8 +33,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic HBM bytes per grid point and launch of each kernel kind in the
-# mixed form (float16 coefficients: 6 face arrays of 2 B; float32 Krylov
-# vectors: 4 B; float16 preconditioner intermediate: 2 B; float64 solution).
+# mixed form (float16 preconditioner coefficients: 6 face arrays of 2 B;
+# float32 Krylov vectors: 4 B; float16 preconditioner intermediate: 2 B).
 # The step-2 update kernel and the L/step-4 kernels depend on the window
 # position nu; the counts below are the averages over a GCR(3) cycle
 # (nu = 0, 1, 2).  Constant-size kernels are preferred for the roofline.
@@ -43,8 +43,9 @@ ALG_BYTES_MIXED = {
     "sweep2": 22.0,
 }
 ALG_BYTES_FP64 = {
-    # q_in (8) + r (8) + 6 coefficient arrays (48) -> e (8)
-    "sweep2": 72.0,
+    # q_in (8) + r (8) + Phi* and H* (16; the coefficients are formed from
+    # them on the fly) -> e (8)
+    "sweep2": 40.0,
 }
 HBM_PEAK_GBS = 8000.0
 # HBM traffic of the roofline kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE

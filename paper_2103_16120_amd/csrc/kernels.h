@@ -18,10 +18,6 @@ enum {
 // ---------------------------------------------------------------------------
 // precision-specific coefficient access (wave-uniform choice per row)
 // ---------------------------------------------------------------------------
-struct CoefF64 {
-  const double* a[NCOEF];
-  const double* c;            // Helmholtz coefficient per global row
-};
 
 // float16 storage in the interior, float32 in the polar rows, float32 maths.
 struct CoefMixed {
@@ -40,6 +36,18 @@ struct CoefRow {
     ldr<M>(a[k] + start, l, L, v);
   }
   __device__ __forceinline__ T helm(int g) const { return c[g]; }
+  // A^xx east faces and A^yy north / south faces of row R (row solves)
+  template <int M>
+  __device__ __forceinline__ void faces(const RowCtx& R, T (&axe)[M], T (&ayn)[M], T (&ays)[M]) const {
+    const int l = R.lane, L = R.L;
+    row(C_AXX, R.rc, l, L, axe);
+    row(C_AYY, R.rc, l, L, ayn);
+    if (R.south) row(C_AYY, R.rc - R.nx, l, L, ays);
+    else {
+#pragma unroll
+      for (int k = 0; k < M; ++k) ays[k] = (T)0;
+    }
+  }
   // the nine face-coefficient rows the stencil of row R needs
   template <int M>
   __device__ __forceinline__ void load9(const RowCtx& R, T (&axe)[M], T (&axy)[M], T (&bx)[M], T (&ayn)[M],
@@ -83,6 +91,32 @@ template <typename T>
 struct CoefFly {
   FlyPools<T> P;
   __device__ __forceinline__ T helm(int g) const { return P.c[g]; }
+  // A^xx east faces and A^yy north / south faces of row R (row solves)
+  template <int M>
+  __device__ __forceinline__ void faces(const RowCtx& R, T (&axe)[M], T (&ayn)[M], T (&ays)[M]) const {
+    const int l = R.lane, L = R.L;
+    T pc[M], pce[M], pn[M];
+    ldr<M>(P.phi + R.rc, l, L, pc);
+    if (R.north) ldr<M>(P.phi + R.rc + R.nx, l, L, pn);
+    else across_pole(pc, pn, l, L);
+    east_of(pc, pce, l, L);
+    const T* f = P.fac + (long long)R.g * NFAC;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      axe[k] = (f[FA_KE] * (pc[k] + pce[k])) * f[FA_FXX];
+      ayn[k] = (f[FA_KN] * (pc[k] + pn[k])) * f[FA_FYY];
+    }
+    if (R.south) {
+      T ps[M];
+      ldr<M>(P.phi + R.rc - R.nx, l, L, ps);
+      const T* fs = P.fac + (long long)(R.g - 1) * NFAC;
+#pragma unroll
+      for (int k = 0; k < M; ++k) ays[k] = (fs[FA_KN] * (ps[k] + pc[k])) * fs[FA_FYY];
+    } else {
+#pragma unroll
+      for (int k = 0; k < M; ++k) ays[k] = (T)0;
+    }
+  }
   // the nine face-coefficient rows the stencil of row R needs
   template <int M>
   __device__ __forceinline__ void load9(const RowCtx& R, T (&axe)[M], T (&axy)[M], T (&bx)[M], T (&ayn)[M],
@@ -184,7 +218,6 @@ struct Fields {
   MemberState* state;
   double* part;               // [rows][NDOT] per-row partial inner products
   const double* scale;        // per member: mixed-form operator scale dt/(2 a^2)
-  CoefF64 c64;
   CoefMixed cmx;
   FlyPools<double> fly64;     // on-the-fly coefficients (float64 operator)
   FlyPools<float> fly32;      // on-the-fly coefficients, scaled (float32 operator)
@@ -215,7 +248,7 @@ struct Fields {
 template <typename P, typename Fn>
 __device__ __forceinline__ void with_coef(const Fields& F, const MemberGeom& G, int j, bool op, Fn&& fn) {
   if constexpr (!P::mixed) {
-    fn(CoefRow<double, double>{F.c64.a, F.c64.c});
+    fn(CoefFly<double>{F.fly64});
   } else {
     const bool f32 = (op && P::op_f32) || (j < G.polar) || (j >= G.ny - G.polar);
     if (f32) fn(CoefRow<float, float>{F.cmx.f, F.cmx.c});
@@ -309,33 +342,16 @@ __device__ __forceinline__ void stencil_row(const RowCtx& R, const CV& cv, const
 template <typename T, int M, typename CV>
 __device__ __forceinline__ void row_faces(const RowCtx& R, const CV& cv, T (&axe)[M], T (&axw)[M], T (&ayn)[M],
                                           T (&ays)[M]) {
-  const int l = R.lane, L = R.L;
-  cv.row(C_AXX, R.rc, l, L, axe);
-  west_of(axe, axw, l, L);
-  cv.row(C_AYY, R.rc, l, L, ayn);
-  if (R.south) cv.row(C_AYY, R.rc - R.nx, l, L, ays);
-  else {
-#pragma unroll
-    for (int k = 0; k < M; ++k) ays[k] = (T)0;
-  }
+  cv.template faces<M>(R, axe, ayn, ays);
+  west_of(axe, axw, R.lane, R.L);
 }
 
 // diagonal of L on a row
 template <typename T, int M, typename CV>
 __device__ __forceinline__ void diag_row(const RowCtx& R, const CV& cv, T (&d)[M]) {
   const int l = R.lane, L = R.L;
-  T axe[M], axw[M], bx[M], bxw[M], ayn[M], byn[M], ays[M], bys[M];
-  cv.row(C_AXX, R.rc, l, L, axe);
-  cv.row(C_BX, R.rc, l, L, bx);
-  cv.row(C_AYY, R.rc, l, L, ayn);
-  cv.row(C_BY, R.rc, l, L, byn);
-  if (R.south) {
-    cv.row(C_AYY, R.rc - R.nx, l, L, ays);
-    cv.row(C_BY, R.rc - R.nx, l, L, bys);
-  } else {
-#pragma unroll
-    for (int k = 0; k < M; ++k) ays[k] = bys[k] = (T)0;
-  }
+  T axe[M], axw[M], axy[M], bx[M], bxw[M], ayn[M], ayxn[M], byn[M], ays[M], ayxs[M], bys[M];
+  cv.template load9<M>(R, axe, axy, bx, ayn, ayxn, byn, ays, ayxs, bys);
   west_of(axe, axw, l, L);
   west_of(bx, bxw, l, L);
   const T helm = cv.helm(R.g);
@@ -757,7 +773,6 @@ struct AsmMember {             // one member of a batched assembly
 struct AssembleArgs {
   const AsmMember* tab;       // [count]
   const MemberGeom* geom;
-  double* a64[NCOEF];
   __half* a16[NCOEF];
   float* a32[NCOEF];
   double* c64;                // per global row
@@ -881,7 +896,6 @@ __global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
     const long long o16 = rowoff + half_slot(slot % Lr, slot / Lr, Lr);   // float16 rows pair elements
 #pragma unroll
     for (int k = 0; k < NCOEF; ++k) {
-      A.a64[k][o] = out[k];
       if (polar) A.a32[k][o] = (float)(s * out[k]);
       A.a16[k][o16] = __float2half_rn((float)(s * out[k]));
     }

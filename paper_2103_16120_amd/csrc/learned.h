@@ -164,7 +164,7 @@ __global__ __launch_bounds__(WG) void k_learn_features(Fields F, const double* r
   const long long np = (long long)G.nx * G.ny;
   const float cz = (float)learn_cos(R.j, G.ny);
   double lo[M], di[M], up[M];
-  learn_row_system<double, M>(R, CoefRow<double, double>{F.c64.a, F.c64.c}, lo, di, up);
+  learn_row_system<double, M>(R, CoefFly<double>{F.fly64}, lo, di, up);
   if (!R.act) return;
   // stored position of natural point i of the row: (i mod M) * L + i / M
   auto at = [&](const double* v, int i) {

@@ -70,7 +70,6 @@ struct gcr_solver {
   MemberState* state = nullptr;
   double* part = nullptr;
   double* scale = nullptr;
-  double* a64[NCOEF] = {};
   float* a32[NCOEF] = {};
   __half* a16[NCOEF] = {};
   double* c64 = nullptr;
@@ -215,11 +214,9 @@ static Fields make_fields(gcr_solver* s) {
   F.part = s->part;
   F.scale = s->scale;
   for (int k = 0; k < NCOEF; ++k) {
-    F.c64.a[k] = s->a64[k];
     F.cmx.h[k] = s->a16[k];
     F.cmx.f[k] = s->a32[k];
   }
-  F.c64.c = s->c64;
   F.cmx.c = s->c32;
   F.fly64 = FlyPools<double>{s->phi64, s->hs64, s->fac64, s->c64};
   F.fly32 = FlyPools<float>{s->phi32, s->hs32, s->fac32, s->c32};
@@ -375,7 +372,6 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   s->part = (double*)track(dalloc<double>((size_t)R * NDOT, herr));
   s->scale = (double*)track(dalloc<double>(P.batch, herr));
   for (int k = 0; k < NCOEF; ++k) {
-    s->a64[k] = (double*)track(dalloc<double>(N, herr));
     s->a32[k] = (float*)track(dalloc<float>(N, herr));
     s->a16[k] = (__half*)track(dalloc<__half>(N, herr));
   }
@@ -513,7 +509,6 @@ extern "C" int gcr_set_operators(gcr_solver* s, int32_t count, const int32_t* me
   A.tab = s->asm_tab;
   A.geom = s->geom;
   for (int k = 0; k < NCOEF; ++k) {
-    A.a64[k] = s->a64[k];
     A.a32[k] = s->a32[k];
     A.a16[k] = s->a16[k];
   }
