@@ -70,17 +70,24 @@ __device__ __forceinline__ bf16x8 ld8(const __bf16* p) {
 // 3x3 convolution, 32 input channels, NT*16 output channels.
 // OUT: 0 = bf16 NHWC (32 channels written, the upper 16 zero when NT == 1),
 //      1 = float32 channel 0 only.
-// One wave computes 64 consecutive pixels of one row; the workgroup's four
-// waves share the weight fragments staged in LDS.
+// One wave computes 64 consecutive pixels of one row, two 16-pixel tiles at
+// a time (the 18 input fragments of a tile pair are loaded before the MFMAs
+// that use them, which keeps loads in flight while the matrix cores work).
+// The workgroup's four waves share the weight fragments staged in LDS; each
+// [tap][out channel] row of 32 input channels is padded to 40 elements so
+// that the 16 lanes reading one 16-byte column hit distinct banks.
 // ---------------------------------------------------------------------------
+constexpr int WROW = CH + 8;
+
 template <int NT, int OUT>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs A) {
-  __shared__ __attribute__((aligned(16))) __bf16 sw[2][TAPS * CH * CH];
+  __shared__ __attribute__((aligned(16))) __bf16 sw[2][TAPS * CH * WROW];
   const int tid = threadIdx.x;
-  // stage both weight sets (regular and across-pole taps)
-  for (int k = tid * 8; k < TAPS * CH * CH; k += 256 * 8) {
-    *(bf16x8*)&sw[0][k] = ld8(A.w + k);
-    *(bf16x8*)&sw[1][k] = ld8(A.wpole + k);
+  // stage both weight sets (regular and across-pole taps), 16 bytes a thread
+  for (int k = tid; k < TAPS * CH * 4; k += 256) {
+    const int row = k >> 2, q = 8 * (k & 3);
+    *(bf16x8*)&sw[0][row * WROW + q] = ld8(A.w + row * CH + q);
+    *(bf16x8*)&sw[1][row * WROW + q] = ld8(A.wpole + row * CH + q);
   }
   __syncthreads();
   const int lane = tid & 63;
@@ -95,41 +102,56 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs A) {
   const int kq = 8 * (lane >> 4);          // channel block of this lane (A and B operands)
   const int ml = lane & 15;
 #pragma unroll 1
-  for (int mt = 0; mt < CONV_MT; ++mt) {
-    f32x4 acc[NT];
-#pragma unroll
-    for (int n = 0; n < NT; ++n) acc[n] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int i = i0 + 16 * mt + ml;
+  for (int mt = 0; mt < CONV_MT; mt += 2) {
+    bf16x8 a[2][TAPS];
 #pragma unroll
     for (int t = 0; t < TAPS; ++t) {
       const int dy = t / 3 - 1, dx = t % 3 - 1;
-      int jj, ii;
-      bool ghost;
-      sphere_src(j, i, dy, dx, A.nx, A.ny, jj, ii, ghost);   // ghost is uniform over the wave
-      const bf16x8 a = ld8(img + ((long long)jj * A.nx + ii) * CH + kq);
-      const __bf16* wt = &sw[ghost ? 1 : 0][t * CH * CH];
 #pragma unroll
-      for (int n = 0; n < NT; ++n) {
-        const bf16x8 bw = *(const bf16x8*)&wt[(16 * n + ml) * CH + kq];
-        acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[n], 0, 0, 0);
+      for (int h = 0; h < 2; ++h) {
+        int jj, ii;
+        bool ghost;
+        sphere_src(j, i0 + 16 * (mt + h) + ml, dy, dx, A.nx, A.ny, jj, ii, ghost);
+        a[h][t] = ld8(img + ((long long)jj * A.nx + ii) * CH + kq);
       }
     }
-    // epilogue: lane holds output channel co = 16n + ml for 4 pixels
+    f32x4 acc[2][NT];
 #pragma unroll
-    for (int n = 0; n < NT; ++n) {
-      const int co = 16 * n + ml;
-      const float bias = A.bias ? A.bias[co] : 0.f;
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const long long pix = (long long)b * npix + p0 + 16 * mt + 4 * (lane >> 4) + r;
-        float v = acc[n][r] + bias;
-        if (A.relu) v = fmaxf(v, 0.f);
-        if (A.mask && !((float)A.mask[pix * CH + co] > 0.f)) v = 0.f;
-        if (OUT == 1) {
-          if (co == 0) A.out32[pix] = v;
-        } else {
-          A.out[pix * CH + co] = (__bf16)v;
-          if (NT == 1) A.out[pix * CH + co + 16] = (__bf16)0.f;
+      for (int n = 0; n < NT; ++n) acc[h][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < TAPS; ++t) {
+      const int dy = t / 3 - 1;
+      // taps reading across a pole use the pole weight set (wave-uniform)
+      const bool ghost = (dy < 0 && j == 0) || (dy > 0 && j == A.ny - 1);
+      const __bf16* wt = &sw[ghost ? 1 : 0][t * CH * WROW];
+#pragma unroll
+      for (int n = 0; n < NT; ++n) {
+        const bf16x8 bw = *(const bf16x8*)&wt[(16 * n + ml) * WROW + kq];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) acc[h][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[h][t], bw, acc[h][n], 0, 0, 0);
+      }
+    }
+    // epilogue: lane holds output channel co = 16n + ml for 4 pixels of each tile
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int n = 0; n < NT; ++n) {
+        const int co = 16 * n + ml;
+        const float bias = A.bias ? A.bias[co] : 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const long long pix = (long long)b * npix + p0 + 16 * (mt + h) + 4 * (lane >> 4) + r;
+          float v = acc[h][n][r] + bias;
+          if (A.relu) v = fmaxf(v, 0.f);
+          if (A.mask && !((float)A.mask[pix * CH + co] > 0.f)) v = 0.f;
+          if (OUT == 1) {
+            if (co == 0) A.out32[pix] = v;
+          } else {
+            A.out[pix * CH + co] = (__bf16)v;
+            if (NT == 1) A.out[pix * CH + co + 16] = (__bf16)0.f;
+          }
         }
       }
     }
@@ -244,12 +266,23 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs A) {
   if (lane < CH) part[TAPS * CH * CH + lane] = dbias;
 }
 
-// grad[k] = sum over waves of part[w][k], fixed order
-__global__ void k_wgrad_reduce(const float* part, int nwaves, float* grad) {
+// grad[k] = sum over waves of part[w][k] in a fixed order, in two levels:
+// segment sums (blockIdx.y = segment of the wave range), then their sum
+constexpr int WG_SEG = 64;
+__global__ void k_wgrad_reduce(const float* part, int nwaves, float* seg) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= WG_PART) return;
+  const int per = (nwaves + WG_SEG - 1) / WG_SEG;
+  const int w0 = blockIdx.y * per, w1 = min(nwaves, w0 + per);
+  float s = 0.f;
+  for (int w = w0; w < w1; ++w) s += part[(long long)w * WG_PART + k];
+  seg[(long long)blockIdx.y * WG_PART + k] = s;
+}
+__global__ void k_wgrad_reduce2(const float* seg, float* grad) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= WG_PART) return;
   float s = 0.f;
-  for (int w = 0; w < nwaves; ++w) s += part[(long long)w * WG_PART + k];
+  for (int g = 0; g < WG_SEG; ++g) s += seg[(long long)g * WG_PART + k];
   grad[k] = s;
 }
 

@@ -91,21 +91,38 @@ __global__ void k_pack_weights(PackW P) {
   if (t == 0 && c == 0) P.bias[l * CH + a] = a < co_n ? w[(long long)co_n * ci_n * 9 + a] : 0.f;
 }
 
-// NCHW float32 [B][c_in][ny][nx] -> NHWC bf16 [B][ny][nx][CH]
+// NCHW float32 [B][c_in][ny][nx] -> NHWC bf16 [B][ny][nx][CH], one pixel
+// (four 16-byte stores) per thread
 __global__ void k_pack_input(const float* in, __bf16* out, int c_in, long long npix, int batch) {
   const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (k >= npix * batch) return;
   const long long b = k / npix, p = k % npix;
-  for (int c = 0; c < CH; ++c)
-    out[k * CH + c] = (__bf16)(c < c_in ? in[(b * c_in + c) * npix + p] : 0.f);
+  bf16x8* dst = (bf16x8*)(out + k * CH);
+#pragma unroll
+  for (int q = 0; q < CH / 8; ++q) {
+    bf16x8 v;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int ch = 8 * q + c;
+      v[c] = (__bf16)(ch < c_in ? in[(b * c_in + ch) * npix + p] : 0.f);
+    }
+    dst[q] = v;
+  }
 }
 
 // float32 [B][npix] -> NHWC bf16 channel 0 (others zero)
 __global__ void k_pack_grad(const float* g, __bf16* out, long long n) {
   const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (k >= n) return;
-  out[k * CH] = (__bf16)g[k];
-  for (int c = 1; c < CH; ++c) out[k * CH + c] = (__bf16)0.f;
+  bf16x8 v;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) v[c] = (__bf16)0.f;
+  bf16x8* dst = (bf16x8*)(out + k * CH);
+  dst[1] = v;
+  dst[2] = v;
+  dst[3] = v;
+  v[0] = (__bf16)g[k];
+  dst[0] = v;
 }
 
 // mean squared error: per-block partial sums of (y-t)^2 (fixed order) and
@@ -184,6 +201,7 @@ static int alloc_all(cnn_net* n) {
   n->wg_waves_max = (n->wg_waves_max + WG_WAVES - 1) / WG_WAVES * WG_WAVES;
   A((void**)&n->wg_part, (size_t)n->wg_waves_max * WG_PART * sizeof(float));
   A((void**)&n->wg_sum, (size_t)WG_PART * sizeof(float));
+  A((void**)&n->wg_seg, (size_t)WG_SEG * WG_PART * sizeof(float));
   A((void**)&n->loss_part, 1024 * sizeof(double));
   if (e != hipSuccess) return cfail(n, e == hipErrorOutOfMemory ? GCR_ENOMEM : GCR_EHIP, "allocation: %s",
                                     hipGetErrorString(e));
@@ -366,8 +384,10 @@ static int backward(cnn_net* n, int batch, const float* dyv) {
     const int waves = (int)((W.total_chunks + W.chunks - 1) / W.chunks);
     const int blocks = (waves + WG_WAVES - 1) / WG_WAVES;
     hipLaunchKernelGGL(k_wgrad, dim3(blocks), dim3(256), 0, n->stream, W);
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((WG_PART + 255) / 256), dim3(256), 0, n->stream, (const float*)n->wg_part,
-                       waves, n->wg_sum);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((WG_PART + 255) / 256, WG_SEG), dim3(256), 0, n->stream,
+                       (const float*)n->wg_part, waves, n->wg_seg);
+    hipLaunchKernelGGL(k_wgrad_reduce2, dim3((WG_PART + 255) / 256), dim3(256), 0, n->stream, (const float*)n->wg_seg,
+                       n->wg_sum);
     UnpackG U{};
     U.g = n->wg_sum;
     U.flat = n->grads + off[l];

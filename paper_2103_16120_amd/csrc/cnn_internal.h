@@ -36,6 +36,7 @@ struct cnn_net {
   float* dy = nullptr;       // loss gradient [B][ny][nx]
   float* wg_part = nullptr;  // per-wave weight-gradient partials
   float* wg_sum = nullptr;
+  float* wg_seg = nullptr;   // segment sums of the weight-gradient partials
   int wg_chunks = 0, wg_waves_max = 0;
   double* loss_part = nullptr;
   double* loss_host = nullptr;
