@@ -660,10 +660,12 @@ __global__ __launch_bounds__(WG) void k_apply_L(Fields F, const void* in, void* 
 }
 
 // ---------------------------------------------------------------------------
-// residual r = L(x) - R in float64 (eq. Residual).  Writes r64 and, if asked,
-// the Krylov copy r = s*r64 (s = 1 in the float64 form).  Partials: <r,r>
-// (slot DOT_RR, in the Krylov scaling); with `lp_slot` >= 0 also <r, L p_slot>.
-// `respect_done`: skip finished members (restart) or not (final check).
+// residual r = L(x) - R in float64 (eq. Residual).  `write_krylov`: 0 writes
+// nothing but the partials (final true residual), 1 the Krylov copy
+// r = s*r (s = 1 in the float64 form; solve start and restarts), 2 the float64
+// r64 (stand-alone use).  Partials: <r,r> (slot DOT_RR, in the Krylov
+// scaling); with `lp_slot` >= 0 also <r, L p_slot>.  `respect_done`: skip
+// finished members (restart) or not (final check).
 // ---------------------------------------------------------------------------
 template <typename P, int M>
 __device__ __forceinline__ void row_residual(const Fields& F, const RowCtx& R, int write_krylov, int lp_slot) {
@@ -680,8 +682,8 @@ __device__ __forceinline__ void row_residual(const Fields& F, const RowCtx& R, i
     rr[k] = zon + rest - helm * xc - b[k];
     acc0 += rr[k] * rr[k];
   });
-  if (R.act) str<M>(F.r64 + R.rc, l, L, rr);
-  if (write_krylov) {
+  if (write_krylov == 2 && R.act) str<M>(F.r64 + R.rc, l, L, rr);
+  if (write_krylov == 1) {
     double rk[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) rk[k] = (double)(V)(s * rr[k]);

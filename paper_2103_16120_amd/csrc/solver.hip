@@ -864,7 +864,7 @@ extern "C" int gcr_learned_features(gcr_solver* s, int32_t member, const double*
   // r = L(x) - rhs and its <r,r> partials
   KLAUNCH(s, KT_COPY, k_to_pool, cg, dim3(256), 0, s->stream, x, s->x, G);
   KLAUNCH(s, KT_COPY, k_to_pool, cg, dim3(256), 0, s->stream, rhs, s->rhs, G);
-  ROWS_LAUNCH(s, cls, F, KT_RESIDUAL, k_residual, PrecF64, 0, -1, 0);
+  ROWS_LAUNCH(s, cls, F, KT_RESIDUAL, k_residual, PrecF64, 2, -1, 0);
   F.r = s->r64;
   LearnArgs A{};
   A.r = s->r64;
