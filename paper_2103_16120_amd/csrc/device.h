@@ -67,6 +67,16 @@ struct MemberState {
 __device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
 __device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b mod 8), and each XCD has its own L2.  Row kernels read the rows above and
+// below their own, so the logical block order is remapped to give every XCD
+// one contiguous range of blocks: neighbouring rows then meet in the same L2.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_block(int b, int n) {
+  const int q = n / NXCD, r = n % NXCD, x = b % NXCD;
+  return x * q + (x < r ? x : r) + b / NXCD;
+}
+
 // ---------------------------------------------------------------------------
 // cross-lane helpers (wave64)
 // ---------------------------------------------------------------------------

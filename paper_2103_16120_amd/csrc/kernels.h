@@ -261,7 +261,7 @@ __device__ __forceinline__ void with_coef(const Fields& F, const MemberGeom& G, 
 __device__ __forceinline__ bool wave_row(const Fields& F, int& g, int& m, MemberGeom& G, int& lane, int& w) {
   lane = threadIdx.x & 63;
   w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  g = F.row_base + blockIdx.x * WPB + w;
+  g = F.row_base + xcd_block(blockIdx.x, gridDim.x) * WPB + w;
   if (g >= F.row_end) return false;
   m = F.rowmap[g];
   G = F.geom[m];
@@ -812,7 +812,7 @@ __global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
   extern __shared__ double asm_lds[];
   const AsmMember P = A.tab[blockIdx.y];
   const MemberGeom G = A.geom[P.member];
-  const int nx = G.nx, ny = G.ny, j = blockIdx.x;
+  const int nx = G.nx, ny = G.ny, j = xcd_block(blockIdx.x, gridDim.x);
   if (j >= ny) return;
   const int half = nx >> 1;
   const int lm = G.log2m, Mr = 1 << lm, Lr = nx >> lm;
