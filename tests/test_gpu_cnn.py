@@ -363,3 +363,38 @@ def test_learned_errors(gpu_lib):
         gpu_lib.Solver([(64, 16), (128, 16)], precond=gpu_lib.PC_LEARNED)
     with pytest.raises(gpu_lib.GcrError):
         gpu_lib.Network(48, 16, 1)
+
+
+def test_trained_network_gain(gpu_lib, capsys):
+    """What the shipped, trained network gains over the plain preconditioner
+    on held-out problems of the benchmark family (parity unpinned: the gain is
+    measured and reported, not pinned).  Both must reach the tolerance by their
+    float64 true residual and agree on the solution."""
+    from paper_2103_16120_amd.learned import load_weights, DEFAULT_WEIGHTS
+    params, head = load_weights(DEFAULT_WEIGHTS)
+    nx, ny, B = 512, 256, 8
+    prs = [problem(2, nx, ny, instance=m, dt=600.0) for m in range(B)]
+    f = gpu_lib.Solver([(nx, ny)] * B, precision=gpu_lib.FP64)
+    depth = [dev(p["depth"]) for p in prs]
+    for m, p in enumerate(prs):
+        f.set_operator(m, depth[m], p["dt"])
+    rhs = [f.apply_operator(m, dev(p["x_true"])) for m, p in enumerate(prs)]
+    out = {}
+    for name, pc in (("plain", gpu_lib.PC_SEMI_IMPLICIT), ("learned", gpu_lib.PC_LEARNED)):
+        s = gpu_lib.Solver([(nx, ny)] * B, precision=gpu_lib.MIXED_HALF_PC, precond=pc)
+        if pc == gpu_lib.PC_LEARNED:
+            s.set_learned(params)
+        for m, p in enumerate(prs):
+            s.set_operator(m, depth[m], p["dt"])
+        x = [torch.zeros_like(r) for r in rhs]
+        reps = s.solve(rhs, x)
+        for rp in reps:
+            assert rp.status in (gpu_lib.OK, gpu_lib.FALLBACK_USED) and rp.rel_res_true <= 1.05e-8, rp
+        out[name] = (np.mean([r.iterations for r in reps]), [host(v) for v in x])
+        s.close()
+    for a, b in zip(out["plain"][1], out["learned"][1]):
+        assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(a)
+    with capsys.disabled():
+        print(f"\n[trained network] mean GCR iterations: plain {out['plain'][0]:.2f}, "
+              f"learned {out['learned'][0]:.2f} (training loss {head.get('loss_last'):.3g} "
+              f"of target mean square {head.get('target_mean_square'):.3g})")
