@@ -786,6 +786,7 @@ struct AssembleArgs {
   float* hs32;
   double* fac64;              // per global row: NFAC factors (float32: scaled by s)
   float* fac32;
+  int rows;                   // rows per workgroup (1..ASM_ROWS; the staged rows must fit the LDS)
 };
 
 __device__ __forceinline__ double absorber_at(double lat, double amax) {
@@ -804,24 +805,26 @@ __device__ __forceinline__ double absorber_at(double lat, double amax) {
 // Everything that depends on the latitude only is folded into per-row
 // factors, leaving no division in the per-point work.
 constexpr int ASM_WG = 256;
+constexpr int ASM_ROWS = ASM_WG / 64;   // rows per workgroup, one wave each
 
 __host__ __device__ constexpr int asm_row_lds(int nx) { return nx + 16; }   // doubles per staged row (M <= 16)
 
 __global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
-  // dynamic LDS: Phi* rows j-1, j, j+1, then (with orography) H* rows
+  // dynamic LDS: Phi* rows j0-1 .. j0+ASM_ROWS, then (with orography) H* rows
   extern __shared__ double asm_lds[];
   const AsmMember P = A.tab[blockIdx.y];
   const MemberGeom G = A.geom[P.member];
-  const int nx = G.nx, ny = G.ny, j = xcd_block(blockIdx.x, gridDim.x);
-  if (j >= ny) return;
+  const int nx = G.nx, ny = G.ny, j0 = xcd_block(blockIdx.x, gridDim.x) * A.rows;
+  if (j0 >= ny) return;
   const int half = nx >> 1;
   const int lm = G.log2m, Mr = 1 << lm, Lr = nx >> lm;
   const int rs = asm_row_lds(nx);
   auto lidx = [&](int i) { return (i & (Mr - 1)) * (Lr + 1) + (i >> lm); };
-  double* sd0 = asm_lds;
-  double* sh0 = P.oro ? asm_lds + 3 * rs : asm_lds;
-  for (int r = 0; r < 3; ++r) {
-    int jj = j - 1 + r, sh_ = 0;
+  double* sd_all = asm_lds;
+  double* sh_all = P.oro ? asm_lds + (A.rows + 2) * rs : asm_lds;
+  for (int r = 0; r < A.rows + 2; ++r) {
+    int jj = j0 - 1 + r, sh_ = 0;
+    if (jj > ny) break;                 // beyond the ghost row of the north pole
     if (jj < 0) { jj = 0; sh_ = half; }
     if (jj >= ny) { jj = ny - 1; sh_ = half; }
     const double* drow = P.depth + (long long)jj * nx;
@@ -829,11 +832,17 @@ __global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
     for (int i = threadIdx.x; i < nx; i += ASM_WG) {
       const int src = (i + sh_) & (nx - 1);
       const double d = drow[src];
-      sd0[r * rs + lidx(i)] = d;
-      if (orow) sh0[r * rs + lidx(i)] = d + orow[src];
+      sd_all[r * rs + lidx(i)] = d;
+      if (orow) sh_all[r * rs + lidx(i)] = d + orow[src];
     }
   }
   __syncthreads();
+  // wave w assembles row j = j0 + w from staged rows w, w+1, w+2
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = j0 + w;
+  if (w >= A.rows || j >= ny) return;
+  const double* sd0 = sd_all + w * rs;
+  const double* sh0 = sh_all + w * rs;
   const double kPi = 3.14159265358979323846;
   const double dlam = 2.0 * kPi / nx, dphi = kPi / ny;
   const double delta = 0.5 * P.dt;
@@ -863,7 +872,7 @@ __global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
   // the row just below the northern polar rows)
   const bool polar = j < G.polar || j >= ny - G.polar - 1;
   const long long rowoff = G.off + (long long)j * nx;
-  for (int slot = threadIdx.x; slot < nx; slot += ASM_WG) {
+  for (int slot = lane; slot < nx; slot += 64) {
     const int i = (slot % Lr) * Mr + slot / Lr;   // natural column stored at this slot
     const int c = lidx(i), ce = lidx((i + 1) & (nx - 1)), cw = lidx((i - 1) & (nx - 1));
     const double d1 = sd0[rs + c];
@@ -907,10 +916,10 @@ __global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
     A.phi32[o] = (float)d1;
     A.hs32[o] = (float)h1;
   }
-  if (threadIdx.x < NFAC) {   // latitude factors of the on-the-fly coefficients
+  if (lane < NFAC) {   // latitude factors of the on-the-fly coefficients
     const double gb = P.b_terms ? 1.0 : 0.0, nf = north ? 1.0 : 0.0;
     double v;
-    switch (threadIdx.x) {
+    switch (lane) {
       case FA_KE: v = ke; break;
       case FA_FXX: v = fxx; break;
       case FA_FXY: v = fxy; break;
@@ -924,11 +933,11 @@ __global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
       case FA_BLN: v = bl_n; break;
       default: v = bp_n; break;
     }
-    const bool scaled = threadIdx.x == FA_KE || threadIdx.x == FA_GBX || threadIdx.x == FA_KN || threadIdx.x == FA_GBY;
-    A.fac64[(long long)(G.row0 + j) * NFAC + threadIdx.x] = v;
-    A.fac32[(long long)(G.row0 + j) * NFAC + threadIdx.x] = (float)(scaled ? s * v : v);
+    const bool scaled = lane == FA_KE || lane == FA_GBX || lane == FA_KN || lane == FA_GBY;
+    A.fac64[(long long)(G.row0 + j) * NFAC + lane] = v;
+    A.fac32[(long long)(G.row0 + j) * NFAC + lane] = (float)(scaled ? s * v : v);
   }
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
     if (j == 0) A.scale[P.member] = s;
     const double c = 2.0 * P.radius * P.radius * cs_c / P.dt;
     A.c64[G.row0 + j] = c;

@@ -523,8 +523,14 @@ extern "C" int gcr_set_operators(gcr_solver* s, int32_t count, const int32_t* me
   A.fac32 = s->fac32;
   bool any_oro = false;
   for (int t = 0; t < count; ++t) any_oro = any_oro || ops[t].orography;
-  const size_t lds = (any_oro ? 6 : 3) * (size_t)asm_row_lds(s->nxmax) * sizeof(double);
-  KLAUNCH(s, KT_ASSEMBLE, k_assemble, dim3(maxrows, count), dim3(ASM_WG), lds, s->stream, A);
+  // rows per workgroup: as many as the staged rows (two halo rows, times two
+  // fields with orography) fit in 64 KiB of LDS
+  const size_t row_bytes = (any_oro ? 2 : 1) * (size_t)asm_row_lds(s->nxmax) * sizeof(double);
+  A.rows = ASM_ROWS;
+  while (A.rows > 1 && (A.rows + 2) * row_bytes > 65536) --A.rows;
+  const size_t lds = (A.rows + 2) * row_bytes;
+  KLAUNCH(s, KT_ASSEMBLE, k_assemble, dim3((maxrows + A.rows - 1) / A.rows, count), dim3(ASM_WG), lds, s->stream,
+          A);
   HIPCHK(s, hipGetLastError());
   bool host_inputs = false;
   for (int t = 0; t < count; ++t) host_inputs = host_inputs || !ops[t].mem_is_device;
