@@ -996,11 +996,41 @@ __global__ void k_apply_increments(Fields F, long long total) {
 // control: one wave per member; sums the member's per-row partials in a
 // fixed order (deterministic) and updates the device-resident scalars.
 // ---------------------------------------------------------------------------
+// Sums of the slots [first, first + ns) (ns <= NS) of the member's per-row
+// partials.  Each lane adds its rows in a fixed order (rows lane, lane + 64,
+// ...); the loads of MS_UNROLL rows and all slots are issued before the first
+// addition, so the wave waits for memory once per chunk, not once per row.
+constexpr int MS_UNROLL = 4;
+
+template <typename A, int NS>
+__device__ __forceinline__ void member_sums(const Fields& F, const MemberGeom& G, int first, int ns, double* out) {
+  const int lane = threadIdx.x;
+  A s[NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) s[i] = (A)0;
+  const double* base = F.part + (long long)G.row0 * NDOT + first;
+  for (int j0 = 0; j0 < G.ny; j0 += 64 * MS_UNROLL) {
+    double v[MS_UNROLL][NS];
+#pragma unroll
+    for (int u = 0; u < MS_UNROLL; ++u) {
+      const int jj = j0 + u * 64 + lane;
+#pragma unroll
+      for (int i = 0; i < NS; ++i) v[u][i] = (jj < G.ny && i < ns) ? base[(long long)jj * NDOT + i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < MS_UNROLL; ++u)
+#pragma unroll
+      for (int i = 0; i < NS; ++i) s[i] += (A)v[u][i];
+  }
+#pragma unroll
+  for (int i = 0; i < NS; ++i) out[i] = (double)wave_sum(s[i]);
+}
+
 template <typename A>
 __device__ __forceinline__ double member_sum(const Fields& F, const MemberGeom& G, int slot) {
-  A s = (A)0;
-  for (int jj = threadIdx.x; jj < G.ny; jj += 64) s += (A)F.part[(long long)(G.row0 + jj) * NDOT + slot];
-  return (double)wave_sum(s);
+  double o[1];
+  member_sums<A, 1>(F, G, slot, 1, o);
+  return o[0];
 }
 
 enum { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_STAGNATED = 2, ST_FALLBACK = 3 };
@@ -1036,8 +1066,10 @@ __global__ void k_ctrl_beta(Fields F, int slot) {
   MemberState& S = F.state[m];
   if (S.done) return;
   const MemberGeom G = F.geom[m];
-  const double lpsq = member_sum<A>(F, G, DOT_LP_LP);
-  const double num = member_sum<A>(F, G, DOT_R_LP);
+  static_assert(DOT_LP_LP == DOT_R_LP + 1, "slot order");
+  double d[2];
+  member_sums<A, 2>(F, G, DOT_R_LP, 2, d);
+  const double num = d[0], lpsq = d[1];
   if (threadIdx.x == 0) {
     S.lpsq[slot] = lpsq;
     const double beta = -num / lpsq;
@@ -1056,9 +1088,11 @@ __global__ void k_ctrl_alpha(Fields F, int nl, Slots sl, int cycle_end, int min_
   MemberState& S = F.state[m];
   if (S.done) return;
   const MemberGeom G = F.geom[m];
-  const double rr = member_sum<A>(F, G, DOT_RR);
-  double dots[KMAX];
-  for (int l = 0; l < KMAX; ++l) dots[l] = l < nl ? member_sum<A>(F, G, DOT_LE_LP + l) : 0.0;
+  static_assert(DOT_LE_LP == DOT_RR + 1, "slot order");
+  double d[KMAX + 1];
+  member_sums<A, KMAX + 1>(F, G, DOT_RR, nl + 1, d);
+  const double rr = d[0];
+  const double* dots = d + 1;
   if (threadIdx.x == 0) {
     S.it += 1;
     const double rn = sqrt(rr);
