@@ -169,8 +169,10 @@ int gcr_set_operators(gcr_solver* s, int32_t count, const int32_t* members, cons
 
 /* Solve L(x_m) = rhs_m for every member m (paper Section 2.3).
  * rhs, x: host arrays [batch] of device pointers to float64 [NY][NX] fields;
- * x[m] holds the initial guess on entry and the solution on return; x[m]
- * must not overlap rhs[m] or another member's x.  reports: host array
+ * x[m] holds the initial guess on entry and the solution on return.  Both
+ * are used in place: rhs is read by every residual recomputation, x is read
+ * by the first kernel and written by the last one, so no x[m] may overlap an
+ * rhs field or another member's x.  reports: host array
  * [batch], or NULL.  Returns the worst soft status over the members (or a
  * hard error, with every x untouched).  Synchronises the solver's stream.
  * Errors: GCR_EINVAL (NULL pointers), GCR_ESTATE (a member without operator),

@@ -65,7 +65,11 @@ struct CoefRow {
       row(C_BY, R.rc - R.nx, l, L, bys);
     } else {           // the south pole face carries no flux
 #pragma unroll
-      for (int k = 0; k < M; ++k) ays[k] = ayxs[k] = bys[k] = (T)0;
+      for (int k = 0; k < M; ++k) {   // three stores: a chained assignment left a stack slot
+        ays[k] = (T)0;
+        ayxs[k] = (T)0;
+        bys[k] = (T)0;
+      }
     }
   }
 };
@@ -170,7 +174,11 @@ struct CoefFly {
       }
     } else {         // the south pole face carries no flux
 #pragma unroll
-      for (int k = 0; k < M; ++k) ays[k] = ayxs[k] = bys[k] = (T)0;
+      for (int k = 0; k < M; ++k) {   // three stores: a chained assignment left a stack slot
+        ays[k] = (T)0;
+        ayxs[k] = (T)0;
+        bys[k] = (T)0;
+      }
     }
   }
 };
@@ -222,7 +230,9 @@ struct Fields {
   FlyPools<double> fly64;     // on-the-fly coefficients (float64 operator)
   FlyPools<float> fly32;      // on-the-fly coefficients, scaled (float32 operator)
   double* x;                  // solution, float64 pool
-  const double* rhs;          // right-hand side, float64 pool
+  const double* rhs;          // right-hand side, float64 pool (stand-alone entry points)
+  const double* const* rhs_tab;  // caller right-hand sides, natural [NY][NX] order, per member
+  double* const* x_tab;       // caller solutions, natural order, per member
   double* r64;                // float64 residual (float64 form, restart scratch)
   void* r;                    // residual in the Krylov type
   void* e;                    // preconditioner output P^{-1}(r)
@@ -275,6 +285,32 @@ struct RowReader {
   template <int M>
   __device__ __forceinline__ void row(long long start, int l, int L, T (&v)[M], int /*row_g*/) const {
     ldr<M>(p + start, l, L, v);
+  }
+};
+
+// Caller fields in natural [NY][NX] order: lane l loads points
+// l*M .. l*M + M - 1 of a row, the same points its registers hold in the
+// pooled layout, so the stencil code is shared.
+template <int M>
+__device__ __forceinline__ void ldn(const double* row, int l, double (&v)[M]) {
+  const double* q = row + (long long)l * M;
+#pragma unroll
+  for (int k = 0; k < M; ++k) v[k] = q[k];
+}
+
+template <int M>
+__device__ __forceinline__ void stn(double* row, int l, const double (&v)[M]) {
+  double* q = row + (long long)l * M;
+#pragma unroll
+  for (int k = 0; k < M; ++k) q[k] = v[k];
+}
+
+struct NatReader {
+  const double* p;            // the member's field, natural order
+  long long off;              // pooled offset of the member's first point
+  template <int M>
+  __device__ __forceinline__ void row(long long start, int l, int /*L*/, double (&v)[M], int /*row_g*/) const {
+    ldn<M>(p + (start - off), l, v);
   }
 };
 
@@ -576,16 +612,20 @@ template <typename P, int M>
 __device__ __forceinline__ void row_jacobi(const Fields& F, const RowCtx& R, const MemberGeom& G, int qin, int qout) {
   using T = typename P::T;
   using V = typename P::V;
+  // buffer pointers taken before the lambda: indexing F.q inside it made the
+  // compiler copy all of F to the stack
+  const V* qin_p = (const V*)F.q[qin];
+  void* out_p = qout < 0 ? F.e : F.q[qout];
   with_coef<P>(F, G, R.j, false, [&](const auto& cv) {
     const T helm = cv.helm(R.g);
-    RowReader<T, V> X{(const V*)F.q[qin]};
+    RowReader<T, V> X{qin_p};
     T rv[M], d[M], o[M];
     diag_row<T, M>(R, cv, d);
     ldr<M>((const V*)F.r + R.rc, R.lane, R.L, rv);
     stencil_row<T, M>(R, cv, X, [&](int k, T zon, T rest, T xc, T, T, T, T) {
       o[k] = xc - ((zon + rest - helm * xc) - rv[k]) / d[k];
     });
-    store_v<P, M>(qout < 0 ? F.e : F.q[qout], R, o);
+    store_v<P, M>(out_p, R, o);
   });
 }
 
@@ -665,23 +705,37 @@ __global__ __launch_bounds__(WG) void k_apply_L(Fields F, const void* in, void* 
 // r = s*r (s = 1 in the float64 form; solve start and restarts), 2 the float64
 // r64 (stand-alone use).  Partials: <r,r> (slot DOT_RR, in the Krylov
 // scaling); with `lp_slot` >= 0 also <r, L p_slot>.  `respect_done`: skip
-// finished members (restart) or not (final check).
+// finished members (restart) or not (final check).  `io` moves the caller's
+// fields (natural order) in the same pass: RES_RHS_TAB reads R from them,
+// RES_X_IN reads x from them and writes the pooled x (solve start), RES_X_OUT
+// writes the pooled x back to them (solve end).
 // ---------------------------------------------------------------------------
+enum { RES_X_IN = 1, RES_X_OUT = 2, RES_RHS_TAB = 4 };
+
 template <typename P, int M>
-__device__ __forceinline__ void row_residual(const Fields& F, const RowCtx& R, int write_krylov, int lp_slot) {
+__device__ __forceinline__ void row_residual(const Fields& F, const RowCtx& R, const MemberGeom& G, int write_krylov,
+                                             int lp_slot, int io) {
   using V = typename P::V;
   const int l = R.lane, L = R.L;
   const CoefFly<double> cv{F.fly64};
   const double helm = cv.helm(R.g);
   const double s = P::mixed ? F.scale[R.m] : 1.0;
-  RowReader<double, double> X{F.x};
-  double rr[M], b[M];
-  ldr<M>(F.rhs + R.rc, l, L, b);
+  const long long nat = R.rc - G.off;     // the row's offset in natural order
+  double rr[M], b[M], xk[M];
+  if (io & RES_RHS_TAB) ldn<M>(F.rhs_tab[R.m] + nat, l, b);
+  else ldr<M>(F.rhs + R.rc, l, L, b);
   double acc0 = 0.0, acc1 = 0.0;
-  stencil_row<double, M>(R, cv, X, [&](int k, double zon, double rest, double xc, double, double, double, double) {
-    rr[k] = zon + rest - helm * xc - b[k];
-    acc0 += rr[k] * rr[k];
-  });
+  auto body = [&](const auto& X) {
+    stencil_row<double, M>(R, cv, X, [&](int k, double zon, double rest, double xc, double, double, double, double) {
+      rr[k] = zon + rest - helm * xc - b[k];
+      acc0 += rr[k] * rr[k];
+      xk[k] = xc;
+    });
+  };
+  if (io & RES_X_IN) body(NatReader{F.x_tab[R.m], G.off});
+  else body(RowReader<double, double>{F.x});
+  if ((io & RES_X_IN) && R.act) str<M>(F.x + R.rc, l, L, xk);
+  if ((io & RES_X_OUT) && R.act) stn<M>(F.x_tab[R.m] + nat, l, xk);
   if (write_krylov == 2 && R.act) str<M>(F.r64 + R.rc, l, L, rr);
   if (write_krylov == 1) {
     double rk[M];
@@ -701,12 +755,12 @@ __device__ __forceinline__ void row_residual(const Fields& F, const RowCtx& R, i
 }
 
 template <typename P, int M>
-__global__ __launch_bounds__(WG) void k_residual(Fields F, int write_krylov, int lp_slot, int respect_done) {
+__global__ __launch_bounds__(WG) void k_residual(Fields F, int write_krylov, int lp_slot, int respect_done, int io) {
   int g, m, lane, w;
   MemberGeom G;
   const bool active = wave_row(F, g, m, G, lane, w);
   if (g >= F.row_end || (respect_done && !active)) return;
-  row_residual<P, M>(F, make_row(G, m, g, lane, M), write_krylov, lp_slot);
+  row_residual<P, M>(F, make_row(G, m, g, lane, M), G, write_krylov, lp_slot, io);
 }
 
 // ---------------------------------------------------------------------------
@@ -946,28 +1000,12 @@ __global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// gather / scatter between caller fields (natural [NY][NX]) and the pools
-// (row-interleaved storage)
+// copies between one member's caller field (natural [NY][NX]) and the pools
+// (row-interleaved storage), for the stand-alone entry points
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ long long pool_index(const MemberGeom& G, long long k) {
   const int j = (int)(k >> G.log2nx), i = (int)(k & (G.nx - 1));
   return G.off + ((long long)j << G.log2nx) + row_slot(i, G.log2m, G.nx >> G.log2m);
-}
-
-__global__ void k_gather(const double* const* src, double* dst, const MemberGeom* geom) {
-  const int m = blockIdx.y;
-  const MemberGeom G = geom[m];
-  const long long n = (long long)G.nx * G.ny;
-  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
-    dst[pool_index(G, k)] = src[m][k];
-}
-
-__global__ void k_scatter(const double* src, double* const* dst, const MemberGeom* geom) {
-  const int m = blockIdx.y;
-  const MemberGeom G = geom[m];
-  const long long n = (long long)G.nx * G.ny;
-  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
-    dst[m][k] = src[pool_index(G, k)];
 }
 
 // one member, direct pointers

@@ -222,6 +222,8 @@ static Fields make_fields(gcr_solver* s) {
   F.fly32 = FlyPools<float>{s->phi32, s->hs32, s->fac32, s->c32};
   F.x = s->x;
   F.rhs = s->rhs;
+  F.rhs_tab = s->ptr_rhs;
+  F.x_tab = s->ptr_x;
   F.r64 = s->r64;
   F.r = s->r;
   F.e = s->e;
@@ -624,7 +626,7 @@ static int run_solve(gcr_solver* s) {
   const dim3 ctl(B), wave(64);
 
   // step 1: r_0 = L(x_0) - R (float64), p_0 = P^{-1}(r_0), L(p_0)
-  ROWS_LAUNCH(s, s->classes, F, KT_RESIDUAL, k_residual, P, 1, -1, 0);
+  ROWS_LAUNCH(s, s->classes, F, KT_RESIDUAL, k_residual, P, 1, -1, 0, RES_X_IN | RES_RHS_TAB);
   KLAUNCH(s, KT_CONTROL, k_ctrl_init<double>, ctl, wave, 0, s->stream, F);
   {
     Fields F0 = F;
@@ -655,7 +657,7 @@ static int run_solve(gcr_solver* s) {
   // end of a cycle: (p_0, L p_0) := (p_k, L p_k); residual replacement; flags
   auto cycle_end = [&](int base_next, int ring) -> int {
     if (replace) {
-      ROWS_LAUNCH(s, s->classes, F, KT_RESIDUAL, k_residual, P, 1, base_next, 1);
+      ROWS_LAUNCH(s, s->classes, F, KT_RESIDUAL, k_residual, P, 1, base_next, 1, RES_RHS_TAB);
       KLAUNCH(s, KT_CONTROL, k_ctrl_restart<double>, ctl, wave, 0, s->stream, F, base_next);
     }
     HIPCHK(s, hipMemcpyAsync(s->state_ring[ring], s->state, B * sizeof(MemberState), hipMemcpyDeviceToHost,
@@ -689,7 +691,7 @@ static int run_solve(gcr_solver* s) {
     KLAUNCH(s, KT_COPY, k_apply_increments, g, dim3(256), 0, s->stream, F, s->npts);
   }
   // true residual of every member in float64
-  ROWS_LAUNCH(s, s->classes, F, KT_RESIDUAL, k_residual, P, 0, -1, 0);
+  ROWS_LAUNCH(s, s->classes, F, KT_RESIDUAL, k_residual, P, 0, -1, 0, RES_X_OUT | RES_RHS_TAB);
   KLAUNCH(s, KT_CONTROL, k_ctrl_true, ctl, wave, 0, s->stream, F);
   HIPCHK(s, hipGetLastError());
   return GCR_OK;
@@ -713,9 +715,8 @@ extern "C" int gcr_solve(gcr_solver* s, const double* const* rhs, double* const*
   HIPCHK(s, hipMemcpyAsync(s->ptr_rhs, s->ptr_stage, B * sizeof(void*), hipMemcpyHostToDevice, s->stream));
   HIPCHK(s, hipMemcpyAsync(s->ptr_x, s->ptr_stage + B, B * sizeof(void*), hipMemcpyHostToDevice, s->stream));
   HIPCHK(s, hipEventRecord(s->stage_ev[0], s->stream));
-  const dim3 gg(64, B);
-  KLAUNCH(s, KT_COPY, k_gather, gg, dim3(256), 0, s->stream, s->ptr_rhs, s->rhs, s->geom);
-  KLAUNCH(s, KT_COPY, k_gather, gg, dim3(256), 0, s->stream, (const double* const*)s->ptr_x, s->x, s->geom);
+  // the caller's rhs and x are read in place by the residual kernels (x is
+  // copied into the pool by the first one and back by the last one)
   if (s->dx) HIPCHK(s, hipMemsetAsync(s->dx, 0, s->npts * sizeof(float), s->stream));
   HIPCHK(s, hipGetLastError());
   int rc;
@@ -726,7 +727,6 @@ extern "C" int gcr_solve(gcr_solver* s, const double* const* rhs, double* const*
     default: rc = run_solve<PrecMixedP>(s); break;
   }
   if (rc != GCR_OK) return rc;
-  KLAUNCH(s, KT_COPY, k_scatter, gg, dim3(256), 0, s->stream, s->x, s->ptr_x, s->geom);
   HIPCHK(s, hipGetLastError());
   HIPCHK(s, hipMemcpyAsync(s->state_h, s->state, B * sizeof(MemberState), hipMemcpyDeviceToHost, s->stream));
   std::vector<double> hist_h;
@@ -870,7 +870,7 @@ extern "C" int gcr_learned_features(gcr_solver* s, int32_t member, const double*
   // r = L(x) - rhs and its <r,r> partials
   KLAUNCH(s, KT_COPY, k_to_pool, cg, dim3(256), 0, s->stream, x, s->x, G);
   KLAUNCH(s, KT_COPY, k_to_pool, cg, dim3(256), 0, s->stream, rhs, s->rhs, G);
-  ROWS_LAUNCH(s, cls, F, KT_RESIDUAL, k_residual, PrecF64, 2, -1, 0);
+  ROWS_LAUNCH(s, cls, F, KT_RESIDUAL, k_residual, PrecF64, 2, -1, 0, 0);
   F.r = s->r64;
   LearnArgs A{};
   A.r = s->r64;
