@@ -202,6 +202,44 @@ def test_zero_rhs_and_exact_guess(gpu_lib):
     assert torch.allclose(x2, xt, rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("precision", [0, 3])
+def test_warm_start_batch_all_widths(gpu_lib, precision):
+    """Nonzero initial guesses in a batch spanning every points-per-lane class
+    (nx = 8 .. 1024): the caller's x and rhs are read in place by the first
+    residual (pole rows included) and x is written back by the last one.
+    Same guess in the oracle: same r_0 and, in float64, the same solution."""
+    sizes = [(8, 4), (64, 16), (128, 32), (256, 16), (1024, 8)]
+    rtol = 1e-10 if precision == 0 else 1e-8
+    s = make_solver(gpu_lib, sizes, precision=precision, rtol=rtol, max_iters=100)
+    rng = np.random.default_rng(7)
+    ops, rhs, x0, xs = [], [], [], []
+    for m, (nx, ny) in enumerate(sizes):
+        pr = problem(2, nx, ny, instance=m, dt=600.0)
+        op = EllipticOperator(nx, ny, pr["depth"], 600.0)
+        s.set_operator(m, pr["depth"], 600.0)
+        ops.append(op)
+        rhs.append(op.apply(pr["x_true"]))
+        g = pr["x_true"] + 0.3 * np.std(pr["x_true"]) * rng.standard_normal((ny, nx))
+        x0.append(g)
+        xs.append(dev(g))
+    rhs_d = [dev(r) for r in rhs]
+    reps = s.solve(rhs_d, xs)
+    for m, (nx, ny) in enumerate(sizes):
+        op = ops[m]
+        ores = gcr(op, rhs[m], x0=x0[m], rtol=rtol, max_iters=100)
+        x = host(xs[m])
+        rep = reps[m]
+        assert np.array_equal(host(rhs_d[m]), rhs[m]), "rhs must be read only"
+        assert rep.r0_norm == pytest.approx(ores.r0_norm, rel=1e-12), (nx, ny)
+        true_res = np.linalg.norm(op.apply(x) - rhs[m]) / ores.r0_norm
+        assert rep.rel_res_true == pytest.approx(true_res, rel=1e-6, abs=1e-14), (nx, ny)
+        assert rep.status == gpu_lib.OK and true_res <= rtol, (nx, ny, rep)
+        err = np.linalg.norm(x - ores.x) / np.linalg.norm(ores.x)
+        assert err <= (1e-9 if precision == 0 else 1e-6), (nx, ny, err)
+        if precision == 0:
+            assert abs(rep.iterations - ores.iterations) <= 1, (nx, ny, rep.iterations, ores.iterations)
+
+
 def test_max_iters_reached(gpu_lib):
     pr = problem(1, 64, 32)
     op = EllipticOperator(64, 32, pr["depth"], 600.0)
