@@ -31,6 +31,7 @@ struct ConvArgs {
   __bf16* out;             // [B][ny][nx][CH] (bf16 output modes)
   float* out32;            // [B][ny][nx] channel 0 (float32 output mode)
   const __bf16* mask;      // multiply by (mask > 0), [B][ny][nx][CH], or null
+  const int* active;       // [B]: images with 0 are skipped (output left as is), or null (all)
   int nx, ny, log2nx, batch;
   int relu;
 };
@@ -82,6 +83,7 @@ constexpr int WROW = CH + 8;
 template <int NT, int OUT>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs A) {
   __shared__ __attribute__((aligned(16))) __bf16 sw[2][TAPS * CH * WROW];
+  if (A.active && !A.active[blockIdx.y]) return;   // the whole workgroup: one image
   const int tid = threadIdx.x;
   // stage both weight sets (regular and across-pole taps), 16 bytes a thread
   for (int k = tid; k < TAPS * CH * 4; k += 256) {

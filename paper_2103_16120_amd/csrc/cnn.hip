@@ -318,9 +318,10 @@ static dim3 conv_grid(const cnn_net* n, int batch) {
 }
 
 // forward from act[0] (already packed) to y (float32 [B][npix])
-int cnn_forward_packed(cnn_net* n, int batch, float* y, hipStream_t st) {
+int cnn_forward_packed(cnn_net* n, int batch, float* y, hipStream_t st, const int* active) {
   for (int l = 0; l < CNN_LAYERS; ++l) {
     ConvArgs A = conv_args(n, batch);
+    A.active = active;
     A.in = n->act[l];
     A.w = n->wf + (size_t)l * TAPS * CH * CH;
     A.wpole = A.w;

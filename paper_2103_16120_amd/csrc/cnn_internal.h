@@ -42,5 +42,6 @@ struct cnn_net {
   double* loss_host = nullptr;
 };
 
-// forward pass from the packed input act[0] to `y` on stream `st`
-int cnn_forward_packed(cnn_net* n, int batch, float* y, hipStream_t st);
+// forward pass from the packed input act[0] to `y` on stream `st`; images b
+// with active[b] == 0 are skipped (active: device array [batch], or null)
+int cnn_forward_packed(cnn_net* n, int batch, float* y, hipStream_t st, const int* active = nullptr);

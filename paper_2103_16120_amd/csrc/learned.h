@@ -22,6 +22,7 @@ struct LearnArgs {
   __bf16* feat;          // network input [batch][ny][nx][32] (bf16, NHWC)
   const float* y;        // network output [batch][ny][nx]
   int use_part;          // sigma from the per-row <r,r> partials (1) or from r (0)
+  int* active;           // [batch]: members corrected by this application (network input mask), or null
 };
 
 // cosine of the cell-centre latitude of row j (rows from the south pole)
@@ -31,13 +32,17 @@ __device__ __forceinline__ bool learn_skip(const Fields& F, const MemberState& S
   return !F.ignore_done && (S.done || S.fallback);
 }
 
-// sigma of each member: RMS of its residual in the form's units
+// sigma of each member: RMS of its residual in the form's units.  One block
+// per member of the batch; members outside [member0, member0 + count) or
+// skipped are marked inactive, so the network does not run on their images.
 template <typename P>
-__global__ void k_learn_sigma(Fields F, LearnArgs A, int member0) {
+__global__ void k_learn_sigma(Fields F, LearnArgs A, int member0, int count) {
   using V = typename P::V;
-  const int m = member0 + blockIdx.x;
+  const int m = blockIdx.x;
   MemberState& S = F.state[m];
-  if (learn_skip(F, S)) return;
+  const bool act = m >= member0 && m < member0 + count && !learn_skip(F, S);
+  if (A.active && threadIdx.x == 0) A.active[m] = act ? 1 : 0;
+  if (!act) return;
   const MemberGeom G = F.geom[m];
   double rr;
   if (A.use_part) {

@@ -107,6 +107,7 @@ struct gcr_solver {
   hipEvent_t stage_ev[2] = {};       // recorded after the uploads from ptr_stage / asm_stage
   AsmMember* asm_tab = nullptr;      // device assembly table [batch]
   cnn_net* net = nullptr;            // learned preconditioner (GCR_PC_LEARNED), owned
+  int* learn_active = nullptr;       // [batch] images the network runs on in one application
   double fallback_ratio = 0.5;
 
   // optional per-kernel timing with HIP events on the solver's stream
@@ -563,10 +564,11 @@ static void learned_correction(gcr_solver* s, const std::vector<RowClass>& cls, 
   A.feat = s->net->act[0];
   A.y = s->net->y;
   A.use_part = use_part;
-  KLAUNCH(s, KT_LEARNED, k_learn_sigma<P>, dim3(count), dim3(64), 0, s->stream, F, A, member0);
+  A.active = s->learn_active;
+  KLAUNCH(s, KT_LEARNED, k_learn_sigma<P>, dim3(s->prm.batch), dim3(64), 0, s->stream, F, A, member0, count);
   ROWS_LAUNCH(s, cls, F, KT_LEARNED, k_learn_pack, P, A);
   s->tm_begin(KT_LEARNED);
-  (void)cnn_forward_packed(s->net, s->prm.batch, s->net->y, s->stream);
+  (void)cnn_forward_packed(s->net, s->prm.batch, s->net->y, s->stream, s->learn_active);
   s->tm_end();
   ROWS_LAUNCH(s, cls, F, KT_LEARNED, k_learn_apply, P, A);
 }
@@ -834,6 +836,10 @@ extern "C" int gcr_set_learned(gcr_solver* s, const float* params, int64_t count
   if (!(fallback_ratio > 0.0 && fallback_ratio <= 1.0))
     return fail(s, GCR_EINVAL, "fallback_ratio must be in (0, 1]");
   if (!s->net) {
+    hipError_t herr = hipSuccess;
+    s->learn_active = dalloc<int>(s->prm.batch, herr);
+    if (herr != hipSuccess) return fail(s, GCR_ENOMEM, "learned preconditioner: %s", hipGetErrorString(herr));
+    s->allocs.push_back(s->learn_active);
     const int rc = cnn_create(s->nx[0], s->ny[0], s->prm.batch, GCR_LEARNED_CHANNELS, s->stream, &s->net);
     if (rc != GCR_OK) return fail(s, rc, "network: %s", cnn_last_error(nullptr));
   }
@@ -875,7 +881,7 @@ extern "C" int gcr_learned_features(gcr_solver* s, int32_t member, const double*
   LearnArgs A{};
   A.r = s->r64;
   A.use_part = 1;
-  KLAUNCH(s, KT_LEARNED, k_learn_sigma<PrecF64>, dim3(1), dim3(64), 0, s->stream, F, A, member);
+  KLAUNCH(s, KT_LEARNED, k_learn_sigma<PrecF64>, dim3(s->prm.batch), dim3(64), 0, s->stream, F, A, member, 1);
   F.e = elo;
   launch_precond<PrecF64>(s, cls, F, 0, 0, -1);
   if (hi_iters > 0) {
