@@ -32,26 +32,61 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic HBM bytes per grid point and launch of each kernel kind in the
-# mixed form (float16 preconditioner coefficients: 6 face arrays of 2 B;
-# float32 Krylov vectors: 4 B; float16 preconditioner intermediate: 2 B).
-# The step-2 update kernel and the L/step-4 kernels depend on the window
-# position nu; the counts below are the averages over a GCR(3) cycle
-# (nu = 0, 1, 2).  Constant-size kernels are preferred for the roofline.
-ALG_BYTES_MIXED = {
-    # q_in (2) + r (4) + 6 coefficient arrays (12) -> e (4)
-    "sweep2": 22.0,
-}
-ALG_BYTES_FP64 = {
-    # q_in (8) + r (8) + Phi* and H* (16; the coefficients are formed from
-    # them on the fly) -> e (8)
-    "sweep2": 40.0,
-}
+# Algorithmic HBM bytes per grid point of each kernel pass: every array the
+# pass reads or writes counted once (halo rows and re-reads are not counted).
+# Sizes per point: Krylov vector V (4 B mixed, 8 B float64), preconditioner
+# intermediate Q (float16 2 B / float64 8 B), float64 solution X = 8 B, one
+# float16 coefficient array C = 2 B (the 2.3% polar rows read float32 and are
+# counted at the float16 size), and the depth pools the operators form their
+# coefficients from on the fly (Phi* and H*: 2 x 4 B for the float32 operator,
+# 2 x 8 B for float64; the float64 row solves read Phi* only).  nu is the
+# position in the GCR(k) window (nu + 1 directions are combined).
+def pass_bytes(form):
+    mixed = form == "mixed"
+    V, Q, X = (4, 2, 8) if mixed else (8, 8, 8)
+    faces = 2 * 2 if mixed else 8              # A^xx, A^yy (float16) or Phi* (float64)
+    pre6 = 6 * 2 if mixed else 16              # six coefficient arrays or Phi*, H*
+    op = 8 if mixed else 16                    # operator inside the iteration: Phi*, H*
+    return {
+        "update_sweep1": {
+            "setup": V + faces + Q,                              # r -> q1
+            "iter": 3 * V + X + faces + X + V + Q,               # r, p, Lp, x -> x, r, q1
+        },
+        "sweep2": {"pass": Q + V + pre6 + V},                    # q1, r -> e
+        "apply_L": {
+            "setup": V + op + V + V,                             # p0 -> L p0, with <r, L p0>
+            "iter": lambda nu: V + op + V + V * (nu + 1),        # e -> L e, with <L e, L p_l>
+        },
+        "orth": {"iter": lambda nu: 5 * V + 2 * V * (nu + 1)},   # e, Le, r, p_l, Lp_l -> p, Lp
+        "residual": {                                            # float64, coefficients from Phi*, H*
+            "init": X + 8 + 16 + V + X,                          # caller x, R -> r, pooled x
+            "restart": X + 8 + 16 + V + V,                       # x, R, L p_0 -> r
+            "final": X + 8 + 16 + X,                             # x, R -> caller x
+        },
+    }
+
+
+def step_bytes(form, iters, restarts, k, pts):
+    """Algorithmic bytes per kernel kind for members that took `iters`
+    iterations and `restarts` residual recomputations (arrays over members)."""
+    pb = pass_bytes(form)
+    tot = {name: 0.0 for name in pb}
+    for n, nr in zip(np.ravel(iters), np.ravel(restarts)):
+        n, nr = int(n), int(nr)
+        nus = [(i - 1) % k for i in range(1, n + 1)]
+        tot["update_sweep1"] += pb["update_sweep1"]["setup"] + n * pb["update_sweep1"]["iter"]
+        tot["sweep2"] += (1 + n) * pb["sweep2"]["pass"]
+        tot["apply_L"] += pb["apply_L"]["setup"] + sum(pb["apply_L"]["iter"](nu) for nu in nus)
+        tot["orth"] += sum(pb["orth"]["iter"](nu) for nu in nus[:-1])   # none after the exit test
+        tot["residual"] += pb["residual"]["init"] + nr * pb["residual"]["restart"] + pb["residual"]["final"]
+    return {name: v * pts for name, v in tot.items()}
+
+
 HBM_PEAK_GBS = 8000.0
 # HBM traffic of the roofline kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # counter runs (scaled by a plain copy of known size), valid only for the
 # kernel sources it was taken with
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep2_traffic_512x256_b64.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "kernel_traffic_512x256_b64.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2103_16120_amd", "csrc", f) for f in ("device.h", "kernels.h")]
 
 
@@ -139,20 +174,30 @@ class Leg:
         return dt, np.array(iters), ktimes, kiters
 
 
-def roofline(ktimes, iters, reports, pts, table, name="sweep2"):
-    """Achieved algorithmic bandwidth of kernel `name`: every member is
-    processed once in the setup and once per iteration it performs."""
-    n, ms = ktimes.get(name, (0, 0.0))
-    if n == 0 or ms <= 0:
-        return None
-    member_passes = float(np.sum(1 + iters))            # over all timed steps
-    bytes_total = member_passes * pts * table[name]
-    achieved = bytes_total / (ms * 1e-3) / 1e9
-    per_launch = bytes_total / n
-    return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "avg_launch_us": round(ms * 1e3 / n, 2), "launches": n,
-            "alg_bytes_per_launch": int(per_launch)}
+def roofline(ktimes, iters, reports, pts, form, k=3):
+    """Achieved algorithmic bandwidth of every row kernel over the timed
+    steps (bytes of step_bytes / kernel time from HIP events, empty launches on
+    finished members included), and the roofline object of the dominant one
+    (largest time)."""
+    restarts = np.array([[r.restarts for r in reports]] * len(iters))
+    alg = step_bytes(form, iters, restarts, k, pts)
+    kernels = {}
+    for name, b in alg.items():
+        n, ms = ktimes.get(name, (0, 0.0))
+        if n == 0 or ms <= 0:
+            continue
+        achieved = b / (ms * 1e-3) / 1e9
+        kernels[name] = {"achieved": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "launches": n, "avg_launch_us": round(ms * 1e3 / n, 2),
+                         "alg_bytes_per_launch": int(b / n)}
+    if not kernels:
+        return None, {}
+    name = max(kernels, key=lambda q: ktimes[q][1])
+    kr = kernels[name]
+    top = {"kernel": name, "bound": "hbm", "achieved": kr["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": kr["frac"], "traffic": None, "avg_launch_us": kr["avg_launch_us"], "launches": kr["launches"],
+           "alg_bytes_per_launch": kr["alg_bytes_per_launch"]}
+    return top, kernels
 
 
 def kernel_source_hash():
@@ -165,18 +210,19 @@ def kernel_source_hash():
 
 
 def measured_traffic(kernel, workload):
-    """Bytes per launch from the committed counter summary, or None when it
-    is missing, for another kernel/workload, or older than the sources."""
+    """HBM bytes per launch of `kernel` (mean over its dispatches) from the
+    committed counter summary, or None when it is missing, for another
+    workload, or older than the kernel sources."""
     try:
         with open(TRAFFIC_FILE) as fh:
-            rec = json.loads([l for l in fh if l.startswith("{")][-1])
-    except (OSError, ValueError, IndexError):
+            recs = [json.loads(l) for l in fh if l.startswith("{")]
+    except (OSError, ValueError):
         return None
-    if rec.get("kernel") != kernel or rec.get("workload") != workload:
-        return None
-    if rec.get("source_sha256") != kernel_source_hash():
-        return None
-    return rec.get("bytes_per_launch")
+    h = kernel_source_hash()
+    for rec in recs:
+        if rec.get("kernel") == kernel and rec.get("workload") == workload and rec.get("source_sha256") == h:
+            return rec.get("bytes_per_launch")
+    return None
 
 
 def cpu_baseline(args, probs, budget_s):
@@ -263,9 +309,9 @@ def main():
     }
     if not args.no_timing:
         ts = len(kit_mixed)
-        out["roofline"] = roofline(kt_mixed, kit_mixed, rep_m, pts, ALG_BYTES_MIXED)
+        out["roofline"], out["roofline_kernels"] = roofline(kt_mixed, kit_mixed, rep_m, pts, "mixed")
         if out["roofline"] is not None and args.batch == 64 and (args.nx, args.ny) == (512, 256):
-            out["roofline"]["traffic"] = measured_traffic("sweep2", "mixed_half_pc 64x512x256")
+            out["roofline"]["traffic"] = measured_traffic(out["roofline"]["kernel"], "mixed_half_pc 64x512x256")
         out["kernel_ms_per_step"] = {k: round(v[1] / ts, 4) for k, v in kt_mixed.items() if v[0]}
         out["kernel_launches_per_step"] = {k: v[0] / ts for k, v in kt_mixed.items() if v[0]}
     mixed.solver.close()
@@ -277,7 +323,8 @@ def main():
                        "gcr_iters_mean": float(it64.mean()),
                        "rel_res_true_max": max(r.rel_res_true for r in f64.reports)}
         if not args.no_timing:
-            out["fp64"]["roofline"] = roofline(kt64, kit64, f64.reports, pts, ALG_BYTES_FP64)
+            out["fp64"]["roofline"], out["fp64"]["roofline_kernels"] = roofline(kt64, kit64, f64.reports, pts,
+                                                                                "fp64")
         out["speedup_mixed_vs_fp64"] = round(t64 / t_mixed, 3)
         f64.solver.close()
 

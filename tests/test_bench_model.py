@@ -1,0 +1,34 @@
+"""The benchmark's algorithmic-bytes model (host logic, no GPU): per-kernel
+bytes per grid point of one solve, counted by hand from the arrays each pass
+reads and writes (see bench.pass_bytes)."""
+import os
+import sys
+
+import numpy as np
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import bench  # noqa: E402
+
+
+def test_mixed_form_six_iterations_one_restart():
+    # GCR(3), 6 iterations (window positions 0,1,2,0,1,2), one restart
+    b = bench.step_bytes("mixed", np.array([[6]]), np.array([[1]]), 3, 1)
+    # update+sweep1: setup r 4 + faces 4 -> q 2; iteration r,p,Lp 12 + x 8 + faces 4 -> x 8, r 4, q 2
+    assert b["update_sweep1"] == 10 + 6 * 38
+    # sweep2: q 2, r 4, six float16 arrays 12 -> e 4; setup + 6 iterations
+    assert b["sweep2"] == 7 * 22
+    # apply_L: setup 20; iteration 16 + 4 (nu + 1)
+    assert b["apply_L"] == 20 + 2 * (20 + 24 + 28)
+    # step 4 after iterations 1..5: 20 + 8 (nu + 1)
+    assert b["orth"] == 28 + 36 + 44 + 28 + 36
+    # float64 residual: start 44, one restart 40, final 40
+    assert b["residual"] == 44 + 40 + 40
+
+
+def test_fp64_form_and_member_sum():
+    b1 = bench.step_bytes("fp64", np.array([[4]]), np.array([[0]]), 3, 10)
+    b2 = bench.step_bytes("fp64", np.array([[4, 4]]), np.array([[0, 0]]), 3, 10)
+    assert all(b2[k] == 2 * b1[k] for k in b1)
+    assert b1["sweep2"] == 10 * 5 * 40
+    assert b1["orth"] == 10 * ((40 + 16) + (40 + 32) + (40 + 48))
+    assert b1["residual"] == 10 * (48 + 40)
