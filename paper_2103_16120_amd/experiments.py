@@ -1,7 +1,14 @@
 """Measurements of the batched and time-sequence workloads (one JSON line each).
 
+    python -m paper_2103_16120_amd.experiments single     # one solve (64x32 at 1e-10, 256x128 at 1e-8)
     python -m paper_2103_16120_amd.experiments batch      # 64 members of uneven grids
     python -m paper_2103_16120_amd.experiments sequence   # 200 warm-started solves at 1024x512
+
+single: one member of the configuration family (depth 8000 m + 500 m x
+degree<=8 harmonics, dt 600 s, R = L(degree<=12 field)), 64x32 solved to 1e-10
+and 256x128 to 1e-8, in every precision form; a step is assembly + solve of
+the one member, repeated.  Each form's error is its solution's relative L2
+distance to the float64 solution.
 
 batch: 64 independent solves, grids drawn from {128x64, 256x128, 512x256},
 depth 4000-10000 m, dt in [300, 1200] s, solved in one batch in every
@@ -35,6 +42,48 @@ def _lib():
     import torch
     from paper_2103_16120_amd import lib
     return torch, lib
+
+
+def single(args):
+    torch, lib = _lib()
+    from workloads import problem
+    out = {"workload": "one solve per step: 64x32 (rtol 1e-10) and 256x128 (rtol 1e-8), dt 600 s", "cases": {}}
+    for cfg, nx, ny, rtol in ((1, 64, 32, 1e-10), (2, 256, 128, 1e-8)):
+        pr = problem(cfg, nx, ny, dt=600.0)
+        depth = torch.from_numpy(pr["depth"]).cuda()
+        f = lib.Solver([(nx, ny)], precision=lib.FP64)
+        f.set_operator(0, depth, pr["dt"])
+        rhs = f.apply_operator(0, torch.from_numpy(pr["x_true"]).cuda()).clone()
+        f.close()
+        case, ref = {}, None
+        for name, prec in (("fp64", lib.FP64), ("mixed_half_pc", lib.MIXED_HALF_PC),
+                           ("mixed_fp64dot", lib.MIXED_FP64DOT), ("mixed", lib.MIXED)):
+            s = lib.Solver([(nx, ny)], precision=prec, rtol=rtol, max_iters=100)
+            x = torch.zeros_like(rhs)
+
+            def step():
+                s.set_operator(0, depth, pr["dt"])
+                x.zero_()
+                return s.solve([rhs], [x])[0]
+
+            for _ in range(args.warmup):
+                step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                rep = step()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.steps
+            sol = x.cpu().numpy()
+            if ref is None:
+                ref = sol
+            case[name] = {"solves_per_s": round(1.0 / dt, 1), "ms_per_solve": round(1e3 * dt, 3),
+                          "iterations": rep.iterations, "status": rep.status, "rel_res_true": rep.rel_res_true,
+                          "rel_l2_vs_fp64": float(np.linalg.norm(sol - ref) / np.linalg.norm(ref))}
+            s.close()
+            print(f"# {nx}x{ny} {name}: {json.dumps(case[name])}", flush=True)
+        out["cases"][f"{nx}x{ny}"] = case
+    print(json.dumps(out), flush=True)
 
 
 def batch(args):
@@ -147,6 +196,9 @@ def sequence(args):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
+    g = sub.add_parser("single")
+    g.add_argument("--steps", type=int, default=200)
+    g.add_argument("--warmup", type=int, default=10)
     b = sub.add_parser("batch")
     b.add_argument("--count", type=int, default=64)
     b.add_argument("--steps", type=int, default=5)
@@ -160,7 +212,9 @@ def main(argv=None):
     q.add_argument("--rtol", type=float, default=1e-8)
     q.add_argument("--no-learned", action="store_true")
     args = ap.parse_args(argv)
-    if args.cmd == "batch":
+    if args.cmd == "single":
+        single(args)
+    elif args.cmd == "batch":
         batch(args)
     else:
         sequence(args)
