@@ -32,6 +32,10 @@ struct ConvArgs {
   float* out32;            // [B][ny][nx] channel 0 (float32 output mode)
   const __bf16* mask;      // multiply by (mask > 0), [B][ny][nx][CH], or null
   const int* active;       // [B]: images with 0 are skipped (output left as is), or null (all)
+  int row_begin, row_end;  // rows computed (all: 0, ny)
+  int pole_row;            // -1: taps use `w`, across-pole taps `wpole` only if wpole == w (forward);
+                           // 0 or ny-1: the launch covers that polar row alone and its
+                           // across-pole taps use `wpole`
   int nx, ny, log2nx, batch;
   int relu;
 };
@@ -71,89 +75,128 @@ __device__ __forceinline__ bf16x8 ld8(const __bf16* p) {
 // 3x3 convolution, 32 input channels, NT*16 output channels.
 // OUT: 0 = bf16 NHWC (32 channels written, the upper 16 zero when NT == 1),
 //      1 = float32 channel 0 only.
-// One wave computes 64 consecutive pixels of one row, two 16-pixel tiles at
-// a time (the 18 input fragments of a tile pair are loaded before the MFMAs
+// A workgroup covers CONV_SPW groups of four consecutive 64-pixel strips, one
+// strip per wave at a time; a wave computes its strip two 16-pixel tiles at a
+// time (the 18 input fragments of a tile pair are loaded before the MFMAs
 // that use them, which keeps loads in flight while the matrix cores work).
-// The workgroup's four waves share the weight fragments staged in LDS; each
-// [tap][out channel] row of 32 input channels is padded to 40 elements so
-// that the 16 lanes reading one 16-byte column hit distinct banks.
+// The four waves share the weight fragments staged in LDS once per workgroup;
+// each [tap][out channel] row of 32 input channels is padded to 40 elements so
+// that the 16 lanes reading one 16-byte column hit distinct banks.  When the
+// taps that read across a pole need other weights than the rest (the adjoint
+// in the backward pass), the two polar rows are computed by launches of their
+// own (`pole_row`) whose staged set takes those taps from `wpole`, so the LDS
+// holds one set of nine taps.  bf16 outputs go through a per-wave
+// LDS tile so that each lane stores 16 contiguous bytes (8 channels of one
+// pixel); the backward ReLU mask is applied there, 8 channels at a time.
 // ---------------------------------------------------------------------------
 constexpr int WROW = CH + 8;
+constexpr int CONV_SPW = 4;              // strip groups per workgroup
+constexpr int OROW = CH + 8;             // padded pixel row of the output tile
 
 template <int NT, int OUT>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs A) {
-  __shared__ __attribute__((aligned(16))) __bf16 sw[2][TAPS * CH * WROW];
+  __shared__ __attribute__((aligned(16))) __bf16 sw[TAPS * CH * WROW];
+  __shared__ __attribute__((aligned(16))) __bf16 so[WG_WAVES][16 * OROW];
   if (A.active && !A.active[blockIdx.y]) return;   // the whole workgroup: one image
   const int tid = threadIdx.x;
-  // stage both weight sets (regular and across-pole taps), 16 bytes a thread
+  const int npix = A.nx * A.ny;
+  const int spr = A.nx >> 6;                       // 64-pixel strips per row
+  const long long s_first = (long long)A.row_begin * spr + (long long)blockIdx.x * CONV_SPW * WG_WAVES;
+  const long long s_end = (long long)A.row_end * spr;
+  // stage the weights, 16 bytes a thread; in a polar-row launch the taps that
+  // read across the pole come from the across-pole set
   for (int k = tid; k < TAPS * CH * 4; k += 256) {
     const int row = k >> 2, q = 8 * (k & 3);
-    *(bf16x8*)&sw[0][row * WROW + q] = ld8(A.w + row * CH + q);
-    *(bf16x8*)&sw[1][row * WROW + q] = ld8(A.wpole + row * CH + q);
+    const int dy = (row >> 5) / 3 - 1;             // row = tap * CH + out channel
+    const bool across = A.pole_row >= 0 && ((dy < 0 && A.pole_row == 0) || (dy > 0 && A.pole_row == A.ny - 1));
+    *(bf16x8*)&sw[row * WROW + q] = ld8((across ? A.wpole : A.w) + row * CH + q);
   }
   __syncthreads();
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int npix = A.nx * A.ny;
-  const long long strip = (long long)blockIdx.x * WG_WAVES + wave;   // 64-pixel strip of image blockIdx.y
-  if (strip * 64 >= npix) return;
   const int b = blockIdx.y;
-  const int p0 = (int)(strip * 64);
-  const int j = p0 >> A.log2nx, i0 = p0 & (A.nx - 1);
   const __bf16* img = A.in + (long long)b * npix * CH;
   const int kq = 8 * (lane >> 4);          // channel block of this lane (A and B operands)
   const int ml = lane & 15;
+  __bf16* tile = so[wave];
 #pragma unroll 1
-  for (int mt = 0; mt < CONV_MT; mt += 2) {
-    bf16x8 a[2][TAPS];
+  for (int g = 0; g < CONV_SPW; ++g) {
+    const long long strip = s_first + g * WG_WAVES + wave;
+    if (strip >= s_end) break;
+    const int p0 = (int)(strip * 64);
+    const int j = p0 >> A.log2nx, i0 = p0 & (A.nx - 1);
+#pragma unroll 1
+    for (int mt = 0; mt < CONV_MT; mt += 2) {
+      bf16x8 a[2][TAPS];
 #pragma unroll
-    for (int t = 0; t < TAPS; ++t) {
-      const int dy = t / 3 - 1, dx = t % 3 - 1;
+      for (int t = 0; t < TAPS; ++t) {
+        const int dy = t / 3 - 1, dx = t % 3 - 1;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          int jj, ii;
+          bool ghost;
+          sphere_src(j, i0 + 16 * (mt + h) + ml, dy, dx, A.nx, A.ny, jj, ii, ghost);
+          a[h][t] = ld8(img + ((long long)jj * A.nx + ii) * CH + kq);
+        }
+      }
+      f32x4 acc[2][NT];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[h][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < TAPS; ++t) {
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+          const bf16x8 bw = *(const bf16x8*)&sw[(t * CH + 16 * n + ml) * WROW + kq];
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            acc[h][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[h][t], bw, acc[h][n], 0, 0, 0);
+        }
+      }
+      // epilogue: lane holds output channel co = 16n + ml of pixels 4*(lane/16) .. +3 of each tile
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        int jj, ii;
-        bool ghost;
-        sphere_src(j, i0 + 16 * (mt + h) + ml, dy, dx, A.nx, A.ny, jj, ii, ghost);
-        a[h][t] = ld8(img + ((long long)jj * A.nx + ii) * CH + kq);
-      }
-    }
-    f32x4 acc[2][NT];
+        const long long pt = (long long)b * npix + p0 + 16 * (mt + h);   // first pixel of the tile
+        if (OUT == 1) {
+          if (ml == 0) {
+            const float bias = A.bias ? A.bias[0] : 0.f;
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int n = 0; n < NT; ++n) acc[h][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int t = 0; t < TAPS; ++t) {
-      const int dy = t / 3 - 1;
-      // taps reading across a pole use the pole weight set (wave-uniform)
-      const bool ghost = (dy < 0 && j == 0) || (dy > 0 && j == A.ny - 1);
-      const __bf16* wt = &sw[ghost ? 1 : 0][t * CH * WROW];
-#pragma unroll
-      for (int n = 0; n < NT; ++n) {
-        const bf16x8 bw = *(const bf16x8*)&wt[(16 * n + ml) * WROW + kq];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) acc[h][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[h][t], bw, acc[h][n], 0, 0, 0);
-      }
-    }
-    // epilogue: lane holds output channel co = 16n + ml for 4 pixels of each tile
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-#pragma unroll
-      for (int n = 0; n < NT; ++n) {
-        const int co = 16 * n + ml;
-        const float bias = A.bias ? A.bias[co] : 0.f;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const long long pix = (long long)b * npix + p0 + 16 * (mt + h) + 4 * (lane >> 4) + r;
-          float v = acc[h][n][r] + bias;
-          if (A.relu) v = fmaxf(v, 0.f);
-          if (A.mask && !((float)A.mask[pix * CH + co] > 0.f)) v = 0.f;
-          if (OUT == 1) {
-            if (co == 0) A.out32[pix] = v;
-          } else {
-            A.out[pix * CH + co] = (__bf16)v;
-            if (NT == 1) A.out[pix * CH + co + 16] = (__bf16)0.f;
+            for (int r = 0; r < 4; ++r) {
+              float v = acc[h][0][r] + bias;
+              if (A.relu) v = fmaxf(v, 0.f);
+              A.out32[pt + 4 * (lane >> 4) + r] = v;
+            }
           }
+        } else {
+#pragma unroll
+          for (int n = 0; n < NT; ++n) {
+            const int co = 16 * n + ml;
+            const float bias = A.bias ? A.bias[co] : 0.f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              float v = acc[h][n][r] + bias;
+              if (A.relu) v = fmaxf(v, 0.f);
+              tile[(4 * (lane >> 4) + r) * OROW + co] = (__bf16)v;
+            }
+          }
+          if (NT == 1) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tile[(4 * (lane >> 4) + r) * OROW + 16 + ml] = (__bf16)0.f;
+          }
+          wave_sync_lds();
+          // lane: pixel lane/4 of the tile, channels 8*(lane%4) .. +7
+          const int px = lane >> 2, c8 = 8 * (lane & 3);
+          bf16x8 v = *(const bf16x8*)&tile[px * OROW + c8];
+          const long long o = (pt + px) * CH + c8;
+          if (A.mask) {
+            const bf16x8 mk = ld8(A.mask + o);
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+              if (!((float)mk[c] > 0.f)) v[c] = (__bf16)0.f;
+          }
+          *(bf16x8*)(A.out + o) = v;
+          wave_sync_lds();   // the tile is rewritten by the next tile's epilogue
         }
       }
     }

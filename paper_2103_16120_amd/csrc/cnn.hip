@@ -309,12 +309,39 @@ static ConvArgs conv_args(const cnn_net* n, int batch) {
   A.ny = n->ny;
   A.log2nx = n->log2nx;
   A.batch = batch;
+  A.row_begin = 0;
+  A.row_end = n->ny;
+  A.pole_row = -1;
   return A;
 }
 
-static dim3 conv_grid(const cnn_net* n, int batch) {
-  const long long strips = (long long)n->nx * n->ny / 64;
-  return dim3((unsigned)((strips + WG_WAVES - 1) / WG_WAVES), batch);
+static dim3 conv_grid(const cnn_net* n, int batch, int rows) {
+  const long long strips = (long long)(n->nx / 64) * rows;
+  const long long per_wg = (long long)WG_WAVES * CONV_SPW;
+  return dim3((unsigned)((strips + per_wg - 1) / per_wg), batch);
+}
+
+// A over all rows; when the across-pole taps need their own weights
+// (A.wpole != A.w), the interior rows and each polar row are separate launches
+template <int NT, int OUT>
+static void launch_conv(const cnn_net* n, int batch, ConvArgs A, hipStream_t st) {
+  if (A.wpole == A.w) {
+    hipLaunchKernelGGL((k_conv<NT, OUT>), conv_grid(n, batch, n->ny), dim3(256), 0, st, A);
+    return;
+  }
+  if (n->ny > 2) {
+    ConvArgs I = A;
+    I.row_begin = 1;
+    I.row_end = n->ny - 1;
+    hipLaunchKernelGGL((k_conv<NT, OUT>), conv_grid(n, batch, n->ny - 2), dim3(256), 0, st, I);
+  }
+  for (int pr : {0, n->ny - 1}) {
+    ConvArgs P = A;
+    P.row_begin = pr;
+    P.row_end = pr + 1;
+    P.pole_row = pr;
+    hipLaunchKernelGGL((k_conv<NT, OUT>), conv_grid(n, batch, 1), dim3(256), 0, st, P);
+  }
 }
 
 // forward from act[0] (already packed) to y (float32 [B][npix])
@@ -329,11 +356,11 @@ int cnn_forward_packed(cnn_net* n, int batch, float* y, hipStream_t st, const in
     if (l < CNN_LAYERS - 1) {
       A.out = n->act[l + 1];
       A.relu = 1;
-      hipLaunchKernelGGL((k_conv<2, 0>), conv_grid(n, batch), dim3(256), 0, st, A);
+      launch_conv<2, 0>(n, batch, A, st);
     } else {
       A.out32 = y;
       A.relu = 0;
-      hipLaunchKernelGGL((k_conv<1, 1>), conv_grid(n, batch), dim3(256), 0, st, A);
+      launch_conv<1, 1>(n, batch, A, st);
     }
   }
   CHK(n, hipGetLastError());
@@ -404,7 +431,7 @@ static int backward(cnn_net* n, int batch, const float* dyv) {
     A.out = n->dbuf[cur ^ 1];
     A.mask = n->act[l];
     A.relu = 0;
-    hipLaunchKernelGGL((k_conv<2, 0>), conv_grid(n, batch), dim3(256), 0, n->stream, A);
+    launch_conv<2, 0>(n, batch, A, n->stream);
     cur ^= 1;
   }
   CHK(n, hipGetLastError());
