@@ -240,6 +240,55 @@ def test_warm_start_batch_all_widths(gpu_lib, precision):
             assert abs(rep.iterations - ores.iterations) <= 1, (nx, ny, rep.iterations, ores.iterations)
 
 
+@pytest.mark.parametrize("precision", [0, 3])
+def test_largest_grid_solve(gpu_lib, precision):
+    """The largest grid the library takes (1024 x 4096, 4.2 M points, polar
+    rows 9.6 m wide): too large for the oracle's GCR, so the GPU solution is
+    checked through the oracle's operator -- its true residual and r_0 --
+    which holds at any size."""
+    nx, ny, rtol = 1024, 4096, 1e-8
+    pr = problem(2, nx, ny, dt=600.0)
+    op = EllipticOperator(nx, ny, pr["depth"], 600.0)
+    rhs = op.apply(pr["x_true"])
+    s = make_solver(gpu_lib, [(nx, ny)], precision=precision, rtol=rtol, max_iters=200)
+    s.set_operator(0, pr["depth"], 600.0)
+    x = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    rep = s.solve([dev(rhs)], [x])[0]
+    print(f"\n{nx}x{ny} precision={precision}: status={rep.status} it={rep.iterations} "
+          f"true={rep.rel_res_true:.3e}")
+    r0 = np.linalg.norm(rhs)
+    assert rep.r0_norm == pytest.approx(r0, rel=1e-12)
+    true_res = np.linalg.norm(op.apply(host(x)) - rhs) / r0
+    assert rep.status == gpu_lib.OK and true_res <= rtol
+    assert rep.rel_res_true == pytest.approx(true_res, rel=1e-6, abs=1e-14)
+    err = np.linalg.norm(host(x) - pr["x_true"]) / np.linalg.norm(pr["x_true"])
+    assert err <= 1e-5
+
+
+def test_largest_batch_of_smallest_grids(gpu_lib):
+    """4096 members (the largest batch) of 8 x 4 grids, each with its own
+    depth field and time step, in one solve; sampled members vs the oracle."""
+    nx, ny, B = 8, 4, 4096
+    prs = [problem(2, nx, ny, instance=m, dt=300.0 + 900.0 * (m % 7) / 6) for m in range(B)]
+    s = make_solver(gpu_lib, [(nx, ny)] * B, rtol=1e-10, max_iters=100)
+    depth = [dev(p["depth"]) for p in prs]
+    s.set_operators(list(range(B)), depth, [p["dt"] for p in prs])
+    ops = {}
+    rhs = []
+    for m, p in enumerate(prs):
+        op = EllipticOperator(nx, ny, p["depth"], p["dt"])
+        ops[m] = op
+        rhs.append(dev(op.apply(p["x_true"])))
+    xs = [torch.zeros((ny, nx), dtype=torch.float64, device="cuda") for _ in range(B)]
+    reps = s.solve(rhs, xs)
+    assert all(r.status == gpu_lib.OK and r.rel_res_true <= 1e-10 for r in reps)
+    for m in (0, 1, 2047, 3000, 4095):
+        ores = gcr(ops[m], host(rhs[m]), rtol=1e-10, max_iters=100)
+        assert abs(reps[m].iterations - ores.iterations) <= 1, m
+        err = np.linalg.norm(host(xs[m]) - ores.x) / np.linalg.norm(ores.x)
+        assert err <= 1e-9, (m, err)
+
+
 def test_max_iters_reached(gpu_lib):
     pr = problem(1, 64, 32)
     op = EllipticOperator(64, 32, pr["depth"], 600.0)
