@@ -38,15 +38,18 @@ sys.path.insert(0, ROOT)
 # intermediate Q (float16 2 B / float64 8 B), float64 solution X = 8 B, one
 # float16 coefficient array C = 2 B (the 2.3% polar rows read float32 and are
 # counted at the float16 size), and the depth pools the operators form their
-# coefficients from on the fly (Phi* and H*: 2 x 4 B for the float32 operator,
-# 2 x 8 B for float64; the float64 row solves read Phi* only).  nu is the
-# position in the GCR(k) window (nu + 1 directions are combined).
-def pass_bytes(form):
+# coefficients from on the fly (Phi*, and H* = Phi* + H0 only with orography:
+# 4 B each for the float32 operator, 8 B for float64; the float64 row solves
+# read Phi* only).  nu is the position in the GCR(k) window (nu + 1 directions
+# are combined).
+def pass_bytes(form, flat=True):
     mixed = form == "mixed"
     V, Q, X = (4, 2, 8) if mixed else (8, 8, 8)
+    npool = 1 if flat else 2                   # Phi* (and H*)
     faces = 2 * 2 if mixed else 8              # A^xx, A^yy (float16) or Phi* (float64)
-    pre6 = 6 * 2 if mixed else 16              # six coefficient arrays or Phi*, H*
-    op = 8 if mixed else 16                    # operator inside the iteration: Phi*, H*
+    pre6 = 6 * 2 if mixed else 8 * npool       # six coefficient arrays or the float64 pools
+    op = 4 * npool if mixed else 8 * npool     # operator inside the iteration: the pools
+    res = 8 * npool                            # float64 residual: the float64 pools
     return {
         "update_sweep1": {
             "setup": V + faces + Q,                              # r -> q1
@@ -58,18 +61,18 @@ def pass_bytes(form):
             "iter": lambda nu: V + op + V + V * (nu + 1),        # e -> L e, with <L e, L p_l>
         },
         "orth": {"iter": lambda nu: 5 * V + 2 * V * (nu + 1)},   # e, Le, r, p_l, Lp_l -> p, Lp
-        "residual": {                                            # float64, coefficients from Phi*, H*
-            "init": X + 8 + 16 + V + X,                          # caller x, R -> r, pooled x
-            "restart": X + 8 + 16 + V + V,                       # x, R, L p_0 -> r
-            "final": X + 8 + 16 + X,                             # x, R -> caller x
+        "residual": {                                            # float64, coefficients from the pools
+            "init": X + 8 + res + V + X,                         # caller x, R -> r, pooled x
+            "restart": X + 8 + res + V + V,                      # x, R, L p_0 -> r
+            "final": X + 8 + res + X,                            # x, R -> caller x
         },
     }
 
 
-def step_bytes(form, iters, restarts, k, pts):
+def step_bytes(form, iters, restarts, k, pts, flat=True):
     """Algorithmic bytes per kernel kind for members that took `iters`
     iterations and `restarts` residual recomputations (arrays over members)."""
-    pb = pass_bytes(form)
+    pb = pass_bytes(form, flat)
     tot = {name: 0.0 for name in pb}
     for n, nr in zip(np.ravel(iters), np.ravel(restarts)):
         n, nr = int(n), int(nr)

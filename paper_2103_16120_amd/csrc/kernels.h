@@ -86,9 +86,10 @@ enum { FA_KE = 0, FA_FXX, FA_FXY, FA_GBX, FA_BLE, FA_BPE, FA_KN, FA_FYY, FA_FYX,
 template <typename T>
 struct FlyPools {
   const T* phi;               // Phi*, pooled
-  const T* hs;                // H* = Phi* + H0, pooled
+  const T* hs;                // H* = Phi* + H0, pooled (not written for members without orography)
   const T* fac;               // [rows][NFAC]
   const T* c;                 // Helmholtz coefficient per global row
+  const int* flat;            // per member: 1 without orography (H* = Phi*: only Phi* is read)
 };
 
 template <typename T>
@@ -127,21 +128,25 @@ struct CoefFly {
                                         T (&ayxn)[M], T (&byn)[M], T (&ays)[M], T (&ayxs)[M], T (&bys)[M]) const {
     const int l = R.lane, L = R.L;
     T pc[M], ps[M], pn[M], hc[M], hsr[M], hn[M];
+    const bool flat = P.flat[R.m] != 0;
     ldr<M>(P.phi + R.rc, l, L, pc);
-    ldr<M>(P.hs + R.rc, l, L, hc);
-    if (R.south) {
-      ldr<M>(P.phi + R.rc - R.nx, l, L, ps);
-      ldr<M>(P.hs + R.rc - R.nx, l, L, hsr);
+    if (R.south) ldr<M>(P.phi + R.rc - R.nx, l, L, ps);
+    else across_pole(pc, ps, l, L);
+    if (R.north) ldr<M>(P.phi + R.rc + R.nx, l, L, pn);
+    else across_pole(pc, pn, l, L);
+    if (flat) {   // H* = Phi* exactly
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        hc[k] = pc[k];
+        hsr[k] = ps[k];
+        hn[k] = pn[k];
+      }
     } else {
-      across_pole(pc, ps, l, L);
-      across_pole(hc, hsr, l, L);
-    }
-    if (R.north) {
-      ldr<M>(P.phi + R.rc + R.nx, l, L, pn);
-      ldr<M>(P.hs + R.rc + R.nx, l, L, hn);
-    } else {
-      across_pole(pc, pn, l, L);
-      across_pole(hc, hn, l, L);
+      ldr<M>(P.hs + R.rc, l, L, hc);
+      if (R.south) ldr<M>(P.hs + R.rc - R.nx, l, L, hsr);
+      else across_pole(hc, hsr, l, L);
+      if (R.north) ldr<M>(P.hs + R.rc + R.nx, l, L, hn);
+      else across_pole(hc, hn, l, L);
     }
     T pce[M], hce[M], hcw[M], hne[M], hnw[M], hse[M], hsw[M];
     east_of(pc, pce, l, L);
@@ -840,6 +845,7 @@ struct AssembleArgs {
   float* hs32;
   double* fac64;              // per global row: NFAC factors (float32: scaled by s)
   float* fac32;
+  int* flat;                  // per member: 1 without orography (the H* pools are then not written)
   int rows;                   // rows per workgroup (1..ASM_ROWS; the staged rows must fit the LDS)
 };
 
@@ -964,11 +970,13 @@ __global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
       if (polar) A.a32[k][o] = (float)(s * out[k]);
       A.a16[k][o16] = __float2half_rn((float)(s * out[k]));
     }
-    const double h1 = sh0[rs + c];
     A.phi64[o] = d1;
-    A.hs64[o] = h1;
     A.phi32[o] = (float)d1;
-    A.hs32[o] = (float)h1;
+    if (P.oro) {
+      const double h1 = sh0[rs + c];
+      A.hs64[o] = h1;
+      A.hs32[o] = (float)h1;
+    }
   }
   if (lane < NFAC) {   // latitude factors of the on-the-fly coefficients
     const double gb = P.b_terms ? 1.0 : 0.0, nf = north ? 1.0 : 0.0;
@@ -992,7 +1000,10 @@ __global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
     A.fac32[(long long)(G.row0 + j) * NFAC + lane] = (float)(scaled ? s * v : v);
   }
   if (lane == 0) {
-    if (j == 0) A.scale[P.member] = s;
+    if (j == 0) {
+      A.scale[P.member] = s;
+      A.flat[P.member] = P.oro ? 0 : 1;
+    }
     const double c = 2.0 * P.radius * P.radius * cs_c / P.dt;
     A.c64[G.row0 + j] = c;
     A.c32[G.row0 + j] = (float)(s * c);

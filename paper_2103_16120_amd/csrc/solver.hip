@@ -78,6 +78,7 @@ struct gcr_solver {
   double* hs64 = nullptr;
   float* phi32 = nullptr;
   float* hs32 = nullptr;
+  int* flat = nullptr;                // per member: no orography (H* = Phi*)
   double* fac64 = nullptr;           // [rows][NFAC] latitude factors
   float* fac32 = nullptr;
   double* x = nullptr;
@@ -219,8 +220,8 @@ static Fields make_fields(gcr_solver* s) {
     F.cmx.f[k] = s->a32[k];
   }
   F.cmx.c = s->c32;
-  F.fly64 = FlyPools<double>{s->phi64, s->hs64, s->fac64, s->c64};
-  F.fly32 = FlyPools<float>{s->phi32, s->hs32, s->fac32, s->c32};
+  F.fly64 = FlyPools<double>{s->phi64, s->hs64, s->fac64, s->c64, s->flat};
+  F.fly32 = FlyPools<float>{s->phi32, s->hs32, s->fac32, s->c32, s->flat};
   F.x = s->x;
   F.rhs = s->rhs;
   F.rhs_tab = s->ptr_rhs;
@@ -384,6 +385,7 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   s->hs64 = (double*)track(dalloc<double>(N, herr));
   s->phi32 = (float*)track(dalloc<float>(N, herr));
   s->hs32 = (float*)track(dalloc<float>(N, herr));
+  s->flat = (int*)track(dalloc<int>(P.batch, herr));
   s->fac64 = (double*)track(dalloc<double>((size_t)R * NFAC, herr));
   s->fac32 = (float*)track(dalloc<float>((size_t)R * NFAC, herr));
   s->x = (double*)track(dalloc<double>(N, herr));
@@ -432,6 +434,7 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
     herr = hipMemcpyAsync(s->rowmap, rowmap_h.data(), R * sizeof(int), hipMemcpyHostToDevice, s->stream);
   if (herr == hipSuccess) herr = hipMemsetAsync(s->state, 0, P.batch * sizeof(MemberState), s->stream);
   if (herr == hipSuccess) herr = hipMemsetAsync(s->part, 0, (size_t)R * NDOT * sizeof(double), s->stream);
+  if (herr == hipSuccess) herr = hipMemsetAsync(s->flat, 0, P.batch * sizeof(int), s->stream);
   for (int i = 0; i < 2 && herr == hipSuccess; ++i) herr = hipEventRecord(s->stage_ev[i], s->stream);
   if (herr == hipSuccess) herr = hipStreamSynchronize(s->stream);
   if (herr != hipSuccess) {
@@ -524,6 +527,7 @@ extern "C" int gcr_set_operators(gcr_solver* s, int32_t count, const int32_t* me
   A.hs32 = s->hs32;
   A.fac64 = s->fac64;
   A.fac32 = s->fac32;
+  A.flat = s->flat;
   bool any_oro = false;
   for (int t = 0; t < count; ++t) any_oro = any_oro || ops[t].orography;
   // rows per workgroup: as many as the staged rows (two halo rows, times two
