@@ -93,7 +93,9 @@ constexpr int WROW = CH + 8;
 constexpr int CONV_SPW = 4;              // strip groups per workgroup
 constexpr int OROW = CH + 8;             // padded pixel row of the output tile
 
-template <int NT, int OUT>
+// CIN: channels stored per input pixel (8 for the first layer's packed input,
+// whose channels beyond are zero and not stored; else CH).
+template <int NT, int OUT, int CIN>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs A) {
   __shared__ __attribute__((aligned(16))) __bf16 sw[TAPS * CH * WROW];
   __shared__ __attribute__((aligned(16))) __bf16 so[WG_WAVES][16 * OROW];
@@ -115,8 +117,9 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs A) {
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int b = blockIdx.y;
-  const __bf16* img = A.in + (long long)b * npix * CH;
+  const __bf16* img = A.in + (long long)b * npix * CIN;
   const int kq = 8 * (lane >> 4);          // channel block of this lane (A and B operands)
+  const bool kin = CIN == CH || kq < CIN;  // this lane's input channels are stored
   const int ml = lane & 15;
   __bf16* tile = so[wave];
 #pragma unroll 1
@@ -136,7 +139,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs A) {
           int jj, ii;
           bool ghost;
           sphere_src(j, i0 + 16 * (mt + h) + ml, dy, dx, A.nx, A.ny, jj, ii, ghost);
-          a[h][t] = ld8(img + ((long long)jj * A.nx + ii) * CH + kq);
+          a[h][t] = kin ? ld8(img + ((long long)jj * A.nx + ii) * CIN + kq) : bf16x8{};
         }
       }
       f32x4 acc[2][NT];
@@ -216,10 +219,11 @@ constexpr int WG_LD = WG_Q + 8;          // padded LDS row (16-byte aligned)
 constexpr int WG_PART = TAPS * CH * CH + CH;
 
 struct WgradArgs {
-  const __bf16* in;        // layer input [B][ny][nx][CH]
+  const __bf16* in;        // layer input [B][ny][nx][in_stride]
   const __bf16* dpre;      // gradient at the layer output before activation [B][ny][nx][CH]
   float* part;             // [nwaves][WG_PART]
   int nx, ny, log2nx, batch;
+  int in_stride;           // channels stored per input pixel (8 or CH; channels beyond are zero)
   int chunks;              // 32-pixel chunks per wave
   long long total_chunks;
 };
@@ -277,8 +281,9 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs A) {
       int jj, ii;
       bool ghost;
       sphere_src(j, i0 + ql, dy, dx, A.nx, A.ny, jj, ii, ghost);
-      const __bf16* src = A.in + ((long long)b * npix + (long long)jj * A.nx + ii) * CH + ch0;
-      const bf16x8 v0 = ld8(src), v1 = ld8(src + 8);
+      const __bf16* src = A.in + ((long long)b * npix + (long long)jj * A.nx + ii) * A.in_stride + ch0;
+      const bf16x8 v0 = ch0 < A.in_stride ? ld8(src) : bf16x8{};
+      const bf16x8 v1 = ch0 + 8 < A.in_stride ? ld8(src + 8) : bf16x8{};
       wave_sync_lds();   // previous tap's reads of sa are complete
 #pragma unroll
       for (int k = 0; k < 8; ++k) {

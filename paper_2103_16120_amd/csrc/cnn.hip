@@ -91,15 +91,14 @@ __global__ void k_pack_weights(PackW P) {
   if (t == 0 && c == 0) P.bias[l * CH + a] = a < co_n ? w[(long long)co_n * ci_n * 9 + a] : 0.f;
 }
 
-// NCHW float32 [B][c_in][ny][nx] -> NHWC bf16 [B][ny][nx][CH], one pixel
+// NCHW float32 [B][c_in][ny][nx] -> NHWC bf16 [B][ny][nx][stride], one pixel
 // (four 16-byte stores) per thread
-__global__ void k_pack_input(const float* in, __bf16* out, int c_in, long long npix, int batch) {
+__global__ void k_pack_input(const float* in, __bf16* out, int c_in, long long npix, int batch, int stride) {
   const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (k >= npix * batch) return;
   const long long b = k / npix, p = k % npix;
-  bf16x8* dst = (bf16x8*)(out + k * CH);
-#pragma unroll
-  for (int q = 0; q < CH / 8; ++q) {
+  bf16x8* dst = (bf16x8*)(out + k * stride);
+  for (int q = 0; q < stride / 8; ++q) {
     bf16x8 v;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
@@ -191,7 +190,7 @@ static int alloc_all(cnn_net* n) {
   A((void**)&n->wa, (size_t)CNN_LAYERS * TAPS * CH * CH * sizeof(__bf16));
   A((void**)&n->wp, (size_t)CNN_LAYERS * TAPS * CH * CH * sizeof(__bf16));
   A((void**)&n->bias, (size_t)CNN_LAYERS * CH * sizeof(float));
-  for (int l = 0; l < CNN_LAYERS; ++l) A((void**)&n->act[l], npix * CH * sizeof(__bf16));
+  for (int l = 0; l < CNN_LAYERS; ++l) A((void**)&n->act[l], npix * (l == 0 ? n->in_stride : CH) * sizeof(__bf16));
   A((void**)&n->dbuf[0], npix * CH * sizeof(__bf16));
   A((void**)&n->dbuf[1], npix * CH * sizeof(__bf16));
   A((void**)&n->y, npix * sizeof(float));
@@ -234,6 +233,7 @@ extern "C" int cnn_create(int32_t nx, int32_t ny, int32_t max_batch, int32_t c_i
   while ((1 << n->log2nx) < nx) ++n->log2nx;
   n->max_batch = max_batch;
   n->c_in = c_in;
+  n->in_stride = c_in <= 8 ? 8 : CH;
   n->stream = (hipStream_t)stream;
   n->nparams = cnn_param_count(c_in);
   int rc = alloc_all(n);
@@ -323,24 +323,24 @@ static dim3 conv_grid(const cnn_net* n, int batch, int rows) {
 
 // A over all rows; when the across-pole taps need their own weights
 // (A.wpole != A.w), the interior rows and each polar row are separate launches
-template <int NT, int OUT>
+template <int NT, int OUT, int CIN = CH>
 static void launch_conv(const cnn_net* n, int batch, ConvArgs A, hipStream_t st) {
   if (A.wpole == A.w) {
-    hipLaunchKernelGGL((k_conv<NT, OUT>), conv_grid(n, batch, n->ny), dim3(256), 0, st, A);
+    hipLaunchKernelGGL((k_conv<NT, OUT, CIN>), conv_grid(n, batch, n->ny), dim3(256), 0, st, A);
     return;
   }
   if (n->ny > 2) {
     ConvArgs I = A;
     I.row_begin = 1;
     I.row_end = n->ny - 1;
-    hipLaunchKernelGGL((k_conv<NT, OUT>), conv_grid(n, batch, n->ny - 2), dim3(256), 0, st, I);
+    hipLaunchKernelGGL((k_conv<NT, OUT, CIN>), conv_grid(n, batch, n->ny - 2), dim3(256), 0, st, I);
   }
   for (int pr : {0, n->ny - 1}) {
     ConvArgs P = A;
     P.row_begin = pr;
     P.row_end = pr + 1;
     P.pole_row = pr;
-    hipLaunchKernelGGL((k_conv<NT, OUT>), conv_grid(n, batch, 1), dim3(256), 0, st, P);
+    hipLaunchKernelGGL((k_conv<NT, OUT, CIN>), conv_grid(n, batch, 1), dim3(256), 0, st, P);
   }
 }
 
@@ -356,7 +356,8 @@ int cnn_forward_packed(cnn_net* n, int batch, float* y, hipStream_t st, const in
     if (l < CNN_LAYERS - 1) {
       A.out = n->act[l + 1];
       A.relu = 1;
-      launch_conv<2, 0>(n, batch, A, st);
+      if (l == 0 && n->in_stride == 8) launch_conv<2, 0, 8>(n, batch, A, st);
+      else launch_conv<2, 0>(n, batch, A, st);
     } else {
       A.out32 = y;
       A.relu = 0;
@@ -379,7 +380,7 @@ extern "C" int cnn_forward(cnn_net* n, int32_t batch, const float* in, float* ou
   if (!in || !out) return cfail(n, GCR_EINVAL, "NULL tensor");
   const long long npix = (long long)n->nx * n->ny;
   hipLaunchKernelGGL(k_pack_input, dim3((unsigned)((npix * batch + 255) / 256)), dim3(256), 0, n->stream, in,
-                     n->act[0], n->c_in, npix, batch);
+                     n->act[0], n->c_in, npix, batch, n->in_stride);
   return cnn_forward_packed(n, batch, out, n->stream);
 }
 
@@ -401,6 +402,7 @@ static int backward(cnn_net* n, int batch, const float* dyv) {
     // weight gradient of layer l: input act[l], gradient at its output dbuf[cur]
     WgradArgs W{};
     W.in = n->act[l];
+    W.in_stride = l == 0 ? n->in_stride : CH;
     W.dpre = n->dbuf[cur];
     W.part = n->wg_part;
     W.nx = n->nx;

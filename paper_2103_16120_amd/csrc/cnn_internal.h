@@ -29,8 +29,11 @@ struct cnn_net {
   __bf16* wp = nullptr;
   float* bias = nullptr;
   // activations [B][ny][nx][32] bf16: act[0] is the packed input, act[l] the
-  // input of layer l; two buffers for gradients flowing backwards
+  // input of layer l; two buffers for gradients flowing backwards.  The packed
+  // input holds in_stride channels per pixel: 8 when c_in <= 8 (the rest of
+  // the 32 the first layer's MFMA takes are zero, not stored), else 32.
   __bf16* act[5] = {};
+  int in_stride = 32;
   __bf16* dbuf[2] = {};
   float* y = nullptr;        // network output [B][ny][nx]
   float* dy = nullptr;       // loss gradient [B][ny][nx]

@@ -19,7 +19,8 @@ constexpr int LEARN_CIN = 3;
 struct LearnArgs {
   const void* r;         // residual in the form's vector type (pooled, row-interleaved)
   void* e;               // preconditioner output to correct (same type and layout)
-  __bf16* feat;          // network input [batch][ny][nx][32] (bf16, NHWC)
+  __bf16* feat;          // network input [batch][ny][nx][feat_stride] (bf16, NHWC)
+  int feat_stride;       // channels stored per pixel (8 or 32)
   const float* y;        // network output [batch][ny][nx]
   int use_part;          // sigma from the per-row <r,r> partials (1) or from r (0)
   int* active;           // [batch]: members corrected by this application (network input mask), or null
@@ -103,14 +104,9 @@ __global__ __launch_bounds__(WG) void k_learn_pack(Fields F, LearnArgs A) {
     v0[0] = (__bf16)(float)(rv[k] * fr);
     v0[1] = (__bf16)(float)(ev[k] * fe);
     v0[2] = cz;
-    bf16x8 zero;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) zero[c] = (__bf16)0.f;
-    bf16x8* dst = (bf16x8*)(A.feat + (row_pix + i) * CH);
+    bf16x8* dst = (bf16x8*)(A.feat + (row_pix + i) * A.feat_stride);
     dst[0] = v0;
-    dst[1] = zero;
-    dst[2] = zero;
-    dst[3] = zero;
+    for (int q = 1; q < A.feat_stride / 8; ++q) dst[q] = bf16x8{};
   }
 }
 

@@ -566,6 +566,7 @@ static void learned_correction(gcr_solver* s, const std::vector<RowClass>& cls, 
   A.r = F.r;
   A.e = F.e;
   A.feat = s->net->act[0];
+  A.feat_stride = s->net->in_stride;
   A.y = s->net->y;
   A.use_part = use_part;
   A.active = s->learn_active;

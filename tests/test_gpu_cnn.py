@@ -111,6 +111,23 @@ def test_forward_exact(gpu_lib, nx, ny, batch):
     net.close()
 
 
+@pytest.mark.parametrize("c_in", [8, 9, 32])
+def test_input_channel_counts_exact(gpu_lib, c_in):
+    """Inputs of up to 8 channels are stored 8 per pixel, more as 32: both
+    layouts, forward and every gradient, bit-exact on rounding-free data."""
+    nx, ny, batch = 64, 8, 2
+    params, x, dy, yref, gref = exact_case(nx, ny, batch, seed=100 + c_in, c_in=c_in)
+    net = gpu_lib.Network(nx, ny, batch, c_in)
+    net.set_params(E.flatten(params))
+    y = host(net.forward(dev(x, torch.float32)))
+    assert np.array_equal(y, yref), np.abs(y - yref).max()
+    g = E.unflatten(net.gradients(dev(x, torch.float32), dev(dy, torch.float32)), c_in)
+    for n, ((gw, gb), (rw, rb)) in enumerate(zip(g, gref)):
+        assert np.array_equal(gw, rw), (n, np.abs(gw - rw).max())
+        assert np.array_equal(gb, rb), (n, gb, rb)
+    net.close()
+
+
 @pytest.mark.parametrize("nx,ny,batch", GRIDS)
 def test_gradient_exact(gpu_lib, nx, ny, batch):
     params, x, dy, _, gref = exact_case(nx, ny, batch, seed=3 * nx + ny)
