@@ -252,6 +252,8 @@ struct Fields {
   int row_base;               // global row handled by wave 0 of workgroup 0
   int row_end;                // one past the last global row of the launch
   int ignore_done;            // process finished members too (stand-alone operator calls)
+  const int* morder;          // members in row order (control kernels: block b -> morder[q0 + b])
+  int q0;
   int learned;                // learned preconditioner active (fallback test at cycle ends)
   double fallback_ratio;      // required residual reduction per cycle with it
 };
@@ -1042,7 +1044,8 @@ __global__ void k_apply_increments(Fields F, long long total) {
 }
 
 // ---------------------------------------------------------------------------
-// control: one wave per member; sums the member's per-row partials in a
+// control: one wave per member (block b takes member morder[q0 + b], so a
+// launch can cover one group of members); sums the member's per-row partials in a
 // fixed order (deterministic) and updates the device-resident scalars.
 // ---------------------------------------------------------------------------
 // Sums of the slots [first, first + ns) (ns <= NS) of the member's per-row
@@ -1086,7 +1089,7 @@ enum { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_STAGNATED = 2, ST_FALLBACK = 3 };
 
 template <typename A>
 __global__ void k_ctrl_init(Fields F) {
-  const int m = blockIdx.x;
+  const int m = F.morder[F.q0 + blockIdx.x];
   const MemberGeom G = F.geom[m];
   const double rr = member_sum<double>(F, G, DOT_RR);
   if (threadIdx.x == 0) {
@@ -1111,7 +1114,7 @@ __global__ void k_ctrl_init(Fields F) {
 
 template <typename A>
 __global__ void k_ctrl_beta(Fields F, int slot) {
-  const int m = blockIdx.x;
+  const int m = F.morder[F.q0 + blockIdx.x];
   MemberState& S = F.state[m];
   if (S.done) return;
   const MemberGeom G = F.geom[m];
@@ -1133,7 +1136,7 @@ __global__ void k_ctrl_beta(Fields F, int slot) {
 // after step 3: exit test on the updated residual, then step-4 coefficients
 template <typename A>
 __global__ void k_ctrl_alpha(Fields F, int nl, Slots sl, int cycle_end, int min_iters, int max_iters, double rtol) {
-  const int m = blockIdx.x;
+  const int m = F.morder[F.q0 + blockIdx.x];
   MemberState& S = F.state[m];
   if (S.done) return;
   const MemberGeom G = F.geom[m];
@@ -1183,7 +1186,7 @@ __global__ void k_ctrl_alpha(Fields F, int nl, Slots sl, int cycle_end, int min_
 // after a float64 residual recomputation at a restart: replace ||r|| and beta
 template <typename A>
 __global__ void k_ctrl_restart(Fields F, int slot0) {
-  const int m = blockIdx.x;
+  const int m = F.morder[F.q0 + blockIdx.x];
   MemberState& S = F.state[m];
   if (S.done) return;
   const MemberGeom G = F.geom[m];
@@ -1204,7 +1207,7 @@ __global__ void k_ctrl_restart(Fields F, int slot0) {
 
 // final float64 true residual of every member
 __global__ void k_ctrl_true(Fields F) {
-  const int m = blockIdx.x;
+  const int m = F.morder[F.q0 + blockIdx.x];
   const MemberGeom G = F.geom[m];
   const double rr = member_sum<double>(F, G, DOT_RR);
   if (threadIdx.x == 0) F.state[m].rtrue = sqrt(rr);

@@ -9,6 +9,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
+#include <thread>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -49,6 +53,10 @@ T* dalloc(size_t n, hipError_t& err) {
 
 }  // namespace
 
+// Stream of the launches the calling thread enqueues: a group's stream inside
+// a solve, else the solver's stream.
+static thread_local hipStream_t t_stream = nullptr;
+
 struct gcr_solver {
   gcr_params prm{};
   std::vector<int> nx, ny;
@@ -60,6 +68,33 @@ struct gcr_solver {
   int nxmax = 0;
   std::vector<RowClass> classes;     // contiguous row ranges of equal points-per-lane
   hipStream_t stream = nullptr;
+  // Groups of members with rows contiguous in row order, each solved on a
+  // stream of its own, so that one group's kernel boundaries (the drain of
+  // the last waves, the start of the next kernel) overlap the others' work.
+  // Empty: the whole batch on `stream`.
+  struct Group {
+    int q0 = 0, q1 = 0;                // members morder[q0 .. q1)
+    std::vector<RowClass> classes;     // the group's rows
+    hipStream_t st = nullptr;
+    hipEvent_t cycle_ev[2] = {};
+    MemberState* ring[2] = {};         // pinned copies of the scalars after a cycle
+    hipEvent_t done_ev = nullptr;
+  };
+  std::vector<Group> groups;
+  std::vector<int> morder_h;         // members in row order
+  int* morder = nullptr;
+  hipEvent_t fork_ev = nullptr;
+  // one host thread per group beyond the first enqueues that group's work
+  // (one thread cannot enqueue four groups' launches as fast as the GPU runs them)
+  std::vector<std::thread> workers;
+  std::mutex mu;
+  std::condition_variable cv_job, cv_done;
+  std::function<int(int)> job;       // job(group) of the current solve
+  std::vector<int> job_rc;
+  long job_gen = 0;
+  int job_pending = 0;
+  bool quit = false;
+  std::mutex err_mu;
   int device = 0;
   std::string err;
 
@@ -129,11 +164,11 @@ struct gcr_solver {
     }
     if (ev_kind.size() < ev.size() / 2) ev_kind.resize(ev.size() / 2);
     ev_kind[ev_used / 2] = kind;
-    (void)hipEventRecord(ev[ev_used], stream);
+    (void)hipEventRecord(ev[ev_used], t_stream ? t_stream : stream);
   }
   void tm_end() {
     if (!timing) return;
-    (void)hipEventRecord(ev[ev_used + 1], stream);
+    (void)hipEventRecord(ev[ev_used + 1], t_stream ? t_stream : stream);
     ev_used += 2;
   }
   void tm_collect() {  // after a stream synchronisation
@@ -148,14 +183,22 @@ struct gcr_solver {
   }
 };
 
+static hipStream_t cur_stream(const gcr_solver* s) { return t_stream ? t_stream : s->stream; }
+static void worker_main(gcr_solver* s, int w);
+static void stop_workers(gcr_solver* s);
+
 static int fail(gcr_solver* s, int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
-  if (s) s->err = buf;
-  else g_create_error = buf;
+  if (s) {
+    std::lock_guard<std::mutex> lk(s->err_mu);
+    s->err = buf;
+  } else {
+    g_create_error = buf;
+  }
   return code;
 }
 
@@ -176,7 +219,7 @@ static int fail(gcr_solver* s, int code, const char* fmt, ...) {
 template <typename... KArgs, typename... Args>
 static void launch(gcr_solver* s, int kind, void (*kern)(KArgs...), dim3 grid, dim3 block, Args... args) {
   s->tm_begin(kind);
-  hipLaunchKernelGGL(kern, grid, block, 0, s->stream, args...);
+  hipLaunchKernelGGL(kern, grid, block, 0, cur_stream(s), args...);
   s->tm_end();
 }
 
@@ -226,6 +269,8 @@ static Fields make_fields(gcr_solver* s) {
   F.rhs = s->rhs;
   F.rhs_tab = s->ptr_rhs;
   F.x_tab = s->ptr_x;
+  F.morder = s->morder;
+  F.q0 = 0;
   F.r64 = s->r64;
   F.r = s->r;
   F.e = s->e;
@@ -265,8 +310,21 @@ extern "C" int gcr_default_params(gcr_params* p) {
 }
 
 static void free_all(gcr_solver* s) {
+  stop_workers(s);
   if (s->net) (void)cnn_destroy(s->net);
   s->net = nullptr;
+  for (auto& g : s->groups) {
+    if (g.st) (void)hipStreamSynchronize(g.st);
+    for (int i = 0; i < 2; ++i) {
+      if (g.ring[i]) (void)hipHostFree(g.ring[i]);
+      if (g.cycle_ev[i]) (void)hipEventDestroy(g.cycle_ev[i]);
+    }
+    if (g.done_ev) (void)hipEventDestroy(g.done_ev);
+    if (g.st && g.st != s->stream) (void)hipStreamDestroy(g.st);
+  }
+  s->groups.clear();
+  if (s->fork_ev) (void)hipEventDestroy(s->fork_ev);
+  s->fork_ev = nullptr;
   for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
   s->ev.clear();
   for (void* a : s->allocs)
@@ -288,6 +346,55 @@ static void free_all(gcr_solver* s) {
   s->ptr_stage = nullptr;
   s->state_h = nullptr;
   s->asm_stage = nullptr;
+}
+
+// Up to GROUPS_MAX groups of members, of about equal row counts, each with a
+// stream (group 0: the solver's own; the others: streams of the library,
+// default priority), two cycle events and two pinned rings.  Four streams in
+// all match the hardware queues a process gets by default, so no two groups
+// share one.  The learned preconditioner keeps one group: its network runs
+// over the whole batch at once.
+constexpr int GROUPS_MAX = 4;
+
+static hipError_t make_groups(gcr_solver* s) {
+  const int B = s->prm.batch;
+  const int G = s->prm.precond == GCR_PC_LEARNED ? 1 : std::min(GROUPS_MAX, B);
+  if (G < 2) return hipSuccess;
+  hipError_t e = hipEventCreateWithFlags(&s->fork_ev, hipEventDisableTiming);
+  int q = 0, row = 0;
+  for (int g = 0; g < G && e == hipSuccess; ++g) {
+    gcr_solver::Group grp;
+    grp.q0 = q;
+    const int r0 = row;
+    const long long target = (long long)s->rows * (g + 1) / G;
+    // at least one member per group, and leave one for each later group
+    while (q < B - (G - 1 - g) && (q == grp.q0 || row < target)) row += s->geom_h[s->morder_h[q++]].ny;
+    if (g == G - 1)
+      while (q < B) row += s->geom_h[s->morder_h[q++]].ny;
+    grp.q1 = q;
+    for (const RowClass& c : s->classes) {
+      const int b = std::max(c.row_begin, r0), en = std::min(c.row_end, row);
+      if (en > b) grp.classes.push_back(RowClass{c.log2m, b, en});
+    }
+    s->groups.push_back(grp);
+    gcr_solver::Group& gr = s->groups.back();
+    if (g == 0) gr.st = s->stream;
+    else e = hipStreamCreateWithFlags(&gr.st, hipStreamNonBlocking);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+      e = hipEventCreateWithFlags(&gr.cycle_ev[i], hipEventDisableTiming);
+      if (e == hipSuccess) e = hipHostMalloc((void**)&gr.ring[i], B * sizeof(MemberState), 0);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&gr.done_ev, hipEventDisableTiming);
+  }
+  if (e == hipSuccess) {
+    const int dev = s->device;
+    for (int w = 0; w + 1 < G; ++w)
+      s->workers.emplace_back([s, w, dev] {
+        (void)hipSetDevice(dev);
+        worker_main(s, w);
+      });
+  }
+  return e;
 }
 
 extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
@@ -355,6 +462,7 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
     c.row_end = s->rows;
     if (c.row_end > c.row_begin) s->classes.push_back(c);
   }
+  for (int r = 0; r < s->rows; r += s->geom_h[rowmap_h[r]].ny) s->morder_h.push_back(rowmap_h[r]);
 
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
@@ -372,6 +480,7 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   const size_t qsz = vsz;  // float16 intermediates (option 3) or Krylov-type ones (options 0-2)
   s->geom = (MemberGeom*)track(dalloc<MemberGeom>(P.batch, herr));
   s->rowmap = (int*)track(dalloc<int>(R, herr));
+  s->morder = (int*)track(dalloc<int>(P.batch, herr));
   s->state = (MemberState*)track(dalloc<MemberState>(P.batch, herr));
   s->part = (double*)track(dalloc<double>((size_t)R * NDOT, herr));
   s->scale = (double*)track(dalloc<double>(P.batch, herr));
@@ -432,6 +541,9 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   herr = hipMemcpyAsync(s->geom, s->geom_h.data(), P.batch * sizeof(MemberGeom), hipMemcpyHostToDevice, s->stream);
   if (herr == hipSuccess)
     herr = hipMemcpyAsync(s->rowmap, rowmap_h.data(), R * sizeof(int), hipMemcpyHostToDevice, s->stream);
+  if (herr == hipSuccess)
+    herr = hipMemcpyAsync(s->morder, s->morder_h.data(), P.batch * sizeof(int), hipMemcpyHostToDevice, s->stream);
+  if (herr == hipSuccess) herr = make_groups(s);
   if (herr == hipSuccess) herr = hipMemsetAsync(s->state, 0, P.batch * sizeof(MemberState), s->stream);
   if (herr == hipSuccess) herr = hipMemsetAsync(s->part, 0, (size_t)R * NDOT * sizeof(double), s->stream);
   if (herr == hipSuccess) herr = hipMemsetAsync(s->flat, 0, P.batch * sizeof(int), s->stream);
@@ -570,10 +682,10 @@ static void learned_correction(gcr_solver* s, const std::vector<RowClass>& cls, 
   A.y = s->net->y;
   A.use_part = use_part;
   A.active = s->learn_active;
-  KLAUNCH(s, KT_LEARNED, k_learn_sigma<P>, dim3(s->prm.batch), dim3(64), 0, s->stream, F, A, member0, count);
+  KLAUNCH(s, KT_LEARNED, k_learn_sigma<P>, dim3(s->prm.batch), dim3(64), 0, cur_stream(s), F, A, member0, count);
   ROWS_LAUNCH(s, cls, F, KT_LEARNED, k_learn_pack, P, A);
   s->tm_begin(KT_LEARNED);
-  (void)cnn_forward_packed(s->net, s->prm.batch, s->net->y, s->stream, s->learn_active);
+  (void)cnn_forward_packed(s->net, s->prm.batch, s->net->y, cur_stream(s), s->learn_active);
   s->tm_end();
   ROWS_LAUNCH(s, cls, F, KT_LEARNED, k_learn_apply, P, A);
 }
@@ -617,32 +729,39 @@ static void launch_precond(gcr_solver* s, const std::vector<RowClass>& cls, cons
   }
 }
 
-// The solve is enqueued one GCR cycle at a time.  After the k iterations of a
-// cycle (and, in the residual-replacement forms, the float64 restart) the
-// members' scalars are copied to pinned host memory and an event is
-// recorded.  Before waiting for that event the host already enqueues the
-// first iteration of the next cycle, so the GPU keeps working while the host
-// decides; members that have finished make every later kernel return at
-// once, so speculative work on converged members costs only empty launches.
+// The solve of one group of members is enqueued one GCR cycle at a time on
+// the group's stream.  After the k iterations of a cycle (and, in the
+// residual-replacement forms, the float64 restart) the members' scalars are
+// copied to pinned host memory and an event is recorded.  Before waiting for
+// that event the host already enqueues the first iteration of the next cycle,
+// so the GPU keeps working while the host decides; members that have finished
+// make every later kernel return at once, so speculative work on converged
+// members costs only empty launches.
 template <typename P>
-static int run_solve(gcr_solver* s) {
+static int run_group(gcr_solver* s, const gcr_solver::Group& g) {
   using A = typename P::A;
+  struct StreamScope {   // this thread's launches go to the group's stream
+    explicit StreamScope(hipStream_t st) { t_stream = st; }
+    ~StreamScope() { t_stream = nullptr; }
+  } scope(g.st);
   const int k = s->prm.k, B = s->prm.batch, maxit = s->prm.max_iters;
   Fields F = make_fields(s);
+  F.q0 = g.q0;
   const bool replace = s->prm.precision == GCR_MIXED_FP64DOT || s->prm.precision == GCR_MIXED_HALF_PC;
-  const dim3 ctl(B), wave(64);
+  const dim3 ctl(g.q1 - g.q0), wave(64);
+  const std::vector<RowClass>& cls = g.classes;
 
   // step 1: r_0 = L(x_0) - R (float64), p_0 = P^{-1}(r_0), L(p_0)
-  ROWS_LAUNCH(s, s->classes, F, KT_RESIDUAL, k_residual, P, 1, -1, 0, RES_X_IN | RES_RHS_TAB);
-  KLAUNCH(s, KT_CONTROL, k_ctrl_init<double>, ctl, wave, 0, s->stream, F);
+  ROWS_LAUNCH(s, cls, F, KT_RESIDUAL, k_residual, P, 1, -1, 0, RES_X_IN | RES_RHS_TAB);
+  KLAUNCH(s, KT_CONTROL, k_ctrl_init<double>, ctl, wave, 0, g.st, F);
   {
     Fields F0 = F;
     F0.e = s->p[0];   // p_0 = P^{-1}(r_0) written in place
-    launch_precond<P>(s, s->classes, F0, 0, 0);
+    launch_precond<P>(s, cls, F0, 0, 0);
   }
   Slots sl0{};
-  ROWS_LAUNCH(s, s->classes, F, KT_APPLY_L, k_apply_L, P, (const void*)s->p[0], s->lp[0], 1, 0, sl0);
-  KLAUNCH(s, KT_CONTROL, k_ctrl_beta<A>, ctl, wave, 0, s->stream, F, 0);
+  ROWS_LAUNCH(s, cls, F, KT_APPLY_L, k_apply_L, P, (const void*)s->p[0], s->lp[0], 1, 0, sl0);
+  KLAUNCH(s, KT_CONTROL, k_ctrl_beta<A>, ctl, wave, 0, g.st, F, 0);
   HIPCHK(s, hipGetLastError());
 
   // iteration `it` (1-based) at window position nu of a cycle whose p_0 sits
@@ -652,24 +771,24 @@ static int run_solve(gcr_solver* s) {
     for (int l = 0; l <= k; ++l) sl.s[l] = (base + l) % (k + 1);
     (void)it;
     // step 2 (+ first row solve of step 3)
-    launch_precond<P>(s, s->classes, F, 1, sl.s[nu]);
+    launch_precond<P>(s, cls, F, 1, sl.s[nu]);
     // step 3: L(e) with <L e, L p_l>, l = 0..nu
-    ROWS_LAUNCH(s, s->classes, F, KT_APPLY_L, k_apply_L, P, (const void*)s->e, s->le, 0, nu + 1, sl);
-    KLAUNCH(s, KT_CONTROL, k_ctrl_alpha<A>, ctl, wave, 0, s->stream, F, nu + 1, sl, nu == k - 1 ? 1 : 0,
+    ROWS_LAUNCH(s, cls, F, KT_APPLY_L, k_apply_L, P, (const void*)s->e, s->le, 0, nu + 1, sl);
+    KLAUNCH(s, KT_CONTROL, k_ctrl_alpha<A>, ctl, wave, 0, g.st, F, nu + 1, sl, nu == k - 1 ? 1 : 0,
             s->prm.min_iters, maxit, s->prm.rtol);
     // step 4
-    ROWS_LAUNCH(s, s->classes, F, KT_ORTH, k_orth, P, nu + 1, sl, sl.s[nu + 1]);
-    KLAUNCH(s, KT_CONTROL, k_ctrl_beta<A>, ctl, wave, 0, s->stream, F, sl.s[nu + 1]);
+    ROWS_LAUNCH(s, cls, F, KT_ORTH, k_orth, P, nu + 1, sl, sl.s[nu + 1]);
+    KLAUNCH(s, KT_CONTROL, k_ctrl_beta<A>, ctl, wave, 0, g.st, F, sl.s[nu + 1]);
   };
   // end of a cycle: (p_0, L p_0) := (p_k, L p_k); residual replacement; flags
   auto cycle_end = [&](int base_next, int ring) -> int {
     if (replace) {
-      ROWS_LAUNCH(s, s->classes, F, KT_RESIDUAL, k_residual, P, 1, base_next, 1, RES_RHS_TAB);
-      KLAUNCH(s, KT_CONTROL, k_ctrl_restart<double>, ctl, wave, 0, s->stream, F, base_next);
+      ROWS_LAUNCH(s, cls, F, KT_RESIDUAL, k_residual, P, 1, base_next, 1, RES_RHS_TAB);
+      KLAUNCH(s, KT_CONTROL, k_ctrl_restart<double>, ctl, wave, 0, g.st, F, base_next);
     }
-    HIPCHK(s, hipMemcpyAsync(s->state_ring[ring], s->state, B * sizeof(MemberState), hipMemcpyDeviceToHost,
-                             s->stream));
-    HIPCHK(s, hipEventRecord(s->cycle_ev[ring], s->stream));
+    // the whole array; only the group's own members are read from it
+    HIPCHK(s, hipMemcpyAsync(g.ring[ring], s->state, B * sizeof(MemberState), hipMemcpyDeviceToHost, g.st));
+    HIPCHK(s, hipEventRecord(g.cycle_ev[ring], g.st));
     return GCR_OK;
   };
 
@@ -683,24 +802,115 @@ static int run_solve(gcr_solver* s) {
     // speculative first iteration of the next cycle
     const bool more = it < maxit;
     if (more) iteration(++it, 0, base);
-    HIPCHK(s, hipEventSynchronize(s->cycle_ev[cycle & 1]));
-    bool all_done = true;
-    for (int m = 0; m < B; ++m) all_done = all_done && s->state_ring[cycle & 1][m].done;
-    if (all_done || !more) break;
+    HIPCHK(s, hipEventSynchronize(g.cycle_ev[cycle & 1]));
+    bool done = true;
+    for (int q = g.q0; q < g.q1; ++q) done = done && g.ring[cycle & 1][s->morder_h[q]].done;
+    if (done || !more) break;
     for (int nu = 1; nu < k && it < maxit; ++nu) iteration(++it, nu, base);
     base = (base + k) % (k + 1);
     ++cycle;
     if ((rc = cycle_end(base, cycle & 1)) != GCR_OK) return rc;
     HIPCHK(s, hipGetLastError());
   }
+  // true residual of the group's members in float64 (GCR_MIXED: after its
+  // increments are added, over the whole batch)
+  if (s->prm.precision != GCR_MIXED) {
+    ROWS_LAUNCH(s, cls, F, KT_RESIDUAL, k_residual, P, 0, -1, 0, RES_X_OUT | RES_RHS_TAB);
+    KLAUNCH(s, KT_CONTROL, k_ctrl_true, ctl, wave, 0, g.st, F);
+    HIPCHK(s, hipGetLastError());
+  }
+  return GCR_OK;
+}
+
+// Worker thread w enqueues group w + 1 of each solve.
+static void worker_main(gcr_solver* s, int w) {
+  long seen = 0;
+  for (;;) {
+    std::function<int(int)> job;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_job.wait(lk, [&] { return s->quit || s->job_gen != seen; });
+      if (s->quit) return;
+      seen = s->job_gen;
+      job = s->job;
+    }
+    const int rc = job(w + 1);
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->job_rc[w + 1] = rc;
+      if (--s->job_pending == 0) s->cv_done.notify_all();
+    }
+  }
+}
+
+static void stop_workers(gcr_solver* s) {
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->quit = true;
+  }
+  s->cv_job.notify_all();
+  for (std::thread& t : s->workers)
+    if (t.joinable()) t.join();
+  s->workers.clear();
+}
+
+// The whole solve: the groups (forked from the solver's stream, each enqueued
+// by its own host thread), joined back on the solver's stream.  Per-kernel
+// timing runs one group on the solver's stream (the timing events need one
+// stream and one thread).
+template <typename P>
+static int run_solve(gcr_solver* s) {
+  const int B = s->prm.batch;
+  const bool split = !s->groups.empty() && !s->timing;
+  if (!split) {
+    gcr_solver::Group whole;
+    whole.q0 = 0;
+    whole.q1 = B;
+    whole.classes = s->classes;
+    whole.st = s->stream;
+    for (int i = 0; i < 2; ++i) {
+      whole.cycle_ev[i] = s->cycle_ev[i];
+      whole.ring[i] = s->state_ring[i];
+    }
+    const int rc = run_group<P>(s, whole);
+    if (rc != GCR_OK) return rc;
+  } else {
+    HIPCHK(s, hipEventRecord(s->fork_ev, s->stream));
+    for (gcr_solver::Group& g : s->groups)
+      if (g.st != s->stream) HIPCHK(s, hipStreamWaitEvent(g.st, s->fork_ev, 0));
+    const int G = (int)s->groups.size();
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->job = [s](int gi) { return run_group<P>(s, s->groups[gi]); };
+      s->job_rc.assign(G, GCR_OK);
+      s->job_pending = G - 1;
+      ++s->job_gen;
+    }
+    s->cv_job.notify_all();
+    const int rc0 = run_group<P>(s, s->groups[0]);
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_done.wait(lk, [&] { return s->job_pending == 0; });
+    }
+    if (rc0 != GCR_OK) return rc0;
+    for (int gi = 1; gi < G; ++gi)
+      if (s->job_rc[gi] != GCR_OK) return s->job_rc[gi];
+    for (gcr_solver::Group& g : s->groups) {
+      if (g.st == s->stream) continue;
+      HIPCHK(s, hipEventRecord(g.done_ev, g.st));
+      HIPCHK(s, hipStreamWaitEvent(s->stream, g.done_ev, 0));
+    }
+  }
   if (s->prm.precision == GCR_MIXED) {
+    // float32 increments added to the solution, then the true residual
+    const Fields F = make_fields(s);
+    const dim3 ctl(B), wave(64);
     const dim3 g((unsigned)std::min<long long>((s->npts + 255) / 256, 65535));
     KLAUNCH(s, KT_COPY, k_apply_increments, g, dim3(256), 0, s->stream, F, s->npts);
+    ROWS_LAUNCH(s, s->classes, F, KT_RESIDUAL, k_residual, P, 0, -1, 0, RES_X_OUT | RES_RHS_TAB);
+    KLAUNCH(s, KT_CONTROL, k_ctrl_true, ctl, wave, 0, s->stream, F);
+    HIPCHK(s, hipGetLastError());
   }
-  // true residual of every member in float64
-  ROWS_LAUNCH(s, s->classes, F, KT_RESIDUAL, k_residual, P, 0, -1, 0, RES_X_OUT | RES_RHS_TAB);
-  KLAUNCH(s, KT_CONTROL, k_ctrl_true, ctl, wave, 0, s->stream, F);
-  HIPCHK(s, hipGetLastError());
   return GCR_OK;
 }
 
