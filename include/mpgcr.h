@@ -90,6 +90,10 @@ enum {
 
 /* flags */
 #define GCR_F_RECORD_HISTORY 0x1u  /* keep ||r_nu||/||r_0|| per iteration in reports  */
+#define GCR_F_ONE_STREAM 0x2u      /* solve the whole batch on the solver's stream; by
+                                      default a batch is split into up to four groups
+                                      of members solved on streams of the library,
+                                      forked from and joined back to that stream   */
 
 typedef struct {
   int32_t batch;          /* number of independent solves, 1..4096                    */

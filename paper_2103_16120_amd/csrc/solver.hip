@@ -348,29 +348,43 @@ static void free_all(gcr_solver* s) {
   s->asm_stage = nullptr;
 }
 
-// Up to GROUPS_MAX groups of members, of about equal row counts, each with a
-// stream (group 0: the solver's own; the others: streams of the library,
+// Up to GROUPS_MAX groups of members, of about equal point counts, each with
+// a stream (group 0: the solver's own; the others: streams of the library,
 // default priority), two cycle events and two pinned rings.  Four streams in
 // all match the hardware queues a process gets by default, so no two groups
-// share one.  The learned preconditioner keeps one group: its network runs
-// over the whole batch at once.
+// share one.  Every group launches each kernel once per row class it holds,
+// and the host enqueues a launch in a few microseconds whatever its size: the
+// batch is split only while each group keeps about GROUP_PTS points per
+// class and launch, below which the GPU would wait for the host.  The learned
+// preconditioner keeps one group: its network runs over the whole batch.
 constexpr int GROUPS_MAX = 4;
+constexpr long long GROUP_PTS = 1LL << 21;
 
 static hipError_t make_groups(gcr_solver* s) {
   const int B = s->prm.batch;
-  const int G = s->prm.precond == GCR_PC_LEARNED ? 1 : std::min(GROUPS_MAX, B);
+  long long total = 0;   // groups of about equal points
+  for (int m = 0; m < B; ++m) total += (long long)s->geom_h[m].nx * s->geom_h[m].ny;
+  const long long fit = total / (GROUP_PTS * (long long)s->classes.size());
+  int G = (int)std::min<long long>(std::min(GROUPS_MAX, B), std::max<long long>(fit, 1));
+  if (s->prm.precond == GCR_PC_LEARNED || (s->prm.flags & GCR_F_ONE_STREAM)) G = 1;
   if (G < 2) return hipSuccess;
   hipError_t e = hipEventCreateWithFlags(&s->fork_ev, hipEventDisableTiming);
   int q = 0, row = 0;
+  long long pts = 0;
   for (int g = 0; g < G && e == hipSuccess; ++g) {
     gcr_solver::Group grp;
     grp.q0 = q;
     const int r0 = row;
-    const long long target = (long long)s->rows * (g + 1) / G;
+    const long long target = total * (g + 1) / G;
     // at least one member per group, and leave one for each later group
-    while (q < B - (G - 1 - g) && (q == grp.q0 || row < target)) row += s->geom_h[s->morder_h[q++]].ny;
+    auto take = [&] {
+      const MemberGeom& M = s->geom_h[s->morder_h[q++]];
+      row += M.ny;
+      pts += (long long)M.nx * M.ny;
+    };
+    while (q < B - (G - 1 - g) && (q == grp.q0 || pts < target)) take();
     if (g == G - 1)
-      while (q < B) row += s->geom_h[s->morder_h[q++]].ny;
+      while (q < B) take();
     grp.q1 = q;
     for (const RowClass& c : s->classes) {
       const int b = std::max(c.row_begin, r0), en = std::min(c.row_end, row);
@@ -414,7 +428,8 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   if (P.min_iters < -1 || P.min_iters > P.max_iters) return fail(nullptr, GCR_EINVAL, "min_iters out of range");
   if (!(P.rtol >= 0.0) || !std::isfinite(P.rtol)) return fail(nullptr, GCR_EINVAL, "rtol must be finite and >= 0");
   if (P.polar_rows < -1) return fail(nullptr, GCR_EINVAL, "polar_rows must be >= -1");
-  if (P.flags & ~GCR_F_RECORD_HISTORY) return fail(nullptr, GCR_EINVAL, "unknown flags 0x%x", P.flags);
+  if (P.flags & ~(GCR_F_RECORD_HISTORY | GCR_F_ONE_STREAM))
+    return fail(nullptr, GCR_EINVAL, "unknown flags 0x%x", P.flags);
   for (int m = 0; m < P.batch; ++m) {
     const int nx = P.nx[m], ny = P.ny[m];
     if (!is_pow2(nx) || nx < 8 || nx > NXMAX)

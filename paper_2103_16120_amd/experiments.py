@@ -104,7 +104,7 @@ def batch(args):
     ref = None
     for name, prec in (("fp64", lib.FP64), ("mixed_half_pc", lib.MIXED_HALF_PC),
                        ("mixed_fp64dot", lib.MIXED_FP64DOT), ("mixed", lib.MIXED)):
-        s = lib.Solver(sizes, precision=prec, rtol=args.rtol, max_iters=100)
+        s = lib.Solver(sizes, precision=prec, rtol=args.rtol, max_iters=100, one_stream=args.one_stream)
         xs = [torch.zeros_like(r) for r in rhs]
 
         def step():
@@ -204,6 +204,7 @@ def main(argv=None):
     b.add_argument("--steps", type=int, default=5)
     b.add_argument("--warmup", type=int, default=1)
     b.add_argument("--rtol", type=float, default=1e-8)
+    b.add_argument("--one-stream", action="store_true", help="whole batch on one stream (no member groups)")
     q = sub.add_parser("sequence")
     q.add_argument("--nx", type=int, default=1024)
     q.add_argument("--ny", type=int, default=512)

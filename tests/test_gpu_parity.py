@@ -289,6 +289,36 @@ def test_largest_batch_of_smallest_grids(gpu_lib):
         assert err <= 1e-9, (m, err)
 
 
+@pytest.mark.parametrize("precision", [0, 3])
+def test_member_groups_equal_one_stream(gpu_lib, precision):
+    """A batch large enough to be split into member groups on four streams
+    (64 x 512x256) gives bitwise the solutions and reports of the same solve
+    on one stream, on every one of repeated solves."""
+    B, nx, ny = 64, 512, 256
+    prs = [problem(2, nx, ny, instance=m, dt=600.0) for m in range(B)]
+    depth = [dev(p["depth"]) for p in prs]
+    dts = [p["dt"] for p in prs]
+    f = make_solver(gpu_lib, [(nx, ny)] * B)
+    f.set_operators(list(range(B)), depth, dts)
+    rhs = [f.apply_operator(m, dev(p["x_true"])).clone() for m, p in enumerate(prs)]
+    f.close()
+    results = []
+    for one in (True, False):
+        s = make_solver(gpu_lib, [(nx, ny)] * B, precision=precision, one_stream=one)
+        s.set_operators(list(range(B)), depth, dts)
+        for rep_i in range(1 if one else 3):
+            xs = [torch.zeros((ny, nx), dtype=torch.float64, device="cuda") for _ in range(B)]
+            reps = s.solve(rhs, xs)
+            results.append(([host(x) for x in xs], [(r.status, r.iterations, r.restarts, r.rel_res_true)
+                                                    for r in reps]))
+        s.close()
+    ref_x, ref_r = results[0]
+    assert all(st == gpu_lib.OK for st, _, _, _ in ref_r)
+    for xs, rr in results[1:]:
+        assert rr == ref_r
+        assert all(np.array_equal(a, b) for a, b in zip(xs, ref_x))
+
+
 def test_max_iters_reached(gpu_lib):
     pr = problem(1, 64, 32)
     op = EllipticOperator(64, 32, pr["depth"], 600.0)
