@@ -92,8 +92,8 @@ struct FlyPools {
   const int* flat;            // per member: 1 without orography (H* = Phi*: only Phi* is read)
 };
 
-template <typename T>
-struct CoefFly {
+template <typename T, bool FLAT_ONLY = false>
+struct CoefFly {             // FLAT_ONLY: every member the launch covers has no orography
   FlyPools<T> P;
   __device__ __forceinline__ T helm(int g) const { return P.c[g]; }
   // A^xx east faces and A^yy north / south faces of row R (row solves)
@@ -262,10 +262,10 @@ struct Fields {
 // operator applied inside the Krylov iteration (`op`) or of the
 // preconditioner; polar rows always use float32 in the mixed forms.  The
 // choice is wave-uniform and made once per row.
-template <typename P, typename Fn>
+template <typename P, bool FL = false, typename Fn>
 __device__ __forceinline__ void with_coef(const Fields& F, const MemberGeom& G, int j, bool op, Fn&& fn) {
   if constexpr (!P::mixed) {
-    fn(CoefFly<double>{F.fly64});
+    fn(CoefFly<double, FL>{F.fly64});
   } else {
     const bool f32 = (op && P::op_f32) || (j < G.polar) || (j >= G.ny - G.polar);
     if (f32) fn(CoefRow<float, float>{F.cmx.f, F.cmx.c});
@@ -346,8 +346,129 @@ struct ScaledHalfReader {
 // Rows beyond the poles are the polar row seen across the pole.  The field
 // rows are held whole; the coefficients stream through per point.
 // ---------------------------------------------------------------------------
+template <bool A, typename X>
+__device__ __forceinline__ X& pick(X& a, X& b) {
+  if constexpr (A) return a;
+  else return b;
+}
+
+// The same stencil with the face coefficients formed point by point from the
+// depth rows (on-the-fly coefficients): the wave holds three rows of the field
+// and three of Phi* (and three of H* with orography) instead of nine
+// coefficient rows, which halves the registers of the float64 kernels.  The
+// per-point expressions are those of CoefFly::load9.  FLAT: H* = Phi*.
+template <typename T, int M, bool FLAT, typename CV, typename XR, typename Emit>
+__device__ __forceinline__ void stencil_row_fly(const RowCtx& R, const CV& cv, const XR& X, Emit&& emit) {
+  const int l = R.lane, L = R.L;
+  const int wl = (l - 1) & (L - 1), el = (l + 1) & (L - 1);
+  T xc[M], xs[M], xn[M];
+  X.row(R.rc, l, L, xc, R.g);
+  if (R.south) X.row(R.rc - R.nx, l, L, xs, R.g - 1);
+  if (R.north) X.row(R.rc + R.nx, l, L, xn, R.g + 1);
+  T pc[M], ps[M], pn[M], hc_[M], hs_[M], hn_[M];
+  const T* phi = cv.P.phi;
+  ldr<M>(phi + R.rc, l, L, pc);
+  if (R.south) ldr<M>(phi + R.rc - R.nx, l, L, ps);
+  if (R.north) ldr<M>(phi + R.rc + R.nx, l, L, pn);
+  if constexpr (!FLAT) {
+    const T* hp = cv.P.hs;
+    ldr<M>(hp + R.rc, l, L, hc_);
+    if (R.south) ldr<M>(hp + R.rc - R.nx, l, L, hs_);
+    if (R.north) ldr<M>(hp + R.rc + R.nx, l, L, hn_);
+  }
+  T(&hc)[M] = pick<FLAT>(pc, hc_);
+  T(&hs)[M] = pick<FLAT>(ps, hs_);
+  T(&hn)[M] = pick<FLAT>(pn, hn_);
+  if (!R.south) {
+    across_pole(xc, xs, l, L);
+    across_pole(pc, ps, l, L);
+    if constexpr (!FLAT) across_pole(hc_, hs_, l, L);
+  }
+  if (!R.north) {
+    across_pole(xc, xn, l, L);
+    across_pole(pc, pn, l, L);
+    if constexpr (!FLAT) across_pole(hc_, hn_, l, L);
+  }
+  // chunk-edge neighbours from the adjacent lanes
+  const T cw0 = shfl(xc[M - 1], wl), ceM = shfl(xc[0], el);
+  const T sw0 = shfl(xs[M - 1], wl), seM = shfl(xs[0], el);
+  const T nw0 = shfl(xn[M - 1], wl), neM = shfl(xn[0], el);
+  const T pw0 = shfl(pc[M - 1], wl), peM = shfl(pc[0], el);
+  T hcw0 = pw0, hceM = peM, hsw0, hseM, hnw0, hneM;
+  if constexpr (!FLAT) {
+    hcw0 = shfl(hc[M - 1], wl);
+    hceM = shfl(hc[0], el);
+  }
+  hsw0 = shfl(hs[M - 1], wl);
+  hseM = shfl(hs[0], el);
+  hnw0 = shfl(hn[M - 1], wl);
+  hneM = shfl(hn[0], el);
+  // values at chunk index i in -1 .. M (the ends from the adjacent lanes)
+  auto at = [](const T (&v)[M], int i, T w, T e) { return i < 0 ? w : (i >= M ? e : v[i]); };
+  const T* f = cv.P.fac + (long long)R.g * NFAC;
+  const T fKE = f[FA_KE], fXX = f[FA_FXX], fXY = f[FA_FXY], fGBX = f[FA_GBX], fBLE = f[FA_BLE], fBPE = f[FA_BPE];
+  const T fKN = f[FA_KN], fYY = f[FA_FYY], fYX = f[FA_FYX], fGBY = f[FA_GBY], fBLN = f[FA_BLN], fBPN = f[FA_BPN];
+  // the south face is the north face of row j-1; none at the south pole
+  const T* fs = cv.P.fac + (long long)(R.south ? R.g - 1 : R.g) * NFAC;
+  const T sKN = R.south ? fs[FA_KN] : (T)0, sYY = R.south ? fs[FA_FYY] : (T)0, sYX = R.south ? fs[FA_FYX] : (T)0;
+  const T sGBY = R.south ? fs[FA_GBY] : (T)0, sBLN = R.south ? fs[FA_BLN] : (T)0,
+          sBPN = R.south ? fs[FA_BPN] : (T)0;
+  // east face of chunk point i (i = -1: the west face of point 0)
+  auto east = [&](int i, T& axe, T& axy, T& bx) {
+    const T kap_e = fKE * (at(pc, i, pw0, peM) + at(pc, i + 1, pw0, peM));
+    axe = kap_e * fXX;
+    axy = kap_e * fXY;
+    bx = fGBX * (fBLE * (at(hc, i + 1, hcw0, hceM) - at(hc, i, hcw0, hceM)) +
+                 fBPE * ((at(hn, i, hnw0, hneM) - at(hs, i, hsw0, hseM)) +
+                         (at(hn, i + 1, hnw0, hneM) - at(hs, i + 1, hsw0, hseM))));
+  };
+  T axe_p, axy_p, bx_p;
+  east(-1, axe_p, axy_p, bx_p);
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    T axe, axy, bx;
+    east(k, axe, axy, bx);
+    const T hce = at(hc, k + 1, hcw0, hceM), hcw = at(hc, k - 1, hcw0, hceM);
+    const T kap_n = fKN * (pc[k] + pn[k]);
+    const T ayn = kap_n * fYY, ayxn = kap_n * fYX;
+    const T byn = fGBY * (fBLN * ((hce - hcw) + (at(hn, k + 1, hnw0, hneM) - at(hn, k - 1, hnw0, hneM))) +
+                          fBPN * (hn[k] - hc[k]));
+    const T kap_s = sKN * (ps[k] + pc[k]);
+    const T ays = kap_s * sYY, ayxs = kap_s * sYX;
+    const T bys = sGBY * (sBLN * ((at(hs, k + 1, hsw0, hseM) - at(hs, k - 1, hsw0, hseM)) + (hce - hcw)) +
+                          sBPN * (hc[k] - hs[k]));
+    const T c = xc[k], w = k > 0 ? xc[k - 1] : cw0, e = k < M - 1 ? xc[k + 1] : ceM;
+    const T sc = xs[k], sw = k > 0 ? xs[k - 1] : sw0, se = k < M - 1 ? xs[k + 1] : seM;
+    const T nc = xn[k], nw = k > 0 ? xn[k - 1] : nw0, ne = k < M - 1 ? xn[k + 1] : neM;
+    const T zon = axe * (e - c) - axe_p * (c - w);
+    T r = axy * ((nc - sc) + (ne - se)) - axy_p * ((nw - sw) + (nc - sc));
+    r += bx * (c + e) - bx_p * (w + c);
+    r += ayn * (nc - c) + ayxn * ((e - w) + (ne - nw)) + byn * (c + nc);
+    r -= ays * (c - sc) + ayxs * ((se - sw) + (e - w)) + bys * (sc + c);
+    emit(k, zon, r, c, axe, axe_p, ayn, ays);
+    axe_p = axe;
+    axy_p = axy;
+    bx_p = bx;
+  }
+}
+
+template <typename T>
+struct is_coef_fly : std::false_type {
+  static constexpr bool flat_only = false;
+};
+template <typename T, bool B>
+struct is_coef_fly<CoefFly<T, B>> : std::true_type {
+  static constexpr bool flat_only = B;
+};
+
 template <typename T, int M, typename CV, typename XR, typename Emit>
 __device__ __forceinline__ void stencil_row(const RowCtx& R, const CV& cv, const XR& X, Emit&& emit) {
+  if constexpr (is_coef_fly<CV>::value) {
+    if constexpr (is_coef_fly<CV>::flat_only) stencil_row_fly<T, M, true>(R, cv, X, emit);
+    else if (cv.P.flat[R.m] != 0) stencil_row_fly<T, M, true>(R, cv, X, emit);
+    else stencil_row_fly<T, M, false>(R, cv, X, emit);
+    return;
+  }
   const int l = R.lane, L = R.L;
   const int wl = (l - 1) & (L - 1), el = (l + 1) & (L - 1);
   T xc[M], xs[M], xn[M];
@@ -540,12 +661,12 @@ __global__ __launch_bounds__(WG) void k_update_sweep1(Fields F, int do_update, i
 //   q_out = T^{-1}( q_in + eta (P^M q_in - r) )
 // `qout` = -1 writes the final iterate to e.
 // ---------------------------------------------------------------------------
-template <typename P, int M>
+template <typename P, int M, bool FL>
 __device__ __forceinline__ void row_sweep2(const Fields& F, const RowCtx& R, const MemberGeom& G, int qin,
                                            int qout) {
   using T = typename P::T;
   using V = typename P::V;
-  with_coef<P>(F, G, R.j, false, [&](const auto& cv) {
+  with_coef<P, FL>(F, G, R.j, false, [&](const auto& cv) {
     const T helm = cv.helm(R.g);
     T rv[M];
     ldr<M>((const V*)F.r + R.rc, R.lane, R.L, rv);
@@ -570,12 +691,12 @@ __device__ __forceinline__ void row_sweep2(const Fields& F, const RowCtx& R, con
   });
 }
 
-template <typename P, int M>
+template <typename P, int M, bool FL>
 __global__ __launch_bounds__(WG) void k_sweep2(Fields F, int qin, int qout) {
   int g, m, lane, w;
   MemberGeom G;
   if (!wave_row(F, g, m, G, lane, w)) return;
-  row_sweep2<P, M>(F, make_row(G, m, g, lane, M), G, qin, qout);
+  row_sweep2<P, M, FL>(F, make_row(G, m, g, lane, M), G, qin, qout);
 }
 
 // ---------------------------------------------------------------------------
@@ -615,7 +736,7 @@ __global__ __launch_bounds__(WG) void k_update_simple(Fields F, int do_update, i
   row_update_simple<P, M>(F, make_row(G, m, g, lane, M), G, do_update, slot_nu, use_diag, qout);
 }
 
-template <typename P, int M>
+template <typename P, int M, bool FL>
 __device__ __forceinline__ void row_jacobi(const Fields& F, const RowCtx& R, const MemberGeom& G, int qin, int qout) {
   using T = typename P::T;
   using V = typename P::V;
@@ -623,7 +744,7 @@ __device__ __forceinline__ void row_jacobi(const Fields& F, const RowCtx& R, con
   // compiler copy all of F to the stack
   const V* qin_p = (const V*)F.q[qin];
   void* out_p = qout < 0 ? F.e : F.q[qout];
-  with_coef<P>(F, G, R.j, false, [&](const auto& cv) {
+  with_coef<P, FL>(F, G, R.j, false, [&](const auto& cv) {
     const T helm = cv.helm(R.g);
     RowReader<T, V> X{qin_p};
     T rv[M], d[M], o[M];
@@ -636,12 +757,12 @@ __device__ __forceinline__ void row_jacobi(const Fields& F, const RowCtx& R, con
   });
 }
 
-template <typename P, int M>
+template <typename P, int M, bool FL>
 __global__ __launch_bounds__(WG) void k_jacobi(Fields F, int qin, int qout) {
   int g, m, lane, w;
   MemberGeom G;
   if (!wave_row(F, g, m, G, lane, w)) return;
-  row_jacobi<P, M>(F, make_row(G, m, g, lane, M), G, qin, qout);
+  row_jacobi<P, M, FL>(F, make_row(G, m, g, lane, M), G, qin, qout);
 }
 
 // ---------------------------------------------------------------------------
@@ -654,7 +775,7 @@ struct Slots {
   int s[KMAX + 1];
 };
 
-template <typename P, int M>
+template <typename P, int M, bool FL>
 __device__ __forceinline__ void row_apply_L(const Fields& F, const RowCtx& R, const MemberGeom& G, const void* in,
                                             void* out, int mode, int nl, const Slots& sl) {
   using T = typename P::T;
@@ -693,17 +814,17 @@ __device__ __forceinline__ void row_apply_L(const Fields& F, const RowCtx& R, co
   };
   // float64 and float32 operators: coefficients from the depth fields;
   // float16 operator storage (the paper's mixed form): the stored arrays
-  if constexpr (!P::mixed) body(CoefFly<double>{F.fly64});
-  else if constexpr (P::op_f32) body(CoefFly<float>{F.fly32});
+  if constexpr (!P::mixed) body(CoefFly<double, FL>{F.fly64});
+  else if constexpr (P::op_f32) body(CoefFly<float, FL>{F.fly32});
   else with_coef<P>(F, G, R.j, true, body);
 }
 
-template <typename P, int M>
+template <typename P, int M, bool FL>
 __global__ __launch_bounds__(WG) void k_apply_L(Fields F, const void* in, void* out, int mode, int nl, Slots sl) {
   int g, m, lane, w;
   MemberGeom G;
   if (!wave_row(F, g, m, G, lane, w)) return;
-  row_apply_L<P, M>(F, make_row(G, m, g, lane, M), G, in, out, mode, nl, sl);
+  row_apply_L<P, M, FL>(F, make_row(G, m, g, lane, M), G, in, out, mode, nl, sl);
 }
 
 // ---------------------------------------------------------------------------
@@ -719,12 +840,12 @@ __global__ __launch_bounds__(WG) void k_apply_L(Fields F, const void* in, void* 
 // ---------------------------------------------------------------------------
 enum { RES_X_IN = 1, RES_X_OUT = 2, RES_RHS_TAB = 4 };
 
-template <typename P, int M>
+template <typename P, int M, bool FL>
 __device__ __forceinline__ void row_residual(const Fields& F, const RowCtx& R, const MemberGeom& G, int write_krylov,
                                              int lp_slot, int io) {
   using V = typename P::V;
   const int l = R.lane, L = R.L;
-  const CoefFly<double> cv{F.fly64};
+  const CoefFly<double, FL> cv{F.fly64};
   const double helm = cv.helm(R.g);
   const double s = P::mixed ? F.scale[R.m] : 1.0;
   const long long nat = R.rc - G.off;     // the row's offset in natural order
@@ -761,13 +882,13 @@ __device__ __forceinline__ void row_residual(const Fields& F, const RowCtx& R, c
   write_partial<double>(F, R, DOT_R_LP, R.act ? acc1 : 0.0);
 }
 
-template <typename P, int M>
+template <typename P, int M, bool FL>
 __global__ __launch_bounds__(WG) void k_residual(Fields F, int write_krylov, int lp_slot, int respect_done, int io) {
   int g, m, lane, w;
   MemberGeom G;
   const bool active = wave_row(F, g, m, G, lane, w);
   if (g >= F.row_end || (respect_done && !active)) return;
-  row_residual<P, M>(F, make_row(G, m, g, lane, M), G, write_krylov, lp_slot, io);
+  row_residual<P, M, FL>(F, make_row(G, m, g, lane, M), G, write_krylov, lp_slot, io);
 }
 
 // ---------------------------------------------------------------------------

@@ -38,6 +38,7 @@ thread_local std::string g_create_error;
 // and are processed by one kernel specialisation.
 struct RowClass {
   int log2m, row_begin, row_end;
+  int flat;   // every member of the range has no orography (set by refresh_flat)
 };
 
 namespace {
@@ -62,6 +63,7 @@ struct gcr_solver {
   std::vector<int> nx, ny;
   std::vector<MemberGeom> geom_h;
   std::vector<int> have_op;
+  std::vector<int> flat_h;            // per member: no orography (mirrors `flat` on the device)
   std::vector<double> scale_h;
   int rows = 0;
   long long npts = 0;
@@ -241,8 +243,29 @@ static void launch(gcr_solver* s, int kind, void (*kern)(KArgs...), dim3 grid, d
 
 static std::vector<RowClass> member_class(const gcr_solver* s, int member) {
   const MemberGeom& G = s->geom_h[member];
-  return {RowClass{G.log2m, G.row0, G.row0 + G.ny}};
+  return {RowClass{G.log2m, G.row0, G.row0 + G.ny, s->flat_h[member]}};
 }
+
+// As ROWS_LAUNCH, for the kernels that evaluate the stencil with coefficients
+// formed from the depth fields: a class whose members all lack orography takes
+// the variant that reads Phi* only (FL = true), which holds fewer registers.
+#define ROWS_LAUNCH_F(s, CLASSES, F, KIND, KNAME, P, ...)                                   \
+  for (const RowClass& c_ : (CLASSES)) {                                                 \
+    Fields f_ = (F);                                                                     \
+    f_.row_base = c_.row_begin;                                                          \
+    f_.row_end = c_.row_end;                                                             \
+    const dim3 g_((c_.row_end - c_.row_begin + WPB - 1) / WPB), b_(WG);                  \
+    switch (std::min(c_.log2m, 4) * 2 + (c_.flat ? 1 : 0)) {                             \
+      case 2: launch(s, KIND, &KNAME<P, 2, false>, g_, b_, f_, ##__VA_ARGS__); break;     \
+      case 3: launch(s, KIND, &KNAME<P, 2, true>, g_, b_, f_, ##__VA_ARGS__); break;      \
+      case 4: launch(s, KIND, &KNAME<P, 4, false>, g_, b_, f_, ##__VA_ARGS__); break;     \
+      case 5: launch(s, KIND, &KNAME<P, 4, true>, g_, b_, f_, ##__VA_ARGS__); break;      \
+      case 6: launch(s, KIND, &KNAME<P, 8, false>, g_, b_, f_, ##__VA_ARGS__); break;     \
+      case 7: launch(s, KIND, &KNAME<P, 8, true>, g_, b_, f_, ##__VA_ARGS__); break;      \
+      case 9: launch(s, KIND, &KNAME<P, 16, true>, g_, b_, f_, ##__VA_ARGS__); break;     \
+      default: launch(s, KIND, &KNAME<P, 16, false>, g_, b_, f_, ##__VA_ARGS__); break;   \
+    }                                                                                    \
+  }
 
 static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 static int ilog2(int v) {
@@ -411,6 +434,23 @@ static hipError_t make_groups(gcr_solver* s) {
   return e;
 }
 
+// Flat bits of the row classes (the solver's and each group's): a class is
+// flat when none of its members has orography.
+static void refresh_flat(gcr_solver* s) {
+  auto mark = [s](std::vector<RowClass>& cls) {
+    for (RowClass& c : cls) {
+      int all = 1;
+      for (int m : s->morder_h) {
+        const MemberGeom& G = s->geom_h[m];
+        if (G.row0 >= c.row_begin && G.row0 < c.row_end) all &= s->flat_h[m];
+      }
+      c.flat = all;
+    }
+  };
+  mark(s->classes);
+  for (gcr_solver::Group& g : s->groups) mark(g.classes);
+}
+
 extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   if (out) *out = nullptr;
   if (!prm || !out) return fail(nullptr, GCR_EINVAL, "gcr_create: NULL argument");
@@ -449,6 +489,7 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   s->nx.assign(P.nx, P.nx + P.batch);
   s->ny.assign(P.ny, P.ny + P.batch);
   s->have_op.assign(P.batch, 0);
+  s->flat_h.assign(P.batch, 0);
   s->scale_h.assign(P.batch, 1.0);
   for (int m = 0; m < P.batch; ++m) {
     MemberGeom G{};
@@ -669,7 +710,11 @@ extern "C" int gcr_set_operators(gcr_solver* s, int32_t count, const int32_t* me
   bool host_inputs = false;
   for (int t = 0; t < count; ++t) host_inputs = host_inputs || !ops[t].mem_is_device;
   if (host_inputs) HIPCHK(s, hipStreamSynchronize(s->stream));  // host arrays are read asynchronously
-  for (int t = 0; t < count; ++t) s->have_op[members[t]] = 1;
+  for (int t = 0; t < count; ++t) {
+    s->have_op[members[t]] = 1;
+    s->flat_h[members[t]] = s->asm_stage[t].oro ? 0 : 1;   // as k_assemble sets `flat`
+  }
+  refresh_flat(s);
   return GCR_OK;
 }
 
@@ -725,7 +770,7 @@ static void launch_precond(gcr_solver* s, const std::vector<RowClass>& cls, cons
       int cur = 0;
       for (int mu = 1; mu < ri; ++mu) {
         const int nxt = mu + 1 == ri ? -1 : cur ^ 1;
-        ROWS_LAUNCH(s, cls, F, KT_SWEEP2, k_jacobi, P, cur, nxt);
+        ROWS_LAUNCH_F(s, cls, F, KT_SWEEP2, k_jacobi, P, cur, nxt);
         cur ^= 1;
       }
       break;
@@ -735,7 +780,7 @@ static void launch_precond(gcr_solver* s, const std::vector<RowClass>& cls, cons
       int cur = 0;
       for (int mu = 1; mu < ri; ++mu) {
         const int nxt = mu + 1 == ri ? -1 : cur ^ 1;
-        ROWS_LAUNCH(s, cls, F, KT_SWEEP2, k_sweep2, P, cur, nxt);
+        ROWS_LAUNCH_F(s, cls, F, KT_SWEEP2, k_sweep2, P, cur, nxt);
         cur ^= 1;
       }
       if (s->prm.precond == GCR_PC_LEARNED && learned >= 0 && s->net)
@@ -767,7 +812,7 @@ static int run_group(gcr_solver* s, const gcr_solver::Group& g) {
   const std::vector<RowClass>& cls = g.classes;
 
   // step 1: r_0 = L(x_0) - R (float64), p_0 = P^{-1}(r_0), L(p_0)
-  ROWS_LAUNCH(s, cls, F, KT_RESIDUAL, k_residual, P, 1, -1, 0, RES_X_IN | RES_RHS_TAB);
+  ROWS_LAUNCH_F(s, cls, F, KT_RESIDUAL, k_residual, P, 1, -1, 0, RES_X_IN | RES_RHS_TAB);
   KLAUNCH(s, KT_CONTROL, k_ctrl_init<double>, ctl, wave, 0, g.st, F);
   {
     Fields F0 = F;
@@ -775,7 +820,7 @@ static int run_group(gcr_solver* s, const gcr_solver::Group& g) {
     launch_precond<P>(s, cls, F0, 0, 0);
   }
   Slots sl0{};
-  ROWS_LAUNCH(s, cls, F, KT_APPLY_L, k_apply_L, P, (const void*)s->p[0], s->lp[0], 1, 0, sl0);
+  ROWS_LAUNCH_F(s, cls, F, KT_APPLY_L, k_apply_L, P, (const void*)s->p[0], s->lp[0], 1, 0, sl0);
   KLAUNCH(s, KT_CONTROL, k_ctrl_beta<A>, ctl, wave, 0, g.st, F, 0);
   HIPCHK(s, hipGetLastError());
 
@@ -788,7 +833,7 @@ static int run_group(gcr_solver* s, const gcr_solver::Group& g) {
     // step 2 (+ first row solve of step 3)
     launch_precond<P>(s, cls, F, 1, sl.s[nu]);
     // step 3: L(e) with <L e, L p_l>, l = 0..nu
-    ROWS_LAUNCH(s, cls, F, KT_APPLY_L, k_apply_L, P, (const void*)s->e, s->le, 0, nu + 1, sl);
+    ROWS_LAUNCH_F(s, cls, F, KT_APPLY_L, k_apply_L, P, (const void*)s->e, s->le, 0, nu + 1, sl);
     KLAUNCH(s, KT_CONTROL, k_ctrl_alpha<A>, ctl, wave, 0, g.st, F, nu + 1, sl, nu == k - 1 ? 1 : 0,
             s->prm.min_iters, maxit, s->prm.rtol);
     // step 4
@@ -798,7 +843,7 @@ static int run_group(gcr_solver* s, const gcr_solver::Group& g) {
   // end of a cycle: (p_0, L p_0) := (p_k, L p_k); residual replacement; flags
   auto cycle_end = [&](int base_next, int ring) -> int {
     if (replace) {
-      ROWS_LAUNCH(s, cls, F, KT_RESIDUAL, k_residual, P, 1, base_next, 1, RES_RHS_TAB);
+      ROWS_LAUNCH_F(s, cls, F, KT_RESIDUAL, k_residual, P, 1, base_next, 1, RES_RHS_TAB);
       KLAUNCH(s, KT_CONTROL, k_ctrl_restart<double>, ctl, wave, 0, g.st, F, base_next);
     }
     // the whole array; only the group's own members are read from it
@@ -830,7 +875,7 @@ static int run_group(gcr_solver* s, const gcr_solver::Group& g) {
   // true residual of the group's members in float64 (GCR_MIXED: after its
   // increments are added, over the whole batch)
   if (s->prm.precision != GCR_MIXED) {
-    ROWS_LAUNCH(s, cls, F, KT_RESIDUAL, k_residual, P, 0, -1, 0, RES_X_OUT | RES_RHS_TAB);
+    ROWS_LAUNCH_F(s, cls, F, KT_RESIDUAL, k_residual, P, 0, -1, 0, RES_X_OUT | RES_RHS_TAB);
     KLAUNCH(s, KT_CONTROL, k_ctrl_true, ctl, wave, 0, g.st, F);
     HIPCHK(s, hipGetLastError());
   }
@@ -922,7 +967,7 @@ static int run_solve(gcr_solver* s) {
     const dim3 ctl(B), wave(64);
     const dim3 g((unsigned)std::min<long long>((s->npts + 255) / 256, 65535));
     KLAUNCH(s, KT_COPY, k_apply_increments, g, dim3(256), 0, s->stream, F, s->npts);
-    ROWS_LAUNCH(s, s->classes, F, KT_RESIDUAL, k_residual, P, 0, -1, 0, RES_X_OUT | RES_RHS_TAB);
+    ROWS_LAUNCH_F(s, s->classes, F, KT_RESIDUAL, k_residual, P, 0, -1, 0, RES_X_OUT | RES_RHS_TAB);
     KLAUNCH(s, KT_CONTROL, k_ctrl_true, ctl, wave, 0, s->stream, F);
     HIPCHK(s, hipGetLastError());
   }
@@ -1020,7 +1065,7 @@ extern "C" int gcr_apply_operator(gcr_solver* s, int32_t member, const double* x
   F.row_end = G.row0 + G.ny;
   F.ignore_done = 1;
   Slots sl{};
-  ROWS_LAUNCH(s, member_class(s, member), F, KT_APPLY_L, k_apply_L, PrecF64, (const void*)(s->x), (void*)s->r64, 2,
+  ROWS_LAUNCH_F(s, member_class(s, member), F, KT_APPLY_L, k_apply_L, PrecF64, (const void*)(s->x), (void*)s->r64, 2,
               0, sl);
   KLAUNCH(s, KT_COPY, k_from_pool, cg, dim3(256), 0, s->stream, (const double*)s->r64, y, G);
   HIPCHK(s, hipGetLastError());
@@ -1106,7 +1151,7 @@ extern "C" int gcr_learned_features(gcr_solver* s, int32_t member, const double*
   // r = L(x) - rhs and its <r,r> partials
   KLAUNCH(s, KT_COPY, k_to_pool, cg, dim3(256), 0, s->stream, x, s->x, G);
   KLAUNCH(s, KT_COPY, k_to_pool, cg, dim3(256), 0, s->stream, rhs, s->rhs, G);
-  ROWS_LAUNCH(s, cls, F, KT_RESIDUAL, k_residual, PrecF64, 2, -1, 0, 0);
+  ROWS_LAUNCH_F(s, cls, F, KT_RESIDUAL, k_residual, PrecF64, 2, -1, 0, 0);
   F.r = s->r64;
   LearnArgs A{};
   A.r = s->r64;

@@ -369,6 +369,36 @@ def test_batch_members_equal_solo_solves(gpu_lib, precision):
         assert np.linalg.norm(host(x1) - ores.x) / np.linalg.norm(ores.x) <= (1e-9 if precision == 0 else 1e-5)
 
 
+@pytest.mark.parametrize("precision", [0, 3])
+def test_orography_and_flat_members_in_one_class(gpu_lib, precision):
+    """Members with and without orography in one row class, then the same
+    solver after operators change between the two kinds: every solve must
+    match the oracle with each member's own operator (a class that is all
+    flat runs the kernels that read Phi* only)."""
+    nx, ny, n = 128, 64, 4
+    probs = [problem(2, nx, ny, instance=m, dt=400.0) for m in range(n)]
+    oros = [1500.0 * np.random.default_rng(90 + m).random((ny, nx)) for m in range(n)]
+    s = make_solver(gpu_lib, [(nx, ny)] * n, precision=precision)
+    tol = 1e-9 if precision == 0 else 1e-5
+    for kinds in ((0, 1, 0, 1), (0, 0, 0, 1), (0, 0, 0, 0), (1, 1, 1, 1)):
+        ops = []
+        for m, p in enumerate(probs):
+            oro = oros[m] if kinds[m] else None
+            s.set_operator(m, p["depth"], p["dt"], orography=oro)
+            ops.append(EllipticOperator(nx, ny, p["depth"], p["dt"], orography=oro))
+        rhs = [dev(op.apply(p["x_true"])) for op, p in zip(ops, probs)]
+        x = [torch.zeros((ny, nx), dtype=torch.float64, device="cuda") for _ in range(n)]
+        reps = s.solve(rhs, x)
+        for m in range(n):
+            assert reps[m].status == gpu_lib.OK, (kinds, m, reps[m])
+            ores = gcr(ops[m], host(rhs[m]), rtol=1e-8)
+            err = np.linalg.norm(host(x[m]) - ores.x) / np.linalg.norm(ores.x)
+            assert err <= tol, (kinds, m, err)
+            xt = probs[m]["x_true"]
+            y = host(s.apply_operator(m, dev(xt)))
+            assert np.all(np.abs(y - ops[m].apply(xt)) <= 32 * EPS * stencil_magnitude(ops[m], xt)), (kinds, m)
+
+
 def test_solve_is_deterministic(gpu_lib):
     pr = problem(2, 256, 128)
     op = EllipticOperator(256, 128, pr["depth"], 600.0)
