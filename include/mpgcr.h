@@ -214,7 +214,8 @@ enum {
   GCR_K_CONTROL = 6,    /* per-member scalar updates                                 */
   GCR_K_COPY = 7,       /* gather/scatter of caller fields                           */
   GCR_K_LEARNED = 8,    /* learned correction: features, five convolutions, update   */
-  GCR_K_COUNT = 9
+  GCR_K_SOLUTION = 9,   /* step-2 solution updates, applied once per GCR cycle       */
+  GCR_K_COUNT = 10
 };
 
 /* Enable (1) or disable (0) timing of every kernel the solver launches with

@@ -61,6 +61,14 @@ struct MemberState {
   int fallback, pad1, pad2, pad3;
 };
 
+// Step-2 solution updates of the current cycle not yet applied to x, per member.
+struct Pending {
+  double beta[KMAX];
+  int slot[KMAX];             // ring slots of their directions
+  int n;
+  int pad;
+};
+
 // Quotient a / b: exact in float64; in float32 (the mixed forms' row solves,
 // whose inputs are stored in float16) the hardware reciprocal, which is
 // within 1 ulp, times a.

@@ -12,7 +12,7 @@ namespace mpgcr {
 // kernel kinds for the optional per-kernel timing (values match the header)
 enum {
   KT_ASSEMBLE = 0, KT_RESIDUAL, KT_SWEEP1, KT_SWEEP2, KT_APPLY_L, KT_ORTH, KT_CONTROL, KT_COPY, KT_LEARNED,
-  KT_COUNT
+  KT_SOLUTION, KT_COUNT
 };
 
 // ---------------------------------------------------------------------------
@@ -229,6 +229,8 @@ struct Fields {
   const MemberGeom* geom;
   const int* rowmap;
   MemberState* state;
+  Pending* pend;              // per member: recorded step-2 updates (k_apply_pending)
+  int* done_flag;             // per member: copy of state.done, what the host polls
   double* part;               // [rows][NDOT] per-row partial inner products
   const double* scale;        // per member: mixed-form operator scale dt/(2 a^2)
   CoefMixed cmx;
@@ -578,7 +580,8 @@ __device__ __forceinline__ void write_partial(const Fields& F, const RowCtx& R, 
   if (R.lane == 0 && R.act) F.part[(long long)R.g * NDOT + slot] = (double)v;
 }
 
-// step 2 on one row: x += beta p_nu ; r += beta L p_nu ; returns r and <r,r>
+// step 2 on one row: r += beta L p_nu ; returns r and <r,r>.  The solution
+// update x += beta p_nu of the same step is deferred to k_apply_pending.
 template <typename P, int M>
 __device__ __forceinline__ typename P::A row_update(const Fields& F, const RowCtx& R, int slot_nu,
                                                     typename P::T (&rv)[M]) {
@@ -588,22 +591,8 @@ __device__ __forceinline__ typename P::A row_update(const Fields& F, const RowCt
   const int l = R.lane, L = R.L;
   const double beta = F.state[R.m].beta;
   V* r = (V*)F.r + R.rc;
-  T pv[M], lv[M];
-  ldr<M>((const V*)F.p[slot_nu] + R.rc, l, L, pv);
+  T lv[M];
   ldr<M>((const V*)F.lp[slot_nu] + R.rc, l, L, lv);
-  if (P::mixed && F.dx) {
-    float xv[M];
-    ldr<M>(F.dx + R.rc, l, L, xv);
-#pragma unroll
-    for (int k = 0; k < M; ++k) xv[k] += (float)beta * (float)pv[k];
-    if (R.act) str<M>(F.dx + R.rc, l, L, xv);
-  } else {
-    double xv[M];
-    ldr<M>(F.x + R.rc, l, L, xv);
-#pragma unroll
-    for (int k = 0; k < M; ++k) xv[k] += beta * (double)pv[k];
-    if (R.act) str<M>(F.x + R.rc, l, L, xv);
-  }
   A acc = (A)0;
 #pragma unroll
   for (int k = 0; k < M; ++k) {
@@ -615,8 +604,57 @@ __device__ __forceinline__ typename P::A row_update(const Fields& F, const RowCt
 }
 
 // ---------------------------------------------------------------------------
+// The solution updates of step 2, x += beta p_nu, deferred to the end of the
+// GCR cycle: k_ctrl_alpha records each update made (beta and the ring slot
+// of p_nu), and this pass applies the recorded ones before anything reads x
+// (the restart and final residuals) and before the ring slots are reused.
+// The float64 operations (GCR_MIXED: float32 increments) and their order are
+// those of updating at every iteration; x is read and written once per cycle
+// instead of once per iteration.  Finished members apply their last updates
+// too.
+// ---------------------------------------------------------------------------
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_apply_pending(Fields F) {
+  using T = typename P::T;
+  using V = typename P::V;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = F.row_base + xcd_block(blockIdx.x, gridDim.x) * WPB + w;
+  if (g >= F.row_end) return;
+  const int m = F.rowmap[g];
+  const Pending& S = F.pend[m];
+  const int n = S.n;
+  if (n == 0) return;
+  const RowCtx R = make_row(F.geom[m], m, g, lane, M);
+  const int l = R.lane, L = R.L;
+  if (P::mixed && F.dx) {
+    float xv[M];
+    ldr<M>(F.dx + R.rc, l, L, xv);
+    for (int i = 0; i < n; ++i) {
+      const double beta = S.beta[i];
+      T pv[M];
+      ldr<M>((const V*)F.p[S.slot[i]] + R.rc, l, L, pv);
+#pragma unroll
+      for (int k = 0; k < M; ++k) xv[k] += (float)beta * (float)pv[k];
+    }
+    if (R.act) str<M>(F.dx + R.rc, l, L, xv);
+  } else {
+    double xv[M];
+    ldr<M>(F.x + R.rc, l, L, xv);
+    for (int i = 0; i < n; ++i) {
+      const double beta = S.beta[i];
+      T pv[M];
+      ldr<M>((const V*)F.p[S.slot[i]] + R.rc, l, L, pv);
+#pragma unroll
+      for (int k = 0; k < M; ++k) xv[k] += beta * (double)pv[k];
+    }
+    if (R.act) str<M>(F.x + R.rc, l, L, xv);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // step 2 + first semi-implicit Richardson iteration (q_0 = 0, eq. P_Operator):
-//   (update)  x += beta p_nu ; r += beta L p_nu ; partial <r,r>
+//   (update)  r += beta L p_nu ; partial <r,r>  (x: k_apply_pending)
 //   q1 = T^{-1}(-eta r),  T = I - eta (P^Z - P^H)
 // `qout` = -1 writes the result to e (single Richardson iteration).
 // ---------------------------------------------------------------------------
@@ -1222,6 +1260,7 @@ __global__ void k_ctrl_init(Fields F) {
     S.restarts = 0;
     S.fallback = 0;
     S.beta = 0.0;
+    F.pend[m].n = 0;
     S.rtrue = -1.0;
     S.status = ST_NOT_CONVERGED;
     S.done = 0;
@@ -1230,6 +1269,7 @@ __global__ void k_ctrl_init(Fields F) {
       S.done = 1;
     }
     if (F.hist) F.hist[(long long)m * F.hist_stride] = 1.0;
+    F.done_flag[m] = S.done;
   }
 }
 
@@ -1249,6 +1289,7 @@ __global__ void k_ctrl_beta(Fields F, int slot) {
     if (!(lpsq > 0.0) || !isfinite(beta)) {
       S.status = ST_STAGNATED;
       S.done = 1;
+      F.done_flag[m] = 1;
     }
     S.beta = beta;
   }
@@ -1267,40 +1308,50 @@ __global__ void k_ctrl_alpha(Fields F, int nl, Slots sl, int cycle_end, int min_
   const double rr = d[0];
   const double* dots = d + 1;
   if (threadIdx.x == 0) {
-    S.it += 1;
-    const double rn = sqrt(rr);
-    S.rn = rn;
-    if (F.hist && S.it < F.hist_stride) F.hist[(long long)m * F.hist_stride + S.it] = rn / S.rho0;
-    if (!isfinite(rn)) {
-      S.status = ST_STAGNATED;
-      S.done = 1;
-      return;
-    }
-    if (S.it >= min_iters && rn <= rtol * S.rho0) {
-      S.status = S.fallback ? ST_FALLBACK : ST_OK;
-      S.done = 1;
-      return;
-    }
-    if (S.it >= max_iters) {
-      S.status = ST_NOT_CONVERGED;
-      S.done = 1;
-      return;
-    }
-    for (int l = 0; l < nl; ++l) S.alpha[l] = -dots[l] / S.lpsq[sl.s[l]];
-    if (cycle_end) {
-      // learned correction not reducing the residual enough: drop it
-      if (F.learned && !S.fallback && !(rn <= F.fallback_ratio * S.rn_cycle)) {
-        S.fallback = 1;
-        S.rn_cycle = rn;
-        return;
+    [&] {
+      // the step-2 update of this iteration was made: record it for x
+      Pending& pd = F.pend[m];
+      if (pd.n < KMAX) {
+        pd.beta[pd.n] = S.beta;
+        pd.slot[pd.n] = sl.s[nl - 1];
+        pd.n += 1;
       }
-      if (rn >= S.rn_cycle) {
+      S.it += 1;
+      const double rn = sqrt(rr);
+      S.rn = rn;
+      if (F.hist && S.it < F.hist_stride) F.hist[(long long)m * F.hist_stride + S.it] = rn / S.rho0;
+      if (!isfinite(rn)) {
         S.status = ST_STAGNATED;
         S.done = 1;
         return;
       }
-      S.rn_cycle = rn;
-    }
+      if (S.it >= min_iters && rn <= rtol * S.rho0) {
+        S.status = S.fallback ? ST_FALLBACK : ST_OK;
+        S.done = 1;
+        return;
+      }
+      if (S.it >= max_iters) {
+        S.status = ST_NOT_CONVERGED;
+        S.done = 1;
+        return;
+      }
+      for (int l = 0; l < nl; ++l) S.alpha[l] = -dots[l] / S.lpsq[sl.s[l]];
+      if (cycle_end) {
+        // learned correction not reducing the residual enough: drop it
+        if (F.learned && !S.fallback && !(rn <= F.fallback_ratio * S.rn_cycle)) {
+          S.fallback = 1;
+          S.rn_cycle = rn;
+          return;
+        }
+        if (rn >= S.rn_cycle) {
+          S.status = ST_STAGNATED;
+          S.done = 1;
+          return;
+        }
+        S.rn_cycle = rn;
+      }
+    }();
+    F.done_flag[m] = S.done;
   }
 }
 
@@ -1309,6 +1360,7 @@ template <typename A>
 __global__ void k_ctrl_restart(Fields F, int slot0) {
   const int m = F.morder[F.q0 + blockIdx.x];
   MemberState& S = F.state[m];
+  if (threadIdx.x == 0) F.pend[m].n = 0;   // applied by k_apply_pending before the residual
   if (S.done) return;
   const MemberGeom G = F.geom[m];
   const double rr = member_sum<double>(F, G, DOT_RR);
@@ -1321,9 +1373,15 @@ __global__ void k_ctrl_restart(Fields F, int slot0) {
     if (!isfinite(beta)) {
       S.status = ST_STAGNATED;
       S.done = 1;
+      F.done_flag[m] = 1;
     }
     S.beta = beta;
   }
+}
+
+// the recorded step-2 updates were applied (forms without a restart residual)
+__global__ void k_ctrl_applied(Fields F) {
+  if (threadIdx.x == 0) F.pend[F.morder[F.q0 + blockIdx.x]].n = 0;
 }
 
 // final float64 true residual of every member

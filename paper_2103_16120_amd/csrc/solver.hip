@@ -79,7 +79,7 @@ struct gcr_solver {
     std::vector<RowClass> classes;     // the group's rows
     hipStream_t st = nullptr;
     hipEvent_t cycle_ev[2] = {};
-    MemberState* ring[2] = {};         // pinned copies of the scalars after a cycle
+    int* ring[2] = {};                 // pinned copies of the done flags after a cycle
     hipEvent_t done_ev = nullptr;
   };
   std::vector<Group> groups;
@@ -105,6 +105,8 @@ struct gcr_solver {
   MemberGeom* geom = nullptr;
   int* rowmap = nullptr;
   MemberState* state = nullptr;
+  Pending* pend = nullptr;            // per member: recorded step-2 updates
+  int* done_flag = nullptr;           // per member: the done flag the host polls
   double* part = nullptr;
   double* scale = nullptr;
   float* a32[NCOEF] = {};
@@ -139,7 +141,7 @@ struct gcr_solver {
   double** ptr_x = nullptr;
   const void** ptr_stage = nullptr;  // pinned host staging for the tables
   MemberState* state_h = nullptr;    // pinned host copy
-  MemberState* state_ring[2] = {};   // pinned copies of the scalars after a cycle
+  int* state_ring[2] = {};           // pinned copies of the done flags after a cycle
   hipEvent_t cycle_ev[2] = {};       // recorded after each copy
   AsmMember* asm_stage = nullptr;    // pinned staging of the assembly table
   hipEvent_t stage_ev[2] = {};       // recorded after the uploads from ptr_stage / asm_stage
@@ -227,6 +229,8 @@ static void launch(gcr_solver* s, int kind, void (*kern)(KArgs...), dim3 grid, d
 
 // One launch of row kernel KNAME<P, M> per row class, each covering that
 // class's rows (one wave per row).
+static_assert(KT_COUNT == GCR_K_COUNT, "kernel kinds match the header");
+
 #define ROWS_LAUNCH(s, CLASSES, F, KIND, KNAME, P, ...)                                     \
   for (const RowClass& c_ : (CLASSES)) {                                                 \
     Fields f_ = (F);                                                                     \
@@ -279,6 +283,8 @@ static Fields make_fields(gcr_solver* s) {
   F.geom = s->geom;
   F.rowmap = s->rowmap;
   F.state = s->state;
+  F.pend = s->pend;
+  F.done_flag = s->done_flag;
   F.part = s->part;
   F.scale = s->scale;
   for (int k = 0; k < NCOEF; ++k) {
@@ -419,7 +425,7 @@ static hipError_t make_groups(gcr_solver* s) {
     else e = hipStreamCreateWithFlags(&gr.st, hipStreamNonBlocking);
     for (int i = 0; i < 2 && e == hipSuccess; ++i) {
       e = hipEventCreateWithFlags(&gr.cycle_ev[i], hipEventDisableTiming);
-      if (e == hipSuccess) e = hipHostMalloc((void**)&gr.ring[i], B * sizeof(MemberState), 0);
+      if (e == hipSuccess) e = hipHostMalloc((void**)&gr.ring[i], B * sizeof(int), 0);
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&gr.done_ev, hipEventDisableTiming);
   }
@@ -538,6 +544,8 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   s->rowmap = (int*)track(dalloc<int>(R, herr));
   s->morder = (int*)track(dalloc<int>(P.batch, herr));
   s->state = (MemberState*)track(dalloc<MemberState>(P.batch, herr));
+  s->pend = (Pending*)track(dalloc<Pending>(P.batch, herr));
+  s->done_flag = (int*)track(dalloc<int>(P.batch, herr));
   s->part = (double*)track(dalloc<double>((size_t)R * NDOT, herr));
   s->scale = (double*)track(dalloc<double>(P.batch, herr));
   for (int k = 0; k < NCOEF; ++k) {
@@ -584,7 +592,7 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   if (herr == hipSuccess) herr = hipHostMalloc((void**)&s->state_h, P.batch * sizeof(MemberState), 0);
   if (herr == hipSuccess) herr = hipHostMalloc((void**)&s->asm_stage, P.batch * sizeof(AsmMember), 0);
   for (int i = 0; i < 2 && herr == hipSuccess; ++i) {
-    herr = hipHostMalloc((void**)&s->state_ring[i], P.batch * sizeof(MemberState), 0);
+    herr = hipHostMalloc((void**)&s->state_ring[i], P.batch * sizeof(int), 0);
     if (herr == hipSuccess) herr = hipEventCreateWithFlags(&s->cycle_ev[i], hipEventDisableTiming);
     if (herr == hipSuccess) herr = hipEventCreateWithFlags(&s->stage_ev[i], hipEventDisableTiming);
   }
@@ -601,6 +609,8 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
     herr = hipMemcpyAsync(s->morder, s->morder_h.data(), P.batch * sizeof(int), hipMemcpyHostToDevice, s->stream);
   if (herr == hipSuccess) herr = make_groups(s);
   if (herr == hipSuccess) herr = hipMemsetAsync(s->state, 0, P.batch * sizeof(MemberState), s->stream);
+  if (herr == hipSuccess) herr = hipMemsetAsync(s->pend, 0, P.batch * sizeof(Pending), s->stream);
+  if (herr == hipSuccess) herr = hipMemsetAsync(s->done_flag, 0, P.batch * sizeof(int), s->stream);
   if (herr == hipSuccess) herr = hipMemsetAsync(s->part, 0, (size_t)R * NDOT * sizeof(double), s->stream);
   if (herr == hipSuccess) herr = hipMemsetAsync(s->flat, 0, P.batch * sizeof(int), s->stream);
   for (int i = 0; i < 2 && herr == hipSuccess; ++i) herr = hipEventRecord(s->stage_ev[i], s->stream);
@@ -840,14 +850,19 @@ static int run_group(gcr_solver* s, const gcr_solver::Group& g) {
     ROWS_LAUNCH(s, cls, F, KT_ORTH, k_orth, P, nu + 1, sl, sl.s[nu + 1]);
     KLAUNCH(s, KT_CONTROL, k_ctrl_beta<A>, ctl, wave, 0, g.st, F, sl.s[nu + 1]);
   };
-  // end of a cycle: (p_0, L p_0) := (p_k, L p_k); residual replacement; flags
+  // end of a cycle: the cycle's solution updates; (p_0, L p_0) := (p_k, L p_k);
+  // residual replacement; flags
   auto cycle_end = [&](int base_next, int ring) -> int {
+    ROWS_LAUNCH(s, cls, F, KT_SOLUTION, k_apply_pending, P);
     if (replace) {
       ROWS_LAUNCH_F(s, cls, F, KT_RESIDUAL, k_residual, P, 1, base_next, 1, RES_RHS_TAB);
       KLAUNCH(s, KT_CONTROL, k_ctrl_restart<double>, ctl, wave, 0, g.st, F, base_next);
+    } else {
+      KLAUNCH(s, KT_CONTROL, k_ctrl_applied, ctl, wave, 0, g.st, F);
     }
-    // the whole array; only the group's own members are read from it
-    HIPCHK(s, hipMemcpyAsync(g.ring[ring], s->state, B * sizeof(MemberState), hipMemcpyDeviceToHost, g.st));
+    // the done flags (a few bytes per member: a small copy); only the group's
+    // own members are read from them
+    HIPCHK(s, hipMemcpyAsync(g.ring[ring], s->done_flag, B * sizeof(int), hipMemcpyDeviceToHost, g.st));
     HIPCHK(s, hipEventRecord(g.cycle_ev[ring], g.st));
     return GCR_OK;
   };
@@ -864,7 +879,7 @@ static int run_group(gcr_solver* s, const gcr_solver::Group& g) {
     if (more) iteration(++it, 0, base);
     HIPCHK(s, hipEventSynchronize(g.cycle_ev[cycle & 1]));
     bool done = true;
-    for (int q = g.q0; q < g.q1; ++q) done = done && g.ring[cycle & 1][s->morder_h[q]].done;
+    for (int q = g.q0; q < g.q1; ++q) done = done && g.ring[cycle & 1][s->morder_h[q]] != 0;
     if (done || !more) break;
     for (int nu = 1; nu < k && it < maxit; ++nu) iteration(++it, nu, base);
     base = (base + k) % (k + 1);
@@ -872,8 +887,10 @@ static int run_group(gcr_solver* s, const gcr_solver::Group& g) {
     if ((rc = cycle_end(base, cycle & 1)) != GCR_OK) return rc;
     HIPCHK(s, hipGetLastError());
   }
-  // true residual of the group's members in float64 (GCR_MIXED: after its
-  // increments are added, over the whole batch)
+  // updates made after the last cycle end (none unless the iteration limit
+  // cut the loop), then the true residual of the group's members in float64
+  // (GCR_MIXED: after its increments are added, over the whole batch)
+  ROWS_LAUNCH(s, cls, F, KT_SOLUTION, k_apply_pending, P);
   if (s->prm.precision != GCR_MIXED) {
     ROWS_LAUNCH_F(s, cls, F, KT_RESIDUAL, k_residual, P, 0, -1, 0, RES_X_OUT | RES_RHS_TAB);
     KLAUNCH(s, KT_CONTROL, k_ctrl_true, ctl, wave, 0, g.st, F);
@@ -1231,7 +1248,7 @@ extern "C" int gcr_kernel_time(gcr_solver* s, int32_t kind, int64_t* launches, d
 }
 
 extern "C" const char* gcr_kernel_name(int32_t kind) {
-  static const char* names[KT_COUNT] = {"assemble", "residual", "update_sweep1", "sweep2", "apply_L",
-                                        "orth",     "control",  "copy",          "learned"};
+  static const char* names[KT_COUNT] = {"assemble", "residual", "update_sweep1", "sweep2",  "apply_L",
+                                        "orth",     "control",  "copy",          "learned", "solution"};
   return (kind >= 0 && kind < KT_COUNT) ? names[kind] : "unknown";
 }

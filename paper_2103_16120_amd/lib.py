@@ -85,8 +85,8 @@ _SIGNATURES = {
     "cnn_last_error": (C.c_char_p, [C.c_void_p]),
 }
 
-K_ASSEMBLE, K_RESIDUAL, K_SWEEP1, K_SWEEP2, K_APPLY_L, K_ORTH, K_CONTROL, K_COPY, K_LEARNED = range(9)
-K_COUNT = 9
+K_ASSEMBLE, K_RESIDUAL, K_SWEEP1, K_SWEEP2, K_APPLY_L, K_ORTH, K_CONTROL, K_COPY, K_LEARNED, K_SOLUTION = range(10)
+K_COUNT = 10
 LEARNED_CHANNELS = 3
 
 

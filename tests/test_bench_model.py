@@ -14,8 +14,10 @@ def test_mixed_form_six_iterations_one_restart():
     # GCR(3), 6 iterations (window positions 0,1,2,0,1,2), one restart, with
     # orography (both depth pools read)
     b = bench.step_bytes("mixed", np.array([[6]]), np.array([[1]]), 3, 1, flat=False)
-    # update+sweep1: setup r 4 + faces 4 -> q 2; iteration r,p,Lp 12 + x 8 + faces 4 -> x 8, r 4, q 2
-    assert b["update_sweep1"] == 10 + 6 * 38
+    # update+sweep1: setup r 4 + faces 4 -> q 2; iteration r, Lp 8 + faces 4 -> r 4, q 2
+    assert b["update_sweep1"] == 10 + 6 * 18
+    # solution updates at the two cycle ends: x 8 + three p 12 -> x 8
+    assert b["solution"] == 2 * 28
     # sweep2: q 2, r 4, six float16 arrays 12 -> e 4; setup + 6 iterations
     assert b["sweep2"] == 7 * 22
     # apply_L: setup 20; iteration 16 + 4 (nu + 1)
@@ -33,6 +35,8 @@ def test_fp64_form_and_member_sum():
     assert b1["sweep2"] == 10 * 5 * 40
     assert b1["orth"] == 10 * ((40 + 16) + (40 + 32) + (40 + 48))
     assert b1["residual"] == 10 * (48 + 40)
+    # 4 iterations: cycle ends after 3 updates and after 1 (x 16 + p 8 each)
+    assert b1["solution"] == 10 * ((16 + 24) + (16 + 8))
 
 
 def test_flat_surface_reads_one_depth_pool():
@@ -40,6 +44,6 @@ def test_flat_surface_reads_one_depth_pool():
     b = bench.step_bytes("mixed", np.array([[6]]), np.array([[1]]), 3, 1, flat=True)
     assert b["apply_L"] == 16 + 2 * (16 + 20 + 24)
     assert b["residual"] == 36 + 32 + 32
-    assert b["sweep2"] == 7 * 22 and b["update_sweep1"] == 10 + 6 * 38
+    assert b["sweep2"] == 7 * 22 and b["update_sweep1"] == 10 + 6 * 18
     b = bench.step_bytes("fp64", np.array([[4]]), np.array([[0]]), 3, 1, flat=True)
     assert b["sweep2"] == 5 * 32 and b["residual"] == 40 + 32
