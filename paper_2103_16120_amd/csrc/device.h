@@ -66,7 +66,7 @@ struct Pending {
   double beta[KMAX];
   int slot[KMAX];             // ring slots of their directions
   int n;
-  int pad;
+  int cycle;                  // the GCR cycle they belong to
 };
 
 // Quotient a / b: exact in float64; in float32 (the mixed forms' row solves,

@@ -606,15 +606,16 @@ __device__ __forceinline__ typename P::A row_update(const Fields& F, const RowCt
 // ---------------------------------------------------------------------------
 // The solution updates of step 2, x += beta p_nu, deferred to the end of the
 // GCR cycle: k_ctrl_alpha records each update made (beta and the ring slot
-// of p_nu), and this pass applies the recorded ones before anything reads x
-// (the restart and final residuals) and before the ring slots are reused.
+// of p_nu, stamped with the cycle), and this pass applies those of cycle
+// `cycle` before anything reads x (the restart and final residuals) and
+// before the ring slots are reused.
 // The float64 operations (GCR_MIXED: float32 increments) and their order are
 // those of updating at every iteration; x is read and written once per cycle
 // instead of once per iteration.  Finished members apply their last updates
 // too.
 // ---------------------------------------------------------------------------
 template <typename P, int M>
-__global__ __launch_bounds__(WG) void k_apply_pending(Fields F) {
+__global__ __launch_bounds__(WG) void k_apply_pending(Fields F, int cycle) {
   using T = typename P::T;
   using V = typename P::V;
   const int lane = threadIdx.x & 63;
@@ -623,7 +624,7 @@ __global__ __launch_bounds__(WG) void k_apply_pending(Fields F) {
   if (g >= F.row_end) return;
   const int m = F.rowmap[g];
   const Pending& S = F.pend[m];
-  const int n = S.n;
+  const int n = S.cycle == cycle ? S.n : 0;
   if (n == 0) return;
   const RowCtx R = make_row(F.geom[m], m, g, lane, M);
   const int l = R.lane, L = R.L;
@@ -1261,6 +1262,7 @@ __global__ void k_ctrl_init(Fields F) {
     S.fallback = 0;
     S.beta = 0.0;
     F.pend[m].n = 0;
+    F.pend[m].cycle = -1;
     S.rtrue = -1.0;
     S.status = ST_NOT_CONVERGED;
     S.done = 0;
@@ -1297,7 +1299,8 @@ __global__ void k_ctrl_beta(Fields F, int slot) {
 
 // after step 3: exit test on the updated residual, then step-4 coefficients
 template <typename A>
-__global__ void k_ctrl_alpha(Fields F, int nl, Slots sl, int cycle_end, int min_iters, int max_iters, double rtol) {
+__global__ void k_ctrl_alpha(Fields F, int nl, Slots sl, int cycle_end, int min_iters, int max_iters, double rtol,
+                             int cycle) {
   const int m = F.morder[F.q0 + blockIdx.x];
   MemberState& S = F.state[m];
   if (S.done) return;
@@ -1309,8 +1312,13 @@ __global__ void k_ctrl_alpha(Fields F, int nl, Slots sl, int cycle_end, int min_
   const double* dots = d + 1;
   if (threadIdx.x == 0) {
     [&] {
-      // the step-2 update of this iteration was made: record it for x
+      // the step-2 update of this iteration was made: record it for x (the
+      // first iteration of a cycle starts the cycle's list)
       Pending& pd = F.pend[m];
+      if (pd.cycle != cycle) {
+        pd.cycle = cycle;
+        pd.n = 0;
+      }
       if (pd.n < KMAX) {
         pd.beta[pd.n] = S.beta;
         pd.slot[pd.n] = sl.s[nl - 1];
@@ -1360,7 +1368,6 @@ template <typename A>
 __global__ void k_ctrl_restart(Fields F, int slot0) {
   const int m = F.morder[F.q0 + blockIdx.x];
   MemberState& S = F.state[m];
-  if (threadIdx.x == 0) F.pend[m].n = 0;   // applied by k_apply_pending before the residual
   if (S.done) return;
   const MemberGeom G = F.geom[m];
   const double rr = member_sum<double>(F, G, DOT_RR);
@@ -1377,11 +1384,6 @@ __global__ void k_ctrl_restart(Fields F, int slot0) {
     }
     S.beta = beta;
   }
-}
-
-// the recorded step-2 updates were applied (forms without a restart residual)
-__global__ void k_ctrl_applied(Fields F) {
-  if (threadIdx.x == 0) F.pend[F.morder[F.q0 + blockIdx.x]].n = 0;
 }
 
 // final float64 true residual of every member

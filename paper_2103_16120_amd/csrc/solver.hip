@@ -834,9 +834,9 @@ static int run_group(gcr_solver* s, const gcr_solver::Group& g) {
   KLAUNCH(s, KT_CONTROL, k_ctrl_beta<A>, ctl, wave, 0, g.st, F, 0);
   HIPCHK(s, hipGetLastError());
 
-  // iteration `it` (1-based) at window position nu of a cycle whose p_0 sits
-  // in ring slot `base`
-  auto iteration = [&](int it, int nu, int base) {
+  // iteration `it` (1-based) at window position nu of cycle `cyc`, whose p_0
+  // sits in ring slot `base`
+  auto iteration = [&](int it, int nu, int base, int cyc) {
     Slots sl{};
     for (int l = 0; l <= k; ++l) sl.s[l] = (base + l) % (k + 1);
     (void)it;
@@ -845,20 +845,18 @@ static int run_group(gcr_solver* s, const gcr_solver::Group& g) {
     // step 3: L(e) with <L e, L p_l>, l = 0..nu
     ROWS_LAUNCH_F(s, cls, F, KT_APPLY_L, k_apply_L, P, (const void*)s->e, s->le, 0, nu + 1, sl);
     KLAUNCH(s, KT_CONTROL, k_ctrl_alpha<A>, ctl, wave, 0, g.st, F, nu + 1, sl, nu == k - 1 ? 1 : 0,
-            s->prm.min_iters, maxit, s->prm.rtol);
+            s->prm.min_iters, maxit, s->prm.rtol, cyc);
     // step 4
     ROWS_LAUNCH(s, cls, F, KT_ORTH, k_orth, P, nu + 1, sl, sl.s[nu + 1]);
     KLAUNCH(s, KT_CONTROL, k_ctrl_beta<A>, ctl, wave, 0, g.st, F, sl.s[nu + 1]);
   };
-  // end of a cycle: the cycle's solution updates; (p_0, L p_0) := (p_k, L p_k);
+  // end of cycle `cyc`: its solution updates; (p_0, L p_0) := (p_k, L p_k);
   // residual replacement; flags
-  auto cycle_end = [&](int base_next, int ring) -> int {
-    ROWS_LAUNCH(s, cls, F, KT_SOLUTION, k_apply_pending, P);
+  auto cycle_end = [&](int base_next, int ring, int cyc) -> int {
+    ROWS_LAUNCH(s, cls, F, KT_SOLUTION, k_apply_pending, P, cyc);
     if (replace) {
       ROWS_LAUNCH_F(s, cls, F, KT_RESIDUAL, k_residual, P, 1, base_next, 1, RES_RHS_TAB);
       KLAUNCH(s, KT_CONTROL, k_ctrl_restart<double>, ctl, wave, 0, g.st, F, base_next);
-    } else {
-      KLAUNCH(s, KT_CONTROL, k_ctrl_applied, ctl, wave, 0, g.st, F);
     }
     // the done flags (a few bytes per member: a small copy); only the group's
     // own members are read from them
@@ -869,28 +867,28 @@ static int run_group(gcr_solver* s, const gcr_solver::Group& g) {
 
   int it = 0, base = 0, cycle = 0, rc;
   // cycle 0, complete
-  for (int nu = 0; nu < k && it < maxit; ++nu) iteration(++it, nu, base);
+  for (int nu = 0; nu < k && it < maxit; ++nu) iteration(++it, nu, base, 0);
   base = (base + k) % (k + 1);
-  if ((rc = cycle_end(base, 0)) != GCR_OK) return rc;
+  if ((rc = cycle_end(base, 0, 0)) != GCR_OK) return rc;
   HIPCHK(s, hipGetLastError());
   for (;;) {
     // speculative first iteration of the next cycle
     const bool more = it < maxit;
-    if (more) iteration(++it, 0, base);
+    if (more) iteration(++it, 0, base, cycle + 1);
     HIPCHK(s, hipEventSynchronize(g.cycle_ev[cycle & 1]));
     bool done = true;
     for (int q = g.q0; q < g.q1; ++q) done = done && g.ring[cycle & 1][s->morder_h[q]] != 0;
     if (done || !more) break;
-    for (int nu = 1; nu < k && it < maxit; ++nu) iteration(++it, nu, base);
+    for (int nu = 1; nu < k && it < maxit; ++nu) iteration(++it, nu, base, cycle + 1);
     base = (base + k) % (k + 1);
     ++cycle;
-    if ((rc = cycle_end(base, cycle & 1)) != GCR_OK) return rc;
+    if ((rc = cycle_end(base, cycle & 1, cycle)) != GCR_OK) return rc;
     HIPCHK(s, hipGetLastError());
   }
-  // updates made after the last cycle end (none unless the iteration limit
-  // cut the loop), then the true residual of the group's members in float64
-  // (GCR_MIXED: after its increments are added, over the whole batch)
-  ROWS_LAUNCH(s, cls, F, KT_SOLUTION, k_apply_pending, P);
+  // No update is pending here: the loop leaves right after a cycle end, or
+  // after a speculative iteration that every member skipped (all were done
+  // at that cycle end).  The true residual of the group's members in float64
+  // (GCR_MIXED: after its increments are added, over the whole batch):
   if (s->prm.precision != GCR_MIXED) {
     ROWS_LAUNCH_F(s, cls, F, KT_RESIDUAL, k_residual, P, 0, -1, 0, RES_X_OUT | RES_RHS_TAB);
     KLAUNCH(s, KT_CONTROL, k_ctrl_true, ctl, wave, 0, g.st, F);
