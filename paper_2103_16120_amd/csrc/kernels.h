@@ -1094,50 +1094,70 @@ __global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
   // the row just below the northern polar rows)
   const bool polar = j < G.polar || j >= ny - G.polar - 1;
   const long long rowoff = G.off + (long long)j * nx;
-  for (int slot = lane; slot < nx; slot += 64) {
-    const int i = (slot % Lr) * Mr + slot / Lr;   // natural column stored at this slot
-    const int c = lidx(i), ce = lidx((i + 1) & (nx - 1)), cw = lidx((i - 1) & (nx - 1));
-    const double d1 = sd0[rs + c];
-    double out[NCOEF];
-    {  // east face (i+1/2, j)
-      const double kap = ke * (d1 + sd0[rs + ce]);
-      out[C_AXX] = kap * fxx;
-      out[C_AXY] = kap * fxy;
-      double bx = 0.0;
-      if (P.b_terms) {
-        const double dhl = sh0[rs + ce] - sh0[rs + c];
-        const double dhp = (sh0[2 * rs + c] - sh0[c]) + (sh0[2 * rs + ce] - sh0[ce]);
-        bx = gbx * (bl_e * dhl + bp_e * dhp);
+  const int lL = G.log2nx - lm;   // Lr = 1 << lL lanes hold the row
+  // Each pass of a lane covers one element pair (k, k+1) of stored lane l:
+  // one 32-bit word of every float16 row, two elements of the others.
+  for (int pidx = lane; pidx < half; pidx += 64) {
+    const int l = pidx & (Lr - 1), kp = pidx >> lL;
+    double out[2][NCOEF], dv[2], hv[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = (l << lm) + 2 * kp + h;   // natural column of stored element (l, 2kp + h)
+      const int c = lidx(i), ce = lidx((i + 1) & (nx - 1)), cw = lidx((i - 1) & (nx - 1));
+      const double d1 = sd0[rs + c];
+      dv[h] = d1;
+      hv[h] = sh0[rs + c];
+      {  // east face (i+1/2, j)
+        const double kap = ke * (d1 + sd0[rs + ce]);
+        out[h][C_AXX] = kap * fxx;
+        out[h][C_AXY] = kap * fxy;
+        double bx = 0.0;
+        if (P.b_terms) {
+          const double dhl = sh0[rs + ce] - sh0[rs + c];
+          const double dhp = (sh0[2 * rs + c] - sh0[c]) + (sh0[2 * rs + ce] - sh0[ce]);
+          bx = gbx * (bl_e * dhl + bp_e * dhp);
+        }
+        out[h][C_BX] = bx;
       }
-      out[C_BX] = bx;
-    }
-    if (north) {  // north face (i, j+1/2)
-      const double kap = kn * (d1 + sd0[2 * rs + c]);
-      out[C_AYY] = kap * fyy;
-      out[C_AYX] = kap * fyx;
-      double by = 0.0;
-      if (P.b_terms) {
-        const double dhp = sh0[2 * rs + c] - sh0[rs + c];
-        const double dhl = (sh0[rs + ce] - sh0[rs + cw]) + (sh0[2 * rs + ce] - sh0[2 * rs + cw]);
-        by = gby * (bl_n * dhl + bp_n * dhp);
+      if (north) {  // north face (i, j+1/2)
+        const double kap = kn * (d1 + sd0[2 * rs + c]);
+        out[h][C_AYY] = kap * fyy;
+        out[h][C_AYX] = kap * fyx;
+        double by = 0.0;
+        if (P.b_terms) {
+          const double dhp = sh0[2 * rs + c] - sh0[rs + c];
+          const double dhl = (sh0[rs + ce] - sh0[rs + cw]) + (sh0[2 * rs + ce] - sh0[2 * rs + cw]);
+          by = gby * (bl_n * dhl + bp_n * dhp);
+        }
+        out[h][C_BY] = by;
+      } else {
+        out[h][C_AYY] = 0.0;
+        out[h][C_AYX] = 0.0;
+        out[h][C_BY] = 0.0;
       }
-      out[C_BY] = by;
-    } else {
-      out[C_AYY] = out[C_AYX] = out[C_BY] = 0.0;
     }
-    const long long o = rowoff + slot;
-    const long long o16 = rowoff + half_slot(slot % Lr, slot / Lr, Lr);   // float16 rows pair elements
+    const long long o0 = rowoff + ((long long)(2 * kp) << lL) + l, o1 = o0 + Lr;   // stored slots k*Lr + l
+    const long long o16 = rowoff + ((long long)kp << (lL + 1)) + 2 * l;            // the pair's word (in halves)
 #pragma unroll
     for (int k = 0; k < NCOEF; ++k) {
-      if (polar) A.a32[k][o] = (float)(s * out[k]);
-      A.a16[k][o16] = __float2half_rn((float)(s * out[k]));
+      const float v0 = (float)(s * out[0][k]), v1 = (float)(s * out[1][k]);
+      if (polar) {
+        A.a32[k][o0] = v0;
+        A.a32[k][o1] = v1;
+      }
+      const unsigned lo = __builtin_bit_cast(unsigned short, __float2half_rn(v0));
+      const unsigned hi = __builtin_bit_cast(unsigned short, __float2half_rn(v1));
+      *(unsigned*)(A.a16[k] + o16) = lo | (hi << 16);
     }
-    A.phi64[o] = d1;
-    A.phi32[o] = (float)d1;
+    A.phi64[o0] = dv[0];
+    A.phi64[o1] = dv[1];
+    A.phi32[o0] = (float)dv[0];
+    A.phi32[o1] = (float)dv[1];
     if (P.oro) {
-      const double h1 = sh0[rs + c];
-      A.hs64[o] = h1;
-      A.hs32[o] = (float)h1;
+      A.hs64[o0] = hv[0];
+      A.hs64[o1] = hv[1];
+      A.hs32[o0] = (float)hv[0];
+      A.hs32[o1] = (float)hv[1];
     }
   }
   if (lane < NFAC) {   // latitude factors of the on-the-fly coefficients
