@@ -3,6 +3,8 @@
     python -m paper_2103_16120_amd.experiments single     # one solve (64x32 at 1e-10, 256x128 at 1e-8)
     python -m paper_2103_16120_amd.experiments batch      # 64 members of uneven grids
     python -m paper_2103_16120_amd.experiments sequence   # 200 warm-started solves at 1024x512
+    python -m paper_2103_16120_amd.experiments precond    # preconditioner options 0-3, Richardson count
+    python -m paper_2103_16120_amd.experiments polar      # float32 polar-band width in the mixed forms
 
 single: one member of the configuration family (depth 8000 m + 500 m x
 degree<=8 harmonics, dt 600 s, R = L(degree<=12 field)), 64x32 solved to 1e-10
@@ -22,6 +24,17 @@ warm-started from the previous solution.  Plain float64, the mixed
 half-precision-preconditioner form, and the mixed form with the learned
 preconditioner; total wall time (assembly + solve) and the iteration
 histogram.
+
+precond: the benchmark batch (64 x 512x256, dt 600 s, rtol 1e-8) with each
+preconditioner of paper Section 2.3 -- option 0 (none), 1 (diagonal of L),
+2 (diagonally preconditioned explicit Richardson on L), 3 (semi-implicit
+Richardson, eq. P_Operator) -- and 1 to 4 Richardson iterations for options
+2 and 3; float64 form, and option 3 in the mixed half-precision-
+preconditioner form.  Iterations relative to option 0 and the time per step.
+
+polar: the benchmark batch in the three mixed forms with 0 to 8 rows per pole
+kept in float32 (float16 elsewhere): iterations, the float64 true residual
+and the distance to the float64 solution.
 """
 from __future__ import annotations
 
@@ -136,6 +149,94 @@ def batch(args):
     print(json.dumps(out), flush=True)
 
 
+def _bench_batch(torch, lib, count):
+    from workloads import problem
+    probs = [problem(2, 512, 256, instance=m, dt=600.0) for m in range(count)]
+    depth = [torch.from_numpy(p["depth"]).cuda() for p in probs]
+    f = lib.Solver([(512, 256)] * count, precision=lib.FP64)
+    f.set_operators(list(range(count)), depth, [p["dt"] for p in probs])
+    rhs = [f.apply_operator(m, torch.from_numpy(p["x_true"]).cuda()) for m, p in enumerate(probs)]
+    torch.cuda.synchronize()
+    f.close()
+    return probs, depth, rhs
+
+
+def _time_solver(torch, s, probs, depth, rhs, steps, warmup):
+    # one buffer for all solutions: the zero initial guess is one fill
+    X = torch.zeros((len(rhs),) + tuple(rhs[0].shape), dtype=rhs[0].dtype, device=rhs[0].device)
+    xs = [X[m] for m in range(len(rhs))]
+
+    def step():
+        s.set_operators(list(range(len(probs))), depth, [p["dt"] for p in probs])
+        X.zero_()
+        return s.solve(rhs, xs)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        reps = step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, reps, xs
+
+
+def precond(args):
+    torch, lib = _lib()
+    probs, depth, rhs = _bench_batch(torch, lib, args.count)
+    out = {"workload": f"{args.count} x 512x256, dt 600 s, rtol {args.rtol:g}, GCR(3), max {args.max_iters} iterations",
+           "cases": []}
+    cases = [("fp64", lib.FP64, 0, 1), ("fp64", lib.FP64, 1, 1)]
+    cases += [("fp64", lib.FP64, 2, r) for r in (1, 2, 3, 4)]
+    cases += [("fp64", lib.FP64, 3, r) for r in (1, 2, 3, 4)]
+    cases += [("mixed_half_pc", lib.MIXED_HALF_PC, 3, r) for r in (1, 2, 3, 4)]
+    base = None
+    for form, prec, opt, ri in cases:
+        s = lib.Solver([(512, 256)] * args.count, precision=prec, precond=opt, richardson_iters=ri,
+                       rtol=args.rtol, max_iters=args.max_iters)
+        dt, reps, _ = _time_solver(torch, s, probs, depth, rhs, args.steps, args.warmup)
+        s.close()
+        its = [r.iterations for r in reps]
+        if base is None:
+            base = float(np.mean(its))
+        rec = {"form": form, "option": opt, "richardson_iters": ri if opt >= 2 else None,
+               "iters_mean": float(np.mean(its)), "iters_max": int(max(its)),
+               "iters_vs_option0": round(float(np.mean(its)) / base - 1.0, 3),
+               "statuses": sorted(set(r.status for r in reps)),
+               "rel_res_true_max": float(max(r.rel_res_true for r in reps)),
+               "ms_per_step": round(1e3 * dt, 3), "solves_per_s": round(len(probs) / dt, 1)}
+        out["cases"].append(rec)
+        print(f"# {json.dumps(rec)}", flush=True)
+    print(json.dumps(out), flush=True)
+
+
+def polar(args):
+    torch, lib = _lib()
+    probs, depth, rhs = _bench_batch(torch, lib, args.count)
+    s = lib.Solver([(512, 256)] * args.count, precision=lib.FP64, rtol=args.rtol)
+    _, _, ref = _time_solver(torch, s, probs, depth, rhs, 1, 0)
+    s.close()
+    ref = [x.cpu().numpy() for x in ref]
+    out = {"workload": f"{args.count} x 512x256, dt 600 s, rtol {args.rtol:g}, GCR(3), semi-implicit Richardson x2",
+           "cases": []}
+    for form, prec in (("mixed", lib.MIXED), ("mixed_fp64dot", lib.MIXED_FP64DOT),
+                       ("mixed_half_pc", lib.MIXED_HALF_PC)):
+        for rows in (0, 1, 2, 3, 4, 8):
+            s = lib.Solver([(512, 256)] * args.count, precision=prec, polar_rows=rows, rtol=args.rtol,
+                           max_iters=args.max_iters)
+            dt, reps, xs = _time_solver(torch, s, probs, depth, rhs, args.steps, args.warmup)
+            s.close()
+            err = [float(np.linalg.norm(x.cpu().numpy() - r) / np.linalg.norm(r)) for x, r in zip(xs, ref)]
+            its = [r.iterations for r in reps]
+            rec = {"form": form, "polar_rows": rows, "iters_mean": float(np.mean(its)), "iters_max": int(max(its)),
+                   "statuses": sorted(set(r.status for r in reps)),
+                   "rel_res_true_max": float(max(r.rel_res_true for r in reps)), "rel_l2_vs_fp64_max": max(err),
+                   "ms_per_step": round(1e3 * dt, 3)}
+            out["cases"].append(rec)
+            print(f"# {json.dumps(rec)}", flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def sequence(args):
     torch, lib = _lib()
     from workloads import jet_sequence_depth
@@ -212,13 +313,20 @@ def main(argv=None):
     q.add_argument("--steps", type=int, default=200)
     q.add_argument("--rtol", type=float, default=1e-8)
     q.add_argument("--no-learned", action="store_true")
+    c = sub.add_parser("precond")
+    c.add_argument("--count", type=int, default=64)
+    c.add_argument("--steps", type=int, default=2)
+    c.add_argument("--warmup", type=int, default=1)
+    c.add_argument("--rtol", type=float, default=1e-8)
+    c.add_argument("--max-iters", type=int, default=2000)
+    o = sub.add_parser("polar")
+    o.add_argument("--count", type=int, default=64)
+    o.add_argument("--steps", type=int, default=10)
+    o.add_argument("--warmup", type=int, default=3)
+    o.add_argument("--rtol", type=float, default=1e-8)
+    o.add_argument("--max-iters", type=int, default=200)
     args = ap.parse_args(argv)
-    if args.cmd == "single":
-        single(args)
-    elif args.cmd == "batch":
-        batch(args)
-    else:
-        sequence(args)
+    {"single": single, "batch": batch, "sequence": sequence, "precond": precond, "polar": polar}[args.cmd](args)
 
 
 if __name__ == "__main__":
