@@ -22,6 +22,9 @@ Readings:
 * Exit when ||r_{nu+1}||_2 <= eps ||r_0||_2, but never inside the first full
   GCR(3) cycle: the earliest exit is after iteration k+1, which makes 4 the
   minimum iteration count the paper reports.
+* norm="linf": the same exit test with the maximum norm, the alternative exit
+  condition the paper reports trying (Section 4.1 discussion); the iteration
+  itself, the stagnation test and the reported residuals stay Euclidean.
 * ||r_0|| is the initial residual of this solve, also for warm starts.
 * Breakdown (<L(p) L(p)> == 0 or non-finite scalars) and a cycle without any
   decrease of ||r|| stop the iteration (stagnation).
@@ -55,8 +58,10 @@ class GCRResult:
 
 
 def gcr(op: EllipticOperator, rhs, x0=None, k=3, rtol=1e-8, precond=PC_SEMI_IMPLICIT,
-        richardson_iters=2, min_iters=None, max_iters=200, pc=None, track_orthogonality=False):
+        richardson_iters=2, min_iters=None, max_iters=200, pc=None, track_orthogonality=False, norm="l2"):
     """Solve L(x) = rhs by preconditioned GCR(k)."""
+    if norm not in ("l2", "linf"):
+        raise ValueError(f"norm must be 'l2' or 'linf', got {norm!r}")
     if min_iters is None:
         min_iters = k + 1
     if pc is None:
@@ -67,6 +72,7 @@ def gcr(op: EllipticOperator, rhs, x0=None, k=3, rtol=1e-8, precond=PC_SEMI_IMPL
     # step 1
     r = op.apply(x) - rhs
     rho0 = np.sqrt(dot(r, r))
+    rho0_inf = float(np.max(np.abs(r)))
     if rho0 == 0.0:
         return GCRResult(x, CONVERGED, 0, 0.0, 0.0, 0.0)
     p = [None] * (k + 1)
@@ -97,7 +103,8 @@ def gcr(op: EllipticOperator, rhs, x0=None, k=3, rtol=1e-8, precond=PC_SEMI_IMPL
             if track_orthogonality:
                 orth_log.append(max(abs(dot(r, lp[l])) / (rn * np.sqrt(dot(lp[l], lp[l])))
                                     for l in range(nu + 1)))
-            if it >= min_iters and rn <= rtol * rho0:
+            small = rn <= rtol * rho0 if norm == "l2" else float(np.max(np.abs(r))) <= rtol * rho0_inf
+            if it >= min_iters and small:
                 status, done = CONVERGED, True
                 break
             if it >= max_iters:

@@ -188,6 +188,34 @@ def test_preconditioner_option_ordering():
     assert its[3] <= 0.2 * its[0], its
 
 
+def test_linf_exit_is_the_first_iterate_meeting_the_maximum_norm_test():
+    # norm="linf": the exit is the first iteration after the first full cycle
+    # whose residual satisfies max|r| <= eps max|r_0|.  Checked against the
+    # true residuals L(x_m) - R of forced stops (rtol 0, max_iters m), on a
+    # slowly converging case (no preconditioner) so that every tolerance
+    # below falls between two iterations.
+    pr = problem(1, 64, 32)
+    op = EllipticOperator(64, 32, pr["depth"], 600.0)
+    rhs = op.apply(pr["x_true"])
+    warm = pr["x_true"] + 0.1 * np.random.default_rng(3).standard_normal((32, 64))
+    checked = 0
+    for x0 in (None, warm):
+        r0 = np.max(np.abs(op.apply(np.zeros_like(rhs) if x0 is None else x0) - rhs))
+        ratio = {m: np.max(np.abs(op.apply(gcr(op, rhs, x0=x0, rtol=0.0, max_iters=m, precond=0).x) - rhs)) / r0
+                 for m in range(1, 41)}
+        for eps in np.logspace(-2, -9, 8):
+            hits = [m for m in ratio if m >= 4 and ratio[m] <= eps]
+            if not hits or any(abs(v / eps - 1.0) < 1e-6 for v in ratio.values()):
+                continue   # not reached in 40 iterations, or on an iterate's own value
+            want = min(hits)
+            res = gcr(op, rhs, x0=x0, rtol=eps, precond=0, max_iters=500, norm="linf")
+            assert res.status == CONVERGED and res.iterations == want, (eps, res.iterations, want)
+            checked += 1
+    assert checked >= 10
+    with pytest.raises(ValueError):
+        gcr(op, rhs, norm="l1")
+
+
 def test_warm_start_uses_own_initial_residual():
     pr = problem(1, 64, 32)
     op = EllipticOperator(64, 32, pr["depth"], 600.0)
