@@ -94,6 +94,11 @@ enum {
                                       default a batch is split into up to four groups
                                       of members solved on streams of the library,
                                       forked from and joined back to that stream   */
+#define GCR_F_LINF_EXIT 0x4u       /* exit test in the maximum norm, max|r| <= rtol
+                                      max|r_0| (paper Section 4.1 discussion: the
+                                      alternative exit condition); the iteration,
+                                      its stagnation test and the reported relative
+                                      residuals stay Euclidean                     */
 
 typedef struct {
   int32_t batch;          /* number of independent solves, 1..4096                    */

@@ -31,7 +31,8 @@ constexpr int DOT_RR = 0;               // <r, r> after the step-2 update
 constexpr int DOT_LE_LP = 1;            // <L e, L p_l>, l = 0..k-1  -> slots 1..KMAX
 constexpr int DOT_R_LP = KMAX + 1;      // <r, L p_new>
 constexpr int DOT_LP_LP = KMAX + 2;     // <L p_new, L p_new>
-constexpr int NDOT = KMAX + 3;
+constexpr int DOT_RMAX = KMAX + 3;      // max |r| (maximum-norm exit test only)
+constexpr int NDOT = KMAX + 4;
 
 // Face-coefficient arrays, each [NY][NX], pre-divided by the grid factors of
 // the difference they multiply, so the stencil is weights x differences:
@@ -56,6 +57,7 @@ struct MemberState {
   double alpha[KMAX];         // step-4 coefficients of the current iteration
   double lpsq[KMAX + 1];      // <L p_l, L p_l> per ring slot
   double rtrue;               // ||L x - R|| recomputed in float64
+  double rho0_inf;            // max |r_0| (maximum-norm exit test)
   double sigma;               // RMS of r (learned preconditioner scaling)
   int it, status, done, restarts;
   int fallback, pad1, pad2, pad3;
@@ -103,6 +105,11 @@ __device__ __forceinline__ T wave_sum(T v) {
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
   return v;
 }
 

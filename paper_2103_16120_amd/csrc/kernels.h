@@ -257,6 +257,7 @@ struct Fields {
   const int* morder;          // members in row order (control kernels: block b -> morder[q0 + b])
   int q0;
   int learned;                // learned preconditioner active (fallback test at cycle ends)
+  int linf;                   // exit test in the maximum norm (max |r| partials kept)
   double fallback_ratio;      // required residual reduction per cycle with it
 };
 
@@ -580,6 +581,18 @@ __device__ __forceinline__ void write_partial(const Fields& F, const RowCtx& R, 
   if (R.lane == 0 && R.act) F.part[(long long)R.g * NDOT + slot] = (double)v;
 }
 
+// the row's max |v| into slot DOT_RMAX (maximum-norm exit test)
+template <int M, typename T>
+__device__ __forceinline__ void write_row_max(const Fields& F, const RowCtx& R, const T (&v)[M], double scale) {
+  double mx = 0.0;
+  if (R.act) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) mx = fmax(mx, fabs((double)v[k]));
+  }
+  mx = wave_max(mx);
+  if (R.lane == 0 && R.act) F.part[(long long)R.g * NDOT + DOT_RMAX] = mx * scale;
+}
+
 // step 2 on one row: r += beta L p_nu ; returns r and <r,r>.  The solution
 // update x += beta p_nu of the same step is deferred to k_apply_pending.
 template <typename P, int M>
@@ -600,6 +613,7 @@ __device__ __forceinline__ typename P::A row_update(const Fields& F, const RowCt
     acc += (A)rv[k] * (A)rv[k];
   }
   if (R.act) str<M>(r, l, L, rv);
+  if (F.linf) write_row_max<M>(F, R, rv, 1.0);
   return R.act ? acc : (A)0;
 }
 
@@ -918,6 +932,7 @@ __device__ __forceinline__ void row_residual(const Fields& F, const RowCtx& R, c
   }
   // the Krylov residual lives in scaled units in the mixed forms
   write_partial<double>(F, R, DOT_RR, R.act ? acc0 * s * s : 0.0);
+  if (F.linf) write_row_max<M>(F, R, rr, s);
   write_partial<double>(F, R, DOT_R_LP, R.act ? acc1 : 0.0);
 }
 
@@ -1258,6 +1273,14 @@ __device__ __forceinline__ void member_sums(const Fields& F, const MemberGeom& G
   for (int i = 0; i < NS; ++i) out[i] = (double)wave_sum(s[i]);
 }
 
+// max over the member's rows of one partial slot
+__device__ __forceinline__ double member_max(const Fields& F, const MemberGeom& G, int slot) {
+  double mx = 0.0;
+  const double* base = F.part + (long long)G.row0 * NDOT + slot;
+  for (int j = threadIdx.x; j < G.ny; j += 64) mx = fmax(mx, base[(long long)j * NDOT]);
+  return wave_max(mx);
+}
+
 template <typename A>
 __device__ __forceinline__ double member_sum(const Fields& F, const MemberGeom& G, int slot) {
   double o[1];
@@ -1272,9 +1295,11 @@ __global__ void k_ctrl_init(Fields F) {
   const int m = F.morder[F.q0 + blockIdx.x];
   const MemberGeom G = F.geom[m];
   const double rr = member_sum<double>(F, G, DOT_RR);
+  const double rinf = F.linf ? member_max(F, G, DOT_RMAX) : 0.0;
   if (threadIdx.x == 0) {
     MemberState& S = F.state[m];
     S.rho0 = sqrt(rr);
+    S.rho0_inf = rinf;
     S.rn = S.rho0;
     S.rn_cycle = S.rho0;
     S.it = 0;
@@ -1330,6 +1355,7 @@ __global__ void k_ctrl_alpha(Fields F, int nl, Slots sl, int cycle_end, int min_
   member_sums<A, KMAX + 1>(F, G, DOT_RR, nl + 1, d);
   const double rr = d[0];
   const double* dots = d + 1;
+  const double rinf = F.linf ? member_max(F, G, DOT_RMAX) : 0.0;
   if (threadIdx.x == 0) {
     [&] {
       // the step-2 update of this iteration was made: record it for x (the
@@ -1353,7 +1379,8 @@ __global__ void k_ctrl_alpha(Fields F, int nl, Slots sl, int cycle_end, int min_
         S.done = 1;
         return;
       }
-      if (S.it >= min_iters && rn <= rtol * S.rho0) {
+      const bool small = F.linf ? rinf <= rtol * S.rho0_inf : rn <= rtol * S.rho0;
+      if (S.it >= min_iters && small) {
         S.status = S.fallback ? ST_FALLBACK : ST_OK;
         S.done = 1;
         return;

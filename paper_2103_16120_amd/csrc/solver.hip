@@ -319,6 +319,7 @@ static Fields make_fields(gcr_solver* s) {
   F.row_end = s->rows;
   F.ignore_done = 0;
   F.learned = s->prm.precond == GCR_PC_LEARNED ? 1 : 0;
+  F.linf = (s->prm.flags & GCR_F_LINF_EXIT) ? 1 : 0;
   F.fallback_ratio = s->fallback_ratio;
   return F;
 }
@@ -474,7 +475,7 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   if (P.min_iters < -1 || P.min_iters > P.max_iters) return fail(nullptr, GCR_EINVAL, "min_iters out of range");
   if (!(P.rtol >= 0.0) || !std::isfinite(P.rtol)) return fail(nullptr, GCR_EINVAL, "rtol must be finite and >= 0");
   if (P.polar_rows < -1) return fail(nullptr, GCR_EINVAL, "polar_rows must be >= -1");
-  if (P.flags & ~(GCR_F_RECORD_HISTORY | GCR_F_ONE_STREAM))
+  if (P.flags & ~(GCR_F_RECORD_HISTORY | GCR_F_ONE_STREAM | GCR_F_LINF_EXIT))
     return fail(nullptr, GCR_EINVAL, "unknown flags 0x%x", P.flags);
   for (int m = 0; m < P.batch; ++m) {
     const int nx = P.nx[m], ny = P.ny[m];

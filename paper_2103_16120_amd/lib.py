@@ -22,6 +22,7 @@ FP64, MIXED, MIXED_FP64DOT, MIXED_HALF_PC = 0, 1, 2, 3
 PC_NONE, PC_DIAG, PC_RICHARDSON, PC_SEMI_IMPLICIT, PC_LEARNED = 0, 1, 2, 3, 4
 F_RECORD_HISTORY = 0x1
 F_ONE_STREAM = 0x2
+F_LINF_EXIT = 0x4
 
 RADIUS = 6.371e6
 GRAVITY = 9.80616
@@ -142,7 +143,8 @@ class Solver:
     """A batch of independent GCR(k) depth solves sharing one configuration."""
 
     def __init__(self, sizes, k=3, precision=FP64, precond=PC_SEMI_IMPLICIT, richardson_iters=2,
-                 polar_rows=-1, min_iters=-1, max_iters=200, rtol=1e-8, stream=None, flags=0, one_stream=False):
+                 polar_rows=-1, min_iters=-1, max_iters=200, rtol=1e-8, stream=None, flags=0, one_stream=False,
+                 linf_exit=False):
         self.sizes = [(int(nx), int(ny)) for nx, ny in sizes]
         b = len(self.sizes)
         self._nx = (C.c_int32 * b)(*[s[0] for s in self.sizes])
@@ -157,7 +159,7 @@ class Solver:
         p.richardson_iters, p.polar_rows = richardson_iters, polar_rows
         p.min_iters, p.max_iters, p.rtol = min_iters, max_iters, rtol
         p.stream = C.c_void_p(stream.cuda_stream)
-        p.flags = flags | (F_ONE_STREAM if one_stream else 0)
+        p.flags = flags | (F_ONE_STREAM if one_stream else 0) | (F_LINF_EXIT if linf_exit else 0)
         self.params = p
         h = C.c_void_p()
         rc = _lib.gcr_create(C.byref(p), C.byref(h))

@@ -148,7 +148,7 @@ def test_learned_create_needs_one_size(lib):
 
 
 def test_create_rejects_unknown_flags(lib):
-    p = _params(lib, flags=0x4)
+    p = _params(lib, flags=0x8)
     h = C.c_void_p()
     assert lib._lib.gcr_create(C.byref(p), C.byref(h)) == lib.EINVAL
     assert b"flags" in lib._lib.gcr_last_error(None)

@@ -332,6 +332,49 @@ def test_max_iters_reached(gpu_lib):
     assert np.linalg.norm(host(x) - ores.x) <= 1e-9 * np.linalg.norm(ores.x)
 
 
+def test_linf_exit_matches_oracle(gpu_lib):
+    """Maximum-norm exit on a slowly converging case (no preconditioner,
+    float64): the iteration count and solution of the oracle with the same
+    exit test, over tolerances that fall between iterations; the Euclidean
+    exit stops elsewhere for some of them."""
+    pr = problem(1, 64, 32)
+    op = EllipticOperator(64, 32, pr["depth"], 600.0)
+    rhs = op.apply(pr["x_true"])
+    differs = 0
+    for eps in (1e-3, 1e-5, 1e-7, 1e-9):
+        ores = gcr(op, rhs, rtol=eps, precond=0, max_iters=500, norm="linf")
+        s = make_solver(gpu_lib, [(64, 32)], precond=0, rtol=eps, max_iters=500, linf_exit=True)
+        s.set_operator(0, pr["depth"], 600.0)
+        x = torch.zeros((32, 64), dtype=torch.float64, device="cuda")
+        rep = s.solve([dev(rhs)], [x])[0]
+        assert rep.status == gpu_lib.OK and rep.iterations == ores.iterations, (eps, rep.iterations, ores.iterations)
+        assert np.linalg.norm(host(x) - ores.x) <= 1e-9 * np.linalg.norm(ores.x), eps
+        r = op.apply(host(x)) - rhs
+        assert np.max(np.abs(r)) <= eps * np.max(np.abs(rhs)) * (1 + 1e-6), eps
+        differs += ores.iterations != gcr(op, rhs, rtol=eps, precond=0, max_iters=500).iterations
+    assert differs >= 2
+
+
+@pytest.mark.parametrize("precision", [0, 3])
+def test_linf_exit_benchmark_batch(gpu_lib, precision):
+    """Benchmark-size members (512x256) with the maximum-norm exit: every
+    member's true residual meets the test, and the float64 form takes the
+    oracle's iteration count."""
+    probs = [problem(2, 512, 256, instance=m, dt=600.0) for m in range(4)]
+    s = make_solver(gpu_lib, [(512, 256)] * 4, precision=precision, linf_exit=True, rtol=1e-8)
+    ops = [EllipticOperator(512, 256, p["depth"], p["dt"]) for p in probs]
+    rhs = [op.apply(p["x_true"]) for op, p in zip(ops, probs)]
+    s.set_operators([0, 1, 2, 3], [dev(p["depth"]) for p in probs], [p["dt"] for p in probs])
+    x = [torch.zeros((256, 512), dtype=torch.float64, device="cuda") for _ in probs]
+    reps = s.solve([dev(r) for r in rhs], x)
+    for m, (op, r0) in enumerate(zip(ops, rhs)):
+        assert reps[m].status == gpu_lib.OK, (m, reps[m])
+        r = op.apply(host(x[m])) - r0
+        assert np.max(np.abs(r)) <= 1e-8 * np.max(np.abs(r0)) * 1.05, m
+        if precision == 0 and m == 0:
+            assert reps[m].iterations == gcr(op, r0, rtol=1e-8, norm="linf").iterations
+
+
 @pytest.mark.parametrize("option", [0, 1, 2])
 def test_other_preconditioners_solve(gpu_lib, option):
     pr = problem(1, 64, 32)
