@@ -5,6 +5,7 @@
     python -m paper_2103_16120_amd.experiments sequence   # 200 warm-started solves at 1024x512
     python -m paper_2103_16120_amd.experiments precond    # preconditioner options 0-3, Richardson count
     python -m paper_2103_16120_amd.experiments polar      # float32 polar-band width in the mixed forms
+    python -m paper_2103_16120_amd.experiments exitnorm   # Euclidean vs maximum-norm exit test
 
 single: one member of the configuration family (depth 8000 m + 500 m x
 degree<=8 harmonics, dt 600 s, R = L(degree<=12 field)), 64x32 solved to 1e-10
@@ -35,6 +36,11 @@ preconditioner form.  Iterations relative to option 0 and the time per step.
 polar: the benchmark batch in the three mixed forms with 0 to 8 rows per pole
 kept in float32 (float16 elsewhere): iterations, the float64 true residual
 and the distance to the float64 solution.
+
+exitnorm: the benchmark batch in every precision form with the Euclidean exit
+test (eq. exitcondition) and with the maximum-norm test the paper also tried:
+iterations, time per step and both norms of the final true residual relative
+to the initial one.
 """
 from __future__ import annotations
 
@@ -237,6 +243,35 @@ def polar(args):
     print(json.dumps(out), flush=True)
 
 
+def exitnorm(args):
+    torch, lib = _lib()
+    probs, depth, rhs = _bench_batch(torch, lib, args.count)
+    f = lib.Solver([(512, 256)] * args.count, precision=lib.FP64)
+    f.set_operators(list(range(args.count)), depth, [p["dt"] for p in probs])
+    out = {"workload": f"{args.count} x 512x256, dt 600 s, rtol {args.rtol:g}, GCR(3), semi-implicit Richardson x2",
+           "cases": []}
+    for form, prec in (("fp64", lib.FP64), ("mixed_half_pc", lib.MIXED_HALF_PC),
+                       ("mixed_fp64dot", lib.MIXED_FP64DOT), ("mixed", lib.MIXED)):
+        for norm in ("l2", "linf"):
+            s = lib.Solver([(512, 256)] * args.count, precision=prec, rtol=args.rtol, max_iters=args.max_iters,
+                           linf_exit=norm == "linf")
+            dt, reps, xs = _time_solver(torch, s, probs, depth, rhs, args.steps, args.warmup)
+            s.close()
+            l2, linf = [], []
+            for m, x in enumerate(xs):
+                r = (f.apply_operator(m, x) - rhs[m]).double()
+                l2.append(float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(rhs[m])))
+                linf.append(float(r.abs().max() / rhs[m].abs().max()))
+            its = [r.iterations for r in reps]
+            rec = {"form": form, "exit_norm": norm, "iters_mean": float(np.mean(its)), "iters_max": int(max(its)),
+                   "statuses": sorted(set(r.status for r in reps)), "true_rel_l2_max": max(l2),
+                   "true_rel_linf_max": max(linf), "ms_per_step": round(1e3 * dt, 3)}
+            out["cases"].append(rec)
+            print(f"# {json.dumps(rec)}", flush=True)
+    f.close()
+    print(json.dumps(out), flush=True)
+
+
 def sequence(args):
     torch, lib = _lib()
     from workloads import jet_sequence_depth
@@ -325,8 +360,15 @@ def main(argv=None):
     o.add_argument("--warmup", type=int, default=3)
     o.add_argument("--rtol", type=float, default=1e-8)
     o.add_argument("--max-iters", type=int, default=200)
+    e = sub.add_parser("exitnorm")
+    e.add_argument("--count", type=int, default=64)
+    e.add_argument("--steps", type=int, default=10)
+    e.add_argument("--warmup", type=int, default=3)
+    e.add_argument("--rtol", type=float, default=1e-8)
+    e.add_argument("--max-iters", type=int, default=200)
     args = ap.parse_args(argv)
-    {"single": single, "batch": batch, "sequence": sequence, "precond": precond, "polar": polar}[args.cmd](args)
+    {"single": single, "batch": batch, "sequence": sequence, "precond": precond, "polar": polar,
+     "exitnorm": exitnorm}[args.cmd](args)
 
 
 if __name__ == "__main__":
