@@ -55,8 +55,10 @@ def pass_bytes(form, flat=True):
             "setup": V + faces + Q,                              # r -> q1
             "iter": 2 * V + faces + V + Q,                       # r, Lp -> r, q1
         },
-        # solution updates of a cycle, applied at its end: x, p_0..p_{n-1} -> x
-        "solution": {"apply": lambda n: X + V * n + X},
+        # solution updates of a cycle: by the cycle's last step-4 pass when the
+        # member goes on (x -> x, the directions are loaded there anyway), else
+        # by the per-cycle pass (x, p_0..p_{n-1} -> x)
+        "solution": {"apply": lambda n: X + V * n + X, "in_orth": X + X},
         "sweep2": {"pass": Q + V + pre6 + V},                    # q1, r -> e
         "apply_L": {
             "setup": V + op + V + V,                             # p0 -> L p0, with <r, L p0>
@@ -80,7 +82,11 @@ def step_bytes(form, iters, restarts, k, pts, flat=True):
         n, nr = int(n), int(nr)
         nus = [(i - 1) % k for i in range(1, n + 1)]
         tot["update_sweep1"] += pb["update_sweep1"]["setup"] + n * pb["update_sweep1"]["iter"]
-        tot["solution"] += sum(pb["solution"]["apply"](min(k, n - c)) for c in range(0, n, k))
+        for c in range(0, n, k):
+            if n > c + k:
+                tot["orth"] += pb["solution"]["in_orth"]
+            else:
+                tot["solution"] += pb["solution"]["apply"](min(k, n - c))
         tot["sweep2"] += (1 + n) * pb["sweep2"]["pass"]
         tot["apply_L"] += pb["apply_L"]["setup"] + sum(pb["apply_L"]["iter"](nu) for nu in nus)
         tot["orth"] += sum(pb["orth"]["iter"](nu) for nu in nus[:-1])   # none after the exit test

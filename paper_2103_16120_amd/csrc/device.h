@@ -69,6 +69,8 @@ struct Pending {
   int slot[KMAX];             // ring slots of their directions
   int n;
   int cycle;                  // the GCR cycle they belong to
+  int by_orth;                // applied by the cycle's last step-4 pass (the member went on)
+  int pad;
 };
 
 // Quotient a / b: exact in float64; in float32 (the mixed forms' row solves,

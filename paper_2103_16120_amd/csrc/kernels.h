@@ -620,9 +620,12 @@ __device__ __forceinline__ typename P::A row_update(const Fields& F, const RowCt
 // ---------------------------------------------------------------------------
 // The solution updates of step 2, x += beta p_nu, deferred to the end of the
 // GCR cycle: k_ctrl_alpha records each update made (beta and the ring slot
-// of p_nu, stamped with the cycle), and this pass applies those of cycle
-// `cycle` before anything reads x (the restart and final residuals) and
-// before the ring slots are reused.
+// of p_nu, stamped with the cycle).  A member that goes on past the cycle's
+// last iteration has them applied by that iteration's step-4 pass, which
+// loads p_0 .. p_{k-1} anyway (k_orth); for the others (finished inside the
+// cycle) this pass applies those of cycle `cycle`.  Either way before anything
+// reads x (the restart and final residuals) and before the ring slots are
+// reused.
 // The float64 operations (GCR_MIXED: float32 increments) and their order are
 // those of updating at every iteration; x is read and written once per cycle
 // instead of once per iteration.  Finished members apply their last updates
@@ -638,7 +641,7 @@ __global__ __launch_bounds__(WG) void k_apply_pending(Fields F, int cycle) {
   if (g >= F.row_end) return;
   const int m = F.rowmap[g];
   const Pending& S = F.pend[m];
-  const int n = S.cycle == cycle ? S.n : 0;
+  const int n = (S.cycle == cycle && !S.by_orth) ? S.n : 0;
   if (n == 0) return;
   const RowCtx R = make_row(F.geom[m], m, g, lane, M);
   const int l = R.lane, L = R.L;
@@ -947,17 +950,28 @@ __global__ __launch_bounds__(WG) void k_residual(Fields F, int write_krylov, int
 
 // ---------------------------------------------------------------------------
 // step 4: p_{nu+1} = e + sum alpha_l p_l ; L p_{nu+1} = L e + sum alpha_l L p_l,
-// with fused <r, L p_{nu+1}> and <L p_{nu+1}, L p_{nu+1}>.
+// with fused <r, L p_{nu+1}> and <L p_{nu+1}, L p_{nu+1}>.  In the last
+// iteration of a cycle (`last`) also the cycle's recorded solution updates,
+// x += beta_l p_l for l = 0..k-1 in that order, from the directions loaded
+// here (k_ctrl_alpha sets by_orth when all k were recorded).
 // ---------------------------------------------------------------------------
-template <typename P, int M>
+template <typename P, int M, bool LAST>
 __device__ __forceinline__ void row_orth(const Fields& F, const RowCtx& R, int nl, const Slots& sl, int out_slot) {
   using T = typename P::T;
   using V = typename P::V;
   using A = typename P::A;
   const int l = R.lane, L = R.L;
+  const Pending& pd = F.pend[R.m];
+  const bool upd = LAST && pd.by_orth;
+  const bool upd_dx = upd && P::mixed && F.dx;
+  const bool upd_x = upd && !upd_dx;
   T pv[M], lv[M], rv[M];
+  double xv[M];
+  float dxv[M];
   ldr<M>((const V*)F.e + R.rc, l, L, pv);
   ldr<M>((const V*)F.le + R.rc, l, L, lv);
+  if (upd_x) ldr<M>(F.x + R.rc, l, L, xv);
+  if (upd_dx) ldr<M>(F.dx + R.rc, l, L, dxv);
   for (int li = 0; li < nl; ++li) {
     const T alpha = (T)F.state[R.m].alpha[li];
     T a[M], b[M];
@@ -968,7 +982,19 @@ __device__ __forceinline__ void row_orth(const Fields& F, const RowCtx& R, int n
       pv[k] += alpha * a[k];
       lv[k] += alpha * b[k];
     }
+    if (upd_x) {
+      const double beta = pd.beta[li];
+#pragma unroll
+      for (int k = 0; k < M; ++k) xv[k] += beta * (double)a[k];
+    }
+    if (upd_dx) {
+      const double beta = pd.beta[li];
+#pragma unroll
+      for (int k = 0; k < M; ++k) dxv[k] += (float)beta * (float)a[k];
+    }
   }
+  if (upd_x && R.act) str<M>(F.x + R.rc, l, L, xv);
+  if (upd_dx && R.act) str<M>(F.dx + R.rc, l, L, dxv);
 #pragma unroll
   for (int k = 0; k < M; ++k) {
     pv[k] = (T)(V)pv[k];
@@ -994,7 +1020,16 @@ __global__ __launch_bounds__(WG) void k_orth(Fields F, int nl, Slots sl, int out
   int g, m, lane, w;
   MemberGeom G;
   if (!wave_row(F, g, m, G, lane, w)) return;
-  row_orth<P, M>(F, make_row(G, m, g, lane, M), nl, sl, out_slot);
+  row_orth<P, M, false>(F, make_row(G, m, g, lane, M), nl, sl, out_slot);
+}
+
+// the last iteration of a cycle: step 4 and the cycle's solution updates
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_orth_last(Fields F, int nl, Slots sl, int out_slot) {
+  int g, m, lane, w;
+  MemberGeom G;
+  if (!wave_row(F, g, m, G, lane, w)) return;
+  row_orth<P, M, true>(F, make_row(G, m, g, lane, M), nl, sl, out_slot);
 }
 
 // ---------------------------------------------------------------------------
@@ -1308,6 +1343,7 @@ __global__ void k_ctrl_init(Fields F) {
     S.beta = 0.0;
     F.pend[m].n = 0;
     F.pend[m].cycle = -1;
+    F.pend[m].by_orth = 0;
     S.rtrue = -1.0;
     S.status = ST_NOT_CONVERGED;
     S.done = 0;
@@ -1364,6 +1400,7 @@ __global__ void k_ctrl_alpha(Fields F, int nl, Slots sl, int cycle_end, int min_
       if (pd.cycle != cycle) {
         pd.cycle = cycle;
         pd.n = 0;
+        pd.by_orth = 0;
       }
       if (pd.n < KMAX) {
         pd.beta[pd.n] = S.beta;
@@ -1407,6 +1444,10 @@ __global__ void k_ctrl_alpha(Fields F, int nl, Slots sl, int cycle_end, int min_
       }
     }();
     F.done_flag[m] = S.done;
+    // going on past the cycle's last iteration: its step-4 pass applies the
+    // cycle's recorded solution updates
+    Pending& pd = F.pend[m];
+    pd.by_orth = (cycle_end && !S.done && pd.n == nl) ? 1 : 0;
   }
 }
 

@@ -848,7 +848,11 @@ static int run_group(gcr_solver* s, const gcr_solver::Group& g) {
     KLAUNCH(s, KT_CONTROL, k_ctrl_alpha<A>, ctl, wave, 0, g.st, F, nu + 1, sl, nu == k - 1 ? 1 : 0,
             s->prm.min_iters, maxit, s->prm.rtol, cyc);
     // step 4
-    ROWS_LAUNCH(s, cls, F, KT_ORTH, k_orth, P, nu + 1, sl, sl.s[nu + 1]);
+    if (nu == k - 1) {   // the cycle's last iteration also applies its solution updates
+      ROWS_LAUNCH(s, cls, F, KT_ORTH, k_orth_last, P, nu + 1, sl, sl.s[nu + 1]);
+    } else {
+      ROWS_LAUNCH(s, cls, F, KT_ORTH, k_orth, P, nu + 1, sl, sl.s[nu + 1]);
+    }
     KLAUNCH(s, KT_CONTROL, k_ctrl_beta<A>, ctl, wave, 0, g.st, F, sl.s[nu + 1]);
   };
   // end of cycle `cyc`: its solution updates; (p_0, L p_0) := (p_k, L p_k);

@@ -16,14 +16,15 @@ def test_mixed_form_six_iterations_one_restart():
     b = bench.step_bytes("mixed", np.array([[6]]), np.array([[1]]), 3, 1, flat=False)
     # update+sweep1: setup r 4 + faces 4 -> q 2; iteration r, Lp 8 + faces 4 -> r 4, q 2
     assert b["update_sweep1"] == 10 + 6 * 18
-    # solution updates at the two cycle ends: x 8 + three p 12 -> x 8
-    assert b["solution"] == 2 * 28
+    # solution updates: the first cycle's by its last step-4 pass (x 8 -> x 8),
+    # the second's (the exit cycle) by the per-cycle pass: x 8 + three p 12 -> x 8
+    assert b["solution"] == 28
     # sweep2: q 2, r 4, six float16 arrays 12 -> e 4; setup + 6 iterations
     assert b["sweep2"] == 7 * 22
     # apply_L: setup 20; iteration 16 + 4 (nu + 1)
     assert b["apply_L"] == 20 + 2 * (20 + 24 + 28)
-    # step 4 after iterations 1..5: 20 + 8 (nu + 1)
-    assert b["orth"] == 28 + 36 + 44 + 28 + 36
+    # step 4 after iterations 1..5: 20 + 8 (nu + 1); the third also x 8 -> x 8
+    assert b["orth"] == 28 + 36 + (44 + 16) + 28 + 36
     # float64 residual: start 44, one restart 40, final 40
     assert b["residual"] == 44 + 40 + 40
 
@@ -33,10 +34,11 @@ def test_fp64_form_and_member_sum():
     b2 = bench.step_bytes("fp64", np.array([[4, 4]]), np.array([[0, 0]]), 3, 10, flat=False)
     assert all(b2[k] == 2 * b1[k] for k in b1)
     assert b1["sweep2"] == 10 * 5 * 40
-    assert b1["orth"] == 10 * ((40 + 16) + (40 + 32) + (40 + 48))
+    assert b1["orth"] == 10 * ((40 + 16) + (40 + 32) + (40 + 48 + 16))
     assert b1["residual"] == 10 * (48 + 40)
-    # 4 iterations: cycle ends after 3 updates and after 1 (x 16 + p 8 each)
-    assert b1["solution"] == 10 * ((16 + 24) + (16 + 8))
+    # 4 iterations: the first cycle's updates by its last step-4 pass (above),
+    # the one update of the exit cycle by the per-cycle pass (x 16 + p 8)
+    assert b1["solution"] == 10 * (16 + 8)
 
 
 def test_flat_surface_reads_one_depth_pool():
