@@ -192,6 +192,27 @@ int gcr_solve(gcr_solver* s, const double* const* rhs, double* const* x, gcr_rep
  * [NY][NX]; y must not overlap x.  Asynchronous on the solver's stream. */
 int gcr_apply_operator(gcr_solver* s, int32_t member, const double* x, double* y);
 
+/* Split single-precision residual (paper Section 4.2.1, eq. L_Operator_SP).
+ * The depth is carried as a float32 base Phi_hat plus a float32 correction
+ * Phi_tilde.  gcr_set_split_base stores Phi_hat = fl32(phi0) of member
+ * `member` (device float64 [NY][NX]) and the float32 differences of Phi_hat
+ * that the operator's gradient terms use (taken in float64, rounded once);
+ * the paper renews the base only every so many time steps.  The first call
+ * allocates the solver's split buffers (6 float32 values per pooled point;
+ * GCR_ENOMEM on failure).  Needs the member's operator (GCR_ESTATE).
+ * gcr_residual_split computes r = L_SP(Phi_hat + Phi_tilde) - R: the gradient
+ * terms take the stored differences of Phi_hat plus those of phi_tilde, the B
+ * and C terms take Phi_hat + phi_tilde, all in float32, with the face
+ * coefficients formed in float64 and rounded to float32; the rows within
+ * polar_rows (gcr_params) of either pole use
+ * the float64 operator on Phi_hat + phi_tilde.  phi_tilde: device float32,
+ * rhs and r: device float64, all [NY][NX]; r holds float32 values outside the
+ * polar bands and must not overlap an input.  GCR_ESTATE without a split
+ * base.  Asynchronous on the solver's stream; uses the solver's pooled
+ * scratch fields (not during a solve). */
+int gcr_set_split_base(gcr_solver* s, int32_t member, const double* phi0);
+int gcr_residual_split(gcr_solver* s, int32_t member, const float* phi_tilde, const double* rhs, double* r);
+
 /* e = P^{-1}(r) for member `member` with the solver's preconditioner and
  * Richardson count, in float64 (eq. P_Operator for option 3), device
  * pointers [NY][NX]; e must not overlap r.  Asynchronous on the stream. */

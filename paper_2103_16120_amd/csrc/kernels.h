@@ -949,6 +949,205 @@ __global__ __launch_bounds__(WG) void k_residual(Fields F, int write_krylov, int
 }
 
 // ---------------------------------------------------------------------------
+// Split single-precision residual (paper Section 4.2.1, eq. L_Operator_SP).
+// The depth is a float32 base Phi_hat plus a float32 correction Phi_tilde.
+// The gradient terms take the stored float32 differences of Phi_hat plus
+// those of Phi_tilde; the B and C terms take Phi_SP = Phi_hat + Phi_tilde; all
+// in float32, with the face coefficients formed in float64 from the depth
+// pools and rounded to float32 (forming them in float32 from float32 depths
+// would put the depths' rounding into the B terms' differences of H*, which
+// the 1/cos factor amplifies next to the poles).
+// The rows within G.polar rows of a pole use the float64 operator on
+// Phi_hat + Phi_tilde instead.  The differences are the undivided ones the
+// stencil multiplies (zonal and 4-point meridional at east faces, meridional
+// and 4-point zonal at north faces).
+// ---------------------------------------------------------------------------
+enum { SD_LON_E = 0, SD_LAT_E, SD_LAT_N, SD_LON_N, NSD };
+
+struct SplitArgs {
+  float* hat;                 // Phi_hat, pooled
+  float* d[NSD];              // its stored differences, pooled (north-face ones zero in the last row)
+  const float* tilde;         // Phi_tilde, pooled
+};
+
+// float32 field rows read as float64 sums hat + tilde (the float64 polar rows)
+struct SumReader {
+  const float* a;
+  const float* b;
+  template <int M>
+  __device__ __forceinline__ void row(long long start, int l, int L, double (&v)[M], int /*row_g*/) const {
+    float x[M], y[M];
+    ldr<M>(a + start, l, L, x);
+    ldr<M>(b + start, l, L, y);
+#pragma unroll
+    for (int k = 0; k < M; ++k) v[k] = (double)x[k] + (double)y[k];
+  }
+};
+
+// Phi_hat = fl32(phi) and its float32 differences, from the float64 field in
+// the pooled x; differences taken in float64 of the float32 values.
+template <typename P, int M>   // P: unused (the row-launch helper's signature)
+__global__ __launch_bounds__(WG) void k_split_base(Fields F, SplitArgs S) {
+  int g, m, lane, w;
+  MemberGeom G;
+  if (!wave_row(F, g, m, G, lane, w)) return;
+  const RowCtx R = make_row(G, m, g, lane, M);
+  const int l = R.lane, L = R.L;
+  const int wl = (l - 1) & (L - 1), el = (l + 1) & (L - 1);
+  double c[M], so[M], no[M];
+  ldr<M>(F.x + R.rc, l, L, c);
+  if (R.south) ldr<M>(F.x + R.rc - R.nx, l, L, so);
+  if (R.north) ldr<M>(F.x + R.rc + R.nx, l, L, no);
+  if (!R.south) across_pole(c, so, l, L);
+  if (!R.north) across_pole(c, no, l, L);
+#pragma unroll
+  for (int k = 0; k < M; ++k) {   // the float32 values, as float64
+    c[k] = (double)(float)c[k];
+    so[k] = (double)(float)so[k];
+    no[k] = (double)(float)no[k];
+  }
+  const double cw0 = shfl(c[M - 1], wl), ceM = shfl(c[0], el);
+  const double seM = shfl(so[0], el);
+  const double nw0 = shfl(no[M - 1], wl), neM = shfl(no[0], el);
+  float h[M], dle[M], dte[M], dtn[M], dln[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const double e = k < M - 1 ? c[k + 1] : ceM, wv = k > 0 ? c[k - 1] : cw0;
+    const double se = k < M - 1 ? so[k + 1] : seM;
+    const double ne = k < M - 1 ? no[k + 1] : neM, nw = k > 0 ? no[k - 1] : nw0;
+    h[k] = (float)c[k];
+    dle[k] = (float)(e - c[k]);
+    dte[k] = (float)((no[k] - so[k]) + (ne - se));
+    dtn[k] = R.north ? (float)(no[k] - c[k]) : 0.f;
+    dln[k] = R.north ? (float)((e - wv) + (ne - nw)) : 0.f;
+  }
+  if (R.act) {
+    str<M>(S.hat + R.rc, l, L, h);
+    str<M>(S.d[SD_LON_E] + R.rc, l, L, dle);
+    str<M>(S.d[SD_LAT_E] + R.rc, l, L, dte);
+    str<M>(S.d[SD_LAT_N] + R.rc, l, L, dtn);
+    str<M>(S.d[SD_LON_N] + R.rc, l, L, dln);
+  }
+}
+
+// r = L_SP(Phi_hat + Phi_tilde) - R into the pooled r64 (R: the pooled rhs)
+template <typename P, int M>   // P: unused (the row-launch helper's signature)
+__global__ __launch_bounds__(WG) void k_residual_split(Fields F, SplitArgs S) {
+  int g, m, lane, w;
+  MemberGeom G;
+  if (!wave_row(F, g, m, G, lane, w)) return;
+  const RowCtx R = make_row(G, m, g, lane, M);
+  const int l = R.lane, L = R.L;
+  double b[M], out[M];
+  ldr<M>(F.rhs + R.rc, l, L, b);
+  if (R.j < G.polar || R.j >= G.ny - G.polar) {   // float64 polar bands
+    const CoefFly<double> cv{F.fly64};
+    const double helm = cv.helm(R.g);
+    stencil_row<double, M>(R, cv, SumReader{S.hat, S.tilde},
+                           [&](int k, double zon, double rest, double xc, double, double, double, double) {
+                             out[k] = zon + rest - helm * xc - b[k];
+                           });
+  } else {
+    const int wl = (l - 1) & (L - 1), el = (l + 1) & (L - 1);
+    float axe[M], axy[M], bx[M], ayn[M], ayxn[M], byn[M], ays[M], ayxs[M], bys[M];
+    {
+      const CoefFly<double> cv{F.fly64};
+      double c9[9][M];
+      cv.template load9<M>(R, c9[0], c9[1], c9[2], c9[3], c9[4], c9[5], c9[6], c9[7], c9[8]);
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        axe[k] = (float)c9[0][k];
+        axy[k] = (float)c9[1][k];
+        bx[k] = (float)c9[2][k];
+        ayn[k] = (float)c9[3][k];
+        ayxn[k] = (float)c9[4][k];
+        byn[k] = (float)c9[5][k];
+        ays[k] = (float)c9[6][k];
+        ayxs[k] = (float)c9[7][k];
+        bys[k] = (float)c9[8][k];
+      }
+    }
+    const float helm = (float)F.fly64.c[R.g];
+    float tc[M], ts[M], tn[M], hc[M], hs[M], hn[M];
+    ldr<M>(S.tilde + R.rc, l, L, tc);
+    ldr<M>(S.hat + R.rc, l, L, hc);
+    if (R.south) {
+      ldr<M>(S.tilde + R.rc - R.nx, l, L, ts);
+      ldr<M>(S.hat + R.rc - R.nx, l, L, hs);
+    } else {
+      across_pole(tc, ts, l, L);
+      across_pole(hc, hs, l, L);
+    }
+    if (R.north) {
+      ldr<M>(S.tilde + R.rc + R.nx, l, L, tn);
+      ldr<M>(S.hat + R.rc + R.nx, l, L, hn);
+    } else {
+      across_pole(tc, tn, l, L);
+      across_pole(hc, hn, l, L);
+    }
+    float dle[M], dte[M], dtn[M], dln[M], dtns[M], dlns[M];
+    ldr<M>(S.d[SD_LON_E] + R.rc, l, L, dle);
+    ldr<M>(S.d[SD_LAT_E] + R.rc, l, L, dte);
+    ldr<M>(S.d[SD_LAT_N] + R.rc, l, L, dtn);
+    ldr<M>(S.d[SD_LON_N] + R.rc, l, L, dln);
+    if (R.south) {   // the south face is the north face of row j-1
+      ldr<M>(S.d[SD_LAT_N] + R.rc - R.nx, l, L, dtns);
+      ldr<M>(S.d[SD_LON_N] + R.rc - R.nx, l, L, dlns);
+    } else {
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        dtns[k] = 0.f;
+        dlns[k] = 0.f;
+      }
+    }
+    auto at = [](const float (&v)[M], int i, float w0, float eM) { return i < 0 ? w0 : (i >= M ? eM : v[i]); };
+    const float tcw = shfl(tc[M - 1], wl), tce = shfl(tc[0], el);
+    const float tsw = shfl(ts[M - 1], wl), tse = shfl(ts[0], el);
+    const float tnw = shfl(tn[M - 1], wl), tne = shfl(tn[0], el);
+    const float hcw = shfl(hc[M - 1], wl), hce = shfl(hc[0], el);
+    const float dlew = shfl(dle[M - 1], wl), dtew = shfl(dte[M - 1], wl);
+    float axe_p = shfl(axe[M - 1], wl), axy_p = shfl(axy[M - 1], wl), bx_p = shfl(bx[M - 1], wl);
+    // the full east-face differences of chunk point i (i = -1: the west face of point 0)
+    auto dlon_e = [&](int i) {
+      const float dh = i < 0 ? dlew : dle[i];
+      return dh + (at(tc, i + 1, tcw, tce) - at(tc, i, tcw, tce));
+    };
+    auto dlat_e = [&](int i) {
+      const float dh = i < 0 ? dtew : dte[i];
+      return dh + ((at(tn, i, tnw, tne) - at(ts, i, tsw, tse)) + (at(tn, i + 1, tnw, tne) - at(ts, i + 1, tsw, tse)));
+    };
+    float de_p = dlon_e(-1), te_p = dlat_e(-1);
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const float de = dlon_e(k), te = dlat_e(k);
+      const float dn = dtn[k] + (tn[k] - tc[k]);
+      const float ln = dln[k] + ((at(tc, k + 1, tcw, tce) - at(tc, k - 1, tcw, tce)) +
+                                 (at(tn, k + 1, tnw, tne) - at(tn, k - 1, tnw, tne)));
+      const float dsn = dtns[k] + (tc[k] - ts[k]);
+      const float lsn = dlns[k] + ((at(ts, k + 1, tsw, tse) - at(ts, k - 1, tsw, tse)) +
+                                   (at(tc, k + 1, tcw, tce) - at(tc, k - 1, tcw, tce)));
+      const float csp = hc[k] + tc[k];
+      const float esp = at(hc, k + 1, hcw, hce) + at(tc, k + 1, tcw, tce);
+      const float wsp = at(hc, k - 1, hcw, hce) + at(tc, k - 1, tcw, tce);
+      const float nsp = hn[k] + tn[k], ssp = hs[k] + ts[k];
+      const float zon = axe[k] * de - axe_p * de_p;
+      float r = axy[k] * te - axy_p * te_p;
+      r += bx[k] * (csp + esp) - bx_p * (wsp + csp);
+      r += ayn[k] * dn + ayxn[k] * ln + byn[k] * (csp + nsp);
+      r -= ays[k] * dsn + ayxs[k] * lsn + bys[k] * (ssp + csp);
+      const float lsp = zon + r - helm * csp;
+      out[k] = (double)(float)((double)lsp - b[k]);
+      axe_p = axe[k];
+      axy_p = axy[k];
+      bx_p = bx[k];
+      de_p = de;
+      te_p = te;
+    }
+  }
+  if (R.act) str<M>(F.r64 + R.rc, l, L, out);
+}
+
+// ---------------------------------------------------------------------------
 // step 4: p_{nu+1} = e + sum alpha_l p_l ; L p_{nu+1} = L e + sum alpha_l L p_l,
 // with fused <r, L p_{nu+1}> and <L p_{nu+1}, L p_{nu+1}>.  In the last
 // iteration of a cycle (`last`) also the cycle's recorded solution updates,
@@ -1253,6 +1452,12 @@ __device__ __forceinline__ long long pool_index(const MemberGeom& G, long long k
 
 // one member, direct pointers
 __global__ void k_to_pool(const double* src, double* pool, MemberGeom G) {
+  const long long n = (long long)G.nx * G.ny;
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
+    pool[pool_index(G, k)] = src[k];
+}
+
+__global__ void k_to_pool_f32(const float* src, float* pool, MemberGeom G) {
   const long long n = (long long)G.nx * G.ny;
   for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
     pool[pool_index(G, k)] = src[k];

@@ -107,6 +107,9 @@ struct gcr_solver {
   MemberState* state = nullptr;
   Pending* pend = nullptr;            // per member: recorded step-2 updates
   int* done_flag = nullptr;           // per member: the done flag the host polls
+  float* split = nullptr;             // split residual: Phi_hat, its NSD differences, Phi_tilde (pooled,
+                                      // allocated by the first gcr_set_split_base)
+  std::vector<int> have_split;
   double* part = nullptr;
   double* scale = nullptr;
   float* a32[NCOEF] = {};
@@ -496,6 +499,7 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   s->nx.assign(P.nx, P.nx + P.batch);
   s->ny.assign(P.ny, P.ny + P.batch);
   s->have_op.assign(P.batch, 0);
+  s->have_split.assign(P.batch, 0);
   s->flat_h.assign(P.batch, 0);
   s->scale_h.assign(P.batch, 1.0);
   for (int m = 0; m < P.batch; ++m) {
@@ -1070,6 +1074,64 @@ static int check_member(gcr_solver* s, int32_t member, const void* a, const void
   if (!a || !b) return fail(s, GCR_EINVAL, "NULL field pointer");
   if (a == b) return fail(s, GCR_EINVAL, "input and output must not alias");
   if (!s->have_op[member]) return fail(s, GCR_ESTATE, "member %d has no operator", member);
+  return GCR_OK;
+}
+
+static SplitArgs split_args(const gcr_solver* s) {
+  SplitArgs S{};
+  S.hat = s->split;
+  for (int k = 0; k < NSD; ++k) S.d[k] = s->split + (size_t)(k + 1) * s->npts;
+  S.tilde = s->split + (size_t)(NSD + 1) * s->npts;
+  return S;
+}
+
+extern "C" int gcr_set_split_base(gcr_solver* s, int32_t member, const double* phi0) {
+  if (!s) return GCR_EINVAL;
+  if (member < 0 || member >= s->prm.batch) return fail(s, GCR_EINVAL, "member %d out of range", member);
+  if (!phi0) return fail(s, GCR_EINVAL, "NULL field pointer");
+  if (!s->have_op[member]) return fail(s, GCR_ESTATE, "member %d has no operator", member);
+  if (!s->split) {
+    hipError_t herr = hipSuccess;
+    float* buf = dalloc<float>((size_t)(NSD + 2) * s->npts, herr);
+    if (herr != hipSuccess) return fail(s, GCR_ENOMEM, "split residual buffers: %s", hipGetErrorString(herr));
+    s->allocs.push_back(buf);
+    s->split = buf;
+  }
+  const MemberGeom& G = s->geom_h[member];
+  const long long n = (long long)G.nx * G.ny;
+  const dim3 cg((unsigned)std::min<long long>((n + 255) / 256, 1024));
+  KLAUNCH(s, KT_COPY, k_to_pool, cg, dim3(256), 0, s->stream, phi0, s->x, G);
+  Fields F = make_fields(s);
+  F.row_base = G.row0;
+  F.row_end = G.row0 + G.ny;
+  F.ignore_done = 1;
+  ROWS_LAUNCH(s, member_class(s, member), F, KT_RESIDUAL, k_split_base, PrecF64, split_args(s));
+  HIPCHK(s, hipGetLastError());
+  s->have_split[member] = 1;
+  return GCR_OK;
+}
+
+extern "C" int gcr_residual_split(gcr_solver* s, int32_t member, const float* phi_tilde, const double* rhs,
+                                  double* r) {
+  int rc = check_member(s, member, phi_tilde, r);
+  if (rc != GCR_OK) return rc;
+  if (!rhs) return fail(s, GCR_EINVAL, "NULL rhs");
+  if ((const void*)rhs == (const void*)r || (const void*)phi_tilde == (const void*)r)
+    return fail(s, GCR_EINVAL, "r must not alias an input");
+  if (!s->have_split[member]) return fail(s, GCR_ESTATE, "member %d has no split base (gcr_set_split_base)", member);
+  const MemberGeom& G = s->geom_h[member];
+  const long long n = (long long)G.nx * G.ny;
+  const dim3 cg((unsigned)std::min<long long>((n + 255) / 256, 1024));
+  const SplitArgs S = split_args(s);
+  KLAUNCH(s, KT_COPY, k_to_pool_f32, cg, dim3(256), 0, s->stream, phi_tilde, (float*)S.tilde, G);
+  KLAUNCH(s, KT_COPY, k_to_pool, cg, dim3(256), 0, s->stream, rhs, s->rhs, G);
+  Fields F = make_fields(s);
+  F.row_base = G.row0;
+  F.row_end = G.row0 + G.ny;
+  F.ignore_done = 1;
+  ROWS_LAUNCH(s, member_class(s, member), F, KT_RESIDUAL, k_residual_split, PrecF64, S);
+  KLAUNCH(s, KT_COPY, k_from_pool, cg, dim3(256), 0, s->stream, (const double*)s->r64, r, G);
+  HIPCHK(s, hipGetLastError());
   return GCR_OK;
 }
 

@@ -6,6 +6,7 @@
     python -m paper_2103_16120_amd.experiments precond    # preconditioner options 0-3, Richardson count
     python -m paper_2103_16120_amd.experiments polar      # float32 polar-band width in the mixed forms
     python -m paper_2103_16120_amd.experiments exitnorm   # Euclidean vs maximum-norm exit test
+    python -m paper_2103_16120_amd.experiments split      # split single-precision residual kernel
 
 single: one member of the configuration family (depth 8000 m + 500 m x
 degree<=8 harmonics, dt 600 s, R = L(degree<=12 field)), 64x32 solved to 1e-10
@@ -41,6 +42,13 @@ exitnorm: the benchmark batch in every precision form with the Euclidean exit
 test (eq. exitcondition) and with the maximum-norm test the paper also tried:
 iterations, time per step and both norms of the final true residual relative
 to the initial one.
+
+split: the split single-precision residual (Section 4.2.1, eq.
+L_Operator_SP) of one member per call, 512x256 and 1024x512, three float64
+rows per pole: per-call kernel time of the split residual and of the float64
+operator (per-kernel HIP events), and the split kernel's algorithmic bandwidth
+(Phi_tilde 4, Phi_hat 4, four stored differences 16, Phi* 8, R 8, r 8 bytes per
+point, pooled fields).
 """
 from __future__ import annotations
 
@@ -272,6 +280,46 @@ def exitnorm(args):
     print(json.dumps(out), flush=True)
 
 
+def split(args):
+    torch, lib = _lib()
+    from workloads import problem
+    out = {"workload": "split single-precision residual of one member per call, polar rows 3", "cases": {}}
+    for nx, ny in ((512, 256), (1024, 512)):
+        pr = problem(2, nx, ny, dt=600.0)
+        s = lib.Solver([(nx, ny)], polar_rows=3)
+        depth = torch.from_numpy(pr["depth"]).cuda()
+        s.set_operator(0, depth, 600.0)
+        base = depth - 20.0 * torch.from_numpy(pr["x_true"]).cuda()
+        s.set_split_base(0, base)
+        phi = depth + 3.0 * torch.from_numpy(pr["x_true"]).cuda()
+        tilde = (phi - base.float().double()).float().contiguous()
+        rhs = s.apply_operator(0, phi + 5.0 * torch.from_numpy(pr["x_true"]).cuda()).clone()
+        r = torch.empty_like(rhs)
+        y = torch.empty_like(rhs)
+        for _ in range(args.warmup):
+            s.residual_split(0, tilde, rhs, out=r)
+            s.apply_operator(0, phi, out=y)
+        torch.cuda.synchronize()
+        s.set_kernel_timing(True)
+        for _ in range(args.calls):
+            s.residual_split(0, tilde, rhs, out=r)
+            s.apply_operator(0, phi, out=y)
+        kt = s.kernel_times()
+        s.set_kernel_timing(False)
+        n_res, ms_res = kt["residual"]
+        n_op, ms_op = kt["apply_L"]
+        us_res, us_op = 1e3 * ms_res / n_res, 1e3 * ms_op / n_op
+        pts = nx * ny
+        rel = ((r - (y - rhs)).abs().max() / (y - rhs).abs().max()).item()
+        out["cases"][f"{nx}x{ny}"] = {"split_us": round(us_res, 2), "float64_operator_us": round(us_op, 2),
+                                       "split_GBps": round(48.0 * pts / (us_res * 1e-6) / 1e9, 1),
+                                       "split_frac_of_8TBps": round(48.0 * pts / (us_res * 1e-6) / 8e12, 4),
+                                       "max_rel_diff_vs_float64": rel}
+        s.close()
+        print(f"# {nx}x{ny}: {json.dumps(out['cases'][f'{nx}x{ny}'])}", flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def sequence(args):
     torch, lib = _lib()
     from workloads import jet_sequence_depth
@@ -366,9 +414,12 @@ def main(argv=None):
     e.add_argument("--warmup", type=int, default=3)
     e.add_argument("--rtol", type=float, default=1e-8)
     e.add_argument("--max-iters", type=int, default=200)
+    sp = sub.add_parser("split")
+    sp.add_argument("--calls", type=int, default=50)
+    sp.add_argument("--warmup", type=int, default=5)
     args = ap.parse_args(argv)
     {"single": single, "batch": batch, "sequence": sequence, "precond": precond, "polar": polar,
-     "exitnorm": exitnorm}[args.cmd](args)
+     "exitnorm": exitnorm, "split": split}[args.cmd](args)
 
 
 if __name__ == "__main__":

@@ -63,6 +63,8 @@ _SIGNATURES = {
     "gcr_set_operators": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(GcrOperator)]),
     "gcr_solve": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(GcrReport)]),
     "gcr_apply_operator": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "gcr_set_split_base": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "gcr_residual_split": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gcr_apply_precond": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "gcr_destroy": (C.c_int, [C.c_void_p]),
     "gcr_status_string": (C.c_char_p, [C.c_int]),
@@ -280,6 +282,27 @@ class Solver:
                 raise self._err(rc)
             out[_lib.gcr_kernel_name(k).decode()] = (n.value, ms.value)
         return out
+
+    def set_split_base(self, member, phi0):
+        """Split residual base: Phi_hat = fl32(phi0) and its stored differences."""
+        nx, ny = self.sizes[member]
+        _check_field(phi0, ny, nx, "phi0")
+        rc = _lib.gcr_set_split_base(self._h, member, phi0.data_ptr())
+        if rc < 0:
+            raise self._err(rc)
+
+    def residual_split(self, member, phi_tilde, rhs, out=None):
+        """r = L_SP(Phi_hat + phi_tilde) - rhs (phi_tilde float32, rhs float64)."""
+        nx, ny = self.sizes[member]
+        if phi_tilde.dtype != torch.float32 or not phi_tilde.is_cuda or not phi_tilde.is_contiguous() \
+                or tuple(phi_tilde.shape) != (ny, nx):
+            raise ValueError(f"phi_tilde must be a contiguous float32 CUDA tensor of shape {(ny, nx)}")
+        _check_field(rhs, ny, nx, "rhs")
+        r = torch.empty_like(rhs) if out is None else out
+        rc = _lib.gcr_residual_split(self._h, member, phi_tilde.data_ptr(), rhs.data_ptr(), r.data_ptr())
+        if rc < 0:
+            raise self._err(rc)
+        return r
 
     def apply_operator(self, member, x, out=None):
         nx, ny = self.sizes[member]
