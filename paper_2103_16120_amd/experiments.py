@@ -44,8 +44,8 @@ iterations, time per step and both norms of the final true residual relative
 to the initial one.
 
 split: the split single-precision residual (Section 4.2.1, eq.
-L_Operator_SP) of one member per call, 512x256 and 1024x512, three float64
-rows per pole: per-call kernel time of the split residual and of the float64
+L_Operator_SP) of one member per call, 512x256, 1024x512 and 1024x4096 (the
+largest grid, which alone fills the GPU), three float64 rows per pole: per-call kernel time of the split residual and of the float64
 operator (per-kernel HIP events), and the split kernel's algorithmic bandwidth
 (Phi_tilde 4, Phi_hat 4, four stored differences 16, Phi* 8, R 8, r 8 bytes per
 point, pooled fields).
@@ -284,7 +284,7 @@ def split(args):
     torch, lib = _lib()
     from workloads import problem
     out = {"workload": "split single-precision residual of one member per call, polar rows 3", "cases": {}}
-    for nx, ny in ((512, 256), (1024, 512)):
+    for nx, ny in ((512, 256), (1024, 512), (1024, 4096)):
         pr = problem(2, nx, ny, dt=600.0)
         s = lib.Solver([(nx, ny)], polar_rows=3)
         depth = torch.from_numpy(pr["depth"]).cuda()
