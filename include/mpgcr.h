@@ -72,10 +72,17 @@ enum {
                             solution accumulator, and the residual recomputed in
                             float64 from the solution at every restart
                             (residual replacement)                                 */
-  GCR_MIXED_HALF_PC = 3  /* as GCR_MIXED_FP64DOT, but the operator applied inside
+  GCR_MIXED_HALF_PC = 3, /* as GCR_MIXED_FP64DOT, but the operator applied inside
                             the Krylov iteration keeps float32 coefficients: half
                             precision only in the preconditioner, the step the
                             paper finds most robust to reduced precision          */
+  GCR_SINGLE = 4         /* the paper's single-precision solver cycle (Section 4.2,
+                            option two): operator and preconditioner in float32
+                            (coefficients formed from the float32 depth),
+                            float32 Krylov vectors, inner products and
+                            preconditioner intermediates, float32 solution
+                            increments added to the float64 solution at exit;
+                            float64 initial and final residual                    */
 };
 
 /* preconditioners (paper Section 2.3, options 0-3; 4 is a learned network) */

@@ -198,6 +198,7 @@ struct PrecF64 {              // everything float64
   using T = double;           // arithmetic
   static constexpr bool mixed = false;
   static constexpr bool op_f32 = false;   // operator coefficients in float32 (not float16)
+  static constexpr bool pc_f32 = false;   // preconditioner coefficients in float32 (not float16)
 };
 struct PrecMixed {            // float32 vectors and inner products, float16 coefficients
   using V = float;
@@ -206,6 +207,7 @@ struct PrecMixed {            // float32 vectors and inner products, float16 coe
   using T = float;
   static constexpr bool mixed = true;
   static constexpr bool op_f32 = false;
+  static constexpr bool pc_f32 = false;
 };
 struct PrecMixedD {           // as PrecMixed with float64 inner products
   using V = float;
@@ -214,6 +216,7 @@ struct PrecMixedD {           // as PrecMixed with float64 inner products
   using T = float;
   static constexpr bool mixed = true;
   static constexpr bool op_f32 = false;
+  static constexpr bool pc_f32 = false;
 };
 struct PrecMixedP {           // as PrecMixedD, float16 only in the preconditioner
   using V = float;
@@ -222,6 +225,16 @@ struct PrecMixedP {           // as PrecMixedD, float16 only in the precondition
   using T = float;
   static constexpr bool mixed = true;
   static constexpr bool op_f32 = true;
+  static constexpr bool pc_f32 = false;
+};
+struct PrecSingle {           // float32 throughout the solver cycle (paper Section 4.2, option two)
+  using V = float;
+  using A = float;
+  using Q = float;
+  using T = float;
+  static constexpr bool mixed = true;
+  static constexpr bool op_f32 = true;
+  static constexpr bool pc_f32 = true;
 };
 
 // Everything a kernel may touch, passed by value.
@@ -269,6 +282,8 @@ template <typename P, bool FL = false, typename Fn>
 __device__ __forceinline__ void with_coef(const Fields& F, const MemberGeom& G, int j, bool op, Fn&& fn) {
   if constexpr (!P::mixed) {
     fn(CoefFly<double, FL>{F.fly64});
+  } else if constexpr (P::pc_f32) {   // float32 coefficients formed from the float32 depth, every row
+    fn(CoefFly<float, FL>{F.fly32});
   } else {
     const bool f32 = (op && P::op_f32) || (j < G.polar) || (j >= G.ny - G.polar);
     if (f32) fn(CoefRow<float, float>{F.cmx.f, F.cmx.c});
@@ -551,7 +566,7 @@ __device__ __forceinline__ void store_q(const Fields& F, int qout, const RowCtx&
   using T = typename P::T;
   using Q = typename P::Q;
   Q* q = (Q*)F.q[qout] + R.rc;
-  if constexpr (P::mixed) {
+  if constexpr (std::is_same<Q, __half>::value) {
     float mx = 0.f;
     if (R.act) {
 #pragma unroll
@@ -733,11 +748,12 @@ __device__ __forceinline__ void row_sweep2(const Fields& F, const RowCtx& R, con
       row_system(eta, axe, axw, helm, lo, di, up);
       rs.push(k, lo, di, up, xc + eta * (rest - rv[k]));
     };
-    if constexpr (P::mixed) {
+    using Q = typename P::Q;
+    if constexpr (std::is_same<Q, __half>::value) {
       ScaledHalfReader<T> X{(const __half*)F.q[qin], F.qs[qin]};
       stencil_row<T, M>(R, cv, X, emit);
     } else {
-      RowReader<T, double> X{(const double*)F.q[qin]};
+      RowReader<T, Q> X{(const Q*)F.q[qin]};
       stencil_row<T, M>(R, cv, X, emit);
     }
     T xq[M];

@@ -315,7 +315,7 @@ static Fields make_fields(gcr_solver* s) {
     F.p[i] = s->p[i];
     F.lp[i] = s->lp[i];
   }
-  F.dx = s->prm.precision == GCR_MIXED ? s->dx : nullptr;
+  F.dx = s->dx;   // float32 solution increments (GCR_MIXED, GCR_SINGLE), else null
   F.hist = s->hist;
   F.hist_stride = s->hist_stride;
   F.row_base = 0;
@@ -468,7 +468,7 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   if (P.batch < 1 || P.batch > 4096) return fail(nullptr, GCR_EINVAL, "batch must be in [1, 4096], got %d", P.batch);
   if (!P.nx || !P.ny) return fail(nullptr, GCR_EINVAL, "nx/ny arrays must not be NULL");
   if (P.k < 1 || P.k > KMAX) return fail(nullptr, GCR_EINVAL, "k must be in [1, %d], got %d", KMAX, P.k);
-  if (P.precision < GCR_FP64 || P.precision > GCR_MIXED_HALF_PC)
+  if (P.precision < GCR_FP64 || P.precision > GCR_SINGLE)
     return fail(nullptr, GCR_EINVAL, "unknown precision form %d", P.precision);
   if (P.precond < GCR_PC_NONE || P.precond > GCR_PC_LEARNED)
     return fail(nullptr, GCR_EINVAL, "unsupported preconditioner %d", P.precond);
@@ -580,7 +580,7 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
     s->p[i] = track(dalloc<char>(N * vsz, herr));
     s->lp[i] = track(dalloc<char>(N * vsz, herr));
   }
-  if (P.precision == GCR_MIXED) s->dx = (float*)track(dalloc<float>(N, herr));
+  if (P.precision == GCR_MIXED || P.precision == GCR_SINGLE) s->dx = (float*)track(dalloc<float>(N, herr));
   if (mixed) {
     s->aux_r = (double*)track(dalloc<double>(N, herr));
     s->aux_e = (double*)track(dalloc<double>(N, herr));
@@ -897,8 +897,8 @@ static int run_group(gcr_solver* s, const gcr_solver::Group& g) {
   // No update is pending here: the loop leaves right after a cycle end, or
   // after a speculative iteration that every member skipped (all were done
   // at that cycle end).  The true residual of the group's members in float64
-  // (GCR_MIXED: after its increments are added, over the whole batch):
-  if (s->prm.precision != GCR_MIXED) {
+  // (float32 increments: after they are added, over the whole batch):
+  if (!s->dx) {
     ROWS_LAUNCH_F(s, cls, F, KT_RESIDUAL, k_residual, P, 0, -1, 0, RES_X_OUT | RES_RHS_TAB);
     KLAUNCH(s, KT_CONTROL, k_ctrl_true, ctl, wave, 0, g.st, F);
     HIPCHK(s, hipGetLastError());
@@ -985,7 +985,7 @@ static int run_solve(gcr_solver* s) {
       HIPCHK(s, hipStreamWaitEvent(s->stream, g.done_ev, 0));
     }
   }
-  if (s->prm.precision == GCR_MIXED) {
+  if (s->dx) {
     // float32 increments added to the solution, then the true residual
     const Fields F = make_fields(s);
     const dim3 ctl(B), wave(64);
@@ -1025,6 +1025,7 @@ extern "C" int gcr_solve(gcr_solver* s, const double* const* rhs, double* const*
     case GCR_FP64: rc = run_solve<PrecF64>(s); break;
     case GCR_MIXED: rc = run_solve<PrecMixed>(s); break;
     case GCR_MIXED_FP64DOT: rc = run_solve<PrecMixedD>(s); break;
+    case GCR_SINGLE: rc = run_solve<PrecSingle>(s); break;
     default: rc = run_solve<PrecMixedP>(s); break;
   }
   if (rc != GCR_OK) return rc;

@@ -130,7 +130,7 @@ def batch(args):
            "points": pts, "forms": {}}
     ref = None
     for name, prec in (("fp64", lib.FP64), ("mixed_half_pc", lib.MIXED_HALF_PC),
-                       ("mixed_fp64dot", lib.MIXED_FP64DOT), ("mixed", lib.MIXED)):
+                       ("mixed_fp64dot", lib.MIXED_FP64DOT), ("mixed", lib.MIXED), ("single", lib.SINGLE)):
         s = lib.Solver(sizes, precision=prec, rtol=args.rtol, max_iters=100, one_stream=args.one_stream)
         xs = [torch.zeros_like(r) for r in rhs]
 
