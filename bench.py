@@ -338,6 +338,14 @@ def main():
             out["fp64"]["roofline"], out["fp64"]["roofline_kernels"] = roofline(kt64, kit64, f64.reports, pts,
                                                                                 "fp64")
         out["speedup_mixed_vs_fp64"] = round(t64 / t_mixed, 3)
+        # what the algorithmic-bytes model predicts for the same iterations and
+        # restarts (assembly excluded), beside the paper's flop-cost estimate
+        # for its half-precision solver (x3.3, costs 1 / 0.5 / 0.25)
+        restarts_m = np.array([[r.restarts for r in rep_m]] * len(it_mixed))
+        restarts_64 = np.array([[r.restarts for r in f64.reports]] * len(it64))
+        bm = sum(step_bytes("mixed", it_mixed, restarts_m, 3, pts).values())
+        b64 = sum(step_bytes("fp64", it64, restarts_64, 3, pts).values())
+        out["speedup_models"] = {"bytes_model": round(b64 / bm, 3), "paper_flop_estimate": 3.3}
         f64.solver.close()
 
     if not args.no_learned:
