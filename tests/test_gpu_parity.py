@@ -323,6 +323,30 @@ def test_member_groups_equal_one_stream(gpu_lib, precision):
         assert all(np.array_equal(a, b) for a, b in zip(xs, ref_x))
 
 
+@pytest.mark.parametrize("precision", [0, 3])
+@pytest.mark.parametrize("k", [1, 2, 5, 8])
+def test_gcr_windows_many_cycles(gpu_lib, k, precision):
+    """GCR(k) for other windows, on a case that runs many cycles (no
+    preconditioner): the oracle's iteration count and solution.  Exercises
+    the once-per-cycle solution updates with every window length, including
+    k = 1 (every iteration ends a cycle)."""
+    pr = problem(1, 64, 32)
+    op = EllipticOperator(64, 32, pr["depth"], 600.0)
+    rhs = op.apply(pr["x_true"])
+    ores = gcr(op, rhs, k=k, rtol=1e-7, precond=0, max_iters=800)
+    s = make_solver(gpu_lib, [(64, 32)], k=k, precision=precision, precond=0, rtol=1e-7, max_iters=800)
+    s.set_operator(0, pr["depth"], 600.0)
+    x = torch.zeros((32, 64), dtype=torch.float64, device="cuda")
+    rep = s.solve([dev(rhs)], [x])[0]
+    assert rep.status == gpu_lib.OK
+    err = np.linalg.norm(host(x) - ores.x) / np.linalg.norm(ores.x)
+    if precision == 0:
+        assert rep.iterations == ores.iterations and err <= 1e-9, (rep.iterations, ores.iterations, err)
+    else:
+        assert abs(rep.iterations - ores.iterations) <= 2 and err <= 1e-5, (rep.iterations, ores.iterations, err)
+    assert np.linalg.norm(op.apply(host(x)) - rhs) <= 1.05e-7 * np.linalg.norm(rhs)
+
+
 def test_max_iters_reached(gpu_lib):
     pr = problem(1, 64, 32)
     op = EllipticOperator(64, 32, pr["depth"], 600.0)
