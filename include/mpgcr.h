@@ -98,9 +98,10 @@ enum {
 /* flags */
 #define GCR_F_RECORD_HISTORY 0x1u  /* keep ||r_nu||/||r_0|| per iteration in reports  */
 #define GCR_F_ONE_STREAM 0x2u      /* solve the whole batch on the solver's stream; by
-                                      default a batch is split into up to four groups
-                                      of members solved on streams of the library,
-                                      forked from and joined back to that stream   */
+                                      default a large batch is split into two groups
+                                      of members, one solved on that stream, one on a
+                                      stream of the library forked from and joined
+                                      back to it                                   */
 #define GCR_F_LINF_EXIT 0x4u       /* exit test in the maximum norm, max|r| <= rtol
                                       max|r_0| (paper Section 4.1 discussion: the
                                       alternative exit condition); the iteration,

@@ -87,7 +87,7 @@ struct gcr_solver {
   int* morder = nullptr;
   hipEvent_t fork_ev = nullptr;
   // one host thread per group beyond the first enqueues that group's work
-  // (one thread cannot enqueue four groups' launches as fast as the GPU runs them)
+  // (one thread cannot enqueue several groups' launches as fast as the GPU runs them)
   std::vector<std::thread> workers;
   std::mutex mu;
   std::condition_variable cv_job, cv_done;
@@ -383,14 +383,17 @@ static void free_all(gcr_solver* s) {
 
 // Up to GROUPS_MAX groups of members, of about equal point counts, each with
 // a stream (group 0: the solver's own; the others: streams of the library,
-// default priority), two cycle events and two pinned rings.  Four streams in
-// all match the hardware queues a process gets by default, so no two groups
-// share one.  Every group launches each kernel once per row class it holds,
-// and the host enqueues a launch in a few microseconds whatever its size: the
-// batch is split only while each group keeps about GROUP_PTS points per
-// class and launch, below which the GPU would wait for the host.  The learned
-// preconditioner keeps one group: its network runs over the whole batch.
-constexpr int GROUPS_MAX = 4;
+// default priority), two cycle events and two pinned rings.  Two groups
+// overlap one group's kernel drains with the other's work; more groups add
+// launches faster than the host enqueues them (three and four measured
+// slower on 64 x 512x256), and beyond four streams groups would share the
+// process's hardware queues.  Every group launches each kernel once per row
+// class it holds, and the host enqueues a launch in a few microseconds
+// whatever its size: the batch is split only while each group keeps about
+// GROUP_PTS points per class and launch, below which the GPU would wait for
+// the host.  The learned preconditioner keeps one group: its network runs
+// over the whole batch.
+constexpr int GROUPS_MAX = 2;
 constexpr long long GROUP_PTS = 1LL << 21;
 
 static hipError_t make_groups(gcr_solver* s) {

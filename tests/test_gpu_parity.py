@@ -295,7 +295,7 @@ def test_largest_batch_of_smallest_grids(gpu_lib):
 
 @pytest.mark.parametrize("precision", [0, 3, 4])
 def test_member_groups_equal_one_stream(gpu_lib, precision):
-    """A batch large enough to be split into member groups on four streams
+    """A batch large enough to be split into member groups on two streams
     (64 x 512x256) gives bitwise the solutions and reports of the same solve
     on one stream, on every one of repeated solves."""
     B, nx, ny = 64, 512, 256
