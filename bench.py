@@ -269,7 +269,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(independent solves shard across GPUs without communication; see the design notes)",
+              "(independent solves would shard across GPUs without communication)",
               file=sys.stderr)
         sys.exit(2)
     import torch
