@@ -76,13 +76,17 @@ enum {
                             the Krylov iteration keeps float32 coefficients: half
                             precision only in the preconditioner, the step the
                             paper finds most robust to reduced precision          */
-  GCR_SINGLE = 4         /* the paper's single-precision solver cycle (Section 4.2,
+  GCR_SINGLE = 4,        /* the paper's single-precision solver cycle (Section 4.2,
                             option two): operator and preconditioner in float32
                             (coefficients formed from the float32 depth),
                             float32 Krylov vectors, inner products and
                             preconditioner intermediates, float32 solution
                             increments added to the float64 solution at exit;
                             float64 initial and final residual                    */
+  GCR_SINGLE_POLAR64 = 5 /* as GCR_SINGLE, but the rows within polar_rows of either
+                            pole compute the operator and the preconditioner in
+                            float64 from float64 coefficients (Section 4.2,
+                            option three); vectors stay float32                   */
 };
 
 /* preconditioners (paper Section 2.3, options 0-3; 4 is a learned network) */

@@ -199,6 +199,8 @@ struct PrecF64 {              // everything float64
   static constexpr bool mixed = false;
   static constexpr bool op_f32 = false;   // operator coefficients in float32 (not float16)
   static constexpr bool pc_f32 = false;   // preconditioner coefficients in float32 (not float16)
+  static constexpr bool polar64 = false;  // polar rows in float64 (Polar64<P>)
+  static constexpr bool coef64 = false;   // scaled float64 coefficients (the polar rows of polar64 forms)
 };
 struct PrecMixed {            // float32 vectors and inner products, float16 coefficients
   using V = float;
@@ -208,6 +210,8 @@ struct PrecMixed {            // float32 vectors and inner products, float16 coe
   static constexpr bool mixed = true;
   static constexpr bool op_f32 = false;
   static constexpr bool pc_f32 = false;
+  static constexpr bool polar64 = false;
+  static constexpr bool coef64 = false;
 };
 struct PrecMixedD {           // as PrecMixed with float64 inner products
   using V = float;
@@ -217,6 +221,8 @@ struct PrecMixedD {           // as PrecMixed with float64 inner products
   static constexpr bool mixed = true;
   static constexpr bool op_f32 = false;
   static constexpr bool pc_f32 = false;
+  static constexpr bool polar64 = false;
+  static constexpr bool coef64 = false;
 };
 struct PrecMixedP {           // as PrecMixedD, float16 only in the preconditioner
   using V = float;
@@ -226,6 +232,8 @@ struct PrecMixedP {           // as PrecMixedD, float16 only in the precondition
   static constexpr bool mixed = true;
   static constexpr bool op_f32 = true;
   static constexpr bool pc_f32 = false;
+  static constexpr bool polar64 = false;
+  static constexpr bool coef64 = false;
 };
 struct PrecSingle {           // float32 throughout the solver cycle (paper Section 4.2, option two)
   using V = float;
@@ -235,6 +243,64 @@ struct PrecSingle {           // float32 throughout the solver cycle (paper Sect
   static constexpr bool mixed = true;
   static constexpr bool op_f32 = true;
   static constexpr bool pc_f32 = true;
+  static constexpr bool polar64 = false;
+  static constexpr bool coef64 = false;
+};
+struct PrecSingleD : PrecSingle {   // as PrecSingle, float64 in the polar bands (option three)
+  static constexpr bool polar64 = true;
+};
+// The polar rows of a polar64 form: float64 arithmetic on float64
+// coefficients (scaled like the float32 ones), the form's storage types.
+template <typename P>
+struct Polar64 {
+  using V = typename P::V;
+  using A = double;
+  using Q = typename P::Q;
+  using T = double;
+  static constexpr bool mixed = true;
+  static constexpr bool op_f32 = false;
+  static constexpr bool pc_f32 = false;
+  static constexpr bool polar64 = false;
+  static constexpr bool coef64 = true;
+};
+
+// float64 coefficients formed from the depth pools, times the member's scale
+// dt/(2 a^2) (the mixed forms' units)
+struct CoefScaled64 {
+  CoefFly<double> cv;
+  const double* scale;        // per member
+  const int* rowmap;          // global row -> member
+  __device__ __forceinline__ double helm(int g) const { return scale[rowmap[g]] * cv.helm(g); }
+  template <int M>
+  __device__ __forceinline__ void faces(const RowCtx& R, double (&axe)[M], double (&ayn)[M], double (&ays)[M]) const {
+    cv.template faces<M>(R, axe, ayn, ays);
+    const double s = scale[R.m];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      axe[k] *= s;
+      ayn[k] *= s;
+      ays[k] *= s;
+    }
+  }
+  template <int M>
+  __device__ __forceinline__ void load9(const RowCtx& R, double (&axe)[M], double (&axy)[M], double (&bx)[M],
+                                        double (&ayn)[M], double (&ayxn)[M], double (&byn)[M], double (&ays)[M],
+                                        double (&ayxs)[M], double (&bys)[M]) const {
+    cv.template load9<M>(R, axe, axy, bx, ayn, ayxn, byn, ays, ayxs, bys);
+    const double s = scale[R.m];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      axe[k] *= s;
+      axy[k] *= s;
+      bx[k] *= s;
+      ayn[k] *= s;
+      ayxn[k] *= s;
+      byn[k] *= s;
+      ays[k] *= s;
+      ayxs[k] *= s;
+      bys[k] *= s;
+    }
+  }
 };
 
 // Everything a kernel may touch, passed by value.
@@ -282,6 +348,8 @@ template <typename P, bool FL = false, typename Fn>
 __device__ __forceinline__ void with_coef(const Fields& F, const MemberGeom& G, int j, bool op, Fn&& fn) {
   if constexpr (!P::mixed) {
     fn(CoefFly<double, FL>{F.fly64});
+  } else if constexpr (P::coef64) {
+    fn(CoefScaled64{CoefFly<double>{F.fly64}, F.scale, F.rowmap});
   } else if constexpr (P::pc_f32) {   // float32 coefficients formed from the float32 depth, every row
     fn(CoefFly<float, FL>{F.fly32});
   } else {
@@ -724,7 +792,14 @@ __global__ __launch_bounds__(WG) void k_update_sweep1(Fields F, int do_update, i
   int g, m, lane, w;
   MemberGeom G;
   if (!wave_row(F, g, m, G, lane, w)) return;
-  row_update_sweep1<P, M>(F, make_row(G, m, g, lane, M), G, do_update, slot_nu, qout);
+  const RowCtx R = make_row(G, m, g, lane, M);
+  if constexpr (P::polar64) {
+    if (R.j < G.polar || R.j >= G.ny - G.polar) {
+      row_update_sweep1<Polar64<P>, M>(F, R, G, do_update, slot_nu, qout);
+      return;
+    }
+  }
+  row_update_sweep1<P, M>(F, R, G, do_update, slot_nu, qout);
 }
 
 // ---------------------------------------------------------------------------
@@ -768,7 +843,14 @@ __global__ __launch_bounds__(WG) void k_sweep2(Fields F, int qin, int qout) {
   int g, m, lane, w;
   MemberGeom G;
   if (!wave_row(F, g, m, G, lane, w)) return;
-  row_sweep2<P, M, FL>(F, make_row(G, m, g, lane, M), G, qin, qout);
+  const RowCtx R = make_row(G, m, g, lane, M);
+  if constexpr (P::polar64) {
+    if (R.j < G.polar || R.j >= G.ny - G.polar) {
+      row_sweep2<Polar64<P>, M, false>(F, R, G, qin, qout);
+      return;
+    }
+  }
+  row_sweep2<P, M, FL>(F, R, G, qin, qout);
 }
 
 // ---------------------------------------------------------------------------
@@ -887,6 +969,7 @@ __device__ __forceinline__ void row_apply_L(const Fields& F, const RowCtx& R, co
   // float64 and float32 operators: coefficients from the depth fields;
   // float16 operator storage (the paper's mixed form): the stored arrays
   if constexpr (!P::mixed) body(CoefFly<double, FL>{F.fly64});
+  else if constexpr (P::coef64) body(CoefScaled64{CoefFly<double>{F.fly64}, F.scale, F.rowmap});
   else if constexpr (P::op_f32) body(CoefFly<float, FL>{F.fly32});
   else with_coef<P>(F, G, R.j, true, body);
 }
@@ -896,7 +979,14 @@ __global__ __launch_bounds__(WG) void k_apply_L(Fields F, const void* in, void* 
   int g, m, lane, w;
   MemberGeom G;
   if (!wave_row(F, g, m, G, lane, w)) return;
-  row_apply_L<P, M, FL>(F, make_row(G, m, g, lane, M), G, in, out, mode, nl, sl);
+  const RowCtx R = make_row(G, m, g, lane, M);
+  if constexpr (P::polar64) {
+    if (R.j < G.polar || R.j >= G.ny - G.polar) {
+      row_apply_L<Polar64<P>, M, false>(F, R, G, in, out, mode, nl, sl);
+      return;
+    }
+  }
+  row_apply_L<P, M, FL>(F, R, G, in, out, mode, nl, sl);
 }
 
 // ---------------------------------------------------------------------------

@@ -471,7 +471,7 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   if (P.batch < 1 || P.batch > 4096) return fail(nullptr, GCR_EINVAL, "batch must be in [1, 4096], got %d", P.batch);
   if (!P.nx || !P.ny) return fail(nullptr, GCR_EINVAL, "nx/ny arrays must not be NULL");
   if (P.k < 1 || P.k > KMAX) return fail(nullptr, GCR_EINVAL, "k must be in [1, %d], got %d", KMAX, P.k);
-  if (P.precision < GCR_FP64 || P.precision > GCR_SINGLE)
+  if (P.precision < GCR_FP64 || P.precision > GCR_SINGLE_POLAR64)
     return fail(nullptr, GCR_EINVAL, "unknown precision form %d", P.precision);
   if (P.precond < GCR_PC_NONE || P.precond > GCR_PC_LEARNED)
     return fail(nullptr, GCR_EINVAL, "unsupported preconditioner %d", P.precond);
@@ -583,7 +583,8 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
     s->p[i] = track(dalloc<char>(N * vsz, herr));
     s->lp[i] = track(dalloc<char>(N * vsz, herr));
   }
-  if (P.precision == GCR_MIXED || P.precision == GCR_SINGLE) s->dx = (float*)track(dalloc<float>(N, herr));
+  if (P.precision == GCR_MIXED || P.precision == GCR_SINGLE || P.precision == GCR_SINGLE_POLAR64)
+    s->dx = (float*)track(dalloc<float>(N, herr));
   if (mixed) {
     s->aux_r = (double*)track(dalloc<double>(N, herr));
     s->aux_e = (double*)track(dalloc<double>(N, herr));
@@ -1029,6 +1030,7 @@ extern "C" int gcr_solve(gcr_solver* s, const double* const* rhs, double* const*
     case GCR_MIXED: rc = run_solve<PrecMixed>(s); break;
     case GCR_MIXED_FP64DOT: rc = run_solve<PrecMixedD>(s); break;
     case GCR_SINGLE: rc = run_solve<PrecSingle>(s); break;
+    case GCR_SINGLE_POLAR64: rc = run_solve<PrecSingleD>(s); break;
     default: rc = run_solve<PrecMixedP>(s); break;
   }
   if (rc != GCR_OK) return rc;

@@ -18,7 +18,7 @@ from .build import lib_path
 # status codes / enums (mirroring include/mpgcr.h)
 OK, NOT_CONVERGED, STAGNATED, FALLBACK_USED = 0, 1, 2, 3
 EINVAL, ENOMEM, EHIP, ESTATE = -1, -2, -3, -4
-FP64, MIXED, MIXED_FP64DOT, MIXED_HALF_PC, SINGLE = 0, 1, 2, 3, 4
+FP64, MIXED, MIXED_FP64DOT, MIXED_HALF_PC, SINGLE, SINGLE_POLAR64 = 0, 1, 2, 3, 4, 5
 PC_NONE, PC_DIAG, PC_RICHARDSON, PC_SEMI_IMPLICIT, PC_LEARNED = 0, 1, 2, 3, 4
 F_RECORD_HISTORY = 0x1
 F_ONE_STREAM = 0x2
