@@ -130,7 +130,8 @@ def batch(args):
            "points": pts, "forms": {}}
     ref = None
     for name, prec in (("fp64", lib.FP64), ("mixed_half_pc", lib.MIXED_HALF_PC),
-                       ("mixed_fp64dot", lib.MIXED_FP64DOT), ("mixed", lib.MIXED), ("single", lib.SINGLE)):
+                       ("mixed_fp64dot", lib.MIXED_FP64DOT), ("mixed", lib.MIXED), ("single", lib.SINGLE),
+                       ("single_polar64", lib.SINGLE_POLAR64)):
         s = lib.Solver(sizes, precision=prec, rtol=args.rtol, max_iters=100, one_stream=args.one_stream)
         xs = [torch.zeros_like(r) for r in rhs]
 

@@ -546,3 +546,38 @@ def test_uneven_batch_sampled_against_oracle(gpu_lib):
     for size in ((128, 64), (256, 128), (512, 256)):
         sample.append(next(m for m, p in enumerate(probs) if (p["nx"], p["ny"]) == size))
     _sampled_members_check(gpu_lib, probs, 3, sample, 1e-5)
+
+
+@pytest.mark.parametrize("precision", [4, 5])
+def test_uneven_batch_single_forms(gpu_lib, precision):
+    """The single-precision solver cycles (4: float32 throughout; 5: float64
+    polar bands) on the uneven 64-member batch, every points-per-lane class
+    of its three grid sizes in one launch sequence.  Without residual
+    replacement the true residual stops on a float32 plateau (about 2e-5 at
+    most on this batch), so every member must converge by its own residual
+    with a true residual of at most 1e-4, and one member of each grid size
+    must match the oracle's solution to 1e-6."""
+    probs = batch_problems(3, 64)
+    sizes = [(p["nx"], p["ny"]) for p in probs]
+    s = make_solver(gpu_lib, sizes, precision=precision, max_iters=100)
+    f = make_solver(gpu_lib, sizes)
+    depth = [dev(p["depth"]) for p in probs]
+    for m, p in enumerate(probs):
+        f.set_operator(m, depth[m], p["dt"])
+    rhs = [f.apply_operator(m, dev(p["x_true"])) for m, p in enumerate(probs)]
+    s.set_operators(list(range(len(probs))), depth, [p["dt"] for p in probs])
+    x = [torch.zeros_like(r) for r in rhs]
+    reps = s.solve(rhs, x)
+    for m, rp in enumerate(reps):
+        assert rp.status == gpu_lib.OK and rp.rel_res_true <= 1e-4, (m, rp)
+    for size in ((128, 64), (256, 128), (512, 256)):
+        m = next(i for i, p in enumerate(probs) if (p["nx"], p["ny"]) == size)
+        p = probs[m]
+        op = EllipticOperator(p["nx"], p["ny"], p["depth"], p["dt"])
+        ores = gcr(op, host(rhs[m]), rtol=1e-8)
+        xm = host(x[m])
+        true_res = np.linalg.norm(op.apply(xm) - host(rhs[m])) / ores.r0_norm
+        err = np.linalg.norm(xm - ores.x) / np.linalg.norm(ores.x)
+        print(f"\nprecision={precision} member {m} {size}: true={true_res:.3e} err_vs_oracle={err:.3e}")
+        assert reps[m].rel_res_true == pytest.approx(true_res, rel=1e-6, abs=1e-14)
+        assert err <= 1e-6, (m, err)
