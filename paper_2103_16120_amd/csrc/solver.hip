@@ -980,14 +980,19 @@ static int run_solve(gcr_solver* s) {
       std::unique_lock<std::mutex> lk(s->mu);
       s->cv_done.wait(lk, [&] { return s->job_pending == 0; });
     }
-    if (rc0 != GCR_OK) return rc0;
-    for (int gi = 1; gi < G; ++gi)
-      if (s->job_rc[gi] != GCR_OK) return s->job_rc[gi];
+    // Every group stream is joined back to the solver's stream, also when a
+    // group failed: work already enqueued on it may still read the caller's
+    // buffers after this call returns.
+    int rc = rc0;
+    for (int gi = 1; gi < G && rc == GCR_OK; ++gi) rc = s->job_rc[gi];
     for (gcr_solver::Group& g : s->groups) {
       if (g.st == s->stream) continue;
-      HIPCHK(s, hipEventRecord(g.done_ev, g.st));
-      HIPCHK(s, hipStreamWaitEvent(s->stream, g.done_ev, 0));
+      const hipError_t e1 = hipEventRecord(g.done_ev, g.st);
+      const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(s->stream, g.done_ev, 0) : e1;
+      if (e2 != hipSuccess && rc == GCR_OK)
+        rc = fail(s, GCR_EHIP, "joining member group streams: %s", hipGetErrorString(e2));
     }
+    if (rc != GCR_OK) return rc;
   }
   if (s->dx) {
     // float32 increments added to the solution, then the true residual
