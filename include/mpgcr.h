@@ -230,6 +230,34 @@ int gcr_residual_split(gcr_solver* s, int32_t member, const float* phi_tilde, co
  * pointers [NY][NX]; e must not overlap r.  Asynchronous on the stream. */
 int gcr_apply_precond(gcr_solver* s, int32_t member, const double* r, double* e);
 
+/* The operator and the preconditioner of member `member` in the solver's own
+ * precision form, with the kernels its solve runs (Sections 4.2-4.3: the
+ * storage and arithmetic precision of each quantity as listed for the forms
+ * above).  Device pointers [NY][NX] float64; the output must not overlap the
+ * input.
+ *   gcr_apply_operator_form: y = L(x) as the Krylov iteration applies it to a
+ *     direction: x is rounded to the form's vector type (float32 in every
+ *     form but GCR_FP64), L is evaluated with the form's operator
+ *     coefficients (float16 storage with float32 polar rows in GCR_MIXED and
+ *     GCR_MIXED_FP64DOT; float32 formed from the float32 depth in
+ *     GCR_MIXED_HALF_PC and GCR_SINGLE; float64 polar rows in
+ *     GCR_SINGLE_POLAR64), rounded to the vector type, and returned in
+ *     physical units.
+ *   gcr_apply_precond_form: e = P^{-1}(r) as the solve applies it to a
+ *     residual: r is rounded to the vector type (in the mixed forms' scaled
+ *     units s r, s = dt / (2 a^2)), the preconditioner runs with the form's
+ *     coefficients and intermediate storage (float16 with one scale per row in
+ *     GCR_MIXED, GCR_MIXED_FP64DOT and GCR_MIXED_HALF_PC; float32 in
+ *     GCR_SINGLE; float64 polar rows in GCR_SINGLE_POLAR64), and e is returned
+ *     as held (physical units).  With GCR_PC_LEARNED the network correction
+ *     is applied too.
+ * In GCR_FP64 they equal gcr_apply_operator and gcr_apply_precond.  Both use
+ * the solver's Krylov buffers and are asynchronous on the solver's stream.
+ * Errors: GCR_EINVAL, GCR_ESTATE (no operator; learned without parameters),
+ * GCR_EHIP. */
+int gcr_apply_operator_form(gcr_solver* s, int32_t member, const double* x, double* y);
+int gcr_apply_precond_form(gcr_solver* s, int32_t member, const double* r, double* e);
+
 /* Release every resource of the solver.  NULL is accepted (no-op). */
 int gcr_destroy(gcr_solver* s);
 

@@ -1386,7 +1386,7 @@ constexpr int ASM_ROWS = ASM_WG / 64;   // rows per workgroup, one wave each
 
 __host__ __device__ constexpr int asm_row_lds(int nx) { return nx + 16; }   // doubles per staged row (M <= 16)
 
-__global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
+static __global__ __launch_bounds__(ASM_WG) void k_assemble(AssembleArgs A) {
   // dynamic LDS: Phi* rows j0-1 .. j0+ASM_ROWS, then (with orography) H* rows
   extern __shared__ double asm_lds[];
   const AsmMember P = A.tab[blockIdx.y];
@@ -1557,26 +1557,42 @@ __device__ __forceinline__ long long pool_index(const MemberGeom& G, long long k
 }
 
 // one member, direct pointers
-__global__ void k_to_pool(const double* src, double* pool, MemberGeom G) {
+static __global__ void k_to_pool(const double* src, double* pool, MemberGeom G) {
   const long long n = (long long)G.nx * G.ny;
   for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
     pool[pool_index(G, k)] = src[k];
 }
 
-__global__ void k_to_pool_f32(const float* src, float* pool, MemberGeom G) {
+static __global__ void k_to_pool_f32(const float* src, float* pool, MemberGeom G) {
   const long long n = (long long)G.nx * G.ny;
   for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
     pool[pool_index(G, k)] = src[k];
 }
 
-__global__ void k_from_pool(const double* pool, double* dst, MemberGeom G) {
+static __global__ void k_from_pool(const double* pool, double* dst, MemberGeom G) {
   const long long n = (long long)G.nx * G.ny;
   for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
     dst[k] = pool[pool_index(G, k)];
 }
 
+// natural float64 field -> pooled vector type, times `scale` (rounded once)
+template <typename V>
+__global__ void k_to_pool_v(const double* src, V* pool, MemberGeom G, double scale) {
+  const long long n = (long long)G.nx * G.ny;
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
+    pool[pool_index(G, k)] = (V)(scale * src[k]);
+}
+
+// pooled vector type -> natural float64 field, times `scale`
+template <typename V>
+__global__ void k_from_pool_v(const V* pool, double* dst, MemberGeom G, double scale) {
+  const long long n = (long long)G.nx * G.ny;
+  for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
+    dst[k] = scale * (double)pool[pool_index(G, k)];
+}
+
 // mixed form without float64 accumulator: x += dx at exit, dx = 0
-__global__ void k_apply_increments(Fields F, long long total) {
+static __global__ void k_apply_increments(Fields F, long long total) {
   for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < total;
        k += (long long)gridDim.x * blockDim.x) {
     F.x[k] += (double)F.dx[k];
@@ -1786,7 +1802,7 @@ __global__ void k_ctrl_restart(Fields F, int slot0) {
 }
 
 // final float64 true residual of every member
-__global__ void k_ctrl_true(Fields F) {
+static __global__ void k_ctrl_true(Fields F) {
   const int m = F.morder[F.q0 + blockIdx.x];
   const MemberGeom G = F.geom[m];
   const double rr = member_sum<double>(F, G, DOT_RR);

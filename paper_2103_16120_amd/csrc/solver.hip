@@ -1,331 +1,10 @@
-// Host runtime and C-ABI of the GCR(k) depth solver (see include/mpgcr.h).
-//
-// The solve is driven from the host one GCR cycle at a time: every kernel of
-// an iteration is enqueued on the solver's stream, the per-member scalars
-// (beta, alpha, ||r||, exit decisions) stay on the device, and the host reads
-// the members' "done" flags once per cycle.  Finished members make every
-// later kernel return at once, so a batch runs until its slowest member.
-#include <hip/hip_runtime.h>
+// C-ABI of the GCR(k) depth solver (see include/mpgcr.h): creation,
+// assembly, the solve entry point, stand-alone operator, preconditioner and
+// split-residual calls, the learned preconditioner's set-up and timing.
+#include "solver_impl.h"
 
-#include <algorithm>
-#include <cmath>
-#include <condition_variable>
-#include <functional>
-#include <mutex>
-#include <thread>
-#include <cstdarg>
-#include <cstdio>
-#include <cstring>
-#include <new>
-#include <type_traits>
-#include <string>
-#include <vector>
-
-#include "../../include/mpgcr.h"
-#include "cnn_internal.h"
-#include "kernels.h"
-#include "learned.h"
-
-using namespace mpgcr;
-
-namespace {
-
-thread_local std::string g_create_error;
-
-}  // namespace
-
-// Rows of members with the same points-per-lane M form one contiguous range
-// and are processed by one kernel specialisation.
-struct RowClass {
-  int log2m, row_begin, row_end;
-  int flat;   // every member of the range has no orography (set by refresh_flat)
-};
-
-namespace {
-
-template <typename T>
-T* dalloc(size_t n, hipError_t& err) {
-  void* p = nullptr;
-  if (n == 0) n = 1;
-  hipError_t e = hipMalloc(&p, n * sizeof(T));
-  if (e != hipSuccess && err == hipSuccess) err = e;
-  return (T*)p;
-}
-
-}  // namespace
-
-// Stream of the launches the calling thread enqueues: a group's stream inside
-// a solve, else the solver's stream.
-static thread_local hipStream_t t_stream = nullptr;
-
-struct gcr_solver {
-  gcr_params prm{};
-  std::vector<int> nx, ny;
-  std::vector<MemberGeom> geom_h;
-  std::vector<int> have_op;
-  std::vector<int> flat_h;            // per member: no orography (mirrors `flat` on the device)
-  std::vector<double> scale_h;
-  int rows = 0;
-  long long npts = 0;
-  int nxmax = 0;
-  std::vector<RowClass> classes;     // contiguous row ranges of equal points-per-lane
-  hipStream_t stream = nullptr;
-  // Groups of members with rows contiguous in row order, each solved on a
-  // stream of its own, so that one group's kernel boundaries (the drain of
-  // the last waves, the start of the next kernel) overlap the others' work.
-  // Empty: the whole batch on `stream`.
-  struct Group {
-    int q0 = 0, q1 = 0;                // members morder[q0 .. q1)
-    std::vector<RowClass> classes;     // the group's rows
-    hipStream_t st = nullptr;
-    hipEvent_t cycle_ev[2] = {};
-    int* ring[2] = {};                 // pinned copies of the done flags after a cycle
-    hipEvent_t done_ev = nullptr;
-  };
-  std::vector<Group> groups;
-  std::vector<int> morder_h;         // members in row order
-  int* morder = nullptr;
-  hipEvent_t fork_ev = nullptr;
-  // one host thread per group beyond the first enqueues that group's work
-  // (one thread cannot enqueue several groups' launches as fast as the GPU runs them)
-  std::vector<std::thread> workers;
-  std::mutex mu;
-  std::condition_variable cv_job, cv_done;
-  std::function<int(int)> job;       // job(group) of the current solve
-  std::vector<int> job_rc;
-  long job_gen = 0;
-  int job_pending = 0;
-  bool quit = false;
-  std::mutex err_mu;
-  int device = 0;
-  std::string err;
-
-  // device memory
-  std::vector<void*> allocs;
-  MemberGeom* geom = nullptr;
-  int* rowmap = nullptr;
-  MemberState* state = nullptr;
-  Pending* pend = nullptr;            // per member: recorded step-2 updates
-  int* done_flag = nullptr;           // per member: the done flag the host polls
-  float* split = nullptr;             // split residual: Phi_hat, its NSD differences, Phi_tilde (pooled,
-                                      // allocated by the first gcr_set_split_base)
-  std::vector<int> have_split;
-  double* part = nullptr;
-  double* scale = nullptr;
-  float* a32[NCOEF] = {};
-  __half* a16[NCOEF] = {};
-  double* c64 = nullptr;
-  float* c32 = nullptr;
-  double* phi64 = nullptr;           // depth fields for the on-the-fly coefficients
-  double* hs64 = nullptr;
-  float* phi32 = nullptr;
-  float* hs32 = nullptr;
-  int* flat = nullptr;                // per member: no orography (H* = Phi*)
-  double* fac64 = nullptr;           // [rows][NFAC] latitude factors
-  float* fac32 = nullptr;
-  double* x = nullptr;
-  double* rhs = nullptr;
-  double* r64 = nullptr;
-  void* r = nullptr;
-  void* e = nullptr;
-  void* le = nullptr;
-  void* q[2] = {};
-  float* qs[2] = {};
-  void* p[KMAX + 1] = {};
-  void* lp[KMAX + 1] = {};
-  float* dx = nullptr;
-  double* hist = nullptr;
-  int hist_stride = 0;
-  // float64 scratch for stand-alone preconditioner calls in the mixed forms
-  double* aux_r = nullptr;
-  double* aux_e = nullptr;
-  double* aux_q[2] = {};
-  const double** ptr_rhs = nullptr;  // device tables of caller pointers
-  double** ptr_x = nullptr;
-  const void** ptr_stage = nullptr;  // pinned host staging for the tables
-  MemberState* state_h = nullptr;    // pinned host copy
-  int* state_ring[2] = {};           // pinned copies of the done flags after a cycle
-  hipEvent_t cycle_ev[2] = {};       // recorded after each copy
-  AsmMember* asm_stage = nullptr;    // pinned staging of the assembly table
-  hipEvent_t stage_ev[2] = {};       // recorded after the uploads from ptr_stage / asm_stage
-  AsmMember* asm_tab = nullptr;      // device assembly table [batch]
-  cnn_net* net = nullptr;            // learned preconditioner (GCR_PC_LEARNED), owned
-  int* learn_active = nullptr;       // [batch] images the network runs on in one application
-  double fallback_ratio = 0.5;
-
-  // optional per-kernel timing with HIP events on the solver's stream
-  bool timing = false;
-  std::vector<hipEvent_t> ev;        // pool, pairs (start, stop)
-  std::vector<int> ev_kind;          // kind of each recorded pair
-  size_t ev_used = 0;
-  int64_t kt_count[KT_COUNT] = {};
-  double kt_ms[KT_COUNT] = {};
-  void tm_begin(int kind) {
-    if (!timing) return;
-    if (ev_used + 2 > ev.size()) {
-      for (int i = 0; i < 256; ++i) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) { timing = false; return; }
-        ev.push_back(e);
-      }
-    }
-    if (ev_kind.size() < ev.size() / 2) ev_kind.resize(ev.size() / 2);
-    ev_kind[ev_used / 2] = kind;
-    (void)hipEventRecord(ev[ev_used], t_stream ? t_stream : stream);
-  }
-  void tm_end() {
-    if (!timing) return;
-    (void)hipEventRecord(ev[ev_used + 1], t_stream ? t_stream : stream);
-    ev_used += 2;
-  }
-  void tm_collect() {  // after a stream synchronisation
-    for (size_t i = 0; i + 1 < ev_used; i += 2) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) {
-        kt_count[ev_kind[i / 2]] += 1;
-        kt_ms[ev_kind[i / 2]] += ms;
-      }
-    }
-    ev_used = 0;
-  }
-};
-
-static hipStream_t cur_stream(const gcr_solver* s) { return t_stream ? t_stream : s->stream; }
 static void worker_main(gcr_solver* s, int w);
 static void stop_workers(gcr_solver* s);
-
-static int fail(gcr_solver* s, int code, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
-  va_end(ap);
-  if (s) {
-    std::lock_guard<std::mutex> lk(s->err_mu);
-    s->err = buf;
-  } else {
-    g_create_error = buf;
-  }
-  return code;
-}
-
-#define HIPCHK(s, call)                                                                        \
-  do {                                                                                         \
-    hipError_t e_ = (call);                                                                    \
-    if (e_ != hipSuccess) return fail((s), GCR_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
-
-#define KLAUNCH(s, kind, ...)   \
-  do {                          \
-    (s)->tm_begin(kind);        \
-    hipLaunchKernelGGL(__VA_ARGS__); \
-    (s)->tm_end();              \
-  } while (0)
-
-// Launch a kernel through a pointer to its specialisation, timed if enabled.
-template <typename... KArgs, typename... Args>
-static void launch(gcr_solver* s, int kind, void (*kern)(KArgs...), dim3 grid, dim3 block, Args... args) {
-  s->tm_begin(kind);
-  hipLaunchKernelGGL(kern, grid, block, 0, cur_stream(s), args...);
-  s->tm_end();
-}
-
-// One launch of row kernel KNAME<P, M> per row class, each covering that
-// class's rows (one wave per row).
-static_assert(KT_COUNT == GCR_K_COUNT, "kernel kinds match the header");
-
-#define ROWS_LAUNCH(s, CLASSES, F, KIND, KNAME, P, ...)                                     \
-  for (const RowClass& c_ : (CLASSES)) {                                                 \
-    Fields f_ = (F);                                                                     \
-    f_.row_base = c_.row_begin;                                                          \
-    f_.row_end = c_.row_end;                                                             \
-    const dim3 g_((c_.row_end - c_.row_begin + WPB - 1) / WPB), b_(WG);                  \
-    switch (c_.log2m) {                                                                  \
-      case 1: launch(s, KIND, &KNAME<P, 2>, g_, b_, f_, ##__VA_ARGS__); break;            \
-      case 2: launch(s, KIND, &KNAME<P, 4>, g_, b_, f_, ##__VA_ARGS__); break;            \
-      case 3: launch(s, KIND, &KNAME<P, 8>, g_, b_, f_, ##__VA_ARGS__); break;            \
-      default: launch(s, KIND, &KNAME<P, 16>, g_, b_, f_, ##__VA_ARGS__); break;          \
-    }                                                                                    \
-  }
-
-static std::vector<RowClass> member_class(const gcr_solver* s, int member) {
-  const MemberGeom& G = s->geom_h[member];
-  return {RowClass{G.log2m, G.row0, G.row0 + G.ny, s->flat_h[member]}};
-}
-
-// As ROWS_LAUNCH, for the kernels that evaluate the stencil with coefficients
-// formed from the depth fields: a class whose members all lack orography takes
-// the variant that reads Phi* only (FL = true), which holds fewer registers.
-#define ROWS_LAUNCH_F(s, CLASSES, F, KIND, KNAME, P, ...)                                   \
-  for (const RowClass& c_ : (CLASSES)) {                                                 \
-    Fields f_ = (F);                                                                     \
-    f_.row_base = c_.row_begin;                                                          \
-    f_.row_end = c_.row_end;                                                             \
-    const dim3 g_((c_.row_end - c_.row_begin + WPB - 1) / WPB), b_(WG);                  \
-    switch (std::min(c_.log2m, 4) * 2 + (c_.flat ? 1 : 0)) {                             \
-      case 2: launch(s, KIND, &KNAME<P, 2, false>, g_, b_, f_, ##__VA_ARGS__); break;     \
-      case 3: launch(s, KIND, &KNAME<P, 2, true>, g_, b_, f_, ##__VA_ARGS__); break;      \
-      case 4: launch(s, KIND, &KNAME<P, 4, false>, g_, b_, f_, ##__VA_ARGS__); break;     \
-      case 5: launch(s, KIND, &KNAME<P, 4, true>, g_, b_, f_, ##__VA_ARGS__); break;      \
-      case 6: launch(s, KIND, &KNAME<P, 8, false>, g_, b_, f_, ##__VA_ARGS__); break;     \
-      case 7: launch(s, KIND, &KNAME<P, 8, true>, g_, b_, f_, ##__VA_ARGS__); break;      \
-      case 9: launch(s, KIND, &KNAME<P, 16, true>, g_, b_, f_, ##__VA_ARGS__); break;     \
-      default: launch(s, KIND, &KNAME<P, 16, false>, g_, b_, f_, ##__VA_ARGS__); break;   \
-    }                                                                                    \
-  }
-
-static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
-static int ilog2(int v) {
-  int l = 0;
-  while ((1 << l) < v) ++l;
-  return l;
-}
-
-static Fields make_fields(gcr_solver* s) {
-  Fields F{};
-  F.geom = s->geom;
-  F.rowmap = s->rowmap;
-  F.state = s->state;
-  F.pend = s->pend;
-  F.done_flag = s->done_flag;
-  F.part = s->part;
-  F.scale = s->scale;
-  for (int k = 0; k < NCOEF; ++k) {
-    F.cmx.h[k] = s->a16[k];
-    F.cmx.f[k] = s->a32[k];
-  }
-  F.cmx.c = s->c32;
-  F.fly64 = FlyPools<double>{s->phi64, s->hs64, s->fac64, s->c64, s->flat};
-  F.fly32 = FlyPools<float>{s->phi32, s->hs32, s->fac32, s->c32, s->flat};
-  F.x = s->x;
-  F.rhs = s->rhs;
-  F.rhs_tab = s->ptr_rhs;
-  F.x_tab = s->ptr_x;
-  F.morder = s->morder;
-  F.q0 = 0;
-  F.r64 = s->r64;
-  F.r = s->r;
-  F.e = s->e;
-  F.le = s->le;
-  for (int i = 0; i < 2; ++i) {
-    F.q[i] = s->q[i];
-    F.qs[i] = s->qs[i];
-  }
-  for (int i = 0; i <= s->prm.k; ++i) {
-    F.p[i] = s->p[i];
-    F.lp[i] = s->lp[i];
-  }
-  F.dx = s->dx;   // float32 solution increments (GCR_MIXED, GCR_SINGLE), else null
-  F.hist = s->hist;
-  F.hist_stride = s->hist_stride;
-  F.row_base = 0;
-  F.row_end = s->rows;
-  F.ignore_done = 0;
-  F.learned = s->prm.precond == GCR_PC_LEARNED ? 1 : 0;
-  F.linf = (s->prm.flags & GCR_F_LINF_EXIT) ? 1 : 0;
-  F.fallback_ratio = s->fallback_ratio;
-  return F;
-}
 
 extern "C" int gcr_default_params(gcr_params* p) {
   if (!p) return GCR_EINVAL;
@@ -743,174 +422,6 @@ extern "C" int gcr_set_operator(gcr_solver* s, int32_t member, const gcr_operato
   return gcr_set_operators(s, 1, &member, op);
 }
 
-// ---------------------------------------------------------------------------
-// kernel sequences
-// ---------------------------------------------------------------------------
-// Learned correction of the preconditioner output F.e (members
-// [member0, member0 + count)): residual scale, network input, five
-// convolutions over the whole batch of images, update of e.  `use_part`: the
-// per-row <r,r> partials of F.r are current (inside a solve).
-template <typename P>
-static void learned_correction(gcr_solver* s, const std::vector<RowClass>& cls, const Fields& F, int use_part,
-                               int member0, int count) {
-  LearnArgs A{};
-  A.r = F.r;
-  A.e = F.e;
-  A.feat = s->net->act[0];
-  A.feat_stride = s->net->in_stride;
-  A.y = s->net->y;
-  A.use_part = use_part;
-  A.active = s->learn_active;
-  KLAUNCH(s, KT_LEARNED, k_learn_sigma<P>, dim3(s->prm.batch), dim3(64), 0, cur_stream(s), F, A, member0, count);
-  ROWS_LAUNCH(s, cls, F, KT_LEARNED, k_learn_pack, P, A);
-  s->tm_begin(KT_LEARNED);
-  (void)cnn_forward_packed(s->net, s->prm.batch, s->net->y, cur_stream(s), s->learn_active);
-  s->tm_end();
-  ROWS_LAUNCH(s, cls, F, KT_LEARNED, k_learn_apply, P, A);
-}
-
-// e = P^{-1}(r) on the rows of `cls`, optionally fused with the step-2
-// update along ring slot `slot_nu`.  With the learned preconditioner and
-// `learned` >= 0 the network correction follows (learned = 1: partials of
-// <r,r> current); members [member0, member0 + count) are corrected.
-template <typename P>
-static void launch_precond(gcr_solver* s, const std::vector<RowClass>& cls, const Fields& F, int do_update,
-                           int slot_nu, int learned = 1, int member0 = 0, int count = -1) {
-  const int ri = s->prm.richardson_iters;
-  switch (s->prm.precond) {
-    case GCR_PC_NONE:
-    case GCR_PC_DIAG:
-      ROWS_LAUNCH(s, cls, F, KT_SWEEP1, k_update_simple, P, do_update, slot_nu,
-                  s->prm.precond == GCR_PC_DIAG ? 1 : 0, -1);
-      break;
-    case GCR_PC_RICHARDSON: {
-      // q_1 = r / diag(L); q_{mu+1} = q_mu - (L q_mu - r) / diag(L)
-      ROWS_LAUNCH(s, cls, F, KT_SWEEP1, k_update_simple, P, do_update, slot_nu, 1, ri == 1 ? -1 : 0);
-      int cur = 0;
-      for (int mu = 1; mu < ri; ++mu) {
-        const int nxt = mu + 1 == ri ? -1 : cur ^ 1;
-        ROWS_LAUNCH_F(s, cls, F, KT_SWEEP2, k_jacobi, P, cur, nxt);
-        cur ^= 1;
-      }
-      break;
-    }
-    default: {
-      ROWS_LAUNCH(s, cls, F, KT_SWEEP1, k_update_sweep1, P, do_update, slot_nu, ri == 1 ? -1 : 0);
-      int cur = 0;
-      for (int mu = 1; mu < ri; ++mu) {
-        const int nxt = mu + 1 == ri ? -1 : cur ^ 1;
-        ROWS_LAUNCH_F(s, cls, F, KT_SWEEP2, k_sweep2, P, cur, nxt);
-        cur ^= 1;
-      }
-      if (s->prm.precond == GCR_PC_LEARNED && learned >= 0 && s->net)
-        learned_correction<P>(s, cls, F, learned, member0, count < 0 ? s->prm.batch : count);
-    }
-  }
-}
-
-// The solve of one group of members is enqueued one GCR cycle at a time on
-// the group's stream.  After the k iterations of a cycle (and, in the
-// residual-replacement forms, the float64 restart) the members' scalars are
-// copied to pinned host memory and an event is recorded.  Before waiting for
-// that event the host already enqueues the first iteration of the next cycle,
-// so the GPU keeps working while the host decides; members that have finished
-// make every later kernel return at once, so speculative work on converged
-// members costs only empty launches.
-template <typename P>
-static int run_group(gcr_solver* s, const gcr_solver::Group& g) {
-  using A = typename P::A;
-  struct StreamScope {   // this thread's launches go to the group's stream
-    explicit StreamScope(hipStream_t st) { t_stream = st; }
-    ~StreamScope() { t_stream = nullptr; }
-  } scope(g.st);
-  const int k = s->prm.k, B = s->prm.batch, maxit = s->prm.max_iters;
-  Fields F = make_fields(s);
-  F.q0 = g.q0;
-  const bool replace = s->prm.precision == GCR_MIXED_FP64DOT || s->prm.precision == GCR_MIXED_HALF_PC;
-  const dim3 ctl(g.q1 - g.q0), wave(64);
-  const std::vector<RowClass>& cls = g.classes;
-
-  // step 1: r_0 = L(x_0) - R (float64), p_0 = P^{-1}(r_0), L(p_0)
-  ROWS_LAUNCH_F(s, cls, F, KT_RESIDUAL, k_residual, P, 1, -1, 0, RES_X_IN | RES_RHS_TAB);
-  KLAUNCH(s, KT_CONTROL, k_ctrl_init<double>, ctl, wave, 0, g.st, F);
-  {
-    Fields F0 = F;
-    F0.e = s->p[0];   // p_0 = P^{-1}(r_0) written in place
-    launch_precond<P>(s, cls, F0, 0, 0);
-  }
-  Slots sl0{};
-  ROWS_LAUNCH_F(s, cls, F, KT_APPLY_L, k_apply_L, P, (const void*)s->p[0], s->lp[0], 1, 0, sl0);
-  KLAUNCH(s, KT_CONTROL, k_ctrl_beta<A>, ctl, wave, 0, g.st, F, 0);
-  HIPCHK(s, hipGetLastError());
-
-  // iteration `it` (1-based) at window position nu of cycle `cyc`, whose p_0
-  // sits in ring slot `base`
-  auto iteration = [&](int it, int nu, int base, int cyc) {
-    Slots sl{};
-    for (int l = 0; l <= k; ++l) sl.s[l] = (base + l) % (k + 1);
-    (void)it;
-    // step 2 (+ first row solve of step 3)
-    launch_precond<P>(s, cls, F, 1, sl.s[nu]);
-    // step 3: L(e) with <L e, L p_l>, l = 0..nu
-    ROWS_LAUNCH_F(s, cls, F, KT_APPLY_L, k_apply_L, P, (const void*)s->e, s->le, 0, nu + 1, sl);
-    KLAUNCH(s, KT_CONTROL, k_ctrl_alpha<A>, ctl, wave, 0, g.st, F, nu + 1, sl, nu == k - 1 ? 1 : 0,
-            s->prm.min_iters, maxit, s->prm.rtol, cyc);
-    // step 4
-    if (nu == k - 1) {   // the cycle's last iteration also applies its solution updates
-      ROWS_LAUNCH(s, cls, F, KT_ORTH, k_orth_last, P, nu + 1, sl, sl.s[nu + 1]);
-    } else {
-      ROWS_LAUNCH(s, cls, F, KT_ORTH, k_orth, P, nu + 1, sl, sl.s[nu + 1]);
-    }
-    KLAUNCH(s, KT_CONTROL, k_ctrl_beta<A>, ctl, wave, 0, g.st, F, sl.s[nu + 1]);
-  };
-  // end of cycle `cyc`: its solution updates; (p_0, L p_0) := (p_k, L p_k);
-  // residual replacement; flags
-  auto cycle_end = [&](int base_next, int ring, int cyc) -> int {
-    ROWS_LAUNCH(s, cls, F, KT_SOLUTION, k_apply_pending, P, cyc);
-    if (replace) {
-      ROWS_LAUNCH_F(s, cls, F, KT_RESIDUAL, k_residual, P, 1, base_next, 1, RES_RHS_TAB);
-      KLAUNCH(s, KT_CONTROL, k_ctrl_restart<double>, ctl, wave, 0, g.st, F, base_next);
-    }
-    // the done flags (a few bytes per member: a small copy); only the group's
-    // own members are read from them
-    HIPCHK(s, hipMemcpyAsync(g.ring[ring], s->done_flag, B * sizeof(int), hipMemcpyDeviceToHost, g.st));
-    HIPCHK(s, hipEventRecord(g.cycle_ev[ring], g.st));
-    return GCR_OK;
-  };
-
-  int it = 0, base = 0, cycle = 0, rc;
-  // cycle 0, complete
-  for (int nu = 0; nu < k && it < maxit; ++nu) iteration(++it, nu, base, 0);
-  base = (base + k) % (k + 1);
-  if ((rc = cycle_end(base, 0, 0)) != GCR_OK) return rc;
-  HIPCHK(s, hipGetLastError());
-  for (;;) {
-    // speculative first iteration of the next cycle
-    const bool more = it < maxit;
-    if (more) iteration(++it, 0, base, cycle + 1);
-    HIPCHK(s, hipEventSynchronize(g.cycle_ev[cycle & 1]));
-    bool done = true;
-    for (int q = g.q0; q < g.q1; ++q) done = done && g.ring[cycle & 1][s->morder_h[q]] != 0;
-    if (done || !more) break;
-    for (int nu = 1; nu < k && it < maxit; ++nu) iteration(++it, nu, base, cycle + 1);
-    base = (base + k) % (k + 1);
-    ++cycle;
-    if ((rc = cycle_end(base, cycle & 1, cycle)) != GCR_OK) return rc;
-    HIPCHK(s, hipGetLastError());
-  }
-  // No update is pending here: the loop leaves right after a cycle end, or
-  // after a speculative iteration that every member skipped (all were done
-  // at that cycle end).  The true residual of the group's members in float64
-  // (float32 increments: after they are added, over the whole batch):
-  if (!s->dx) {
-    ROWS_LAUNCH_F(s, cls, F, KT_RESIDUAL, k_residual, P, 0, -1, 0, RES_X_OUT | RES_RHS_TAB);
-    KLAUNCH(s, KT_CONTROL, k_ctrl_true, ctl, wave, 0, g.st, F);
-    HIPCHK(s, hipGetLastError());
-  }
-  return GCR_OK;
-}
-
-// Worker thread w enqueues group w + 1 of each solve.
 static void worker_main(gcr_solver* s, int w) {
   long seen = 0;
   for (;;) {
@@ -946,67 +457,6 @@ static void stop_workers(gcr_solver* s) {
 // by its own host thread), joined back on the solver's stream.  Per-kernel
 // timing runs one group on the solver's stream (the timing events need one
 // stream and one thread).
-template <typename P>
-static int run_solve(gcr_solver* s) {
-  const int B = s->prm.batch;
-  const bool split = !s->groups.empty() && !s->timing;
-  if (!split) {
-    gcr_solver::Group whole;
-    whole.q0 = 0;
-    whole.q1 = B;
-    whole.classes = s->classes;
-    whole.st = s->stream;
-    for (int i = 0; i < 2; ++i) {
-      whole.cycle_ev[i] = s->cycle_ev[i];
-      whole.ring[i] = s->state_ring[i];
-    }
-    const int rc = run_group<P>(s, whole);
-    if (rc != GCR_OK) return rc;
-  } else {
-    HIPCHK(s, hipEventRecord(s->fork_ev, s->stream));
-    for (gcr_solver::Group& g : s->groups)
-      if (g.st != s->stream) HIPCHK(s, hipStreamWaitEvent(g.st, s->fork_ev, 0));
-    const int G = (int)s->groups.size();
-    {
-      std::lock_guard<std::mutex> lk(s->mu);
-      s->job = [s](int gi) { return run_group<P>(s, s->groups[gi]); };
-      s->job_rc.assign(G, GCR_OK);
-      s->job_pending = G - 1;
-      ++s->job_gen;
-    }
-    s->cv_job.notify_all();
-    const int rc0 = run_group<P>(s, s->groups[0]);
-    {
-      std::unique_lock<std::mutex> lk(s->mu);
-      s->cv_done.wait(lk, [&] { return s->job_pending == 0; });
-    }
-    // Every group stream is joined back to the solver's stream, also when a
-    // group failed: work already enqueued on it may still read the caller's
-    // buffers after this call returns.
-    int rc = rc0;
-    for (int gi = 1; gi < G && rc == GCR_OK; ++gi) rc = s->job_rc[gi];
-    for (gcr_solver::Group& g : s->groups) {
-      if (g.st == s->stream) continue;
-      const hipError_t e1 = hipEventRecord(g.done_ev, g.st);
-      const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(s->stream, g.done_ev, 0) : e1;
-      if (e2 != hipSuccess && rc == GCR_OK)
-        rc = fail(s, GCR_EHIP, "joining member group streams: %s", hipGetErrorString(e2));
-    }
-    if (rc != GCR_OK) return rc;
-  }
-  if (s->dx) {
-    // float32 increments added to the solution, then the true residual
-    const Fields F = make_fields(s);
-    const dim3 ctl(B), wave(64);
-    const dim3 g((unsigned)std::min<long long>((s->npts + 255) / 256, 65535));
-    KLAUNCH(s, KT_COPY, k_apply_increments, g, dim3(256), 0, s->stream, F, s->npts);
-    ROWS_LAUNCH_F(s, s->classes, F, KT_RESIDUAL, k_residual, P, 0, -1, 0, RES_X_OUT | RES_RHS_TAB);
-    KLAUNCH(s, KT_CONTROL, k_ctrl_true, ctl, wave, 0, s->stream, F);
-    HIPCHK(s, hipGetLastError());
-  }
-  return GCR_OK;
-}
-
 extern "C" int gcr_solve(gcr_solver* s, const double* const* rhs, double* const* x, gcr_report* reports) {
   if (!s) return GCR_EINVAL;
   if (!rhs || !x) return fail(s, GCR_EINVAL, "gcr_solve: NULL rhs or x table");
@@ -1188,6 +638,30 @@ extern "C" int gcr_apply_precond(gcr_solver* s, int32_t member, const double* r,
   KLAUNCH(s, KT_COPY, k_from_pool, cg, dim3(256), 0, s->stream, (const double*)F.e, e, G);
   HIPCHK(s, hipGetLastError());
   return GCR_OK;
+}
+
+// the operator or preconditioner in the solver's precision form
+static int apply_in_form(gcr_solver* s, int32_t member, int what, const double* in, double* out) {
+  int rc = check_member(s, member, in, out);
+  if (rc != GCR_OK) return rc;
+  if (what == 1 && s->prm.precond == GCR_PC_LEARNED && !s->net)
+    return fail(s, GCR_ESTATE, "learned preconditioner without parameters (call gcr_set_learned)");
+  switch (s->prm.precision) {
+    case GCR_FP64: return apply_form<PrecF64>(s, member, what, in, out);
+    case GCR_MIXED: return apply_form<PrecMixed>(s, member, what, in, out);
+    case GCR_MIXED_FP64DOT: return apply_form<PrecMixedD>(s, member, what, in, out);
+    case GCR_SINGLE: return apply_form<PrecSingle>(s, member, what, in, out);
+    case GCR_SINGLE_POLAR64: return apply_form<PrecSingleD>(s, member, what, in, out);
+    default: return apply_form<PrecMixedP>(s, member, what, in, out);
+  }
+}
+
+extern "C" int gcr_apply_operator_form(gcr_solver* s, int32_t member, const double* x, double* y) {
+  return apply_in_form(s, member, 0, x, y);
+}
+
+extern "C" int gcr_apply_precond_form(gcr_solver* s, int32_t member, const double* r, double* e) {
+  return apply_in_form(s, member, 1, r, e);
 }
 
 // ---------------------------------------------------------------------------

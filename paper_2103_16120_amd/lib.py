@@ -66,6 +66,8 @@ _SIGNATURES = {
     "gcr_set_split_base": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "gcr_residual_split": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "gcr_apply_precond": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "gcr_apply_operator_form": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "gcr_apply_precond_form": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "gcr_destroy": (C.c_int, [C.c_void_p]),
     "gcr_status_string": (C.c_char_p, [C.c_int]),
     "gcr_last_error": (C.c_char_p, [C.c_void_p]),
@@ -350,6 +352,26 @@ class Solver:
         _check_field(r, ny, nx, "r")
         e = torch.empty_like(r) if out is None else out
         rc = _lib.gcr_apply_precond(self._h, member, r.data_ptr(), e.data_ptr())
+        if rc < 0:
+            raise self._err(rc)
+        return e
+
+    def apply_operator_form(self, member, x, out=None):
+        """L(x) with the operator the solve of this precision form applies."""
+        nx, ny = self.sizes[member]
+        _check_field(x, ny, nx, "x")
+        y = torch.empty_like(x) if out is None else out
+        rc = _lib.gcr_apply_operator_form(self._h, member, x.data_ptr(), y.data_ptr())
+        if rc < 0:
+            raise self._err(rc)
+        return y
+
+    def apply_precond_form(self, member, r, out=None):
+        """P^{-1}(r) with the preconditioner the solve of this precision form applies."""
+        nx, ny = self.sizes[member]
+        _check_field(r, ny, nx, "r")
+        e = torch.empty_like(r) if out is None else out
+        rc = _lib.gcr_apply_precond_form(self._h, member, r.data_ptr(), e.data_ptr())
         if rc < 0:
             raise self._err(rc)
         return e

@@ -16,6 +16,8 @@ from oracle.precond import Preconditioner
 from oracle.gcr import gcr, CONVERGED
 from workloads import problem, batch_problems
 
+from form_emul import stencil_magnitude
+
 pytestmark = pytest.mark.gpu
 
 EPS = np.finfo(np.float64).eps
@@ -28,31 +30,6 @@ def dev(a):
 def host(t):
     torch.cuda.synchronize()
     return t.cpu().numpy()
-
-
-def stencil_magnitude(op, x):
-    """Pointwise sum of |summands| of L(x), inflated by the conditioning of the
-    latitude-dependent factors: a latitude computed with or without a fused
-    multiply-add differs by ~1 ulp of pi/2, which changes cos(lat) by a
-    relative ~ulp/cos(lat) -- large next to the poles, where A^xx ~ 1/cos.
-    A small multiple of eps times this bounds the float64 rounding of any
-    evaluation order."""
-    g = op.grid
-    ax = np.abs(x)
-    m = ax
-    mx = np.maximum.reduce([ax, np.roll(ax, 1, 1), np.roll(ax, -1, 1)])
-    ext = np.vstack([np.roll(mx[0], g.nx // 2)[None], mx, np.roll(mx[-1], g.nx // 2)[None]])
-    m3 = np.maximum.reduce([ext[:-2], ext[1:-1], ext[2:]])
-    aw = np.roll(op.axx_e, 1, 1)
-    north, south = op.ayy_north_south()
-    zero = np.zeros((1, g.nx))
-    cross = (np.abs(op.axy_e) + np.abs(np.roll(op.axy_e, 1, 1))) / (4 * g.dlam * g.dphi) * 4
-    cross += (np.abs(np.vstack([op.ayx_n, zero])) + np.abs(np.vstack([zero, op.ayx_n]))) / (4 * g.dlam * g.dphi) * 4
-    bterm = (np.abs(op.bx_e) + np.abs(np.roll(op.bx_e, 1, 1))) / g.dlam
-    bterm += (np.abs(np.vstack([op.by_n, zero])) + np.abs(np.vstack([zero, op.by_n]))) / g.dphi
-    cond = 1.0 + 1.0 / np.cos(g.lat)[:, None]
-    return ((2 * (np.abs(op.axx_e) + np.abs(aw)) / g.dlam ** 2 + 2 * (north + south) / g.dphi ** 2
-             + cross + bterm) * m3 + op.c[:, None] * m) * cond
 
 
 def make_solver(lib, sizes, **kw):
@@ -68,13 +45,18 @@ OPS = [
     (1024, 512, 100.0, dict(orography=True)),
     (8, 2, 600.0, {}),
     (16, 7, 900.0, dict(absorber=1e-3)),
+    (1024, 512, 100.0, dict(orography="smooth")),
 ]
 
 
 def _build(nx, ny, dt, extras, seed=0):
     pr = problem(2, nx, ny, instance=seed, dt=dt)
     oro = None
-    if extras.get("orography"):
+    if extras.get("orography") == "smooth":     # degree <= 16 harmonics, 0..3000 m
+        from workloads import harmonic_field
+        f = harmonic_field(nx, ny, 16, np.random.default_rng(177 + seed), lmin=1)
+        oro = 1500.0 * (1.0 + f / np.max(np.abs(f)))
+    elif extras.get("orography"):               # white noise, 0..1500 m: a stress case
         rng = np.random.default_rng(77 + seed)
         oro = 1500.0 * rng.random((ny, nx))
     kw = dict(absorber=extras.get("absorber", 0.0), b_terms=extras.get("b_terms", True))
@@ -116,14 +98,42 @@ def test_preconditioner_parity(gpu_lib, nx, ny, dt, extras, option, iters):
     r = np.random.default_rng(9).standard_normal((ny, nx))
     e = host(s.apply_precond(0, dev(r)))
     ref = Preconditioner(op, option, iters)(r)
-    # row systems are strictly diagonally dominant; their condition number
-    # bounds the amplification of rounding in either solver
-    from oracle.precond import row_systems
-    lo, di, up = row_systems(op)
-    cond = np.max(di / (di - np.abs(lo) - np.abs(up)))
-    tol = 64 * EPS * cond * iters * max(1.0, np.max(np.abs(ref)))
-    err = np.max(np.abs(e - ref))
-    assert err <= tol * 10, (err, tol)
+    tol = preconditioner_bound(op, option, iters, r, ref)
+    # the bound is relative to the result, so a zero or a 1%-perturbed output
+    # fails: at 90% of the points at least, and everywhere the bound stays
+    # below 1e-6 of max |ref| -- except with white-noise orography and two or
+    # more Richardson iterations, where the zonal B terms of P^M (grid-scale
+    # gradients of H* over cos(lat)) outweigh the meridional terms eta is
+    # scaled by, and the worst-case propagation through the iterations next to
+    # the poles is far above 1e-6 (its rows are still checked at that bound)
+    assert np.mean(0.01 * np.abs(ref) > tol) > 0.9
+    if not (extras.get("orography") is True and option == 3 and iters >= 2):
+        assert np.max(tol) <= 1e-6 * np.max(np.abs(ref))
+    err = np.abs(e - ref)
+    assert np.all(err <= tol), (float(np.max(err / np.maximum(tol, 1e-300))), float(np.max(err)))
+
+
+def preconditioner_bound(op, option, iters, r, ref):
+    """Pointwise float64 rounding bound of P^{-1}(r), 64 eps per rounding
+    step, relative to the local magnitude of the iterates (rows j-1..j+1).
+    Option 3: form_emul.richardson_bound with float64's unit roundoff.
+    Option 2: each later iteration evaluates L (sum |L summands| / |diag|)
+    and propagates an earlier error by at most 1 + that factor."""
+    from form_emul import rows_max3, richardson_bound
+    if option == 0:
+        return np.zeros_like(ref)
+    its = [Preconditioner(op, option, mu)(r) for mu in range(1, iters + 1)] if option in (2, 3) else [ref]
+    local = np.max([rows_max3(q) for q in its], axis=0)
+    c = 64 * EPS
+    if option == 1:
+        return c * local
+    if option == 2:
+        a = np.max(stencil_magnitude(op, np.ones_like(ref)) / np.abs(op.diagonal()), axis=1)[:, None]
+        delta = c * local
+        for _ in range(1, iters):
+            delta = rows_max3(delta) * (1.0 + a) + c * (1.0 + a) * local
+        return delta
+    return richardson_bound(op, iters, local, EPS)
 
 
 def _solve_pair(lib, pr, op, nx, ny, rtol, precision=0, **kw):
