@@ -111,6 +111,25 @@ enum {
                                       alternative exit condition); the iteration,
                                       its stagnation test and the reported relative
                                       residuals stay Euclidean                     */
+#define GCR_F_FAULT_NAN_PC 0x8u    /* tests of the exit logic: the preconditioner
+                                      output computed after iteration k (the first
+                                      one of the second GCR(k) cycle) is replaced
+                                      by NaN in every member; the breakdown is
+                                      reported as GCR_STAGNATED with x the iterate
+                                      after k+1 updates (the last finite one)      */
+#define GCR_F_FAULT_ZERO_DIR 0x10u /* as GCR_F_FAULT_NAN_PC with an all-zero
+                                      preconditioner output, i.e. a zero search
+                                      direction (<L p, L p> = 0)                   */
+#define GCR_F_SPLIT_R0 0x20u       /* GCR_SINGLE / GCR_SINGLE_POLAR64 only: the
+                                      initial residual is the split single-
+                                      precision evaluation of Section 4.2.1 (eq.
+                                      L_Operator_SP) on x_0 = Phi_hat + Phi_tilde,
+                                      Phi_hat the member's base stored by
+                                      gcr_set_split_base (the caller renews it at
+                                      the cadence it chooses; the paper keeps it
+                                      for many time steps), Phi_tilde =
+                                      fl32(x_0 - Phi_hat); every member needs a
+                                      base (GCR_ESTATE otherwise)                 */
 
 typedef struct {
   int32_t batch;          /* number of independent solves, 1..4096                    */
@@ -374,6 +393,20 @@ const char* cnn_last_error(const cnn_net* n);
  * Errors: GCR_EINVAL (wrong precond, uneven sizes, count, ratio), GCR_ENOMEM,
  * GCR_EHIP. */
 int gcr_set_learned(gcr_solver* s, const float* params, int64_t count, double fallback_ratio);
+
+/* Reference residual history for the learned preconditioner's fallback:
+ * rel_res[i] (i = 1..n, host array of n+1 values, entry 0 ignored) is the
+ * relative residual ||r_i|| / ||r_0|| the plain semi-implicit preconditioner
+ * reaches after iteration i on this workload (e.g. the geometric mean over
+ * the members of a plain solve's histories).  A member whose residual after
+ * iteration i <= n is above rel_res[i] has fallen behind the method without
+ * the network and drops the network from its next preconditioner application
+ * on (reported as fallback_used / GCR_FALLBACK_USED).  n = 0 removes the
+ * reference (only the per-cycle fallback_ratio test of gcr_set_learned stays).
+ * n <= max_iters.  Synchronous.  Errors: GCR_EINVAL (no learned
+ * preconditioner, n out of range, NULL with n > 0, values not finite and
+ * positive), GCR_ENOMEM, GCR_EHIP. */
+int gcr_set_learned_reference(gcr_solver* s, const double* rel_res, int32_t n);
 
 /* Training data for member `member`: with r = L(x) - rhs (float64),
  * e_lo = P^{-1}(r) with the solver's Richardson count and, if hi_iters > 0,

@@ -58,8 +58,11 @@ class GCRResult:
 
 
 def gcr(op: EllipticOperator, rhs, x0=None, k=3, rtol=1e-8, precond=PC_SEMI_IMPLICIT,
-        richardson_iters=2, min_iters=None, max_iters=200, pc=None, track_orthogonality=False, norm="l2"):
-    """Solve L(x) = rhs by preconditioned GCR(k)."""
+        richardson_iters=2, min_iters=None, max_iters=200, pc=None, track_orthogonality=False, norm="l2",
+        r0=None):
+    """Solve L(x) = rhs by preconditioned GCR(k).  `r0`: the initial residual
+    as the caller evaluated it (e.g. the split single-precision residual of
+    Section 4.2.1, oracle.split.residual_split); default L(x0) - rhs."""
     if norm not in ("l2", "linf"):
         raise ValueError(f"norm must be 'l2' or 'linf', got {norm!r}")
     if min_iters is None:
@@ -70,7 +73,7 @@ def gcr(op: EllipticOperator, rhs, x0=None, k=3, rtol=1e-8, precond=PC_SEMI_IMPL
     x = np.zeros_like(rhs) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
 
     # step 1
-    r = op.apply(x) - rhs
+    r = op.apply(x) - rhs if r0 is None else np.array(r0, dtype=np.float64, copy=True)
     rho0 = np.sqrt(dot(r, r))
     rho0_inf = float(np.max(np.abs(r)))
     if rho0 == 0.0:

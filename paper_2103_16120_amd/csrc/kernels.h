@@ -338,6 +338,8 @@ struct Fields {
   int learned;                // learned preconditioner active (fallback test at cycle ends)
   int linf;                   // exit test in the maximum norm (max |r| partials kept)
   double fallback_ratio;      // required residual reduction per cycle with it
+  const double* learn_ref;    // reference relative residual after iteration i (plain preconditioner), or null
+  int learn_ref_n;            // entries 1..learn_ref_n of learn_ref are set
 };
 
 // Run fn(coefficient rows) for row j with the storage precision of the
@@ -854,6 +856,26 @@ __global__ __launch_bounds__(WG) void k_sweep2(Fields F, int qin, int qout) {
 }
 
 // ---------------------------------------------------------------------------
+// Fault injection for tests of the exit logic (paper Section 2.3: breakdown
+// and a non-finite result stop the iteration): every member that has
+// completed `at_it` iterations gets a non-finite (mode 1) or an all-zero
+// (mode 2) preconditioner output e in place of the computed one.
+// ---------------------------------------------------------------------------
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_fault_e(Fields F, int mode, int at_it) {
+  using V = typename P::V;
+  int g, m, lane, w;
+  MemberGeom G;
+  if (!wave_row(F, g, m, G, lane, w)) return;
+  if (F.state[m].it != at_it) return;
+  const RowCtx R = make_row(G, m, g, lane, M);
+  V v[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) v[k] = mode == 1 ? (V)__builtin_nan("") : (V)0;
+  if (R.act) str<M>((V*)F.e + R.rc, R.lane, R.L, v);
+}
+
+// ---------------------------------------------------------------------------
 // preconditioner options 0-2 (paper Section 2.3):
 //   first pass  (update as in k_update_sweep1), then q = r or r/diag(L)
 //   Richardson  q_out = q_in - (L q_in - r) / diag(L)
@@ -1136,16 +1158,46 @@ __global__ __launch_bounds__(WG) void k_split_base(Fields F, SplitArgs S) {
   }
 }
 
-// r = L_SP(Phi_hat + Phi_tilde) - R into the pooled r64 (R: the pooled rhs)
-template <typename P, int M>   // P: unused (the row-launch helper's signature)
-__global__ __launch_bounds__(WG) void k_residual_split(Fields F, SplitArgs S) {
+// The split of a solve's initial guess (paper Section 4.2.1): Phi_tilde =
+// fl32(x_0 - Phi_hat) from the caller's x_0 (natural order) and the stored
+// base, and x_0 into the pooled solution, for every member (finished or not).
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_split_tilde(Fields F, SplitArgs S) {
   int g, m, lane, w;
   MemberGeom G;
-  if (!wave_row(F, g, m, G, lane, w)) return;
+  wave_row(F, g, m, G, lane, w);
+  if (g >= F.row_end) return;
+  const RowCtx R = make_row(G, m, g, lane, M);
+  const int l = R.lane, L = R.L;
+  double xv[M];
+  float hv[M], tv[M];
+  ldn<M>(F.x_tab[R.m] + (R.rc - G.off), l, xv);
+  ldr<M>(S.hat + R.rc, l, L, hv);
+#pragma unroll
+  for (int k = 0; k < M; ++k) tv[k] = (float)(xv[k] - (double)hv[k]);
+  if (R.act) {
+    str<M>((float*)S.tilde + R.rc, l, L, tv);
+    str<M>(F.x + R.rc, l, L, xv);
+  }
+}
+
+// r = L_SP(Phi_hat + Phi_tilde) - R.  mode 0 (stand-alone): R from the
+// pooled rhs, r into the pooled r64.  mode 1 (a solve's initial residual):
+// R from the caller's arrays, r into the Krylov residual in the form's units
+// (s r, vector type P::V) with its <r,r> partials (and max |r| with the
+// maximum-norm exit), for every member.
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_residual_split(Fields F, SplitArgs S, int mode) {
+  using V = typename P::V;
+  int g, m, lane, w;
+  MemberGeom G;
+  const bool active = wave_row(F, g, m, G, lane, w);
+  if (g >= F.row_end || (mode == 0 && !active)) return;
   const RowCtx R = make_row(G, m, g, lane, M);
   const int l = R.lane, L = R.L;
   double b[M], out[M];
-  ldr<M>(F.rhs + R.rc, l, L, b);
+  if (mode == 1) ldn<M>(F.rhs_tab[R.m] + (R.rc - G.off), l, b);
+  else ldr<M>(F.rhs + R.rc, l, L, b);
   if (R.j < G.polar || R.j >= G.ny - G.polar) {   // float64 polar bands
     const CoefFly<double> cv{F.fly64};
     const double helm = cv.helm(R.g);
@@ -1250,7 +1302,21 @@ __global__ __launch_bounds__(WG) void k_residual_split(Fields F, SplitArgs S) {
       te_p = te;
     }
   }
-  if (R.act) str<M>(F.r64 + R.rc, l, L, out);
+  if (mode == 0) {
+    if (R.act) str<M>(F.r64 + R.rc, l, L, out);
+    return;
+  }
+  const double s = P::mixed ? F.scale[R.m] : 1.0;
+  double rk[M], acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    rk[k] = (double)(V)(s * out[k]);
+    acc += rk[k] * rk[k];
+  }
+  if (R.act) str<M>((V*)F.r + R.rc, l, L, rk);
+  write_partial<double>(F, R, DOT_RR, R.act ? acc : 0.0);
+  if (F.linf) write_row_max<M>(F, R, rk, 1.0);
+  write_partial<double>(F, R, DOT_R_LP, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1743,6 +1809,10 @@ __global__ void k_ctrl_alpha(Fields F, int nl, Slots sl, int cycle_end, int min_
         S.done = 1;
         return;
       }
+      // learned correction behind the plain preconditioner's reference
+      // residual history: drop it from the next preconditioner application on
+      if (F.learned && !S.fallback && F.learn_ref && S.it <= F.learn_ref_n && !(rn <= F.learn_ref[S.it] * S.rho0))
+        S.fallback = 1;
       const bool small = F.linf ? rinf <= rtol * S.rho0_inf : rn <= rtol * S.rho0;
       if (S.it >= min_iters && small) {
         S.status = S.fallback ? ST_FALLBACK : ST_OK;

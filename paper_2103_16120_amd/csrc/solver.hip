@@ -3,6 +3,8 @@
 // split-residual calls, the learned preconditioner's set-up and timing.
 #include "solver_impl.h"
 
+#include <cstdlib>
+
 static void worker_main(gcr_solver* s, int w);
 static void stop_workers(gcr_solver* s);
 
@@ -82,6 +84,12 @@ static hipError_t make_groups(gcr_solver* s) {
   const long long fit = total / (GROUP_PTS * (long long)s->classes.size());
   int G = (int)std::min<long long>(std::min(GROUPS_MAX, B), std::max<long long>(fit, 1));
   if (s->prm.precond == GCR_PC_LEARNED || (s->prm.flags & GCR_F_ONE_STREAM)) G = 1;
+  // With the runtime's eager code-object loading (HIP_ENABLE_DEFERRED_LOADING=0)
+  // a batch split into member groups (several host threads enqueueing) once
+  // ended in a host segmentation fault whose cause has not been found; that
+  // combination is kept on one stream.
+  if (const char* ev = std::getenv("HIP_ENABLE_DEFERRED_LOADING"))
+    if (ev[0] == '0' && ev[1] == 0) G = 1;
   if (G < 2) return hipSuccess;
   hipError_t e = hipEventCreateWithFlags(&s->fork_ev, hipEventDisableTiming);
   int q = 0, row = 0;
@@ -160,8 +168,13 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   if (P.min_iters < -1 || P.min_iters > P.max_iters) return fail(nullptr, GCR_EINVAL, "min_iters out of range");
   if (!(P.rtol >= 0.0) || !std::isfinite(P.rtol)) return fail(nullptr, GCR_EINVAL, "rtol must be finite and >= 0");
   if (P.polar_rows < -1) return fail(nullptr, GCR_EINVAL, "polar_rows must be >= -1");
-  if (P.flags & ~(GCR_F_RECORD_HISTORY | GCR_F_ONE_STREAM | GCR_F_LINF_EXIT))
+  if (P.flags & ~(GCR_F_RECORD_HISTORY | GCR_F_ONE_STREAM | GCR_F_LINF_EXIT | GCR_F_FAULT_NAN_PC | GCR_F_FAULT_ZERO_DIR |
+                  GCR_F_SPLIT_R0))
     return fail(nullptr, GCR_EINVAL, "unknown flags 0x%x", P.flags);
+  if ((P.flags & GCR_F_SPLIT_R0) && P.precision != GCR_SINGLE && P.precision != GCR_SINGLE_POLAR64)
+    return fail(nullptr, GCR_EINVAL, "GCR_F_SPLIT_R0 needs GCR_SINGLE or GCR_SINGLE_POLAR64");
+  if ((P.flags & GCR_F_FAULT_NAN_PC) && (P.flags & GCR_F_FAULT_ZERO_DIR))
+    return fail(nullptr, GCR_EINVAL, "at most one fault-injection flag");
   for (int m = 0; m < P.batch; ++m) {
     const int nx = P.nx[m], ny = P.ny[m];
     if (!is_pow2(nx) || nx < 8 || nx > NXMAX)
@@ -467,6 +480,9 @@ extern "C" int gcr_solve(gcr_solver* s, const double* const* rhs, double* const*
   }
   if (s->prm.precond == GCR_PC_LEARNED && !s->net)
     return fail(s, GCR_ESTATE, "learned preconditioner without parameters (call gcr_set_learned)");
+  if (s->prm.flags & GCR_F_SPLIT_R0)
+    for (int m = 0; m < B; ++m)
+      if (!s->have_split[m]) return fail(s, GCR_ESTATE, "member %d has no split base (gcr_set_split_base)", m);
   HIPCHK(s, hipEventSynchronize(s->stage_ev[0]));  // staging buffer reuse
   for (int m = 0; m < B; ++m) {
     s->ptr_stage[m] = rhs[m];
@@ -538,14 +554,6 @@ static int check_member(gcr_solver* s, int32_t member, const void* a, const void
   return GCR_OK;
 }
 
-static SplitArgs split_args(const gcr_solver* s) {
-  SplitArgs S{};
-  S.hat = s->split;
-  for (int k = 0; k < NSD; ++k) S.d[k] = s->split + (size_t)(k + 1) * s->npts;
-  S.tilde = s->split + (size_t)(NSD + 1) * s->npts;
-  return S;
-}
-
 extern "C" int gcr_set_split_base(gcr_solver* s, int32_t member, const double* phi0) {
   if (!s) return GCR_EINVAL;
   if (member < 0 || member >= s->prm.batch) return fail(s, GCR_EINVAL, "member %d out of range", member);
@@ -590,7 +598,7 @@ extern "C" int gcr_residual_split(gcr_solver* s, int32_t member, const float* ph
   F.row_base = G.row0;
   F.row_end = G.row0 + G.ny;
   F.ignore_done = 1;
-  ROWS_LAUNCH(s, member_class(s, member), F, KT_RESIDUAL, k_residual_split, PrecF64, S);
+  ROWS_LAUNCH(s, member_class(s, member), F, KT_RESIDUAL, k_residual_split, PrecF64, S, 0);
   KLAUNCH(s, KT_COPY, k_from_pool, cg, dim3(256), 0, s->stream, (const double*)s->r64, r, G);
   HIPCHK(s, hipGetLastError());
   return GCR_OK;
@@ -688,6 +696,30 @@ extern "C" int gcr_set_learned(gcr_solver* s, const float* params, int64_t count
   const int rc = cnn_set_params(s->net, params, count);
   if (rc != GCR_OK) return fail(s, rc, "network: %s", cnn_last_error(s->net));
   s->fallback_ratio = fallback_ratio;
+  return GCR_OK;
+}
+
+extern "C" int gcr_set_learned_reference(gcr_solver* s, const double* rel_res, int32_t n) {
+  if (!s) return GCR_EINVAL;
+  if (s->prm.precond != GCR_PC_LEARNED)
+    return fail(s, GCR_EINVAL, "gcr_set_learned_reference needs a solver created with GCR_PC_LEARNED");
+  if (n < 0 || n > s->prm.max_iters) return fail(s, GCR_EINVAL, "n must be in [0, max_iters]");
+  if (n > 0 && !rel_res) return fail(s, GCR_EINVAL, "NULL reference history");
+  for (int i = 1; i <= n; ++i)
+    if (!(rel_res[i] > 0.0) || !std::isfinite(rel_res[i]))
+      return fail(s, GCR_EINVAL, "reference residual %d must be finite and > 0", i);
+  if (n > 0) {
+    if (!s->learn_ref) {
+      hipError_t herr = hipSuccess;
+      s->learn_ref = dalloc<double>((size_t)s->prm.max_iters + 1, herr);
+      if (herr != hipSuccess) return fail(s, GCR_ENOMEM, "reference history: %s", hipGetErrorString(herr));
+      s->allocs.push_back(s->learn_ref);
+    }
+    HIPCHK(s, hipMemcpyAsync(s->learn_ref, rel_res, ((size_t)n + 1) * sizeof(double), hipMemcpyHostToDevice,
+                             s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+  }
+  s->learn_ref_n = n;
   return GCR_OK;
 }
 

@@ -155,6 +155,8 @@ struct gcr_solver {
   cnn_net* net = nullptr;            // learned preconditioner (GCR_PC_LEARNED), owned
   int* learn_active = nullptr;       // [batch] images the network runs on in one application
   double fallback_ratio = 0.5;
+  double* learn_ref = nullptr;       // [max_iters + 1] reference relative residuals (device), or null
+  int learn_ref_n = 0;
 
   // optional per-kernel timing with HIP events on the solver's stream
   bool timing = false;
@@ -325,6 +327,8 @@ inline Fields make_fields(gcr_solver* s) {
   F.learned = s->prm.precond == GCR_PC_LEARNED ? 1 : 0;
   F.linf = (s->prm.flags & GCR_F_LINF_EXIT) ? 1 : 0;
   F.fallback_ratio = s->fallback_ratio;
+  F.learn_ref = s->learn_ref_n > 0 ? s->learn_ref : nullptr;
+  F.learn_ref_n = s->learn_ref_n;
   return F;
 }
 
@@ -393,6 +397,15 @@ void launch_precond(gcr_solver* s, const std::vector<RowClass>& cls, const Field
   }
 }
 
+// the split-residual buffers: Phi_hat, its stored differences, Phi_tilde
+inline SplitArgs split_args(const gcr_solver* s) {
+  SplitArgs S{};
+  S.hat = s->split;
+  for (int k = 0; k < NSD; ++k) S.d[k] = s->split + (size_t)(k + 1) * s->npts;
+  S.tilde = s->split + (size_t)(NSD + 1) * s->npts;
+  return S;
+}
+
 // Stand-alone operator (what = 0) or preconditioner (what = 1) of member
 // `member` in precision form P, with the kernels a solve of that form runs.
 // The form's vectors are the solver's own Krylov buffers (these calls and a
@@ -448,8 +461,14 @@ int run_group(gcr_solver* s, const gcr_solver::Group& g) {
   const dim3 ctl(g.q1 - g.q0), wave(64);
   const std::vector<RowClass>& cls = g.classes;
 
-  // step 1: r_0 = L(x_0) - R (float64), p_0 = P^{-1}(r_0), L(p_0)
-  ROWS_LAUNCH_F(s, cls, F, KT_RESIDUAL, k_residual, P, 1, -1, 0, RES_X_IN | RES_RHS_TAB);
+  // step 1: r_0 = L(x_0) - R (float64; or the split single-precision
+  // evaluation of paper Section 4.2.1), p_0 = P^{-1}(r_0), L(p_0)
+  if (s->prm.flags & GCR_F_SPLIT_R0) {
+    ROWS_LAUNCH(s, cls, F, KT_RESIDUAL, k_split_tilde, P, split_args(s));
+    ROWS_LAUNCH(s, cls, F, KT_RESIDUAL, k_residual_split, P, split_args(s), 1);
+  } else {
+    ROWS_LAUNCH_F(s, cls, F, KT_RESIDUAL, k_residual, P, 1, -1, 0, RES_X_IN | RES_RHS_TAB);
+  }
   KLAUNCH(s, KT_CONTROL, k_ctrl_init<double>, ctl, wave, 0, g.st, F);
   {
     Fields F0 = F;
@@ -469,6 +488,8 @@ int run_group(gcr_solver* s, const gcr_solver::Group& g) {
     (void)it;
     // step 2 (+ first row solve of step 3)
     launch_precond<P>(s, cls, F, 1, sl.s[nu]);
+    if (s->prm.flags & (GCR_F_FAULT_NAN_PC | GCR_F_FAULT_ZERO_DIR))
+      ROWS_LAUNCH(s, cls, F, KT_SWEEP2, k_fault_e, P, (s->prm.flags & GCR_F_FAULT_NAN_PC) ? 1 : 2, k);
     // step 3: L(e) with <L e, L p_l>, l = 0..nu
     ROWS_LAUNCH_F(s, cls, F, KT_APPLY_L, k_apply_L, P, (const void*)s->e, s->le, 0, nu + 1, sl);
     KLAUNCH(s, KT_CONTROL, k_ctrl_alpha<A>, ctl, wave, 0, g.st, F, nu + 1, sl, nu == k - 1 ? 1 : 0,

@@ -60,6 +60,21 @@ def load_weights(path):
     return params, head
 
 
+def reference_history(reports):
+    """Reference residual history for the learned fallback
+    (gcr_set_learned_reference): entry i is the geometric mean over the
+    members of the plain solve's relative residual after iteration i, for the
+    iterations every member reached (reports: lib.Report with history)."""
+    hs = [r.history for r in reports if r.history]
+    if not hs:
+        return []
+    n = min(len(h) for h in hs)
+    h = np.array([h[:n] for h in hs], dtype=np.float64)
+    with np.errstate(divide="ignore"):
+        ref = np.exp(np.mean(np.log(np.maximum(h, 1e-300)), axis=0))
+    return list(ref)
+
+
 def make_dataset(lib, torch, nx, ny, problems, first_instance, n_max, hi_iters, group=16, log=print):
     """Features [S, 3, ny, nx] and targets [S, ny, nx] (float32 CUDA tensors)."""
     from workloads import problem

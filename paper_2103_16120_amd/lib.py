@@ -23,6 +23,9 @@ PC_NONE, PC_DIAG, PC_RICHARDSON, PC_SEMI_IMPLICIT, PC_LEARNED = 0, 1, 2, 3, 4
 F_RECORD_HISTORY = 0x1
 F_ONE_STREAM = 0x2
 F_LINF_EXIT = 0x4
+F_FAULT_NAN_PC = 0x8
+F_FAULT_ZERO_DIR = 0x10
+F_SPLIT_R0 = 0x20
 
 RADIUS = 6.371e6
 GRAVITY = 9.80616
@@ -76,6 +79,7 @@ _SIGNATURES = {
     "gcr_kernel_time": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "gcr_kernel_name": (C.c_char_p, [C.c_int32]),
     "gcr_set_learned": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double]),
+    "gcr_set_learned_reference": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int32]),
     "gcr_learned_features": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                                        C.c_void_p, C.POINTER(C.c_double)]),
     "cnn_param_count": (C.c_int64, [C.c_int]),
@@ -148,7 +152,7 @@ class Solver:
 
     def __init__(self, sizes, k=3, precision=FP64, precond=PC_SEMI_IMPLICIT, richardson_iters=2,
                  polar_rows=-1, min_iters=-1, max_iters=200, rtol=1e-8, stream=None, flags=0, one_stream=False,
-                 linf_exit=False):
+                 linf_exit=False, record_history=False):
         self.sizes = [(int(nx), int(ny)) for nx, ny in sizes]
         b = len(self.sizes)
         self._nx = (C.c_int32 * b)(*[s[0] for s in self.sizes])
@@ -163,7 +167,8 @@ class Solver:
         p.richardson_iters, p.polar_rows = richardson_iters, polar_rows
         p.min_iters, p.max_iters, p.rtol = min_iters, max_iters, rtol
         p.stream = C.c_void_p(stream.cuda_stream)
-        p.flags = flags | (F_ONE_STREAM if one_stream else 0) | (F_LINF_EXIT if linf_exit else 0)
+        p.flags = (flags | (F_ONE_STREAM if one_stream else 0) | (F_LINF_EXIT if linf_exit else 0)
+                   | (F_RECORD_HISTORY if record_history else 0))
         self.params = p
         h = C.c_void_p()
         rc = _lib.gcr_create(C.byref(p), C.byref(h))
@@ -244,6 +249,8 @@ class Solver:
         b = len(self.sizes)
         if len(rhs) != b or len(x) != b:
             raise ValueError("one rhs and one x per member")
+        if record_history and not (self.params.flags & F_RECORD_HISTORY):
+            raise ValueError("record_history needs a solver created with record_history=True")
         for m, (nx, ny) in enumerate(self.sizes):
             _check_field(rhs[m], ny, nx, f"rhs[{m}]")
             _check_field(x[m], ny, nx, f"x[{m}]")
@@ -320,6 +327,17 @@ class Solver:
         import numpy as np
         arr = np.ascontiguousarray(params, dtype=np.float32).ravel()
         rc = _lib.gcr_set_learned(self._h, arr.ctypes.data, arr.size, float(fallback_ratio))
+        if rc < 0:
+            raise self._err(rc)
+
+    def set_learned_reference(self, rel_res):
+        """Reference relative residuals after iterations 1..n of the plain
+        preconditioner (rel_res[0] is ignored; an empty list removes it)."""
+        import numpy as np
+        arr = np.ascontiguousarray(rel_res, dtype=np.float64).ravel()
+        n = max(0, arr.size - 1)
+        ptr = arr.ctypes.data_as(C.POINTER(C.c_double)) if arr.size else None
+        rc = _lib.gcr_set_learned_reference(self._h, ptr, n)
         if rc < 0:
             raise self._err(rc)
 

@@ -148,7 +148,43 @@ def test_learned_create_needs_one_size(lib):
 
 
 def test_create_rejects_unknown_flags(lib):
-    p = _params(lib, flags=0x8)
+    p = _params(lib, flags=0x40)
     h = C.c_void_p()
     assert lib._lib.gcr_create(C.byref(p), C.byref(h)) == lib.EINVAL
     assert b"flags" in lib._lib.gcr_last_error(None)
+
+
+def test_fault_injection_flags_validated_before_the_device(lib):
+    """The two fault-injection flags are known (a GPU-less create fails on
+    the device, not on the flags), and they exclude each other."""
+    import torch
+    h = C.c_void_p()
+    p = _params(lib, flags=lib.F_FAULT_NAN_PC | lib.F_FAULT_ZERO_DIR)
+    assert lib._lib.gcr_create(C.byref(p), C.byref(h)) == lib.EINVAL
+    assert b"fault" in lib._lib.gcr_last_error(None)
+    if torch.cuda.is_available():
+        return
+    for f in (lib.F_FAULT_NAN_PC, lib.F_FAULT_ZERO_DIR, lib.F_FAULT_NAN_PC | lib.F_RECORD_HISTORY):
+        p = _params(lib, flags=f)
+        assert lib._lib.gcr_create(C.byref(p), C.byref(h)) == lib.EHIP
+        assert h.value is None
+
+
+def test_header_flag_values_match_the_binding(lib):
+    text = open(os.path.join(ROOT, "include", "mpgcr.h")).read()
+    vals = {m.group(1): int(m.group(2), 16) for m in re.finditer(r"#define GCR_F_(\w+)\s+0x([0-9a-fA-F]+)u", text)}
+    for name, v in vals.items():
+        assert getattr(lib, "F_" + name) == v, name
+    assert set(vals) >= {"RECORD_HISTORY", "ONE_STREAM", "LINF_EXIT", "FAULT_NAN_PC", "FAULT_ZERO_DIR", "SPLIT_R0"}
+
+
+def test_split_r0_flag_needs_a_single_precision_cycle(lib):
+    h = C.c_void_p()
+    for prec in (lib.FP64, lib.MIXED_HALF_PC, lib.MIXED):
+        p = _params(lib, flags=lib.F_SPLIT_R0, precision=prec)
+        assert lib._lib.gcr_create(C.byref(p), C.byref(h)) == lib.EINVAL
+        assert b"SPLIT_R0" in lib._lib.gcr_last_error(None)
+
+
+def test_learned_reference_rejects_null_solver(lib):
+    assert lib._lib.gcr_set_learned_reference(None, None, 0) == lib.EINVAL

@@ -5,6 +5,7 @@ import os
 import sys
 
 import numpy as np
+import pytest
 
 sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 import bench  # noqa: E402
@@ -49,3 +50,25 @@ def test_flat_surface_reads_one_depth_pool():
     assert b["sweep2"] == 7 * 22 and b["update_sweep1"] == 10 + 6 * 18
     b = bench.step_bytes("fp64", np.array([[4]]), np.array([[0]]), 3, 1, flat=True)
     assert b["sweep2"] == 5 * 32 and b["residual"] == 40 + 32
+
+
+def test_flop_cost_model():
+    """The paper's Section 4.4 cost model: float64 costs every operation 1;
+    the paper's half-precision solver comes out near the x3.3 the paper
+    prints for it (within 10%), the float32 forms near x2."""
+    import bench
+    for it in (4, 6, 9):
+        f64 = bench.flop_cost("fp64", it)
+        half = f64 / bench.flop_cost("paper_half", it, polar_frac=6 / 256)
+        assert abs(half / 3.3 - 1) < 0.1, half
+        single_like = f64 / bench.flop_cost("mixed_half_pc", it)
+        assert 1.5 < single_like < 2.0
+    # counted by hand for 4 iterations: set-up r_0, p_0, L p_0 (31 + 72 + 31);
+    # step 2 of each iteration (8); steps 3-4 of the first three (72 + 31 + 6 nl)
+    assert bench.flop_cost("fp64", 4) == 134 + 4 * 8 + 3 * 103 + 6 * (1 + 2 + 3)
+    # every operation at one precision: the ratio is that precision's cost
+    bench.PRECISIONS["_all_half"] = dict.fromkeys(bench.FLOPS, "h")
+    try:
+        assert bench.flop_cost("fp64", 5) / bench.flop_cost("_all_half", 5) == pytest.approx(4.0)
+    finally:
+        del bench.PRECISIONS["_all_half"]

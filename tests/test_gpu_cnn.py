@@ -345,9 +345,20 @@ def test_learned_solve_and_fallback(gpu_lib):
     rhs = [dev(o.apply(p["x_true"])) for o, p in zip(ops, prs)]
     bad = E.flatten(random_params(3, 77, last_scale=3.0))
     mild = E.flatten(random_params(3, 78, last_scale=0.01, bias_scale=0.0))
-    for params, ratio, expect_fb in ((bad, 1e-9, True), (bad, 0.5, None), (mild, 0.9, None)):
+    # the default setting: the plain preconditioner's residual history on the
+    # same problems as the reference a learned solve must keep up with
+    from paper_2103_16120_amd.learned import reference_history
+    plain = _setup(gpu_lib, [(nx, ny)] * B, prs, gpu_lib.FP64, gpu_lib.PC_SEMI_IMPLICIT, max_iters=200,
+                   record_history=True)
+    ref = reference_history(plain.solve(rhs, [torch.zeros_like(r) for r in rhs], record_history=True))
+    plain.close()
+    assert len(ref) >= 5
+    for params, ratio, use_ref, expect_fb in ((bad, 1e-9, False, True), (bad, 0.5, True, True),
+                                              (bad, 0.5, False, None), (mild, 0.9, False, None)):
         s = _setup(gpu_lib, [(nx, ny)] * B, prs, gpu_lib.FP64, gpu_lib.PC_LEARNED, max_iters=200)
         s.set_learned(params, fallback_ratio=ratio)
+        if use_ref:
+            s.set_learned_reference(ref)
         x = [torch.zeros_like(r) for r in rhs]
         reps = s.solve(rhs, x)
         for m in range(B):
@@ -396,22 +407,37 @@ def test_trained_network_gain(gpu_lib, capsys):
     for m, p in enumerate(prs):
         f.set_operator(m, depth[m], p["dt"])
     rhs = [f.apply_operator(m, dev(p["x_true"])) for m, p in enumerate(prs)]
+    from paper_2103_16120_amd.learned import reference_history
     out = {}
+    ref = None
     for name, pc in (("plain", gpu_lib.PC_SEMI_IMPLICIT), ("learned", gpu_lib.PC_LEARNED)):
-        s = gpu_lib.Solver([(nx, ny)] * B, precision=gpu_lib.MIXED_HALF_PC, precond=pc)
+        s = gpu_lib.Solver([(nx, ny)] * B, precision=gpu_lib.MIXED_HALF_PC, precond=pc, record_history=True)
         if pc == gpu_lib.PC_LEARNED:
             s.set_learned(params)
+            assert len(ref) >= 5
+            s.set_learned_reference(ref)
         for m, p in enumerate(prs):
             s.set_operator(m, depth[m], p["dt"])
         x = [torch.zeros_like(r) for r in rhs]
-        reps = s.solve(rhs, x)
+        reps = s.solve(rhs, x, record_history=True)
         for rp in reps:
             assert rp.status in (gpu_lib.OK, gpu_lib.FALLBACK_USED) and rp.rel_res_true <= 1.05e-8, rp
-        out[name] = (np.mean([r.iterations for r in reps]), [host(v) for v in x])
+        if ref is None:
+            ref = reference_history(reps)
+        out[name] = (reps, [host(v) for v in x])
         s.close()
     for a, b in zip(out["plain"][1], out["learned"][1]):
         assert np.linalg.norm(a - b) <= 1e-6 * np.linalg.norm(a)
+    # no iteration count regresses: a member keeps the network only while it
+    # is at least as far as the plain preconditioner's history, and the one
+    # that drops it has lost at most the iteration that showed the regression
+    for rp, rl in zip(out["plain"][0], out["learned"][0]):
+        assert rl.iterations <= rp.iterations + (1 if rl.fallback_used else 0), (rp, rl)
+        assert rl.fallback_used or rl.iterations <= rp.iterations
+    it_p = np.mean([r.iterations for r in out["plain"][0]])
+    it_l = np.mean([r.iterations for r in out["learned"][0]])
+    fb = sum(r.fallback_used for r in out["learned"][0])
     with capsys.disabled():
-        print(f"\n[trained network] mean GCR iterations: plain {out['plain'][0]:.2f}, "
-              f"learned {out['learned'][0]:.2f} (training loss {head.get('loss_last'):.3g} "
+        print(f"\n[trained network] mean GCR iterations: plain {it_p:.2f}, learned {it_l:.2f}, "
+              f"{fb} of {B} members fell back (training loss {head.get('loss_last'):.3g} "
               f"of target mean square {head.get('target_mean_square'):.3g})")

@@ -125,8 +125,9 @@ def preconditioner_bound(op, option, iters, r, ref):
     its = [Preconditioner(op, option, mu)(r) for mu in range(1, iters + 1)] if option in (2, 3) else [ref]
     local = np.max([rows_max3(q) for q in its], axis=0)
     c = 64 * EPS
-    if option == 1:
-        return c * local
+    if option == 1:   # e = r / diag(L): the diagonal's own rounding, with the latitude conditioning
+        a = np.max(stencil_magnitude(op, np.ones_like(ref)) / np.abs(op.diagonal()), axis=1)[:, None]
+        return c * a * local
     if option == 2:
         a = np.max(stencil_magnitude(op, np.ones_like(ref)) / np.abs(op.diagonal()), axis=1)[:, None]
         delta = c * local
@@ -139,10 +140,11 @@ def preconditioner_bound(op, option, iters, r, ref):
 def _solve_pair(lib, pr, op, nx, ny, rtol, precision=0, **kw):
     rhs = op.apply(pr["x_true"])
     ores = gcr(op, rhs, rtol=rtol, max_iters=kw.get("max_iters", 200))
-    s = make_solver(lib, [(nx, ny)], precision=precision, rtol=rtol, **kw)
+    s = make_solver(lib, [(nx, ny)], precision=precision, rtol=rtol, record_history=True, **kw)
     s.set_operator(0, pr["depth"], pr["dt"])
     x = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
     rep = s.solve([dev(rhs)], [x], record_history=True)[0]
+    assert len(rep.history) == rep.iterations + 1
     return ores, rep, host(x), rhs
 
 
@@ -159,6 +161,7 @@ def test_config1_fp64_parity(gpu_lib):
     assert np.linalg.norm(x - ores.x) / np.linalg.norm(ores.x) <= 1e-9
     assert rep.r0_norm == pytest.approx(ores.r0_norm, rel=1e-12)
     n = min(len(rep.history), len(ores.history))
+    assert n >= 4
     assert np.allclose(rep.history[:n], ores.history[:n], rtol=1e-6, atol=1e-14)
 
 
@@ -591,3 +594,66 @@ def test_uneven_batch_single_forms(gpu_lib, precision):
         print(f"\nprecision={precision} member {m} {size}: true={true_res:.3e} err_vs_oracle={err:.3e}")
         assert reps[m].rel_res_true == pytest.approx(true_res, rel=1e-6, abs=1e-14)
         assert err <= 1e-6, (m, err)
+
+
+@pytest.mark.parametrize("precision", [0, 3])
+@pytest.mark.parametrize("fault", ["nan", "zero"])
+def test_fault_injection_reports_stagnation(gpu_lib, precision, fault):
+    """A non-finite preconditioner output, or a zero search direction (<L p,
+    L p> = 0), in the first iteration of the second GCR(3) cycle stops every
+    member with STAGNATED (paper Section 2.3: breakdown ends the iteration).
+    x is the last finite iterate -- bitwise that of the same solve stopped
+    by max_iters after k+1 iterations -- and its float64 true residual is
+    reported."""
+    nx, ny, B, k = 128, 64, 3, 3
+    prs = [problem(2, nx, ny, instance=m, dt=600.0) for m in range(B)]
+    ops = [EllipticOperator(nx, ny, p["depth"], 600.0) for p in prs]
+    rhs = [dev(o.apply(p["x_true"])) for o, p in zip(ops, prs)]
+    flag = gpu_lib.F_FAULT_NAN_PC if fault == "nan" else gpu_lib.F_FAULT_ZERO_DIR
+
+    def run(flags, max_iters):
+        s = make_solver(gpu_lib, [(nx, ny)] * B, precision=precision, rtol=1e-15, max_iters=max_iters, flags=flags)
+        for m, p in enumerate(prs):
+            s.set_operator(m, p["depth"], 600.0)
+        x = [torch.zeros_like(r) for r in rhs]
+        reps = s.solve(rhs, x)
+        s.close()
+        return reps, [host(v) for v in x]
+
+    rf, xf = run(flag, 50)
+    rs, xs = run(0, k + 1)
+    for m in range(B):
+        assert rf[m].status == gpu_lib.STAGNATED and rf[m].iterations == k + 1, rf[m]
+        assert rs[m].status == gpu_lib.NOT_CONVERGED and rs[m].iterations == k + 1, rs[m]
+        assert np.all(np.isfinite(xf[m]))
+        assert np.array_equal(xf[m], xs[m])
+        true = np.linalg.norm(ops[m].apply(xf[m]) - host(rhs[m])) / rf[m].r0_norm
+        assert rf[m].rel_res_true == pytest.approx(true, rel=1e-6)
+        assert rf[m].rel_res_true < 1e-3
+
+
+@pytest.mark.parametrize("nx,ny", [(128, 64), (256, 128)])
+def test_mixed_plateau_against_emulated_half(gpu_lib, nx, ny, capsys):
+    """GCR_MIXED (float16 storage of the operator and preconditioner
+    coefficients, float32 arithmetic, no residual replacement) stalls at a
+    true residual of the same order as the paper's half-precision solver,
+    which the oracle emulates with 10-bit significands and float64's exponent
+    range at the paper's rounding points (Sections 3.3, 4.3): both plateau
+    far above the tolerance their recursive residuals reach."""
+    from oracle.emulated import gcr_half
+    pr = problem(2, nx, ny, dt=600.0)
+    op = EllipticOperator(nx, ny, pr["depth"], 600.0)
+    rhs = op.apply(pr["x_true"])
+    polar = max(1, int(np.ceil(np.log2(max(ny // 32, 1)))))
+    emu = gcr_half(op, rhs, rtol=1e-8, polar=polar)
+    s = make_solver(gpu_lib, [(nx, ny)], precision=gpu_lib.MIXED, rtol=1e-8, max_iters=60)
+    s.set_operator(0, pr["depth"], 600.0)
+    x = torch.zeros((ny, nx), dtype=torch.float64, device="cuda")
+    rep = s.solve([dev(rhs)], [x])[0]
+    true_res = np.linalg.norm(op.apply(host(x)) - rhs) / np.linalg.norm(rhs)
+    with capsys.disabled():
+        print(f"\n[plateau {nx}x{ny}] GCR_MIXED true residual {true_res:.2e} ({rep.iterations} it.), "
+              f"emulated half-precision solver {emu.rel_res_true:.2e} ({emu.iterations} it.)")
+    assert rep.rel_res_recursive <= 1e-8 and emu.rel_res_recursive <= 1e-8
+    assert true_res > 1e-7 and emu.rel_res_true > 1e-7
+    assert 0.05 <= true_res / emu.rel_res_true <= 20

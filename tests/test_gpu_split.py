@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 import torch
 
+from oracle.gcr import gcr
 from oracle.operator import EllipticOperator
 from oracle.split import split_fields, base_differences, residual_split, residual_naive_sp
 from workloads import problem
@@ -85,3 +86,57 @@ def test_split_residual_errors(gpu_lib):
         s.residual_split(0, t, rhs, out=rhs)     # r aliases R
     r = host(s.residual_split(0, t, rhs))
     assert np.all(np.isfinite(r))
+
+
+@pytest.mark.parametrize("precision", [4, 5])
+def test_single_solve_from_split_r0_vs_oracle(gpu_lib, precision):
+    """The split residual as a solve's r_0 (GCR_F_SPLIT_R0, paper Section
+    4.2.1): two consecutive warm-started steps of a depth-like unknown share
+    one base taken earlier, as the paper keeps the base for many time steps.
+    Each step's GPU solve (float32 cycle) is compared with oracle/split.py's
+    residual of the same warm start followed by the oracle's GCR from that
+    residual: the two evaluate the split float32 residual in different
+    orders, so their r_0 differ by float32 ulps of the stencil's largest
+    summand (C Phi_SP, about 1e3 times r_0 here), which bounds how far their
+    increments x - x_0 can differ (2e-3 of the increment)."""
+    nx, ny = 256, 128
+    polar = 2                # the default polar rows at NY = 128: the split's float64 bands
+    pr = problem(2, nx, ny, dt=600.0)
+    op = EllipticOperator(nx, ny, pr["depth"], 600.0)
+    base = pr["depth"] - 20.0 * pr["x_true"]
+    hat, _ = split_fields(base)
+    dh = base_differences(hat)
+    s = gpu_lib.Solver([(nx, ny)], precision=precision, rtol=1e-5, max_iters=40, flags=gpu_lib.F_SPLIT_R0)
+    s.set_operator(0, pr["depth"], 600.0)
+    s.set_split_base(0, dev(base))
+    x0 = pr["depth"].copy()
+    for step in range(2):
+        target = pr["depth"] + (3.0 + 2.0 * step) * pr["x_true"]
+        rhs = op.apply(target)
+        tilde = (x0 - hat.astype(np.float64)).astype(np.float32)
+        r0 = residual_split(op, hat, dh, tilde, rhs, polar=polar)
+        ores = gcr(op, rhs, x0=x0, r0=r0, rtol=1e-5)
+        x = dev(x0)
+        rep = s.solve([dev(rhs)], [x])[0]
+        xg = host(x)
+        assert rep.status == gpu_lib.OK, rep
+        assert rep.r0_norm == pytest.approx(np.linalg.norm(r0), rel=1e-3)
+        inc_g, inc_o = xg - x0, ores.x - x0
+        assert np.linalg.norm(inc_g - inc_o) <= 2e-3 * np.linalg.norm(inc_o), (step, rep)
+        # the split start is accurate: against the float64 residual of x_0 the
+        # solve reduces the error of the state by orders of magnitude
+        true0 = np.linalg.norm(op.apply(x0) - rhs)
+        assert np.linalg.norm(op.apply(xg) - rhs) <= 1e-2 * true0
+        x0 = xg
+    s.close()
+
+
+def test_split_r0_needs_a_base(gpu_lib):
+    pr = problem(2, 64, 32, dt=600.0)
+    s = gpu_lib.Solver([(64, 32)], precision=gpu_lib.SINGLE, flags=gpu_lib.F_SPLIT_R0)
+    s.set_operator(0, pr["depth"], 600.0)
+    x = dev(pr["depth"])
+    with pytest.raises(gpu_lib.GcrError) as ei:
+        s.solve([dev(np.zeros((32, 64)))], [x])
+    assert ei.value.code == gpu_lib.ESTATE
+    s.close()
