@@ -277,6 +277,29 @@ int gcr_apply_precond(gcr_solver* s, int32_t member, const double* r, double* e)
 int gcr_apply_operator_form(gcr_solver* s, int32_t member, const double* x, double* y);
 int gcr_apply_precond_form(gcr_solver* s, int32_t member, const double* r, double* e);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): e =
+ * P^{-1}(r) for one member with operator `op`, the semi-implicit Richardson
+ * preconditioner (option 3) with `richardson_iters` iterations in float64 --
+ * the result of gcr_apply_precond on a GCR_FP64 solver whose member has this
+ * operator and Richardson count.  No solver is needed and nothing is
+ * allocated: every buffer besides r and e is a static device array of the
+ * library (about 13 MiB per GPU it runs on, held until the process ends),
+ * and the call only launches kernels on `stream` (hipStream_t, NULL = the
+ * default stream; asynchronous).
+ *   nx: power of two in [8, 1024]; ny in [2, 4096]; nx * ny <=
+ *     GCR_STATIC_MAX_POINTS (larger sizes: GCR_EINVAL);
+ *   op: depth (and orography, or NULL) must be device pointers
+ *     (mem_is_device = 1), [NY][NX] float64, valid until the work on the
+ *     stream has run; r, e: device float64 [NY][NX], not overlapping.
+ * Calls on one GPU share the static array, and the last call's contents stay
+ * in it: calls that overlap on one GPU (unordered streams or threads) race.
+ * Errors: GCR_EINVAL, GCR_EHIP; gcr_last_error(NULL) describes the last
+ * failure on the calling thread. */
+#define GCR_STATIC_MAX_POINTS 131072
+int gcr_apply_precond_static(int32_t nx, int32_t ny, const gcr_operator* op, int32_t richardson_iters,
+                             const double* r, double* e, void* stream);
+
 /* Release every resource of the solver.  NULL is accepted (no-op). */
 int gcr_destroy(gcr_solver* s);
 

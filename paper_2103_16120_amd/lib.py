@@ -72,6 +72,8 @@ _SIGNATURES = {
     "gcr_apply_operator_form": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "gcr_apply_precond_form": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "gcr_destroy": (C.c_int, [C.c_void_p]),
+    "gcr_apply_precond_static": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                           C.c_void_p]),
     "gcr_status_string": (C.c_char_p, [C.c_int]),
     "gcr_last_error": (C.c_char_p, [C.c_void_p]),
     "gcr_version": (C.c_char_p, []),
@@ -393,6 +395,34 @@ class Solver:
         if rc < 0:
             raise self._err(rc)
         return e
+
+
+STATIC_MAX_POINTS = 131072
+
+
+def apply_precond_static(r, depth, dt, orography=None, richardson_iters=2, absorber=0.0, g=GRAVITY,
+                         omega=OMEGA, radius=RADIUS, b_terms=True, out=None, stream=None):
+    """e = P^{-1}(r) of one member without a solver and without any device
+    allocation by the library (gcr_apply_precond_static): r, depth,
+    orography, out are float64 CUDA tensors (ny, nx); nx * ny <=
+    STATIC_MAX_POINTS."""
+    ny, nx = r.shape
+    _check_field(r, ny, nx, "r")
+    _check_field(depth, ny, nx, "depth")
+    if orography is not None:
+        _check_field(orography, ny, nx, "orography")
+    e = torch.empty_like(r) if out is None else out
+    _check_field(e, ny, nx, "out")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    op = GcrOperator(dt=float(dt), g=g, omega=omega, radius=radius, absorber=absorber, depth=depth.data_ptr(),
+                     orography=None if orography is None else orography.data_ptr(), b_terms=1 if b_terms else 0,
+                     mem_is_device=1)
+    rc = _lib.gcr_apply_precond_static(nx, ny, C.addressof(op), int(richardson_iters), r.data_ptr(),
+                                       e.data_ptr(), C.c_void_p(stream.cuda_stream))
+    if rc < 0:
+        raise GcrError(rc, _lib.gcr_last_error(None).decode())
+    return e
 
 
 def _check_f32(t, shape, name):

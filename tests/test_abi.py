@@ -188,3 +188,24 @@ def test_split_r0_flag_needs_a_single_precision_cycle(lib):
 
 def test_learned_reference_rejects_null_solver(lib):
     assert lib._lib.gcr_set_learned_reference(None, None, 0) == lib.EINVAL
+
+
+def test_static_preconditioner_validates_before_the_device(lib):
+    """gcr_apply_precond_static rejects sizes beyond its static work array and
+    bad arguments with GCR_EINVAL and a message, without touching a device."""
+    op = lib.GcrOperator(dt=600.0, g=lib.GRAVITY, omega=lib.OMEGA, radius=lib.RADIUS, absorber=0.0,
+                         depth=C.c_void_p(64), orography=None, b_terms=1, mem_is_device=1)
+    f = lib._lib.gcr_apply_precond_static
+    one, two = C.c_void_p(128), C.c_void_p(256)
+    assert f(512, 512, C.addressof(op), 2, one, two, None) == lib.EINVAL
+    assert b"exceeds" in lib._lib.gcr_last_error(None)
+    assert f(48, 16, C.addressof(op), 2, one, two, None) == lib.EINVAL
+    assert f(64, 1, C.addressof(op), 2, one, two, None) == lib.EINVAL
+    assert f(64, 32, C.addressof(op), 0, one, two, None) == lib.EINVAL
+    assert f(64, 32, None, 2, one, two, None) == lib.EINVAL
+    assert f(64, 32, C.addressof(op), 2, one, one, None) == lib.EINVAL
+    op.mem_is_device = 0
+    assert f(64, 32, C.addressof(op), 2, one, two, None) == lib.EINVAL
+    assert lib.STATIC_MAX_POINTS == 131072
+    text = open(os.path.join(ROOT, "include", "mpgcr.h")).read()
+    assert "#define GCR_STATIC_MAX_POINTS 131072" in text
