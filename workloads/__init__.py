@@ -12,5 +12,7 @@ from .fields import (  # noqa: F401
     problem,
     batch_problems,
     jet_sequence_depth,
+    zonal_flow_state,
+    model_state,
     CONFIG_SEED_BASE,
 )

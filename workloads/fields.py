@@ -134,3 +134,34 @@ def jet_sequence_depth(nx, ny, step, dt, u0=40.0, pert_amp=200.0, pert_lmax=16,
     shift = u0 * step * dt / _A
     pert = harmonic_field(nx, ny, pert_lmax, rng, lmin=1, amplitude=pert_amp, lam_shift=shift)
     return h[:, None] + pert
+
+
+def zonal_flow_state(nx, ny, u0=40.0, pert_amp=0.0, pert_lmax=16, seed_instance=0, config=6):
+    """A state of the shallow-water model for the semi-implicit step: the
+    zonal jet u = u0 cos(lat) with the depth of jet_sequence_depth (gradient-
+    wind balance, plus a degree <= pert_lmax perturbation of amplitude
+    pert_amp), v = 0.  Returns dict(phi, qx, qy) with Q = Phi * velocity."""
+    lam, phi = cell_centres(nx, ny)
+    h = 8000.0 - (_A * _OMEGA * u0 + 0.5 * u0 * u0) * np.sin(phi) ** 2 / _G
+    depth = np.repeat(h[:, None], nx, axis=1)
+    if pert_amp > 0:
+        rng = np.random.default_rng(_seed(config, seed_instance))
+        depth = depth + harmonic_field(nx, ny, pert_lmax, rng, lmin=1, amplitude=pert_amp)
+    u = u0 * np.cos(phi)[:, None] * np.ones((1, nx))
+    return dict(phi=depth, qx=depth * u, qy=np.zeros_like(depth))
+
+
+def model_state(nx, ny, instance=0, u0=40.0, pert_amp=100.0, pert_lmax=16, oro_amp=2000.0, oro_lmax=8, config=7):
+    """A state over synthetic mountains for the semi-implicit step: the zonal
+    jet of zonal_flow_state with its balanced free surface, orography H0 =
+    oro_amp * (degree <= oro_lmax series mapped onto [0, 1]) under it (the
+    fluid thins over the mountains, Phi = surface - H0), plus a degree <=
+    pert_lmax perturbation of the depth.  Returns dict(phi, qx, qy, orography)."""
+    rng = np.random.default_rng(_seed(config, instance))
+    base = zonal_flow_state(nx, ny, u0=u0)
+    f = harmonic_field(nx, ny, oro_lmax, rng, lmin=1, amplitude=1.0)
+    h0 = oro_amp * (f - f.min()) / (f.max() - f.min())
+    depth = base["phi"] - h0 + harmonic_field(nx, ny, pert_lmax, rng, lmin=1, amplitude=pert_amp)
+    u = base["qx"] / base["phi"]
+    return dict(phi=depth, qx=depth * u, qy=np.zeros_like(depth), orography=h0)
+
