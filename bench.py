@@ -164,6 +164,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison leg")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel event timing")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner leg")
+    ap.add_argument("--graph", action="store_true", help="replay iterations and cycle ends from HIP graphs")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (reference for HBM counters)")
     return ap.parse_args()
@@ -192,7 +193,8 @@ class Leg:
                  reference=None):
         self.lib, self.torch = lib, torch
         precond = lib.PC_SEMI_IMPLICIT if precond is None else precond
-        self.solver = lib.Solver(sizes, precision=precision, precond=precond, rtol=args.rtol, max_iters=100)
+        self.solver = lib.Solver(sizes, precision=precision, precond=precond, rtol=args.rtol, max_iters=100,
+                                 graph=args.graph)
         if learned is not None:
             self.solver.set_learned(learned)
             if reference is not None:

@@ -130,6 +130,17 @@ enum {
                                       for many time steps), Phi_tilde =
                                       fl32(x_0 - Phi_hat); every member needs a
                                       base (GCR_ESTATE otherwise)                 */
+#define GCR_F_GRAPH 0x40u          /* replay the kernels of every GCR iteration and
+                                      cycle end from HIP graphs, captured once per
+                                      window position and ring slot on first use
+                                      (the host still reads the done flags once per
+                                      cycle); results are bitwise those without.
+                                      Not used with the learned preconditioner or
+                                      with per-kernel timing.  With a NULL stream
+                                      the solver orders its work on a blocking
+                                      stream of its own (the null stream cannot
+                                      be captured; its work stays ordered with
+                                      that stream's)                              */
 
 typedef struct {
   int32_t batch;          /* number of independent solves, 1..4096                    */
@@ -323,7 +334,8 @@ enum {
   GCR_K_COPY = 7,       /* gather/scatter of caller fields                           */
   GCR_K_LEARNED = 8,    /* learned correction: features, five convolutions, update   */
   GCR_K_SOLUTION = 9,   /* step-2 solution updates, applied once per GCR cycle       */
-  GCR_K_COUNT = 10
+  GCR_K_SI_STEP = 10,   /* gcr_si_step's explicit part and momentum recovery         */
+  GCR_K_COUNT = 11
 };
 
 /* Enable (1) or disable (0) timing of every kernel the solver launches with
@@ -442,6 +454,47 @@ int gcr_set_learned_reference(gcr_solver* s, const double* rel_res, int32_t n);
  * Errors: GCR_EINVAL, GCR_ESTATE (no operator), GCR_EHIP. */
 int gcr_learned_features(gcr_solver* s, int32_t member, const double* x, const double* rhs, int32_t hi_iters,
                          float* feat, float* target, double* sigma);
+
+/* ---- the semi-implicit time step around the solve (paper Sections 2.1-2.2) */
+
+/* One member's state for gcr_si_step.  All fields are device float64
+ * [NY][NX] arrays of the member's size.  Variables: fluid thickness Phi (m),
+ * momenta Q_x, Q_y (Phi times the zonal / meridional velocity, m^2 s^-1). */
+typedef struct {
+  const double* phi;      /* Phi^n                                                   */
+  const double* qx;       /* Q_x^n                                                   */
+  const double* qy;       /* Q_y^n                                                   */
+  const double* phi_old;  /* Phi^{n-1} (first step: Phi^n)                           */
+  const double* qx_old;   /* Q_x^{n-1}                                               */
+  const double* qy_old;   /* Q_y^{n-1}                                               */
+  const double* orography;/* H0, or NULL for a flat surface                          */
+  const double* qbar_x;   /* relaxation target of the polar absorber, or NULL (zero) */
+  const double* qbar_y;
+  double* phi_new;        /* Phi^{n+1} (written; must not alias any input field)     */
+  double* qx_new;         /* Q_x^{n+1}                                               */
+  double* qy_new;         /* Q_y^{n+1}                                               */
+  double dt, g, omega, radius, absorber;   /* as in gcr_operator                     */
+} gcr_si_member;
+
+/* One time step n -> n+1 of the shallow-water equations in the paper's
+ * semi-implicit form (eqs. SWE1-SWE3, RSWE2-RSWE3, MPDATA, rhslin, Qexpr,
+ * Elliptic, vadv) for every member of the solver's batch:
+ *   forcings R^n; Q~ = Q^n + dt/2 R^n; the advective velocity at n + 1/2
+ *   extrapolated from n and n-1 as face Courant numbers; MPDATA (donor cell
+ *   plus one corrective pass, |psi| in the ratios, no limiter) of Phi^n, Q~_x,
+ *   Q~_y giving Phi* and Qhat; the implicit Coriolis / relaxation / pressure
+ *   terms inverted pointwise (eq. Qexpr); the elliptic problem
+ *   L(Phi^{n+1}) = D(F^n) + D(Fhathat) - C Phi^n assembled from Phi* and H0
+ *   (replacing each member's operator) and solved by gcr_solve from Phi^n;
+ *   then Q^{n+1} from eq. Qexpr.
+ * members: host array [batch].  reports: host array [batch] or NULL (the
+ * solve's reports).  The step's work fields (20 per member, ~ 8 * 20 * NX *
+ * (NY+1) bytes) are allocated by the first call and kept.  Returns the
+ * solve's worst soft status, or a hard error.  Synchronous.  Errors:
+ * GCR_EINVAL (NULL fields, aliasing of new and old state, dt / g / radius
+ * not > 0, absorber < 0, and every error of gcr_set_operators / gcr_solve,
+ * e.g. a non-positive Phi*), GCR_ENOMEM, GCR_EHIP. */
+int gcr_si_step(gcr_solver* s, const gcr_si_member* members, gcr_report* reports);
 
 #ifdef __cplusplus
 }

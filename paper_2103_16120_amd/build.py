@@ -23,7 +23,7 @@ ARCH = "gfx950"
 
 # the C-ABI, the network, and one source per precision form's solve
 SOURCES = ["solver.hip", "cnn.hip", "noalloc.hip", "solve_f64.hip", "solve_mixed.hip", "solve_mixed_fp64dot.hip",
-           "solve_mixed_half_pc.hip", "solve_single.hip", "solve_single_polar64.hip"]
+           "solve_mixed_half_pc.hip", "solve_single.hip", "solve_single_polar64.hip", "si_step.hip"]
 HEADERS = ["device.h", "kernels.h", "cnn.h", "cnn_internal.h", "learned.h", "solver_impl.h"]
 
 FLAGS = [

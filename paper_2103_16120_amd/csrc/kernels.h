@@ -12,7 +12,7 @@ namespace mpgcr {
 // kernel kinds for the optional per-kernel timing (values match the header)
 enum {
   KT_ASSEMBLE = 0, KT_RESIDUAL, KT_SWEEP1, KT_SWEEP2, KT_APPLY_L, KT_ORTH, KT_CONTROL, KT_COPY, KT_LEARNED,
-  KT_SOLUTION, KT_COUNT
+  KT_SOLUTION, KT_SI_STEP, KT_COUNT
 };
 
 // ---------------------------------------------------------------------------
@@ -340,6 +340,8 @@ struct Fields {
   double fallback_ratio;      // required residual reduction per cycle with it
   const double* learn_ref;    // reference relative residual after iteration i (plain preconditioner), or null
   int learn_ref_n;            // entries 1..learn_ref_n of learn_ref are set
+  int* cyc;                   // GCR cycle counter of the launch's member group (device; set to 0 by
+                              // k_ctrl_init, advanced by k_cycle_next at every cycle end)
 };
 
 // Run fn(coefficient rows) for row j with the storage precision of the
@@ -371,6 +373,15 @@ __device__ __forceinline__ bool wave_row(const Fields& F, int& g, int& m, Member
   m = F.rowmap[g];
   G = F.geom[m];
   return F.ignore_done || F.state[m].done == 0;
+}
+
+// log2 of the points per lane of the wave's row (0 when the wave has no
+// row): the row class a launch over several classes dispatches on
+__device__ __forceinline__ int row_class(const Fields& F) {
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = F.row_base + xcd_block(blockIdx.x, gridDim.x) * WPB + w;
+  if (g >= F.row_end) return 0;
+  return __builtin_amdgcn_readfirstlane(F.geom[F.rowmap[g]].log2m);
 }
 
 // Field row readers for the stencil (row-interleaved storage), converted to T.
@@ -708,7 +719,8 @@ __device__ __forceinline__ typename P::A row_update(const Fields& F, const RowCt
 // of p_nu, stamped with the cycle).  A member that goes on past the cycle's
 // last iteration has them applied by that iteration's step-4 pass, which
 // loads p_0 .. p_{k-1} anyway (k_orth); for the others (finished inside the
-// cycle) this pass applies those of cycle `cycle`.  Either way before anything
+// cycle) this pass applies those of the current cycle (the group's counter).
+// Either way before anything
 // reads x (the restart and final residuals) and before the ring slots are
 // reused.
 // The float64 operations (GCR_MIXED: float32 increments) and their order are
@@ -717,9 +729,10 @@ __device__ __forceinline__ typename P::A row_update(const Fields& F, const RowCt
 // too.
 // ---------------------------------------------------------------------------
 template <typename P, int M>
-__global__ __launch_bounds__(WG) void k_apply_pending(Fields F, int cycle) {
+__device__ __forceinline__ void kb_apply_pending(const Fields& F) {
   using T = typename P::T;
   using V = typename P::V;
+  const int cycle = *F.cyc;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = F.row_base + xcd_block(blockIdx.x, gridDim.x) * WPB + w;
@@ -752,6 +765,20 @@ __global__ __launch_bounds__(WG) void k_apply_pending(Fields F, int cycle) {
       for (int k = 0; k < M; ++k) xv[k] += beta * (double)pv[k];
     }
     if (R.act) str<M>(F.x + R.rc, l, L, xv);
+  }
+}
+
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_apply_pending(Fields F) {
+  if constexpr (M > 0) {
+    kb_apply_pending<P, M>(F);
+  } else {   // rows of several row classes (M = 2, 4, 8) in one launch
+    switch (row_class(F)) {
+      case 1: kb_apply_pending<P, 2>(F); break;
+      case 2: kb_apply_pending<P, 4>(F); break;
+      case 3: kb_apply_pending<P, 8>(F); break;
+      default: break;
+    }
   }
 }
 
@@ -790,7 +817,7 @@ __device__ __forceinline__ void row_update_sweep1(const Fields& F, const RowCtx&
 }
 
 template <typename P, int M>
-__global__ __launch_bounds__(WG) void k_update_sweep1(Fields F, int do_update, int slot_nu, int qout) {
+__device__ __forceinline__ void kb_update_sweep1(const Fields& F, int do_update, int slot_nu, int qout) {
   int g, m, lane, w;
   MemberGeom G;
   if (!wave_row(F, g, m, G, lane, w)) return;
@@ -802,6 +829,20 @@ __global__ __launch_bounds__(WG) void k_update_sweep1(Fields F, int do_update, i
     }
   }
   row_update_sweep1<P, M>(F, R, G, do_update, slot_nu, qout);
+}
+
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_update_sweep1(Fields F, int do_update, int slot_nu, int qout) {
+  if constexpr (M > 0) {
+    kb_update_sweep1<P, M>(F, do_update, slot_nu, qout);
+  } else {   // rows of several row classes (M = 2, 4, 8) in one launch
+    switch (row_class(F)) {
+      case 1: kb_update_sweep1<P, 2>(F, do_update, slot_nu, qout); break;
+      case 2: kb_update_sweep1<P, 4>(F, do_update, slot_nu, qout); break;
+      case 3: kb_update_sweep1<P, 8>(F, do_update, slot_nu, qout); break;
+      default: break;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -841,7 +882,7 @@ __device__ __forceinline__ void row_sweep2(const Fields& F, const RowCtx& R, con
 }
 
 template <typename P, int M, bool FL>
-__global__ __launch_bounds__(WG) void k_sweep2(Fields F, int qin, int qout) {
+__device__ __forceinline__ void kb_sweep2(const Fields& F, int qin, int qout) {
   int g, m, lane, w;
   MemberGeom G;
   if (!wave_row(F, g, m, G, lane, w)) return;
@@ -855,6 +896,20 @@ __global__ __launch_bounds__(WG) void k_sweep2(Fields F, int qin, int qout) {
   row_sweep2<P, M, FL>(F, R, G, qin, qout);
 }
 
+template <typename P, int M, bool FL>
+__global__ __launch_bounds__(WG) void k_sweep2(Fields F, int qin, int qout) {
+  if constexpr (M > 0) {
+    kb_sweep2<P, M, FL>(F, qin, qout);
+  } else {   // rows of several row classes (M = 2, 4, 8) in one launch
+    switch (row_class(F)) {
+      case 1: kb_sweep2<P, 2, FL>(F, qin, qout); break;
+      case 2: kb_sweep2<P, 4, FL>(F, qin, qout); break;
+      case 3: kb_sweep2<P, 8, FL>(F, qin, qout); break;
+      default: break;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Fault injection for tests of the exit logic (paper Section 2.3: breakdown
 // and a non-finite result stop the iteration): every member that has
@@ -862,7 +917,7 @@ __global__ __launch_bounds__(WG) void k_sweep2(Fields F, int qin, int qout) {
 // (mode 2) preconditioner output e in place of the computed one.
 // ---------------------------------------------------------------------------
 template <typename P, int M>
-__global__ __launch_bounds__(WG) void k_fault_e(Fields F, int mode, int at_it) {
+__device__ __forceinline__ void kb_fault_e(const Fields& F, int mode, int at_it) {
   using V = typename P::V;
   int g, m, lane, w;
   MemberGeom G;
@@ -873,6 +928,20 @@ __global__ __launch_bounds__(WG) void k_fault_e(Fields F, int mode, int at_it) {
 #pragma unroll
   for (int k = 0; k < M; ++k) v[k] = mode == 1 ? (V)__builtin_nan("") : (V)0;
   if (R.act) str<M>((V*)F.e + R.rc, R.lane, R.L, v);
+}
+
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_fault_e(Fields F, int mode, int at_it) {
+  if constexpr (M > 0) {
+    kb_fault_e<P, M>(F, mode, at_it);
+  } else {   // rows of several row classes (M = 2, 4, 8) in one launch
+    switch (row_class(F)) {
+      case 1: kb_fault_e<P, 2>(F, mode, at_it); break;
+      case 2: kb_fault_e<P, 4>(F, mode, at_it); break;
+      case 3: kb_fault_e<P, 8>(F, mode, at_it); break;
+      default: break;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -905,11 +974,25 @@ __device__ __forceinline__ void row_update_simple(const Fields& F, const RowCtx&
 }
 
 template <typename P, int M>
-__global__ __launch_bounds__(WG) void k_update_simple(Fields F, int do_update, int slot_nu, int use_diag, int qout) {
+__device__ __forceinline__ void kb_update_simple(const Fields& F, int do_update, int slot_nu, int use_diag, int qout) {
   int g, m, lane, w;
   MemberGeom G;
   if (!wave_row(F, g, m, G, lane, w)) return;
   row_update_simple<P, M>(F, make_row(G, m, g, lane, M), G, do_update, slot_nu, use_diag, qout);
+}
+
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_update_simple(Fields F, int do_update, int slot_nu, int use_diag, int qout) {
+  if constexpr (M > 0) {
+    kb_update_simple<P, M>(F, do_update, slot_nu, use_diag, qout);
+  } else {   // rows of several row classes (M = 2, 4, 8) in one launch
+    switch (row_class(F)) {
+      case 1: kb_update_simple<P, 2>(F, do_update, slot_nu, use_diag, qout); break;
+      case 2: kb_update_simple<P, 4>(F, do_update, slot_nu, use_diag, qout); break;
+      case 3: kb_update_simple<P, 8>(F, do_update, slot_nu, use_diag, qout); break;
+      default: break;
+    }
+  }
 }
 
 template <typename P, int M, bool FL>
@@ -934,11 +1017,25 @@ __device__ __forceinline__ void row_jacobi(const Fields& F, const RowCtx& R, con
 }
 
 template <typename P, int M, bool FL>
-__global__ __launch_bounds__(WG) void k_jacobi(Fields F, int qin, int qout) {
+__device__ __forceinline__ void kb_jacobi(const Fields& F, int qin, int qout) {
   int g, m, lane, w;
   MemberGeom G;
   if (!wave_row(F, g, m, G, lane, w)) return;
   row_jacobi<P, M, FL>(F, make_row(G, m, g, lane, M), G, qin, qout);
+}
+
+template <typename P, int M, bool FL>
+__global__ __launch_bounds__(WG) void k_jacobi(Fields F, int qin, int qout) {
+  if constexpr (M > 0) {
+    kb_jacobi<P, M, FL>(F, qin, qout);
+  } else {   // rows of several row classes (M = 2, 4, 8) in one launch
+    switch (row_class(F)) {
+      case 1: kb_jacobi<P, 2, FL>(F, qin, qout); break;
+      case 2: kb_jacobi<P, 4, FL>(F, qin, qout); break;
+      case 3: kb_jacobi<P, 8, FL>(F, qin, qout); break;
+      default: break;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -997,7 +1094,7 @@ __device__ __forceinline__ void row_apply_L(const Fields& F, const RowCtx& R, co
 }
 
 template <typename P, int M, bool FL>
-__global__ __launch_bounds__(WG) void k_apply_L(Fields F, const void* in, void* out, int mode, int nl, Slots sl) {
+__device__ __forceinline__ void kb_apply_L(const Fields& F, const void* in, void* out, int mode, int nl, const Slots& sl) {
   int g, m, lane, w;
   MemberGeom G;
   if (!wave_row(F, g, m, G, lane, w)) return;
@@ -1009,6 +1106,20 @@ __global__ __launch_bounds__(WG) void k_apply_L(Fields F, const void* in, void* 
     }
   }
   row_apply_L<P, M, FL>(F, R, G, in, out, mode, nl, sl);
+}
+
+template <typename P, int M, bool FL>
+__global__ __launch_bounds__(WG) void k_apply_L(Fields F, const void* in, void* out, int mode, int nl, Slots sl) {
+  if constexpr (M > 0) {
+    kb_apply_L<P, M, FL>(F, in, out, mode, nl, sl);
+  } else {   // rows of several row classes (M = 2, 4, 8) in one launch
+    switch (row_class(F)) {
+      case 1: kb_apply_L<P, 2, FL>(F, in, out, mode, nl, sl); break;
+      case 2: kb_apply_L<P, 4, FL>(F, in, out, mode, nl, sl); break;
+      case 3: kb_apply_L<P, 8, FL>(F, in, out, mode, nl, sl); break;
+      default: break;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1068,12 +1179,26 @@ __device__ __forceinline__ void row_residual(const Fields& F, const RowCtx& R, c
 }
 
 template <typename P, int M, bool FL>
-__global__ __launch_bounds__(WG) void k_residual(Fields F, int write_krylov, int lp_slot, int respect_done, int io) {
+__device__ __forceinline__ void kb_residual(const Fields& F, int write_krylov, int lp_slot, int respect_done, int io) {
   int g, m, lane, w;
   MemberGeom G;
   const bool active = wave_row(F, g, m, G, lane, w);
   if (g >= F.row_end || (respect_done && !active)) return;
   row_residual<P, M, FL>(F, make_row(G, m, g, lane, M), G, write_krylov, lp_slot, io);
+}
+
+template <typename P, int M, bool FL>
+__global__ __launch_bounds__(WG) void k_residual(Fields F, int write_krylov, int lp_slot, int respect_done, int io) {
+  if constexpr (M > 0) {
+    kb_residual<P, M, FL>(F, write_krylov, lp_slot, respect_done, io);
+  } else {   // rows of several row classes (M = 2, 4, 8) in one launch
+    switch (row_class(F)) {
+      case 1: kb_residual<P, 2, FL>(F, write_krylov, lp_slot, respect_done, io); break;
+      case 2: kb_residual<P, 4, FL>(F, write_krylov, lp_slot, respect_done, io); break;
+      case 3: kb_residual<P, 8, FL>(F, write_krylov, lp_slot, respect_done, io); break;
+      default: break;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1115,7 +1240,7 @@ struct SumReader {
 // Phi_hat = fl32(phi) and its float32 differences, from the float64 field in
 // the pooled x; differences taken in float64 of the float32 values.
 template <typename P, int M>   // P: unused (the row-launch helper's signature)
-__global__ __launch_bounds__(WG) void k_split_base(Fields F, SplitArgs S) {
+__device__ __forceinline__ void kb_split_base(const Fields& F, SplitArgs S) {
   int g, m, lane, w;
   MemberGeom G;
   if (!wave_row(F, g, m, G, lane, w)) return;
@@ -1158,11 +1283,25 @@ __global__ __launch_bounds__(WG) void k_split_base(Fields F, SplitArgs S) {
   }
 }
 
+template <typename P, int M>   // P: unused (the row-launch helper's signature)
+__global__ __launch_bounds__(WG) void k_split_base(Fields F, SplitArgs S) {
+  if constexpr (M > 0) {
+    kb_split_base<P, M>(F, S);
+  } else {   // rows of several row classes (M = 2, 4, 8) in one launch
+    switch (row_class(F)) {
+      case 1: kb_split_base<P, 2>(F, S); break;
+      case 2: kb_split_base<P, 4>(F, S); break;
+      case 3: kb_split_base<P, 8>(F, S); break;
+      default: break;
+    }
+  }
+}
+
 // The split of a solve's initial guess (paper Section 4.2.1): Phi_tilde =
 // fl32(x_0 - Phi_hat) from the caller's x_0 (natural order) and the stored
 // base, and x_0 into the pooled solution, for every member (finished or not).
 template <typename P, int M>
-__global__ __launch_bounds__(WG) void k_split_tilde(Fields F, SplitArgs S) {
+__device__ __forceinline__ void kb_split_tilde(const Fields& F, SplitArgs S) {
   int g, m, lane, w;
   MemberGeom G;
   wave_row(F, g, m, G, lane, w);
@@ -1181,13 +1320,27 @@ __global__ __launch_bounds__(WG) void k_split_tilde(Fields F, SplitArgs S) {
   }
 }
 
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_split_tilde(Fields F, SplitArgs S) {
+  if constexpr (M > 0) {
+    kb_split_tilde<P, M>(F, S);
+  } else {   // rows of several row classes (M = 2, 4, 8) in one launch
+    switch (row_class(F)) {
+      case 1: kb_split_tilde<P, 2>(F, S); break;
+      case 2: kb_split_tilde<P, 4>(F, S); break;
+      case 3: kb_split_tilde<P, 8>(F, S); break;
+      default: break;
+    }
+  }
+}
+
 // r = L_SP(Phi_hat + Phi_tilde) - R.  mode 0 (stand-alone): R from the
 // pooled rhs, r into the pooled r64.  mode 1 (a solve's initial residual):
 // R from the caller's arrays, r into the Krylov residual in the form's units
 // (s r, vector type P::V) with its <r,r> partials (and max |r| with the
 // maximum-norm exit), for every member.
 template <typename P, int M>
-__global__ __launch_bounds__(WG) void k_residual_split(Fields F, SplitArgs S, int mode) {
+__device__ __forceinline__ void kb_residual_split(const Fields& F, SplitArgs S, int mode) {
   using V = typename P::V;
   int g, m, lane, w;
   MemberGeom G;
@@ -1319,6 +1472,20 @@ __global__ __launch_bounds__(WG) void k_residual_split(Fields F, SplitArgs S, in
   write_partial<double>(F, R, DOT_R_LP, 0.0);
 }
 
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_residual_split(Fields F, SplitArgs S, int mode) {
+  if constexpr (M > 0) {
+    kb_residual_split<P, M>(F, S, mode);
+  } else {   // rows of several row classes (M = 2, 4, 8) in one launch
+    switch (row_class(F)) {
+      case 1: kb_residual_split<P, 2>(F, S, mode); break;
+      case 2: kb_residual_split<P, 4>(F, S, mode); break;
+      case 3: kb_residual_split<P, 8>(F, S, mode); break;
+      default: break;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // step 4: p_{nu+1} = e + sum alpha_l p_l ; L p_{nu+1} = L e + sum alpha_l L p_l,
 // with fused <r, L p_{nu+1}> and <L p_{nu+1}, L p_{nu+1}>.  In the last
@@ -1387,20 +1554,48 @@ __device__ __forceinline__ void row_orth(const Fields& F, const RowCtx& R, int n
 }
 
 template <typename P, int M>
-__global__ __launch_bounds__(WG) void k_orth(Fields F, int nl, Slots sl, int out_slot) {
+__device__ __forceinline__ void kb_orth(const Fields& F, int nl, const Slots& sl, int out_slot) {
   int g, m, lane, w;
   MemberGeom G;
   if (!wave_row(F, g, m, G, lane, w)) return;
   row_orth<P, M, false>(F, make_row(G, m, g, lane, M), nl, sl, out_slot);
 }
 
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_orth(Fields F, int nl, Slots sl, int out_slot) {
+  if constexpr (M > 0) {
+    kb_orth<P, M>(F, nl, sl, out_slot);
+  } else {   // rows of several row classes (M = 2, 4, 8) in one launch
+    switch (row_class(F)) {
+      case 1: kb_orth<P, 2>(F, nl, sl, out_slot); break;
+      case 2: kb_orth<P, 4>(F, nl, sl, out_slot); break;
+      case 3: kb_orth<P, 8>(F, nl, sl, out_slot); break;
+      default: break;
+    }
+  }
+}
+
 // the last iteration of a cycle: step 4 and the cycle's solution updates
 template <typename P, int M>
-__global__ __launch_bounds__(WG) void k_orth_last(Fields F, int nl, Slots sl, int out_slot) {
+__device__ __forceinline__ void kb_orth_last(const Fields& F, int nl, const Slots& sl, int out_slot) {
   int g, m, lane, w;
   MemberGeom G;
   if (!wave_row(F, g, m, G, lane, w)) return;
   row_orth<P, M, true>(F, make_row(G, m, g, lane, M), nl, sl, out_slot);
+}
+
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_orth_last(Fields F, int nl, Slots sl, int out_slot) {
+  if constexpr (M > 0) {
+    kb_orth_last<P, M>(F, nl, sl, out_slot);
+  } else {   // rows of several row classes (M = 2, 4, 8) in one launch
+    switch (row_class(F)) {
+      case 1: kb_orth_last<P, 2>(F, nl, sl, out_slot); break;
+      case 2: kb_orth_last<P, 4>(F, nl, sl, out_slot); break;
+      case 3: kb_orth_last<P, 8>(F, nl, sl, out_slot); break;
+      default: break;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1718,8 +1913,15 @@ __device__ __forceinline__ double member_sum(const Fields& F, const MemberGeom& 
 
 enum { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_STAGNATED = 2, ST_FALLBACK = 3 };
 
+// the group's cycle counter to the next cycle (one thread; after the cycle's
+// last kernel that reads it)
+static __global__ void k_cycle_next(int* c) {
+  if (threadIdx.x == 0) *c += 1;
+}
+
 template <typename A>
 __global__ void k_ctrl_init(Fields F) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *F.cyc = 0;
   const int m = F.morder[F.q0 + blockIdx.x];
   const MemberGeom G = F.geom[m];
   const double rr = member_sum<double>(F, G, DOT_RR);
@@ -1773,8 +1975,8 @@ __global__ void k_ctrl_beta(Fields F, int slot) {
 
 // after step 3: exit test on the updated residual, then step-4 coefficients
 template <typename A>
-__global__ void k_ctrl_alpha(Fields F, int nl, Slots sl, int cycle_end, int min_iters, int max_iters, double rtol,
-                             int cycle) {
+__global__ void k_ctrl_alpha(Fields F, int nl, Slots sl, int cycle_end, int min_iters, int max_iters, double rtol) {
+  const int cycle = *F.cyc;
   const int m = F.morder[F.q0 + blockIdx.x];
   MemberState& S = F.state[m];
   if (S.done) return;

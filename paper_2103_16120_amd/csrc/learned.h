@@ -79,7 +79,7 @@ __device__ __forceinline__ void learn_factors(const Fields& F, int m, double sig
 
 // one wave per row: write the row's pixels of the network input
 template <typename P, int M>
-__global__ __launch_bounds__(WG) void k_learn_pack(Fields F, LearnArgs A) {
+__device__ __forceinline__ void kb_learn_pack(const Fields& F, LearnArgs A) {
   using V = typename P::V;
   int g, m, lane, w;
   MemberGeom G;
@@ -110,6 +110,20 @@ __global__ __launch_bounds__(WG) void k_learn_pack(Fields F, LearnArgs A) {
   }
 }
 
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_learn_pack(Fields F, LearnArgs A) {
+  if constexpr (M > 0) {
+    kb_learn_pack<P, M>(F, A);
+  } else {   // rows of several row classes (M = 2, 4, 8) in one launch
+    switch (row_class(F)) {
+      case 1: kb_learn_pack<P, 2>(F, A); break;
+      case 2: kb_learn_pack<P, 4>(F, A); break;
+      case 3: kb_learn_pack<P, 8>(F, A); break;
+      default: break;
+    }
+  }
+}
+
 // T = I - eta (P^Z - P^H) of the lane's points of one row
 template <typename T, int M, typename CV>
 __device__ __forceinline__ void learn_row_system(const RowCtx& R, const CV& cv, T (&lo)[M], T (&di)[M],
@@ -126,7 +140,7 @@ __device__ __forceinline__ void learn_row_system(const RowCtx& R, const CV& cv, 
 
 // one wave per row: e += T^{-1}(fc * y)
 template <typename P, int M>
-__global__ __launch_bounds__(WG) void k_learn_apply(Fields F, LearnArgs A) {
+__device__ __forceinline__ void kb_learn_apply(const Fields& F, LearnArgs A) {
   using T = typename P::T;
   using V = typename P::V;
   int g, m, lane, w;
@@ -149,6 +163,20 @@ __global__ __launch_bounds__(WG) void k_learn_apply(Fields F, LearnArgs A) {
     for (int k = 0; k < M; ++k) ev[k] += z[k];
     if (R.act) str<M>((V*)A.e + R.rc, R.lane, R.L, ev);
   });
+}
+
+template <typename P, int M>
+__global__ __launch_bounds__(WG) void k_learn_apply(Fields F, LearnArgs A) {
+  if constexpr (M > 0) {
+    kb_learn_apply<P, M>(F, A);
+  } else {   // rows of several row classes (M = 2, 4, 8) in one launch
+    switch (row_class(F)) {
+      case 1: kb_learn_apply<P, 2>(F, A); break;
+      case 2: kb_learn_apply<P, 4>(F, A); break;
+      case 3: kb_learn_apply<P, 8>(F, A); break;
+      default: break;
+    }
+  }
 }
 
 // training data, natural [NY][NX] order: features and target T(e_hi - e_lo)

@@ -1,0 +1,419 @@
+// One semi-implicit time step of the shallow-water model around the elliptic
+// solve (paper Sections 2.1-2.2: eqs. SWE1-SWE3, RSWE2-RSWE3, MPDATA, rhslin,
+// Qexpr, Elliptic, vadv), for every member of a solver's batch:
+//   1. the forcings R^n at the cell centres and Q~ = Q^n + dt/2 R^n;
+//   2. face Courant numbers of the advective velocity extrapolated to
+//      n + 1/2 from n and n-1;
+//   3. MPDATA (donor cell + one corrective pass) of Phi^n, Q~_x, Q~_y:
+//      Phi* and Qhat;
+//   4. the implicit momentum inverted pointwise (eq. Qexpr): Qhathat, the
+//      part of Q^{n+1} known before the solve;
+//   5. the right-hand side R = D(F^n) + D(Fhathat) - C Phi^n of the elliptic
+//      problem L(Phi^{n+1}) = R, with the operator assembled from Phi* and
+//      H0 and solved by the solver's own precision form, warm-started from
+//      Phi^n;
+//   6. Q^{n+1} = Qhathat + A grad Phi^{n+1} + B Phi^{n+1} (eq. Qexpr).
+// Fields are natural [NY][NX] float64 arrays; the kernels take one thread per
+// point and one workgroup row (blockIdx.y) per member.  Work arrays are the
+// solver's, allocated on the first call.
+#include "solver_impl.h"
+
+namespace {
+
+struct SiMember {
+  const double *phi, *qx, *qy;         // state at n
+  const double *phi0, *qx0, *qy0;      // state at n-1
+  const double *oro, *qbx, *qby;       // H0, relaxation target (null: zero)
+  double *phi1, *qx1, *qy1;            // state at n+1
+  double dt, g, omega, radius, absorber;
+  int nx, ny, log2nx;
+  long long w;                         // offset of the member's work fields
+};
+
+// work fields per member, each wpts (>= nx * (ny + 1)) values; W_LAT holds
+// the latitude table: per row j, cos(lat_j), sin(lat_j), cos(lat_{j+1/2}),
+// alpha(lat_j)
+enum { W_CX = 0, W_CY, W_P1, W_Q1X, W_Q1Y, W_AXP, W_AYP, W_AXQX, W_AYQX, W_AXQY, W_AYQY, W_PHIS, W_QHX, W_QHY,
+       W_QTX, W_QTY, W_QHHX, W_QHHY, W_RHS, W_LAT, W_COUNT };
+enum { LT_COS = 0, LT_SIN, LT_COSN, LT_ALPHA, LT_N };
+
+struct SiArgs {
+  const SiMember* tab;
+  double* work;
+  long long wpts;                      // values per work field and member
+};
+
+constexpr double kPi = 3.14159265358979323846;
+
+__device__ __forceinline__ double lat_of(int j, int ny) { return -0.5 * kPi + (j + 0.5) * (kPi / ny); }
+
+__device__ __forceinline__ double alpha_at(double lat, double amax) {
+  const double dist = 0.5 * kPi - fabs(lat);
+  const double w = 1.0 - dist / (3.0 * kPi / 64.0);
+  return amax * (w > 0.0 ? w : 0.0);
+}
+
+// value of field f at row jj (may be -1 or ny: the row across the pole,
+// shifted by nx/2, times `sign`) and column ii (periodic)
+__device__ __forceinline__ double at(const double* f, int jj, int ii, int nx, int ny, double sign) {
+  double s = 1.0;
+  if (jj < 0) {
+    jj = 0;
+    ii += nx >> 1;
+    s = sign;
+  } else if (jj >= ny) {
+    jj = ny - 1;
+    ii += nx >> 1;
+    s = sign;
+  }
+  return s * f[(long long)jj * nx + (ii & (nx - 1))];
+}
+
+__device__ __forceinline__ double* wf(const SiArgs& A, const SiMember& M, int k) {
+  return A.work + M.w + (long long)k * A.wpts;
+}
+
+// One thread per point of member blockIdx.y.  gridDim.x is a multiple of the
+// XCD count, so block x of every member runs on XCD x mod 8; xcd_block gives
+// each XCD a contiguous range of rows, and the neighbour rows a stencil reads
+// come from that XCD's own L2.
+#define SI_POINTS(A, M)                                                                      \
+  const SiMember M = (A).tab[blockIdx.y];                                                    \
+  const int n_ = M.nx * M.ny;                                                                \
+  for (int p_ = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; p_ < n_;         \
+       p_ += gridDim.x * blockDim.x)
+
+// the latitude table of every member
+__global__ void k_si_lat(SiArgs A) {
+  const SiMember M = A.tab[blockIdx.y];
+  double* t = wf(A, M, W_LAT);
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < M.ny; j += gridDim.x * blockDim.x) {
+    const double lat = lat_of(j, M.ny);
+    t[LT_N * j + LT_COS] = cos(lat);
+    t[LT_N * j + LT_SIN] = sin(lat);
+    t[LT_N * j + LT_COSN] = cos(-0.5 * kPi + (j + 1.0) * (kPi / M.ny));
+    t[LT_N * j + LT_ALPHA] = alpha_at(lat, M.absorber);
+  }
+}
+
+// velocity of eq. vadv over a^2 at a cell: (Q_x / (a Phi), cos Q_y / (a Phi))
+__device__ __forceinline__ void vel(const double* phi, const double* qx, const double* qy, long long k, double cs,
+                                    double a, double& vx, double& vy) {
+  vx = qx[k] / (a * phi[k]);
+  vy = cs * qy[k] / (a * phi[k]);
+}
+
+// 1-2: forcings, Q~ = Q + dt/2 R^n, and the face Courant numbers at n + 1/2
+__global__ void k_si_prepare(SiArgs A) {
+  SI_POINTS(A, M) {
+    const int j = p_ >> M.log2nx, i = p_ & (M.nx - 1), nx = M.nx, ny = M.ny;
+    const long long k = (long long)j * nx + i;
+    const double* lt = wf(A, M, W_LAT);
+    const double cs = lt[LT_N * j + LT_COS], sn = lt[LT_N * j + LT_SIN];
+    const double a = M.radius, d = 0.5 * M.dt;
+    const double dlam = 2.0 * kPi / nx, dphi = kPi / ny;
+    // gradient of Phi + H0 (central differences, across-pole rows)
+    auto hs = [&](int jj, int ii) {
+      return at(M.phi, jj, ii, nx, ny, 1.0) + (M.oro ? at(M.oro, jj, ii, nx, ny, 1.0) : 0.0);
+    };
+    const double hx = (hs(j, i + 1) - hs(j, i - 1)) / (2.0 * dlam);
+    const double hy = (hs(j + 1, i) - hs(j - 1, i)) / (2.0 * dphi);
+    const double ph = M.phi[k], qx = M.qx[k], qy = M.qy[k];
+    const double f = 2.0 * M.omega * sn, al = lt[LT_N * j + LT_ALPHA], t = sn / cs;
+    const double qbx = M.qbx ? M.qbx[k] : 0.0, qby = M.qby ? M.qby[k] : 0.0;
+    const double rx = -M.g / (a * cs) * ph * hx + f * qy + t * qx * qy / (a * ph) - al * (qx - qbx);
+    const double ry = -M.g / a * ph * hy - f * qx - t * qx * qx / (a * ph) - al * (qy - qby);
+    wf(A, M, W_QTX)[k] = qx + d * rx;
+    wf(A, M, W_QTY)[k] = qy + d * ry;
+    // advective velocity at n + 1/2 = 1.5 v^n - 0.5 v^{n-1}, at the east and north faces
+    auto vext = [&](int jj, int ii, double& vx, double& vy) {
+      const long long kk = (long long)jj * nx + (ii & (nx - 1));
+      const double c = lt[LT_N * jj + LT_COS];
+      double x1, y1, x0, y0;
+      vel(M.phi, M.qx, M.qy, kk, c, a, x1, y1);
+      vel(M.phi0, M.qx0, M.qy0, kk, c, a, x0, y0);
+      vx = 1.5 * x1 - 0.5 * x0;
+      vy = 1.5 * y1 - 0.5 * y0;
+    };
+    double vx, vy, vxe, vye;
+    vext(j, i, vx, vy);
+    vext(j, i + 1, vxe, vye);
+    wf(A, M, W_CX)[k] = 0.5 * (vx + vxe) * M.dt / dlam;
+    double cyn = 0.0;
+    if (j < ny - 1) {
+      double vxn, vyn;
+      vext(j + 1, i, vxn, vyn);
+      cyn = 0.5 * (vy + vyn) * M.dt / dphi;
+    }
+    wf(A, M, W_CY)[k] = cyn;   // face j + 1/2 (zero at the north pole)
+  }
+}
+
+// donor-cell pass of the three advected fields: out = in - (div of upwind
+// fluxes) / cos(lat); `ax*` / `ay*`: the Courant numbers of each field
+struct UpwindSet {
+  int in[3], out[3], cx[3], cy[3];
+  int from_state;                      // pass 1 reads Phi^n and Q~ (in[0] < 0: Phi^n)
+};
+
+__global__ void k_si_upwind(SiArgs A, UpwindSet U) {
+  SI_POINTS(A, M) {
+    const int j = p_ >> M.log2nx, i = p_ & (M.nx - 1), nx = M.nx, ny = M.ny;
+    const long long k = (long long)j * nx + i;
+    const double g = wf(A, M, W_LAT)[LT_N * j + LT_COS];
+    const int ie = (i + 1) & (nx - 1), iw = (i - 1) & (nx - 1);
+    for (int fdx = 0; fdx < 3; ++fdx) {
+      const double* psi = U.in[fdx] < 0 ? M.phi : wf(A, M, U.in[fdx]);
+      const double* cxa = wf(A, M, U.cx[fdx]);
+      const double* cya = wf(A, M, U.cy[fdx]);
+      const long long row = (long long)j * nx;
+      auto flux = [](double c, double l, double r) { return fmax(c, 0.0) * l + fmin(c, 0.0) * r; };
+      const double fe = flux(cxa[k], psi[k], psi[row + ie]);
+      const double fw = flux(cxa[row + iw], psi[row + iw], psi[k]);
+      const double fn = j < ny - 1 ? flux(cya[k], psi[k], psi[k + nx]) : 0.0;
+      const double fs = j > 0 ? flux(cya[k - nx], psi[k - nx], psi[k]) : 0.0;
+      wf(A, M, U.out[fdx])[k] = psi[k] - ((fe - fw) + (fn - fs)) / g;
+    }
+  }
+}
+
+// antidiffusive Courant numbers of the corrective pass for the three fields
+// (|psi| in the ratios; momenta change sign across a pole)
+__global__ void k_si_antidiff(SiArgs A) {
+  SI_POINTS(A, M) {
+    const int j = p_ >> M.log2nx, i = p_ & (M.nx - 1), nx = M.nx, ny = M.ny;
+    const long long k = (long long)j * nx + i;
+    const double* lt = wf(A, M, W_LAT);
+    const double gx = lt[LT_N * j + LT_COS];
+    const double* cx = wf(A, M, W_CX);
+    const double* cy = wf(A, M, W_CY);
+    const int ins[3] = {W_P1, W_Q1X, W_Q1Y};
+    const int oxs[3] = {W_AXP, W_AXQX, W_AXQY};
+    const int oys[3] = {W_AYP, W_AYQX, W_AYQY};
+    const double tiny = 1e-300;
+    // y-face Courant numbers around the east face (i+1/2, j): faces j+1/2 and
+    // j-1/2 of columns i and i+1 (pole faces carry zero)
+    auto cyf = [&](int jj, int ii) {   // face jj + 1/2
+      return (jj < 0 || jj >= ny - 1) ? 0.0 : cy[(long long)jj * nx + (ii & (nx - 1))];
+    };
+    const double cyb = 0.25 * (cyf(j, i) + cyf(j, i + 1) + cyf(j - 1, i) + cyf(j - 1, i + 1));
+    const double c = cx[k];
+    double cxb = 0.0;
+    if (j < ny - 1) {
+      auto cxf = [&](int jj, int ii) { return cx[(long long)jj * nx + (ii & (nx - 1))]; };
+      cxb = 0.25 * (cxf(j, i) + cxf(j, i - 1) + cxf(j + 1, i) + cxf(j + 1, i - 1));
+    }
+    const double cyn = j < ny - 1 ? cy[k] : 0.0;
+    const double gy = lt[LT_N * j + LT_COSN];
+    for (int fdx = 0; fdx < 3; ++fdx) {
+      const double* psi = wf(A, M, ins[fdx]);
+      const double sg = fdx == 0 ? 1.0 : -1.0;
+      auto v = [&](int jj, int ii) { return fabs(at(psi, jj, ii, nx, ny, sg)); };
+      // east face
+      const double pc = v(j, i), pe = v(j, i + 1);
+      const double axr = (pe - pc) / (pe + pc + tiny);
+      const double num = (v(j + 1, i + 1) + v(j + 1, i)) - (v(j - 1, i + 1) + v(j - 1, i));
+      const double den = (v(j + 1, i + 1) + v(j + 1, i)) + (v(j - 1, i + 1) + v(j - 1, i));
+      const double bxr = 0.5 * num / (den + tiny);
+      wf(A, M, oxs[fdx])[k] = (fabs(c) - c * c / gx) * axr - c * cyb / gx * bxr;
+      // north face (interior faces only)
+      double ay = 0.0;
+      if (j < ny - 1) {
+        const double pn = v(j + 1, i);
+        const double ayr = (pn - pc) / (pn + pc + tiny);
+        const double nm = (v(j + 1, i + 1) + v(j, i + 1)) - (v(j + 1, i - 1) + v(j, i - 1));
+        const double dn = (v(j + 1, i + 1) + v(j, i + 1)) + (v(j + 1, i - 1) + v(j, i - 1));
+        const double byr = 0.5 * nm / (dn + tiny);
+        ay = (fabs(cyn) - cyn * cyn / gy) * ayr - cyn * cxb / gy * byr;
+      }
+      wf(A, M, oys[fdx])[k] = ay;
+    }
+  }
+}
+
+// 4: Qhathat, and the initial guess of the solve (Phi^n)
+__global__ void k_si_qhh(SiArgs A) {
+  SI_POINTS(A, M) {
+    const int j = p_ >> M.log2nx, i = p_ & (M.nx - 1), nx = M.nx, ny = M.ny;
+    const long long k = (long long)j * nx + i;
+    const double* lt = wf(A, M, W_LAT);
+    const double cs = lt[LT_N * j + LT_COS], sn = lt[LT_N * j + LT_SIN], t = sn / cs;
+    const double a = M.radius, d = 0.5 * M.dt;
+    const double dlam = 2.0 * kPi / nx, dphi = kPi / ny;
+    const double al = lt[LT_N * j + LT_ALPHA], gam = 1.0 + d * al, b = d * 2.0 * M.omega * sn;
+    const double D = gam * gam + b * b;
+    double h0x = 0.0, h0y = 0.0;
+    if (M.oro) {
+      h0x = (at(M.oro, j, i + 1, nx, ny, 1.0) - at(M.oro, j, i - 1, nx, ny, 1.0)) / (2.0 * dlam);
+      h0y = (at(M.oro, j + 1, i, nx, ny, 1.0) - at(M.oro, j - 1, i, nx, ny, 1.0)) / (2.0 * dphi);
+    }
+    const double mx = t * M.qx[k] * M.qy[k] / (a * M.phi[k]), my = -t * M.qx[k] * M.qx[k] / (a * M.phi[k]);
+    const double mx0 = t * M.qx0[k] * M.qy0[k] / (a * M.phi0[k]), my0 = -t * M.qx0[k] * M.qx0[k] / (a * M.phi0[k]);
+    const double qbx = M.qbx ? M.qbx[k] : 0.0, qby = M.qby ? M.qby[k] : 0.0;
+    const double ps = wf(A, M, W_PHIS)[k];
+    const double ex = wf(A, M, W_QHX)[k] + d * (al * qbx + 2.0 * mx - mx0) - d * M.g / (a * cs) * 0.5 * ps * h0x;
+    const double ey = wf(A, M, W_QHY)[k] + d * (al * qby + 2.0 * my - my0) - d * M.g / a * 0.5 * ps * h0y;
+    wf(A, M, W_QHHX)[k] = (gam * ex + b * ey) / D;
+    wf(A, M, W_QHHY)[k] = (-b * ex + gam * ey) / D;
+    M.phi1[k] = M.phi[k];
+  }
+}
+
+// 5: R = D(F^n) + D(Fhathat) - C Phi^n, F = (a Q_x, a cos Q_y) at the faces
+// (means of the two cells; no flux through the poles)
+__global__ void k_si_rhs(SiArgs A) {
+  SI_POINTS(A, M) {
+    const int j = p_ >> M.log2nx, i = p_ & (M.nx - 1), nx = M.nx, ny = M.ny;
+    const long long k = (long long)j * nx + i;
+    const double a = M.radius;
+    const double dlam = 2.0 * kPi / nx, dphi = kPi / ny;
+    const double* hx = wf(A, M, W_QHHX);
+    const double* hy = wf(A, M, W_QHHY);
+    const long long row = (long long)j * nx;
+    const int ie = (i + 1) & (nx - 1), iw = (i - 1) & (nx - 1);
+    auto qsx = [&](long long kk) { return M.qx[kk] + hx[kk]; };
+    auto qsy = [&](long long kk) { return M.qy[kk] + hy[kk]; };
+    const double fe = a * 0.5 * (qsx(k) + qsx(row + ie)), fw = a * 0.5 * (qsx(row + iw) + qsx(k));
+    const double* lt = wf(A, M, W_LAT);
+    const double cn = lt[LT_N * j + LT_COSN], csf = j > 0 ? lt[LT_N * (j - 1) + LT_COSN] : 0.0;
+    const double fn = j < ny - 1 ? a * cn * 0.5 * (qsy(k) + qsy(k + nx)) : 0.0;
+    const double fs = j > 0 ? a * csf * 0.5 * (qsy(k - nx) + qsy(k)) : 0.0;
+    const double C = 2.0 * a * a * lt[LT_N * j + LT_COS] / M.dt;
+    wf(A, M, W_RHS)[k] = (fe - fw) / dlam + (fn - fs) / dphi - C * M.phi[k];
+  }
+}
+
+// 6: Q^{n+1} = Qhathat + A grad Phi^{n+1} + B Phi^{n+1}
+__global__ void k_si_recover(SiArgs A) {
+  SI_POINTS(A, M) {
+    const int j = p_ >> M.log2nx, i = p_ & (M.nx - 1), nx = M.nx, ny = M.ny;
+    const long long k = (long long)j * nx + i;
+    const double* lt = wf(A, M, W_LAT);
+    const double cs = lt[LT_N * j + LT_COS], sn = lt[LT_N * j + LT_SIN];
+    const double a = M.radius, d = 0.5 * M.dt;
+    const double dlam = 2.0 * kPi / nx, dphi = kPi / ny;
+    const double al = lt[LT_N * j + LT_ALPHA], gam = 1.0 + d * al, b = d * 2.0 * M.omega * sn;
+    const double D = gam * gam + b * b;
+    const double* ps = wf(A, M, W_PHIS);
+    auto hs = [&](int jj, int ii) { return at(ps, jj, ii, nx, ny, 1.0) + (M.oro ? at(M.oro, jj, ii, nx, ny, 1.0) : 0.0); };
+    const double* p1 = M.phi1;
+    const double px = (at(p1, j, i + 1, nx, ny, 1.0) - at(p1, j, i - 1, nx, ny, 1.0)) / (2.0 * dlam);
+    const double py = (at(p1, j + 1, i, nx, ny, 1.0) - at(p1, j - 1, i, nx, ny, 1.0)) / (2.0 * dphi);
+    const double hx = (hs(j, i + 1) - hs(j, i - 1)) / (2.0 * dlam);
+    const double hy = (hs(j + 1, i) - hs(j - 1, i)) / (2.0 * dphi);
+    const double ux = -d * M.g / (a * cs) * 0.5 * (p1[k] * hx + ps[k] * px);
+    const double uy = -d * M.g / a * 0.5 * (p1[k] * hy + ps[k] * py);
+    M.qx1[k] = wf(A, M, W_QHHX)[k] + (gam * ux + b * uy) / D;
+    M.qy1[k] = wf(A, M, W_QHHY)[k] + (-b * ux + gam * uy) / D;
+  }
+}
+
+}  // namespace
+
+extern "C" int gcr_si_step(gcr_solver* s, const gcr_si_member* members, gcr_report* reports) {
+  if (!s) return GCR_EINVAL;
+  if (!members) return fail(s, GCR_EINVAL, "gcr_si_step: NULL member table");
+  const int B = s->prm.batch;
+  long long wpts = 0;
+  for (int m = 0; m < B; ++m) {
+    const gcr_si_member& q = members[m];
+    if (!q.phi || !q.qx || !q.qy || !q.phi_old || !q.qx_old || !q.qy_old || !q.phi_new || !q.qx_new || !q.qy_new)
+      return fail(s, GCR_EINVAL, "member %d: NULL state field", m);
+    if (!(q.dt > 0.0) || !(q.g > 0.0) || !(q.radius > 0.0) || !std::isfinite(q.omega) || !(q.absorber >= 0.0))
+      return fail(s, GCR_EINVAL, "member %d: dt, g, radius must be > 0, absorber >= 0", m);
+    if (q.phi_new == q.phi || q.qx_new == q.qx || q.qy_new == q.qy)
+      return fail(s, GCR_EINVAL, "member %d: the new state must not alias the state at n", m);
+    wpts = std::max(wpts, (long long)s->nx[m] * (s->ny[m] + 1));
+  }
+  wpts = (wpts + 63) / 64 * 64;
+  if (!s->si_work || s->si_wpts < wpts) {
+    hipError_t herr = hipSuccess;
+    if (s->si_work) (void)hipFree(s->si_work);
+    s->si_work = dalloc<double>((size_t)wpts * W_COUNT * B, herr);
+    if (herr != hipSuccess) {
+      s->si_work = nullptr;
+      return fail(s, GCR_ENOMEM, "semi-implicit step work arrays: %s", hipGetErrorString(herr));
+    }
+    s->si_wpts = wpts;
+    if (!s->si_tab) {
+      s->si_tab = dalloc<SiMember>(B, herr);
+      if (herr == hipSuccess) herr = hipHostMalloc(&s->si_stage, (size_t)B * sizeof(SiMember), 0);
+      if (herr != hipSuccess) return fail(s, GCR_ENOMEM, "semi-implicit step tables: %s", hipGetErrorString(herr));
+      s->allocs.push_back(s->si_tab);
+    }
+  }
+  // the staged table may still feed the previous upload
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  SiMember* tab_h = (SiMember*)s->si_stage;
+  int nymax = 0, nptmax = 0;
+  for (int m = 0; m < B; ++m) {
+    const gcr_si_member& q = members[m];
+    SiMember& t = tab_h[m];
+    t.phi = q.phi;
+    t.qx = q.qx;
+    t.qy = q.qy;
+    t.phi0 = q.phi_old;
+    t.qx0 = q.qx_old;
+    t.qy0 = q.qy_old;
+    t.oro = q.orography;
+    t.qbx = q.qbar_x;
+    t.qby = q.qbar_y;
+    t.phi1 = q.phi_new;
+    t.qx1 = q.qx_new;
+    t.qy1 = q.qy_new;
+    t.dt = q.dt;
+    t.g = q.g;
+    t.omega = q.omega;
+    t.radius = q.radius;
+    t.absorber = q.absorber;
+    t.nx = s->nx[m];
+    t.ny = s->ny[m];
+    t.log2nx = ilog2(t.nx);
+    t.w = (long long)m * W_COUNT * wpts;
+    nymax = std::max(nymax, t.ny);
+    nptmax = std::max(nptmax, t.nx * t.ny);
+  }
+  HIPCHK(s, hipMemcpyAsync(s->si_tab, tab_h, (size_t)B * sizeof(SiMember), hipMemcpyHostToDevice, s->stream));
+  SiArgs A{(const SiMember*)s->si_tab, s->si_work, wpts};
+  const int nblk = (std::min((nptmax + 255) / 256, 4096) + NXCD - 1) / NXCD * NXCD;
+  const dim3 grid((unsigned)nblk, (unsigned)B), blk(256);
+  KLAUNCH(s, KT_SI_STEP, k_si_lat, dim3((unsigned)((nymax + 255) / 256), (unsigned)B), blk, 0, s->stream, A);
+  KLAUNCH(s, KT_SI_STEP, k_si_prepare, grid, blk, 0, s->stream, A);
+  UpwindSet U1{{-1, W_QTX, W_QTY}, {W_P1, W_Q1X, W_Q1Y}, {W_CX, W_CX, W_CX}, {W_CY, W_CY, W_CY}, 1};
+  KLAUNCH(s, KT_SI_STEP, k_si_upwind, grid, blk, 0, s->stream, A, U1);
+  KLAUNCH(s, KT_SI_STEP, k_si_antidiff, grid, blk, 0, s->stream, A);
+  UpwindSet U2{{W_P1, W_Q1X, W_Q1Y}, {W_PHIS, W_QHX, W_QHY}, {W_AXP, W_AXQX, W_AXQY}, {W_AYP, W_AYQX, W_AYQY}, 0};
+  KLAUNCH(s, KT_SI_STEP, k_si_upwind, grid, blk, 0, s->stream, A, U2);
+  KLAUNCH(s, KT_SI_STEP, k_si_qhh, grid, blk, 0, s->stream, A);
+  KLAUNCH(s, KT_SI_STEP, k_si_rhs, grid, blk, 0, s->stream, A);
+  HIPCHK(s, hipGetLastError());
+  // the elliptic problem: the operator from Phi* and H0, solved from Phi^n
+  std::vector<gcr_operator> ops(B);
+  std::vector<int32_t> mem(B);
+  std::vector<const double*> rhs(B);
+  std::vector<double*> xs(B);
+  for (int m = 0; m < B; ++m) {
+    const gcr_si_member& q = members[m];
+    gcr_operator& o = ops[m];
+    o.dt = q.dt;
+    o.g = q.g;
+    o.omega = q.omega;
+    o.radius = q.radius;
+    o.absorber = q.absorber;
+    o.depth = s->si_work + (long long)m * W_COUNT * wpts + (long long)W_PHIS * wpts;
+    o.orography = q.orography;
+    o.b_terms = 1;
+    o.mem_is_device = 1;
+    mem[m] = m;
+    rhs[m] = s->si_work + (long long)m * W_COUNT * wpts + (long long)W_RHS * wpts;
+    xs[m] = q.phi_new;
+  }
+  int rc = gcr_set_operators(s, B, mem.data(), ops.data());
+  if (rc < 0) return rc;
+  const int st = gcr_solve(s, rhs.data(), xs.data(), reports);
+  if (st < 0) return st;
+  KLAUNCH(s, KT_SI_STEP, k_si_recover, grid, blk, 0, s->stream, A);
+  HIPCHK(s, hipGetLastError());
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return st;
+}

@@ -27,7 +27,17 @@ static void free_all(gcr_solver* s) {
   stop_workers(s);
   if (s->net) (void)cnn_destroy(s->net);
   s->net = nullptr;
+  auto drop_graphs = [](gcr_solver::Group& g) {
+    for (hipGraphExec_t& e : g.g_iter)
+      if (e) (void)hipGraphExecDestroy(e);
+    for (hipGraphExec_t& e : g.g_end)
+      if (e) (void)hipGraphExecDestroy(e);
+    g.g_iter.clear();
+    g.g_end.clear();
+  };
+  drop_graphs(s->whole);
   for (auto& g : s->groups) {
+    drop_graphs(g);
     if (g.st) (void)hipStreamSynchronize(g.st);
     for (int i = 0; i < 2; ++i) {
       if (g.ring[i]) (void)hipHostFree(g.ring[i]);
@@ -47,6 +57,10 @@ static void free_all(gcr_solver* s) {
   if (s->ptr_stage) (void)hipHostFree(s->ptr_stage);
   if (s->state_h) (void)hipHostFree(s->state_h);
   if (s->asm_stage) (void)hipHostFree(s->asm_stage);
+  if (s->si_stage) (void)hipHostFree(s->si_stage);
+  if (s->si_work) (void)hipFree(s->si_work);
+  s->si_stage = nullptr;
+  s->si_work = nullptr;
   for (int i = 0; i < 2; ++i) {
     if (s->state_ring[i]) (void)hipHostFree(s->state_ring[i]);
     if (s->cycle_ev[i]) (void)hipEventDestroy(s->cycle_ev[i]);
@@ -60,6 +74,11 @@ static void free_all(gcr_solver* s) {
   s->ptr_stage = nullptr;
   s->state_h = nullptr;
   s->asm_stage = nullptr;
+  if (s->own_stream) {
+    (void)hipStreamSynchronize(s->own_stream);
+    (void)hipStreamDestroy(s->own_stream);
+  }
+  s->own_stream = nullptr;
 }
 
 // Up to GROUPS_MAX groups of members, of about equal point counts, each with
@@ -81,7 +100,8 @@ static hipError_t make_groups(gcr_solver* s) {
   const int B = s->prm.batch;
   long long total = 0;   // groups of about equal points
   for (int m = 0; m < B; ++m) total += (long long)s->geom_h[m].nx * s->geom_h[m].ny;
-  const long long fit = total / (GROUP_PTS * (long long)s->classes.size());
+  const long long ncls = merge_classes(s->classes) ? 1 : (long long)s->classes.size();   // launches per kernel
+  const long long fit = total / (GROUP_PTS * ncls);
   int G = (int)std::min<long long>(std::min(GROUPS_MAX, B), std::max<long long>(fit, 1));
   if (s->prm.precond == GCR_PC_LEARNED || (s->prm.flags & GCR_F_ONE_STREAM)) G = 1;
   // With the runtime's eager code-object loading (HIP_ENABLE_DEFERRED_LOADING=0)
@@ -97,6 +117,7 @@ static hipError_t make_groups(gcr_solver* s) {
   for (int g = 0; g < G && e == hipSuccess; ++g) {
     gcr_solver::Group grp;
     grp.q0 = q;
+    grp.gi = g;
     const int r0 = row;
     const long long target = total * (g + 1) / G;
     // at least one member per group, and leave one for each later group
@@ -138,17 +159,32 @@ static hipError_t make_groups(gcr_solver* s) {
 // flat when none of its members has orography.
 static void refresh_flat(gcr_solver* s) {
   auto mark = [s](std::vector<RowClass>& cls) {
+    bool changed = false;
     for (RowClass& c : cls) {
       int all = 1;
       for (int m : s->morder_h) {
         const MemberGeom& G = s->geom_h[m];
         if (G.row0 >= c.row_begin && G.row0 < c.row_end) all &= s->flat_h[m];
       }
+      changed = changed || c.flat != all;
       c.flat = all;
     }
+    return changed;
+  };
+  // captured graphs hold the kernel variant of each class: a class whose
+  // orography status changed drops its group's graphs
+  auto drop = [](gcr_solver::Group& g) {
+    for (hipGraphExec_t& e : g.g_iter)
+      if (e) (void)hipGraphExecDestroy(e);
+    for (hipGraphExec_t& e : g.g_end)
+      if (e) (void)hipGraphExecDestroy(e);
+    g.g_iter.clear();
+    g.g_end.clear();
   };
   mark(s->classes);
-  for (gcr_solver::Group& g : s->groups) mark(g.classes);
+  if (mark(s->whole.classes)) drop(s->whole);
+  for (gcr_solver::Group& g : s->groups)
+    if (mark(g.classes)) drop(g);
 }
 
 extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
@@ -169,7 +205,7 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   if (!(P.rtol >= 0.0) || !std::isfinite(P.rtol)) return fail(nullptr, GCR_EINVAL, "rtol must be finite and >= 0");
   if (P.polar_rows < -1) return fail(nullptr, GCR_EINVAL, "polar_rows must be >= -1");
   if (P.flags & ~(GCR_F_RECORD_HISTORY | GCR_F_ONE_STREAM | GCR_F_LINF_EXIT | GCR_F_FAULT_NAN_PC | GCR_F_FAULT_ZERO_DIR |
-                  GCR_F_SPLIT_R0))
+                  GCR_F_SPLIT_R0 | GCR_F_GRAPH))
     return fail(nullptr, GCR_EINVAL, "unknown flags 0x%x", P.flags);
   if ((P.flags & GCR_F_SPLIT_R0) && P.precision != GCR_SINGLE && P.precision != GCR_SINGLE_POLAR64)
     return fail(nullptr, GCR_EINVAL, "GCR_F_SPLIT_R0 needs GCR_SINGLE or GCR_SINGLE_POLAR64");
@@ -189,6 +225,16 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   s->prm = P;
   if (s->prm.min_iters < 0) s->prm.min_iters = std::min(P.k + 1, P.max_iters);
   s->stream = (hipStream_t)P.stream;
+  if ((P.flags & GCR_F_GRAPH) && !P.stream) {
+    // the null stream cannot be captured: a blocking stream of the solver's
+    // own, which the null stream's work stays ordered with
+    const hipError_t e = hipStreamCreate(&s->own_stream);
+    if (e != hipSuccess) {
+      delete s;
+      return fail(nullptr, GCR_EHIP, "stream creation: %s", hipGetErrorString(e));
+    }
+    s->stream = s->own_stream;
+  }
   s->prm.nx = nullptr;
   s->prm.ny = nullptr;
   s->nx.assign(P.nx, P.nx + P.batch);
@@ -246,6 +292,7 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   s->state = (MemberState*)track(dalloc<MemberState>(P.batch, herr));
   s->pend = (Pending*)track(dalloc<Pending>(P.batch, herr));
   s->done_flag = (int*)track(dalloc<int>(P.batch, herr));
+  s->cyc_ctr = (int*)track(dalloc<int>(GROUPS_MAX + 1, herr));
   s->part = (double*)track(dalloc<double>((size_t)R * NDOT, herr));
   s->scale = (double*)track(dalloc<double>(P.batch, herr));
   for (int k = 0; k < NCOEF; ++k) {
@@ -309,6 +356,18 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   if (herr == hipSuccess)
     herr = hipMemcpyAsync(s->morder, s->morder_h.data(), P.batch * sizeof(int), hipMemcpyHostToDevice, s->stream);
   if (herr == hipSuccess) herr = make_groups(s);
+  {   // the whole batch as one group on the solver's stream
+    gcr_solver::Group& w = s->whole;
+    w.q0 = 0;
+    w.q1 = P.batch;
+    w.gi = 0;
+    w.classes = s->classes;
+    w.st = s->stream;
+    for (int i = 0; i < 2; ++i) {
+      w.cycle_ev[i] = s->cycle_ev[i];
+      w.ring[i] = s->state_ring[i];
+    }
+  }
   if (herr == hipSuccess) herr = hipMemsetAsync(s->state, 0, P.batch * sizeof(MemberState), s->stream);
   if (herr == hipSuccess) herr = hipMemsetAsync(s->pend, 0, P.batch * sizeof(Pending), s->stream);
   if (herr == hipSuccess) herr = hipMemsetAsync(s->done_flag, 0, P.batch * sizeof(int), s->stream);
@@ -831,6 +890,7 @@ extern "C" int gcr_kernel_time(gcr_solver* s, int32_t kind, int64_t* launches, d
 
 extern "C" const char* gcr_kernel_name(int32_t kind) {
   static const char* names[KT_COUNT] = {"assemble", "residual", "update_sweep1", "sweep2",  "apply_L",
-                                        "orth",     "control",  "copy",          "learned", "solution"};
+                                        "orth",     "control",  "copy",          "learned", "solution",
+                                        "si_step"};
   return (kind >= 0 && kind < KT_COUNT) ? names[kind] : "unknown";
 }

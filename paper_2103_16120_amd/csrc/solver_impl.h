@@ -73,19 +73,26 @@ struct gcr_solver {
   int nxmax = 0;
   std::vector<RowClass> classes;     // contiguous row ranges of equal points-per-lane
   hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;  // GCR_F_GRAPH with a NULL stream: the stream used instead
   // Groups of members with rows contiguous in row order, each solved on a
   // stream of its own, so that one group's kernel boundaries (the drain of
   // the last waves, the start of the next kernel) overlap the others' work.
   // Empty: the whole batch on `stream`.
   struct Group {
     int q0 = 0, q1 = 0;                // members morder[q0 .. q1)
+    int gi = 0;                        // index of the group's cycle counter
     std::vector<RowClass> classes;     // the group's rows
     hipStream_t st = nullptr;
     hipEvent_t cycle_ev[2] = {};
     int* ring[2] = {};                 // pinned copies of the done flags after a cycle
     hipEvent_t done_ev = nullptr;
+    // GCR_F_GRAPH: executable graphs of an iteration [nu][ring base] and of a
+    // cycle end [ring base], captured on first use
+    mutable std::vector<hipGraphExec_t> g_iter, g_end;
   };
   std::vector<Group> groups;
+  Group whole;                       // the whole batch on the solver's stream (no member groups)
+  int* cyc_ctr = nullptr;            // per group: the GCR cycle counter (device)
   std::vector<int> morder_h;         // members in row order
   int* morder = nullptr;
   hipEvent_t fork_ev = nullptr;
@@ -157,6 +164,11 @@ struct gcr_solver {
   double fallback_ratio = 0.5;
   double* learn_ref = nullptr;       // [max_iters + 1] reference relative residuals (device), or null
   int learn_ref_n = 0;
+  // gcr_si_step: work fields (allocated by its first call) and member tables
+  double* si_work = nullptr;
+  long long si_wpts = 0;
+  void* si_tab = nullptr;
+  void* si_stage = nullptr;          // pinned staging of si_tab
 
   // optional per-kernel timing with HIP events on the solver's stream
   bool timing = false;
@@ -237,19 +249,41 @@ void launch(gcr_solver* s, int kind, void (*kern)(KArgs...), dim3 grid, dim3 blo
 // class's rows (one wave per row).
 static_assert(KT_COUNT == GCR_K_COUNT, "kernel kinds match the header");
 
+// Several row classes whose points per lane are all <= 8 go in one launch
+// of the KNAME<P, 0> variant, which dispatches on each row's class; one
+// launch per kernel instead of one per class (an uneven batch would else be
+// bound by the host's launch rate).
+inline bool merge_classes(const std::vector<RowClass>& cls) {
+  if (cls.size() < 2) return false;
+  for (const RowClass& c : cls)
+    if (c.log2m > 3) return false;
+  return true;
+}
+
 #define ROWS_LAUNCH(s, CLASSES, F, KIND, KNAME, P, ...)                                     \
-  for (const RowClass& c_ : (CLASSES)) {                                                 \
-    Fields f_ = (F);                                                                     \
-    f_.row_base = c_.row_begin;                                                          \
-    f_.row_end = c_.row_end;                                                             \
-    const dim3 g_((c_.row_end - c_.row_begin + WPB - 1) / WPB), b_(WG);                  \
-    switch (c_.log2m) {                                                                  \
-      case 1: launch(s, KIND, &KNAME<P, 2>, g_, b_, f_, ##__VA_ARGS__); break;            \
-      case 2: launch(s, KIND, &KNAME<P, 4>, g_, b_, f_, ##__VA_ARGS__); break;            \
-      case 3: launch(s, KIND, &KNAME<P, 8>, g_, b_, f_, ##__VA_ARGS__); break;            \
-      default: launch(s, KIND, &KNAME<P, 16>, g_, b_, f_, ##__VA_ARGS__); break;          \
+  do {                                                                                   \
+    const std::vector<RowClass>& cl_ = (CLASSES);                                        \
+    if (merge_classes(cl_)) {                                                            \
+      Fields f_ = (F);                                                                   \
+      f_.row_base = cl_.front().row_begin;                                               \
+      f_.row_end = cl_.back().row_end;                                                   \
+      const dim3 g_((f_.row_end - f_.row_base + WPB - 1) / WPB), b_(WG);                 \
+      launch(s, KIND, &KNAME<P, 0>, g_, b_, f_, ##__VA_ARGS__);                          \
+      break;                                                                             \
     }                                                                                    \
-  }
+    for (const RowClass& c_ : cl_) {                                                     \
+      Fields f_ = (F);                                                                   \
+      f_.row_base = c_.row_begin;                                                        \
+      f_.row_end = c_.row_end;                                                           \
+      const dim3 g_((c_.row_end - c_.row_begin + WPB - 1) / WPB), b_(WG);                \
+      switch (c_.log2m) {                                                                \
+        case 1: launch(s, KIND, &KNAME<P, 2>, g_, b_, f_, ##__VA_ARGS__); break;          \
+        case 2: launch(s, KIND, &KNAME<P, 4>, g_, b_, f_, ##__VA_ARGS__); break;          \
+        case 3: launch(s, KIND, &KNAME<P, 8>, g_, b_, f_, ##__VA_ARGS__); break;          \
+        default: launch(s, KIND, &KNAME<P, 16>, g_, b_, f_, ##__VA_ARGS__); break;        \
+      }                                                                                  \
+    }                                                                                    \
+  } while (0)
 
 inline std::vector<RowClass> member_class(const gcr_solver* s, int member) {
   const MemberGeom& G = s->geom_h[member];
@@ -260,22 +294,36 @@ inline std::vector<RowClass> member_class(const gcr_solver* s, int member) {
 // formed from the depth fields: a class whose members all lack orography takes
 // the variant that reads Phi* only (FL = true), which holds fewer registers.
 #define ROWS_LAUNCH_F(s, CLASSES, F, KIND, KNAME, P, ...)                                   \
-  for (const RowClass& c_ : (CLASSES)) {                                                 \
-    Fields f_ = (F);                                                                     \
-    f_.row_base = c_.row_begin;                                                          \
-    f_.row_end = c_.row_end;                                                             \
-    const dim3 g_((c_.row_end - c_.row_begin + WPB - 1) / WPB), b_(WG);                  \
-    switch (std::min(c_.log2m, 4) * 2 + (c_.flat ? 1 : 0)) {                             \
-      case 2: launch(s, KIND, &KNAME<P, 2, false>, g_, b_, f_, ##__VA_ARGS__); break;     \
-      case 3: launch(s, KIND, &KNAME<P, 2, true>, g_, b_, f_, ##__VA_ARGS__); break;      \
-      case 4: launch(s, KIND, &KNAME<P, 4, false>, g_, b_, f_, ##__VA_ARGS__); break;     \
-      case 5: launch(s, KIND, &KNAME<P, 4, true>, g_, b_, f_, ##__VA_ARGS__); break;      \
-      case 6: launch(s, KIND, &KNAME<P, 8, false>, g_, b_, f_, ##__VA_ARGS__); break;     \
-      case 7: launch(s, KIND, &KNAME<P, 8, true>, g_, b_, f_, ##__VA_ARGS__); break;      \
-      case 9: launch(s, KIND, &KNAME<P, 16, true>, g_, b_, f_, ##__VA_ARGS__); break;     \
-      default: launch(s, KIND, &KNAME<P, 16, false>, g_, b_, f_, ##__VA_ARGS__); break;   \
+  do {                                                                                   \
+    const std::vector<RowClass>& cl_ = (CLASSES);                                        \
+    if (merge_classes(cl_)) {                                                            \
+      Fields f_ = (F);                                                                   \
+      f_.row_base = cl_.front().row_begin;                                               \
+      f_.row_end = cl_.back().row_end;                                                   \
+      const dim3 g_((f_.row_end - f_.row_base + WPB - 1) / WPB), b_(WG);                 \
+      bool fl_ = true;                                                                   \
+      for (const RowClass& c_ : cl_) fl_ = fl_ && c_.flat;                               \
+      if (fl_) launch(s, KIND, &KNAME<P, 0, true>, g_, b_, f_, ##__VA_ARGS__);           \
+      else launch(s, KIND, &KNAME<P, 0, false>, g_, b_, f_, ##__VA_ARGS__);              \
+      break;                                                                             \
     }                                                                                    \
-  }
+    for (const RowClass& c_ : cl_) {                                                     \
+      Fields f_ = (F);                                                                   \
+      f_.row_base = c_.row_begin;                                                        \
+      f_.row_end = c_.row_end;                                                           \
+      const dim3 g_((c_.row_end - c_.row_begin + WPB - 1) / WPB), b_(WG);                \
+      switch (std::min(c_.log2m, 4) * 2 + (c_.flat ? 1 : 0)) {                           \
+        case 2: launch(s, KIND, &KNAME<P, 2, false>, g_, b_, f_, ##__VA_ARGS__); break;   \
+        case 3: launch(s, KIND, &KNAME<P, 2, true>, g_, b_, f_, ##__VA_ARGS__); break;    \
+        case 4: launch(s, KIND, &KNAME<P, 4, false>, g_, b_, f_, ##__VA_ARGS__); break;   \
+        case 5: launch(s, KIND, &KNAME<P, 4, true>, g_, b_, f_, ##__VA_ARGS__); break;    \
+        case 6: launch(s, KIND, &KNAME<P, 8, false>, g_, b_, f_, ##__VA_ARGS__); break;   \
+        case 7: launch(s, KIND, &KNAME<P, 8, true>, g_, b_, f_, ##__VA_ARGS__); break;    \
+        case 9: launch(s, KIND, &KNAME<P, 16, true>, g_, b_, f_, ##__VA_ARGS__); break;   \
+        default: launch(s, KIND, &KNAME<P, 16, false>, g_, b_, f_, ##__VA_ARGS__); break; \
+      }                                                                                  \
+    }                                                                                    \
+  } while (0)
 
 inline bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 inline int ilog2(int v) {
@@ -329,6 +377,7 @@ inline Fields make_fields(gcr_solver* s) {
   F.fallback_ratio = s->fallback_ratio;
   F.learn_ref = s->learn_ref_n > 0 ? s->learn_ref : nullptr;
   F.learn_ref_n = s->learn_ref_n;
+  F.cyc = s->cyc_ctr;
   return F;
 }
 
@@ -457,9 +506,37 @@ int run_group(gcr_solver* s, const gcr_solver::Group& g) {
   const int k = s->prm.k, B = s->prm.batch, maxit = s->prm.max_iters;
   Fields F = make_fields(s);
   F.q0 = g.q0;
+  F.cyc = s->cyc_ctr + g.gi;
   const bool replace = s->prm.precision == GCR_MIXED_FP64DOT || s->prm.precision == GCR_MIXED_HALF_PC;
   const dim3 ctl(g.q1 - g.q0), wave(64);
   const std::vector<RowClass>& cls = g.classes;
+  // GCR_F_GRAPH: the launches of an iteration (per window position and ring
+  // base) and of a cycle end (per ring base) are captured once into a HIP
+  // graph on the group's stream and replayed; their arguments depend on
+  // nothing else (the cycle number lives on the device), and they hold
+  // kernel nodes only.
+  const bool graphs = (s->prm.flags & GCR_F_GRAPH) && !s->timing && s->prm.precond != GCR_PC_LEARNED;
+  if (graphs) {
+    g.g_iter.resize((size_t)k * (k + 1), nullptr);
+    g.g_end.resize((size_t)k + 1, nullptr);
+  }
+  auto via_graph = [&](hipGraphExec_t& exec, auto&& enqueue) -> int {
+    if (!exec) {
+      hipGraph_t graph = nullptr;
+      HIPCHK(s, hipStreamBeginCapture(g.st, hipStreamCaptureModeThreadLocal));
+      enqueue();
+      const hipError_t ec = hipStreamEndCapture(g.st, &graph);
+      if (ec != hipSuccess) return fail(s, GCR_EHIP, "graph capture: %s", hipGetErrorString(ec));
+      const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) {
+        exec = nullptr;
+        return fail(s, GCR_EHIP, "graph instantiation: %s", hipGetErrorString(ei));
+      }
+    }
+    HIPCHK(s, hipGraphLaunch(exec, g.st));
+    return GCR_OK;
+  };
 
   // step 1: r_0 = L(x_0) - R (float64; or the split single-precision
   // evaluation of paper Section 4.2.1), p_0 = P^{-1}(r_0), L(p_0)
@@ -480,12 +557,11 @@ int run_group(gcr_solver* s, const gcr_solver::Group& g) {
   KLAUNCH(s, KT_CONTROL, k_ctrl_beta<A>, ctl, wave, 0, g.st, F, 0);
   HIPCHK(s, hipGetLastError());
 
-  // iteration `it` (1-based) at window position nu of cycle `cyc`, whose p_0
+  // the launches of an iteration at window position nu of a cycle whose p_0
   // sits in ring slot `base`
-  auto iteration = [&](int it, int nu, int base, int cyc) {
+  auto iteration_launches = [&](int nu, int base) {
     Slots sl{};
     for (int l = 0; l <= k; ++l) sl.s[l] = (base + l) % (k + 1);
-    (void)it;
     // step 2 (+ first row solve of step 3)
     launch_precond<P>(s, cls, F, 1, sl.s[nu]);
     if (s->prm.flags & (GCR_F_FAULT_NAN_PC | GCR_F_FAULT_ZERO_DIR))
@@ -493,7 +569,7 @@ int run_group(gcr_solver* s, const gcr_solver::Group& g) {
     // step 3: L(e) with <L e, L p_l>, l = 0..nu
     ROWS_LAUNCH_F(s, cls, F, KT_APPLY_L, k_apply_L, P, (const void*)s->e, s->le, 0, nu + 1, sl);
     KLAUNCH(s, KT_CONTROL, k_ctrl_alpha<A>, ctl, wave, 0, g.st, F, nu + 1, sl, nu == k - 1 ? 1 : 0,
-            s->prm.min_iters, maxit, s->prm.rtol, cyc);
+            s->prm.min_iters, maxit, s->prm.rtol);
     // step 4
     if (nu == k - 1) {   // the cycle's last iteration also applies its solution updates
       ROWS_LAUNCH(s, cls, F, KT_ORTH, k_orth_last, P, nu + 1, sl, sl.s[nu + 1]);
@@ -502,13 +578,27 @@ int run_group(gcr_solver* s, const gcr_solver::Group& g) {
     }
     KLAUNCH(s, KT_CONTROL, k_ctrl_beta<A>, ctl, wave, 0, g.st, F, sl.s[nu + 1]);
   };
-  // end of cycle `cyc`: its solution updates; (p_0, L p_0) := (p_k, L p_k);
-  // residual replacement; flags
-  auto cycle_end = [&](int base_next, int ring, int cyc) -> int {
-    ROWS_LAUNCH(s, cls, F, KT_SOLUTION, k_apply_pending, P, cyc);
+  auto iteration = [&](int nu, int base) -> int {
+    if (graphs) return via_graph(g.g_iter[(size_t)nu * (k + 1) + base], [&] { iteration_launches(nu, base); });
+    iteration_launches(nu, base);
+    return GCR_OK;
+  };
+  // end of a cycle: its solution updates; (p_0, L p_0) := (p_k, L p_k);
+  // residual replacement; the next cycle number; the done flags
+  auto cycle_end_launches = [&](int base_next) {
+    ROWS_LAUNCH(s, cls, F, KT_SOLUTION, k_apply_pending, P);
     if (replace) {
       ROWS_LAUNCH_F(s, cls, F, KT_RESIDUAL, k_residual, P, 1, base_next, 1, RES_RHS_TAB);
       KLAUNCH(s, KT_CONTROL, k_ctrl_restart<double>, ctl, wave, 0, g.st, F, base_next);
+    }
+    KLAUNCH(s, KT_CONTROL, k_cycle_next, dim3(1), wave, 0, g.st, F.cyc);
+  };
+  auto cycle_end = [&](int base_next, int ring) -> int {
+    if (graphs) {
+      const int rc = via_graph(g.g_end[base_next], [&] { cycle_end_launches(base_next); });
+      if (rc != GCR_OK) return rc;
+    } else {
+      cycle_end_launches(base_next);
     }
     // the done flags (a few bytes per member: a small copy); only the group's
     // own members are read from them
@@ -519,22 +609,27 @@ int run_group(gcr_solver* s, const gcr_solver::Group& g) {
 
   int it = 0, base = 0, cycle = 0, rc;
   // cycle 0, complete
-  for (int nu = 0; nu < k && it < maxit; ++nu) iteration(++it, nu, base, 0);
+  for (int nu = 0; nu < k && it < maxit; ++nu, ++it)
+    if ((rc = iteration(nu, base)) != GCR_OK) return rc;
   base = (base + k) % (k + 1);
-  if ((rc = cycle_end(base, 0, 0)) != GCR_OK) return rc;
+  if ((rc = cycle_end(base, 0)) != GCR_OK) return rc;
   HIPCHK(s, hipGetLastError());
   for (;;) {
     // speculative first iteration of the next cycle
     const bool more = it < maxit;
-    if (more) iteration(++it, 0, base, cycle + 1);
+    if (more) {
+      ++it;
+      if ((rc = iteration(0, base)) != GCR_OK) return rc;
+    }
     HIPCHK(s, hipEventSynchronize(g.cycle_ev[cycle & 1]));
     bool done = true;
     for (int q = g.q0; q < g.q1; ++q) done = done && g.ring[cycle & 1][s->morder_h[q]] != 0;
     if (done || !more) break;
-    for (int nu = 1; nu < k && it < maxit; ++nu) iteration(++it, nu, base, cycle + 1);
+    for (int nu = 1; nu < k && it < maxit; ++nu, ++it)
+      if ((rc = iteration(nu, base)) != GCR_OK) return rc;
     base = (base + k) % (k + 1);
     ++cycle;
-    if ((rc = cycle_end(base, cycle & 1, cycle)) != GCR_OK) return rc;
+    if ((rc = cycle_end(base, cycle & 1)) != GCR_OK) return rc;
     HIPCHK(s, hipGetLastError());
   }
   // No update is pending here: the loop leaves right after a cycle end, or
@@ -555,15 +650,7 @@ int run_solve(gcr_solver* s) {
   const int B = s->prm.batch;
   const bool split = !s->groups.empty() && !s->timing;
   if (!split) {
-    gcr_solver::Group whole;
-    whole.q0 = 0;
-    whole.q1 = B;
-    whole.classes = s->classes;
-    whole.st = s->stream;
-    for (int i = 0; i < 2; ++i) {
-      whole.cycle_ev[i] = s->cycle_ev[i];
-      whole.ring[i] = s->state_ring[i];
-    }
+    const gcr_solver::Group& whole = s->whole;
     const int rc = run_group<P>(s, whole);
     if (rc != GCR_OK) return rc;
   } else {

@@ -7,6 +7,7 @@
     python -m paper_2103_16120_amd.experiments polar      # float32 polar-band width in the mixed forms
     python -m paper_2103_16120_amd.experiments exitnorm   # Euclidean vs maximum-norm exit test
     python -m paper_2103_16120_amd.experiments split      # split single-precision residual kernel
+    python -m paper_2103_16120_amd.experiments model      # the semi-implicit step around the solve
 
 single: one member of the configuration family (depth 8000 m + 500 m x
 degree<=8 harmonics, dt 600 s, R = L(degree<=12 field)), 64x32 solved to 1e-10
@@ -49,6 +50,20 @@ largest grid, which alone fills the GPU), three float64 rows per pole: per-call 
 operator (per-kernel HIP events), and the split kernel's algorithmic bandwidth
 (Phi_tilde 4, Phi_hat 4, four stored differences 16, Phi* 8, R 8, r 8 bytes per
 point, pooled fields).
+
+model: the semi-implicit time step of the shallow-water model around the solve
+(gcr_si_step), for 64 members of 512x256 over synthetic mountains (zonal jet
+u = 40 cos(lat) m/s with its balanced free surface, orography up to 2000 m of
+degree <= 8, depth perturbations of 100 m up to degree 16; dt 200 s and polar
+absorbers 1/(200 dt), the paper's settings for this grid).  A step is the
+explicit part (forcings, MPDATA of Phi and Q, the implicit inversion), the
+operator assembly from Phi*, the solve (rtol 1e-8) and the momentum recovery
+for the whole batch; the timed steps repeat one step from the same state, so
+every step does the same work.  Reported: time per step, its explicit-part
+share (per-kernel HIP events in a separate pass), the explicit kernels'
+algorithmic bandwidth (544 bytes per point: 68 float64 reads and writes),
+solver iterations, and a five-step trajectory (iterations, mass drift,
+largest velocity).
 """
 from __future__ import annotations
 
@@ -135,13 +150,17 @@ def batch(args):
     for name, prec in (("fp64", lib.FP64), ("mixed_half_pc", lib.MIXED_HALF_PC),
                        ("mixed_fp64dot", lib.MIXED_FP64DOT), ("mixed", lib.MIXED), ("single", lib.SINGLE),
                        ("single_polar64", lib.SINGLE_POLAR64)):
-        s = lib.Solver(sizes, precision=prec, rtol=args.rtol, max_iters=100, one_stream=args.one_stream)
-        xs = [torch.zeros_like(r) for r in rhs]
+        s = lib.Solver(sizes, precision=prec, rtol=args.rtol, max_iters=100, one_stream=args.one_stream,
+                       graph=args.graph)
+        # one buffer for all solutions (members of several sizes): the zero
+        # initial guess is one fill
+        offs = np.cumsum([0] + [nx * ny for nx, ny in sizes])
+        X = torch.zeros(int(offs[-1]), dtype=torch.float64, device="cuda")
+        xs = [X[offs[m]:offs[m + 1]].view(ny, nx) for m, (nx, ny) in enumerate(sizes)]
 
         def step():
             s.set_operators(list(range(len(probs))), depth, dts)
-            for x in xs:
-                x.zero_()
+            X.zero_()
             return s.solve(rhs, xs)
 
         for _ in range(args.warmup):
@@ -381,6 +400,77 @@ def sequence(args):
     print(json.dumps(out), flush=True)
 
 
+def si_bytes_per_point(orography=True, qbar=False):
+    """Algorithmic bytes per point of the step's explicit kernels: the float64
+    fields each reads and writes once (forcings and Courant numbers 10,
+    donor cell 8 and 12, antidiffusive velocities 11, implicit inversion 12,
+    right-hand side 6, recovery 6), plus H0 in three of them and the two
+    relaxation targets in two."""
+    return 8 * (65 + (3 if orography else 0) + (4 if qbar else 0))
+
+
+def model(args):
+    torch, lib = _lib()
+    from workloads import model_state
+    nx, ny, count, dt = args.nx, args.ny, args.count, args.dt
+    absorber = 1.0 / (200.0 * dt)
+    t0 = time.perf_counter()
+    states = [model_state(nx, ny, m) for m in range(count)]
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    cur = [tuple(dev(st[k]) for k in ("phi", "qx", "qy")) for st in states]
+    oro = [dev(st["orography"]) for st in states]
+    new = [tuple(torch.empty_like(f) for f in c) for c in cur]
+    lat = -0.5 * np.pi + (np.arange(ny) + 0.5) * np.pi / ny
+    wcos = torch.from_numpy(np.cos(lat)[:, None].repeat(nx, 1)).cuda()
+    print(f"# inputs ready in {time.perf_counter() - t0:.1f} s", flush=True)
+    out = {"workload": f"{count} members of {nx}x{ny} over synthetic mountains, dt {dt:g} s, absorber 1/(200 dt), "
+                       f"rtol {args.rtol:g}", "points": count * nx * ny, "forms": {}}
+    for name, prec in (("fp64", lib.FP64), ("mixed_half_pc", lib.MIXED_HALF_PC)):
+        s = lib.Solver([(nx, ny)] * count, precision=prec, rtol=args.rtol, max_iters=200)
+        step = lambda: s.si_step(cur, cur, new, [dt] * count, orographies=oro, absorber=absorber)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            reps = step()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t1) / args.steps
+        its = [r.iterations for r in reps]
+        s.set_kernel_timing(True)
+        step()
+        kt = s.kernel_times()
+        s.set_kernel_timing(False)
+        n_si, ms_si = kt["si_step"]
+        ms_solver = sum(v[1] for k, v in kt.items() if k != "si_step")
+        rec = {"ms_per_step": round(ms, 3), "steps_per_s": round(1e3 / ms, 2),
+               "member_steps_per_s": round(count * 1e3 / ms, 1),
+               "iters_mean": float(np.mean(its)), "iters_max": int(max(its)),
+               "statuses": sorted(set(r.status for r in reps)),
+               "explicit_kernels": {"launches": n_si, "ms": round(ms_si, 4),
+                                    "gb_per_s": round(count * nx * ny * si_bytes_per_point() / (ms_si * 1e-3) / 1e9, 1)},
+               "solver_kernels_ms": round(ms_solver, 4)}
+        # a short trajectory from the initial states
+        a = [tuple(f.clone() for f in c) for c in cur]
+        b = [tuple(f.clone() for f in c) for c in cur]
+        c_ = [tuple(torch.empty_like(f) for f in x) for x in cur]
+        m0 = sum(float((wcos * x[0]).sum()) for x in a)
+        traj = []
+        for n in range(args.trajectory):
+            reps = s.si_step(b, a, c_, [dt] * count, orographies=oro, absorber=absorber)
+            a, b, c_ = b, c_, a
+            m1 = sum(float((wcos * x[0]).sum()) for x in b)
+            vmax = max(float((x[2] / x[0]).abs().max()) for x in b)
+            umax = max(float((x[1] / x[0]).abs().max()) for x in b)
+            traj.append({"step": n + 1, "iters_mean": float(np.mean([r.iterations for r in reps])),
+                         "mass_drift": m1 / m0 - 1.0, "u_max": round(umax, 3), "v_max": round(vmax, 4)})
+        rec["trajectory"] = traj
+        out["forms"][name] = rec
+        s.close()
+        print(f"# {name}: {json.dumps(rec)}", flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -393,6 +483,7 @@ def main(argv=None):
     b.add_argument("--warmup", type=int, default=1)
     b.add_argument("--rtol", type=float, default=1e-8)
     b.add_argument("--one-stream", action="store_true", help="whole batch on one stream (no member groups)")
+    b.add_argument("--graph", action="store_true", help="replay iterations and cycle ends from HIP graphs")
     q = sub.add_parser("sequence")
     q.add_argument("--nx", type=int, default=1024)
     q.add_argument("--ny", type=int, default=512)
@@ -421,8 +512,17 @@ def main(argv=None):
     sp = sub.add_parser("split")
     sp.add_argument("--calls", type=int, default=50)
     sp.add_argument("--warmup", type=int, default=5)
+    md = sub.add_parser("model")
+    md.add_argument("--nx", type=int, default=512)
+    md.add_argument("--ny", type=int, default=256)
+    md.add_argument("--count", type=int, default=64)
+    md.add_argument("--dt", type=float, default=200.0)
+    md.add_argument("--steps", type=int, default=10)
+    md.add_argument("--warmup", type=int, default=2)
+    md.add_argument("--trajectory", type=int, default=5)
+    md.add_argument("--rtol", type=float, default=1e-8)
     args = ap.parse_args(argv)
-    {"single": single, "batch": batch, "sequence": sequence, "precond": precond, "polar": polar,
+    {"model": model, "single": single, "batch": batch, "sequence": sequence, "precond": precond, "polar": polar,
      "exitnorm": exitnorm, "split": split}[args.cmd](args)
 
 

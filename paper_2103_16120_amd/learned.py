@@ -75,32 +75,66 @@ def reference_history(reports):
     return list(ref)
 
 
-def make_dataset(lib, torch, nx, ny, problems, first_instance, n_max, hi_iters, group=16, log=print):
-    """Features [S, 3, ny, nx] and targets [S, ny, nx] (float32 CUDA tensors)."""
+def family_problems(family, nx, ny, first_instance, count):
+    """Seeded problems of a workload family: "bench" -- the benchmark's
+    (depth 8000 m + 500 m degree <= 8 harmonics, dt 600 s); "batch" -- the
+    uneven batch's style at one grid (depth 4000-10000 m, dt uniform in
+    [300, 1200] s), with seeds of its own."""
     from workloads import problem
+    if family == "bench":
+        return [problem(2, nx, ny, instance=first_instance + m, dt=600.0) for m in range(count)]
+    out = []
+    for m in range(count):
+        rng = np.random.default_rng(41_000 + first_instance + m)
+        out.append(problem(4, nx, ny, instance=first_instance + m, dt=float(rng.uniform(300.0, 1200.0)),
+                           depth_mean=7000.0, depth_amp=3000.0))
+    return out
+
+
+def initial_guesses(p, starts):
+    """x_0 of the residual sequences of one problem: zero, then x_true plus
+    seeded smooth perturbations of decreasing size and growing degree (warm
+    starts of a time-stepping run)."""
+    from workloads import harmonic_field
+    nx, ny = p["nx"], p["ny"]
+    out = [np.zeros((ny, nx))]
+    for k in range(1, starts):
+        rng = np.random.default_rng(p["seed"] * 7 + k)
+        amp = 10.0 ** (-k)
+        out.append(p["x_true"] + harmonic_field(nx, ny, 8 + 8 * k, rng, lmin=1, amplitude=amp))
+    return out
+
+
+def make_dataset(lib, torch, nx, ny, problems, first_instance, n_max, hi_iters, group=16, log=print,
+                 family="bench", starts=1):
+    """Features [S, 3, ny, nx] and targets [S, ny, nx] (float32 CUDA tensors):
+    for each problem and each of `starts` initial guesses, the residuals after
+    0..n_max plain float64 GCR(3) iterations."""
     feats, targets = [], []
     for g0 in range(0, problems, group):
         cnt = min(group, problems - g0)
-        prs = [problem(2, nx, ny, instance=first_instance + g0 + m, dt=600.0) for m in range(cnt)]
+        prs = family_problems(family, nx, ny, first_instance + g0, cnt)
         depth = [torch.from_numpy(p["depth"]).cuda() for p in prs]
         fs = lib.Solver([(nx, ny)] * cnt, precision=lib.FP64, precond=lib.PC_SEMI_IMPLICIT)
         for m, p in enumerate(prs):
             fs.set_operator(m, depth[m], p["dt"])
         rhs = [fs.apply_operator(m, torch.from_numpy(p["x_true"]).cuda()) for m, p in enumerate(prs)]
-        for n in range(0, n_max + 1):
-            x = [torch.zeros_like(r) for r in rhs]
-            if n > 0:
-                s = lib.Solver([(nx, ny)] * cnt, precision=lib.FP64, precond=lib.PC_SEMI_IMPLICIT,
-                               min_iters=n, max_iters=n, rtol=0.0)
-                for m, p in enumerate(prs):
-                    s.set_operator(m, depth[m], p["dt"])
-                s.solve(rhs, x)
-                s.close()
-            for m in range(cnt):
-                f, t, sig = fs.learned_features(m, x[m], rhs[m], hi_iters=hi_iters)
-                if sig > 0:
-                    feats.append(f)
-                    targets.append(t)
+        guesses = [initial_guesses(p, starts) for p in prs]
+        for st in range(starts):
+            for n in range(0, n_max + 1):
+                x = [torch.from_numpy(guesses[m][st]).cuda() for m in range(cnt)]
+                if n > 0:
+                    s = lib.Solver([(nx, ny)] * cnt, precision=lib.FP64, precond=lib.PC_SEMI_IMPLICIT,
+                                   min_iters=n, max_iters=n, rtol=0.0)
+                    for m, p in enumerate(prs):
+                        s.set_operator(m, depth[m], p["dt"])
+                    s.solve(rhs, x)
+                    s.close()
+                for m in range(cnt):
+                    f, t, sig = fs.learned_features(m, x[m], rhs[m], hi_iters=hi_iters)
+                    if sig > 0:
+                        feats.append(f)
+                        targets.append(t)
         fs.close()
         log(f"data: {g0 + cnt}/{problems} problems, {len(feats)} samples")
     return torch.stack(feats), torch.stack(targets)
@@ -144,10 +178,11 @@ def train(lib, torch, feats, targets, steps, batch, lr, seed=0, log=print, param
     return params, losses
 
 
-def evaluate(lib, torch, params, nx, ny, count, precision, fallback_ratio=0.5, first_instance=0):
-    """Iterations and solve time of plain vs learned on `count` problems."""
-    from workloads import problem
-    prs = [problem(2, nx, ny, instance=first_instance + m, dt=600.0) for m in range(count)]
+def evaluate(lib, torch, params, nx, ny, count, precision, fallback_ratio=0.5, first_instance=0, family="bench"):
+    """Iterations and solve time of plain vs learned on `count` held-out
+    problems; the learned solve falls back against the plain solve's
+    residual history."""
+    prs = family_problems(family, nx, ny, first_instance, count)
     depth = [torch.from_numpy(p["depth"]).cuda() for p in prs]
     f = lib.Solver([(nx, ny)] * count, precision=lib.FP64)
     for m, p in enumerate(prs):
@@ -155,13 +190,17 @@ def evaluate(lib, torch, params, nx, ny, count, precision, fallback_ratio=0.5, f
     rhs = [f.apply_operator(m, torch.from_numpy(p["x_true"]).cuda()) for m, p in enumerate(prs)]
     f.close()
     out = {}
+    ref = None
     for name, pc in (("plain", lib.PC_SEMI_IMPLICIT), ("learned", lib.PC_LEARNED)):
-        s = lib.Solver([(nx, ny)] * count, precision=precision, precond=pc, max_iters=100)
+        s = lib.Solver([(nx, ny)] * count, precision=precision, precond=pc, max_iters=100, record_history=True)
         if pc == lib.PC_LEARNED:
             s.set_learned(params, fallback_ratio)
+            s.set_learned_reference(ref)
         s.set_operators(list(range(count)), depth, [p["dt"] for p in prs])
         x = [torch.zeros_like(r) for r in rhs]
-        s.solve(rhs, x)                       # warm-up
+        warm = s.solve(rhs, x, record_history=True)      # warm-up
+        if ref is None:
+            ref = reference_history(warm)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for xx in x:
@@ -169,7 +208,7 @@ def evaluate(lib, torch, params, nx, ny, count, precision, fallback_ratio=0.5, f
         reps = s.solve(rhs, x)
         dt = time.perf_counter() - t0
         its = [r.iterations for r in reps]
-        out[name] = dict(iters_mean=float(np.mean(its)), iters_min=int(min(its)), iters_max=int(max(its)),
+        out[name] = dict(iters=its, iters_mean=float(np.mean(its)), iters_min=int(min(its)), iters_max=int(max(its)),
                          fallbacks=int(sum(r.fallback_used for r in reps)),
                          rel_res_true_max=float(max(r.rel_res_true for r in reps)),
                          ms=round(1e3 * dt, 3))
@@ -190,7 +229,9 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--lr-final", type=float, default=1e-5)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--eval", type=int, default=16, help="held-out problems for the comparison")
+    ap.add_argument("--eval", type=int, default=32, help="held-out problems for the comparison")
+    ap.add_argument("--family", default="bench", choices=("bench", "batch"), help="training problems")
+    ap.add_argument("--starts", type=int, default=1, help="initial guesses per problem")
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     args = ap.parse_args(argv)
     import torch
@@ -202,21 +243,28 @@ def main(argv=None):
 
     t0 = time.perf_counter()
     feats, targets = make_dataset(lib, torch, args.nx, args.ny, args.problems, args.first_instance, args.n_max,
-                                  args.hi_iters, log=log)
+                                  args.hi_iters, log=log, family=args.family, starts=args.starts)
     log(f"dataset {tuple(feats.shape)} in {time.perf_counter() - t0:.1f} s; target rms "
         f"{float(targets.double().pow(2).mean().sqrt()):.3e}")
     params, losses = train(lib, torch, feats, targets, args.steps, args.batch, args.lr, args.seed, log=log,
                            lr_final=args.lr_final)
     base = float(targets.double().pow(2).mean())
-    summary = dict(nx=args.nx, ny=args.ny, problems=args.problems, n_max=args.n_max, hi_iters=args.hi_iters,
+    summary = dict(nx=args.nx, ny=args.ny, problems=args.problems, family=args.family, starts=args.starts,
+                   samples=int(feats.shape[0]), n_max=args.n_max, hi_iters=args.hi_iters,
                    steps=args.steps, batch=args.batch, lr=args.lr, lr_final=args.lr_final, seed=args.seed,
                    loss_first=float(np.mean(losses[:20])), loss_last=float(np.mean(losses[-50:])),
                    target_mean_square=base, channels=lib.LEARNED_CHANNELS)
     del feats, targets
     ev = {}
     for prec_name, prec in (("fp64", lib.FP64), ("mixed_half_pc", lib.MIXED_HALF_PC)):
+        # held out: the benchmark's members (instances 0.., disjoint from any
+        # training seed) and further problems of the training family
         ev[prec_name] = evaluate(lib, torch, params, args.nx, args.ny, args.eval, prec)
+        ev[prec_name + "_family"] = evaluate(lib, torch, params, args.nx, args.ny, args.eval, prec,
+                                             first_instance=args.first_instance + args.problems,
+                                             family=args.family)
         log(f"{prec_name}: {json.dumps(ev[prec_name])}")
+        log(f"{prec_name} ({args.family} family): {json.dumps(ev[prec_name + '_family'])}")
     summary["evaluation"] = ev
     save_weights(args.out, params, summary)
     log(json.dumps(summary))

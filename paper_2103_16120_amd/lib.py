@@ -26,6 +26,7 @@ F_LINF_EXIT = 0x4
 F_FAULT_NAN_PC = 0x8
 F_FAULT_ZERO_DIR = 0x10
 F_SPLIT_R0 = 0x20
+F_GRAPH = 0x40
 
 RADIUS = 6.371e6
 GRAVITY = 9.80616
@@ -58,6 +59,12 @@ class GcrReport(C.Structure):
     ]
 
 
+class GcrSiMember(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("phi", "qx", "qy", "phi_old", "qx_old", "qy_old", "orography", "qbar_x",
+                                          "qbar_y", "phi_new", "qx_new", "qy_new")] + [
+        (n, C.c_double) for n in ("dt", "g", "omega", "radius", "absorber")]
+
+
 # every symbol the header declares, with its ctypes signature
 _SIGNATURES = {
     "gcr_default_params": (C.c_int, [C.POINTER(GcrParams)]),
@@ -72,6 +79,7 @@ _SIGNATURES = {
     "gcr_apply_operator_form": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "gcr_apply_precond_form": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "gcr_destroy": (C.c_int, [C.c_void_p]),
+    "gcr_si_step": (C.c_int, [C.c_void_p, C.POINTER(GcrSiMember), C.POINTER(GcrReport)]),
     "gcr_apply_precond_static": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                                            C.c_void_p]),
     "gcr_status_string": (C.c_char_p, [C.c_int]),
@@ -96,8 +104,9 @@ _SIGNATURES = {
     "cnn_last_error": (C.c_char_p, [C.c_void_p]),
 }
 
-K_ASSEMBLE, K_RESIDUAL, K_SWEEP1, K_SWEEP2, K_APPLY_L, K_ORTH, K_CONTROL, K_COPY, K_LEARNED, K_SOLUTION = range(10)
-K_COUNT = 10
+K_ASSEMBLE, K_RESIDUAL, K_SWEEP1, K_SWEEP2, K_APPLY_L, K_ORTH, K_CONTROL, K_COPY, K_LEARNED, K_SOLUTION, \
+    K_SI_STEP = range(11)
+K_COUNT = 11
 LEARNED_CHANNELS = 3
 
 
@@ -154,7 +163,7 @@ class Solver:
 
     def __init__(self, sizes, k=3, precision=FP64, precond=PC_SEMI_IMPLICIT, richardson_iters=2,
                  polar_rows=-1, min_iters=-1, max_iters=200, rtol=1e-8, stream=None, flags=0, one_stream=False,
-                 linf_exit=False, record_history=False):
+                 linf_exit=False, record_history=False, graph=False):
         self.sizes = [(int(nx), int(ny)) for nx, ny in sizes]
         b = len(self.sizes)
         self._nx = (C.c_int32 * b)(*[s[0] for s in self.sizes])
@@ -170,7 +179,7 @@ class Solver:
         p.min_iters, p.max_iters, p.rtol = min_iters, max_iters, rtol
         p.stream = C.c_void_p(stream.cuda_stream)
         p.flags = (flags | (F_ONE_STREAM if one_stream else 0) | (F_LINF_EXIT if linf_exit else 0)
-                   | (F_RECORD_HISTORY if record_history else 0))
+                   | (F_RECORD_HISTORY if record_history else 0) | (F_GRAPH if graph else 0))
         self.params = p
         h = C.c_void_p()
         rc = _lib.gcr_create(C.byref(p), C.byref(h))
@@ -276,6 +285,47 @@ class Solver:
             out.append(Report(r.status, r.iterations, r.restarts, r.fallback_used, r.r0_norm,
                               r.rel_res_recursive, r.rel_res_true, hist))
         return out
+
+    def si_step(self, states, olds, news, dts, orographies=None, qbars=None, absorber=0.0, g=GRAVITY,
+                omega=OMEGA, radius=RADIUS):
+        """One semi-implicit time step of every member (gcr_si_step).
+        states / olds / news: lists (one per member) of (phi, qx, qy) float64
+        CUDA tensors at n, n-1 and n+1 (news written); orographies: list of
+        tensors or None; qbars: list of (qbar_x, qbar_y) or None.  Replaces
+        every member's operator.  Returns the solve's list of Report."""
+        b = len(self.sizes)
+        if len(states) != b or len(olds) != b or len(news) != b:
+            raise ValueError("one state, old state and new state per member")
+        dts = list(dts) if hasattr(dts, "__len__") else [float(dts)] * b
+        mem = (GcrSiMember * b)()
+        for m, (nx, ny) in enumerate(self.sizes):
+            trip = [("state", states[m]), ("old", olds[m]), ("new", news[m])]
+            for what, fields in trip:
+                if len(fields) != 3:
+                    raise ValueError(f"{what}[{m}] must be (phi, qx, qy)")
+                for t in fields:
+                    _check_field(t, ny, nx, f"{what}[{m}]")
+            oro = orographies[m] if orographies is not None else None
+            if oro is not None:
+                _check_field(oro, ny, nx, f"orography[{m}]")
+            qb = qbars[m] if qbars is not None else None
+            if qb is not None:
+                for t in qb:
+                    _check_field(t, ny, nx, f"qbar[{m}]")
+            e = mem[m]
+            e.phi, e.qx, e.qy = (t.data_ptr() for t in states[m])
+            e.phi_old, e.qx_old, e.qy_old = (t.data_ptr() for t in olds[m])
+            e.phi_new, e.qx_new, e.qy_new = (t.data_ptr() for t in news[m])
+            e.orography = oro.data_ptr() if oro is not None else None
+            e.qbar_x, e.qbar_y = (qb[0].data_ptr(), qb[1].data_ptr()) if qb is not None else (None, None)
+            e.dt, e.g, e.omega, e.radius, e.absorber = float(dts[m]), float(g), float(omega), float(radius), \
+                float(absorber)
+        reps = (GcrReport * b)()
+        rc = _lib.gcr_si_step(self._h, mem, reps)
+        if rc < 0:
+            raise self._err(rc)
+        return [Report(r.status, r.iterations, r.restarts, r.fallback_used, r.r0_norm, r.rel_res_recursive,
+                       r.rel_res_true, []) for r in reps]
 
     def set_kernel_timing(self, enable=True):
         rc = _lib.gcr_set_kernel_timing(self._h, 1 if enable else 0)

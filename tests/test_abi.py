@@ -105,6 +105,7 @@ def test_entry_points_reject_null_solver(lib):
     assert lib._lib.gcr_solve(None, None, None, None) == lib.EINVAL
     assert lib._lib.gcr_apply_operator(None, 0, None, None) == lib.EINVAL
     assert lib._lib.gcr_apply_precond(None, 0, None, None) == lib.EINVAL
+    assert lib._lib.gcr_si_step(None, None, None) == lib.EINVAL
 
 
 def test_create_without_gpu_reports_hip_error(lib):
@@ -148,7 +149,7 @@ def test_learned_create_needs_one_size(lib):
 
 
 def test_create_rejects_unknown_flags(lib):
-    p = _params(lib, flags=0x40)
+    p = _params(lib, flags=0x80)
     h = C.c_void_p()
     assert lib._lib.gcr_create(C.byref(p), C.byref(h)) == lib.EINVAL
     assert b"flags" in lib._lib.gcr_last_error(None)
@@ -175,7 +176,7 @@ def test_header_flag_values_match_the_binding(lib):
     vals = {m.group(1): int(m.group(2), 16) for m in re.finditer(r"#define GCR_F_(\w+)\s+0x([0-9a-fA-F]+)u", text)}
     for name, v in vals.items():
         assert getattr(lib, "F_" + name) == v, name
-    assert set(vals) >= {"RECORD_HISTORY", "ONE_STREAM", "LINF_EXIT", "FAULT_NAN_PC", "FAULT_ZERO_DIR", "SPLIT_R0"}
+    assert set(vals) >= {"RECORD_HISTORY", "ONE_STREAM", "LINF_EXIT", "FAULT_NAN_PC", "FAULT_ZERO_DIR", "SPLIT_R0", "GRAPH"}
 
 
 def test_split_r0_flag_needs_a_single_precision_cycle(lib):
@@ -209,3 +210,10 @@ def test_static_preconditioner_validates_before_the_device(lib):
     assert lib.STATIC_MAX_POINTS == 131072
     text = open(os.path.join(ROOT, "include", "mpgcr.h")).read()
     assert "#define GCR_STATIC_MAX_POINTS 131072" in text
+
+
+def test_si_member_layout_matches_the_header(lib):
+    # twelve field pointers, then dt, g, omega, radius, absorber
+    assert C.sizeof(lib.GcrSiMember) == 12 * 8 + 5 * 8
+    assert lib.GcrSiMember.dt.offset == 96 and lib.GcrSiMember.absorber.offset == 128
+

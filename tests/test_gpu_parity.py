@@ -632,7 +632,7 @@ def test_fault_injection_reports_stagnation(gpu_lib, precision, fault):
         assert rf[m].rel_res_true < 1e-3
 
 
-@pytest.mark.parametrize("nx,ny", [(128, 64), (256, 128)])
+@pytest.mark.parametrize("nx,ny", [(128, 64), (256, 128), (512, 256)])
 def test_mixed_plateau_against_emulated_half(gpu_lib, nx, ny, capsys):
     """GCR_MIXED (float16 storage of the operator and preconditioner
     coefficients, float32 arithmetic, no residual replacement) stalls at a
@@ -657,3 +657,54 @@ def test_mixed_plateau_against_emulated_half(gpu_lib, nx, ny, capsys):
     assert rep.rel_res_recursive <= 1e-8 and emu.rel_res_recursive <= 1e-8
     assert true_res > 1e-7 and emu.rel_res_true > 1e-7
     assert 0.05 <= true_res / emu.rel_res_true <= 20
+
+
+def _graph_case(kind):
+    if kind == "uneven":
+        prs = batch_problems(3, 12)
+    elif kind == "groups":      # large enough for two member groups on two streams
+        prs = [problem(2, 512, 256, instance=m, dt=600.0) for m in range(32)]
+    else:
+        prs = [problem(2, 128, 64, instance=m, dt=600.0) for m in range(4)]
+    return prs
+
+
+@pytest.mark.parametrize("kind", ["uniform", "uneven", "groups"])
+@pytest.mark.parametrize("precision", [0, 1, 3])
+def test_graph_replay_equals_stream_launches(gpu_lib, kind, precision):
+    """GCR_F_GRAPH: the iterations and cycle ends are captured into HIP graphs
+    on first use and replayed after.  Three consecutive solves -- a new
+    right-hand side each time, eager work and synchronisations in between,
+    and in the last one a member switched to orography (which drops the
+    captured graphs of its group) -- each bitwise equal to the same solve
+    launched kernel by kernel."""
+    prs = _graph_case(kind)
+    sizes = [(p["nx"], p["ny"]) for p in prs]
+    solvers = {g: make_solver(gpu_lib, sizes, precision=precision, rtol=1e-8, max_iters=60, graph=g)
+               for g in (False, True)}
+    for s in solvers.values():
+        for m, p in enumerate(prs):
+            s.set_operator(m, p["depth"], p["dt"])
+    ops = [EllipticOperator(p["nx"], p["ny"], p["depth"], p["dt"]) for p in prs]
+    for rnd in range(3):
+        if rnd == 2:
+            oro = 300.0 * np.abs(prs[0]["x_true"])
+            for s in solvers.values():
+                s.set_operator(0, prs[0]["depth"], prs[0]["dt"], orography=oro)
+            ops[0] = EllipticOperator(prs[0]["nx"], prs[0]["ny"], prs[0]["depth"], prs[0]["dt"], orography=oro)
+        rhs = [dev(o.apply((1.0 + rnd) * p["x_true"])) for o, p in zip(ops, prs)]
+        out = {}
+        for g, s in solvers.items():
+            x = [torch.zeros_like(r) for r in rhs]
+            reps = s.solve(rhs, x)
+            out[g] = (reps, [host(v) for v in x])
+            torch.cuda.synchronize()
+            _ = torch.randn(1 << 20, device="cuda").sum().item()     # eager work between solves
+        for m in range(len(prs)):
+            ra, rb = out[False][0][m], out[True][0][m]
+            assert (ra.status, ra.iterations, ra.restarts) == (rb.status, rb.iterations, rb.restarts), (rnd, m)
+            assert ra.rel_res_true == rb.rel_res_true
+            assert np.array_equal(out[False][1][m], out[True][1][m]), (rnd, m)
+            assert ra.status == gpu_lib.OK or precision == 1
+    for s in solvers.values():
+        s.close()
