@@ -313,19 +313,20 @@ struct RowSolver {
       dl = rh;
       return;
     }
-    const T hr = (k == M - 2) ? -up : (T)0;   // coupling to y_l moves to the right-hand side
+    // coupling to y_l moves to the right-hand side; it enters at point M-2,
+    // so h is zero before it (not held in registers while rows stream in)
     if (k == 0) {
       const T inv = qdiv((T)1, di);
       cp[0] = up * inv;
       f[0] = rh * inv;
       g[0] = -lo * inv;
-      h[0] = hr * inv;
+      h[0] = (k == M - 2) ? -up * inv : (T)0;
     } else {
       const T inv = qdiv((T)1, di - lo * cp[k - 1]);
       cp[k] = up * inv;
       f[k] = (rh - lo * f[k - 1]) * inv;
       g[k] = (-lo * g[k - 1]) * inv;
-      h[k] = (hr - lo * h[k - 1]) * inv;
+      h[k] = (k == M - 2) ? -up * inv : (T)0;
     }
   }
 

@@ -385,12 +385,33 @@ __device__ __forceinline__ int row_class(const Fields& F) {
 }
 
 // Field row readers for the stencil (row-interleaved storage), converted to T.
+// Elements k and k+1 (k even) of lane `ln` of a pooled row of n elements: the
+// streamed stencil reads rows column pair by column pair (float16 rows hold
+// the pair in one word).
+template <typename S, typename T>
+__device__ __forceinline__ void ld_pair(const S* row, int n, int ln, int k, int L, T& a, T& b) {
+  const __amdgpu_buffer_rsrc_t r = row_rsrc(row, (unsigned)n * sizeof(S));
+  if constexpr (std::is_same<S, __half>::value) {
+    const unsigned w = __builtin_amdgcn_raw_buffer_load_b32(r, (unsigned)ln * 4u, (unsigned)((k >> 1) * L) * 4u, 0);
+    a = (T)__half2float(__builtin_bit_cast(__half, (unsigned short)(w & 0xffffu)));
+    b = (T)__half2float(__builtin_bit_cast(__half, (unsigned short)(w >> 16)));
+  } else {
+    const unsigned vo = (unsigned)ln * sizeof(S);
+    a = from_store<S, T>(RowIO<S>::ld(r, vo, (unsigned)(k * L) * sizeof(S)));
+    b = from_store<S, T>(RowIO<S>::ld(r, vo, (unsigned)((k + 1) * L) * sizeof(S)));
+  }
+}
+
 template <typename T, typename S>
 struct RowReader {
   const S* p;
   template <int M>
   __device__ __forceinline__ void row(long long start, int l, int L, T (&v)[M], int /*row_g*/) const {
     ldr<M>(p + start, l, L, v);
+  }
+  template <int M>
+  __device__ __forceinline__ void pair(long long start, int n, int ln, int k, int L, int /*row_g*/, T& a, T& b) const {
+    ld_pair<S, T>(p + start, n, ln, k, L, a, b);
   }
 };
 
@@ -418,6 +439,13 @@ struct NatReader {
   __device__ __forceinline__ void row(long long start, int l, int /*L*/, double (&v)[M], int /*row_g*/) const {
     ldn<M>(p + (start - off), l, v);
   }
+  template <int M>
+  __device__ __forceinline__ void pair(long long start, int /*n*/, int ln, int k, int /*L*/, int /*row_g*/, double& a,
+                                       double& b) const {
+    const double* q = p + (start - off) + (long long)ln * M + k;
+    a = q[0];
+    b = q[1];
+  }
 };
 
 // float16 storage with one scale per row
@@ -432,6 +460,13 @@ struct ScaledHalfReader {
 #pragma unroll
     for (int k = 0; k < M; ++k) v[k] *= s;
   }
+  template <int M>
+  __device__ __forceinline__ void pair(long long start, int n, int ln, int k, int L, int row_g, T& a, T& b) const {
+    ld_pair<__half, T>(p + start, n, ln, k, L, a, b);
+    const T s = (T)qs[row_g];
+    a *= s;
+    b *= s;
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -443,7 +478,8 @@ struct ScaledHalfReader {
 // delivered point by point, in chunk order, to emit(k, zon, rest, x, axe,
 // axw, ayn, ays) together with the A^xx / A^yy faces the row solves need.
 // Rows beyond the poles are the polar row seen across the pole.  The field
-// rows are held whole; the coefficients stream through per point.
+// rows are held whole (or streamed, below); the coefficients stream through
+// per point.
 // ---------------------------------------------------------------------------
 template <bool A, typename X>
 __device__ __forceinline__ X& pick(X& a, X& b) {
@@ -451,13 +487,12 @@ __device__ __forceinline__ X& pick(X& a, X& b) {
   else return b;
 }
 
-// The same stencil with the face coefficients formed point by point from the
-// depth rows (on-the-fly coefficients): the wave holds three rows of the field
-// and three of Phi* (and three of H* with orography) instead of nine
-// coefficient rows, which halves the registers of the float64 kernels.  The
-// per-point expressions are those of CoefFly::load9.  FLAT: H* = Phi*.
+// The stencil with the face coefficients formed point by point from the
+// depth rows (on-the-fly coefficients): three rows of the field and three of
+// Phi* (and three of H* with orography) instead of nine coefficient rows.
+// The per-point expressions are those of CoefFly::load9.  FLAT: H* = Phi*.
 template <typename T, int M, bool FLAT, typename CV, typename XR, typename Emit>
-__device__ __forceinline__ void stencil_row_fly(const RowCtx& R, const CV& cv, const XR& X, Emit&& emit) {
+__device__ __forceinline__ void stencil_row_fly_whole(const RowCtx& R, const CV& cv, const XR& X, Emit&& emit) {
   const int l = R.lane, L = R.L;
   const int wl = (l - 1) & (L - 1), el = (l + 1) & (L - 1);
   T xc[M], xs[M], xn[M];
@@ -551,6 +586,113 @@ __device__ __forceinline__ void stencil_row_fly(const RowCtx& R, const CV& cv, c
   }
 }
 
+// Streamed form: the rows pass column pair by column pair, each pair loaded
+// one pair ahead, so a wave holds four columns of every row it reads instead
+// of whole rows; the chunk-edge columns come from the adjacent lanes' chunks
+// by loads of their own (instead of shuffles of held values).
+template <typename T, int M, bool FLAT, typename CV, typename XR, typename Emit>
+__device__ __forceinline__ void stencil_row_fly_stream(const RowCtx& R, const CV& cv, const XR& X, Emit&& emit) {
+  const int l = R.lane, L = R.L, n = R.nx;
+  const int lx = (l + (L >> 1)) & (L - 1);
+  // centre, south and north rows: start, lane read by this lane, row index
+  // (float16 row scale); a row beyond a pole is the polar row itself read
+  // with the lanes shifted by L/2 (longitude + NX/2)
+  const long long st[3] = {R.rc, R.south ? R.rc - R.nx : R.rc, R.north ? R.rc + R.nx : R.rc};
+  const int lr[3] = {l, R.south ? l : lx, R.north ? l : lx};
+  const int gr[3] = {R.g, R.south ? R.g - 1 : R.g, R.north ? R.g + 1 : R.g};
+  struct Col {
+    T x[3], p[3], h[3];
+  };
+  // columns k, k+1 (k even) of the lane `dl` lanes away: dl = -1 / +1 give the
+  // chunk-edge columns of the adjacent lanes
+  auto load_pair = [&](int k, int dl, Col& a, Col& b) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const int ln = (lr[r] + dl) & (L - 1);
+      X.template pair<M>(st[r], n, ln, k, L, gr[r], a.x[r], b.x[r]);
+      ld_pair<T, T>(cv.P.phi + st[r], n, ln, k, L, a.p[r], b.p[r]);
+      if constexpr (FLAT) {
+        a.h[r] = a.p[r];
+        b.h[r] = b.p[r];
+      } else {
+        ld_pair<T, T>(cv.P.hs + st[r], n, ln, k, L, a.h[r], b.h[r]);
+      }
+    }
+  };
+  const T* f = cv.P.fac + (long long)R.g * NFAC;
+  const T fKE = f[FA_KE], fXX = f[FA_FXX], fXY = f[FA_FXY], fGBX = f[FA_GBX], fBLE = f[FA_BLE], fBPE = f[FA_BPE];
+  const T fKN = f[FA_KN], fYY = f[FA_FYY], fYX = f[FA_FYX], fGBY = f[FA_GBY], fBLN = f[FA_BLN], fBPN = f[FA_BPN];
+  // the south face is the north face of row j-1; none at the south pole
+  const T* fs = cv.P.fac + (long long)(R.south ? R.g - 1 : R.g) * NFAC;
+  const T sKN = R.south ? fs[FA_KN] : (T)0, sYY = R.south ? fs[FA_FYY] : (T)0, sYX = R.south ? fs[FA_FYX] : (T)0;
+  const T sGBY = R.south ? fs[FA_GBY] : (T)0, sBLN = R.south ? fs[FA_BLN] : (T)0,
+          sBPN = R.south ? fs[FA_BPN] : (T)0;
+  // east face of column c (e: the next column)
+  auto east = [&](const Col& c, const Col& e, T& axe, T& axy, T& bx) {
+    const T kap_e = fKE * (c.p[0] + e.p[0]);
+    axe = kap_e * fXX;
+    axy = kap_e * fXY;
+    bx = fGBX * (fBLE * (e.h[0] - c.h[0]) + fBPE * ((c.h[2] - c.h[1]) + (e.h[2] - e.h[1])));
+  };
+  T axe_p, axy_p, bx_p;
+  auto point = [&](int k, const Col& w, const Col& c, const Col& e) {
+    T axe, axy, bx;
+    east(c, e, axe, axy, bx);
+    const T hce = e.h[0], hcw = w.h[0];
+    const T kap_n = fKN * (c.p[0] + c.p[2]);
+    const T ayn = kap_n * fYY, ayxn = kap_n * fYX;
+    const T byn = fGBY * (fBLN * ((hce - hcw) + (e.h[2] - w.h[2])) + fBPN * (c.h[2] - c.h[0]));
+    const T kap_s = sKN * (c.p[1] + c.p[0]);
+    const T ays = kap_s * sYY, ayxs = kap_s * sYX;
+    const T bys = sGBY * (sBLN * ((e.h[1] - w.h[1]) + (hce - hcw)) + sBPN * (c.h[0] - c.h[1]));
+    const T xc = c.x[0], xw = w.x[0], xe = e.x[0];
+    const T sc = c.x[1], sw = w.x[1], se = e.x[1];
+    const T nc = c.x[2], nw = w.x[2], ne = e.x[2];
+    const T zon = axe * (xe - xc) - axe_p * (xc - xw);
+    T r = axy * ((nc - sc) + (ne - se)) - axy_p * ((nw - sw) + (nc - sc));
+    r += bx * (xc + xe) - bx_p * (xw + xc);
+    r += ayn * (nc - xc) + ayxn * ((xe - xw) + (ne - nw)) + byn * (xc + nc);
+    r -= ays * (xc - sc) + ayxs * ((se - sw) + (xe - xw)) + bys * (sc + xc);
+    emit(k, zon, r, xc, axe, axe_p, ayn, ays);
+    axe_p = axe;
+    axy_p = axy;
+    bx_p = bx;
+  };
+  // columns k-1, k, k+1 in flight at point k; the next pair is loaded one
+  // pair ahead, so a wave holds four columns instead of whole rows
+  Col cm, c0, c1;
+  {
+    Col t;
+    load_pair(M - 2, -1, t, cm);   // column -1: the west lane's last column
+  }
+  load_pair(0, 0, c0, c1);
+  east(cm, c0, axe_p, axy_p, bx_p);
+#pragma unroll
+  for (int kp = 0; kp < M; kp += 2) {
+    Col n0, n1;
+    if (kp + 2 < M) load_pair(kp + 2, 0, n0, n1);
+    else load_pair(0, 1, n0, n1);   // column M: the east lane's first column
+    point(kp, cm, c0, c1);
+    point(kp + 1, c0, c1, n0);
+    cm = c1;
+    c0 = n0;
+    c1 = n1;
+  }
+}
+
+// Whole rows or streamed columns: streaming pays where whole float64 rows of
+// 16 points per lane would leave one wave per SIMD (measured: the float64
+// operator and second sweep at 1024 points per row); elsewhere the whole-row
+// form keeps more loads in flight per wave and is faster.
+template <typename T, int M>
+constexpr bool stream_stencil() { return sizeof(T) == 8 && M >= 16; }
+
+template <typename T, int M, bool FLAT, bool WHOLE, typename CV, typename XR, typename Emit>
+__device__ __forceinline__ void stencil_row_fly(const RowCtx& R, const CV& cv, const XR& X, Emit&& emit) {
+  if constexpr (!WHOLE && stream_stencil<T, M>()) stencil_row_fly_stream<T, M, FLAT>(R, cv, X, emit);
+  else stencil_row_fly_whole<T, M, FLAT>(R, cv, X, emit);
+}
+
 template <typename T>
 struct is_coef_fly : std::false_type {
   static constexpr bool flat_only = false;
@@ -560,12 +702,13 @@ struct is_coef_fly<CoefFly<T, B>> : std::true_type {
   static constexpr bool flat_only = B;
 };
 
-template <typename T, int M, typename CV, typename XR, typename Emit>
+// WHOLE: always hold whole rows (the float64 residual: streaming measured slower)
+template <typename T, int M, bool WHOLE = false, typename CV, typename XR, typename Emit>
 __device__ __forceinline__ void stencil_row(const RowCtx& R, const CV& cv, const XR& X, Emit&& emit) {
   if constexpr (is_coef_fly<CV>::value) {
-    if constexpr (is_coef_fly<CV>::flat_only) stencil_row_fly<T, M, true>(R, cv, X, emit);
-    else if (cv.P.flat[R.m] != 0) stencil_row_fly<T, M, true>(R, cv, X, emit);
-    else stencil_row_fly<T, M, false>(R, cv, X, emit);
+    if constexpr (is_coef_fly<CV>::flat_only) stencil_row_fly<T, M, true, WHOLE>(R, cv, X, emit);
+    else if (cv.P.flat[R.m] != 0) stencil_row_fly<T, M, true, WHOLE>(R, cv, X, emit);
+    else stencil_row_fly<T, M, false, WHOLE>(R, cv, X, emit);
     return;
   }
   const int l = R.lane, L = R.L;
@@ -857,14 +1000,23 @@ __device__ __forceinline__ void row_sweep2(const Fields& F, const RowCtx& R, con
   using V = typename P::V;
   with_coef<P, FL>(F, G, R.j, false, [&](const auto& cv) {
     const T helm = cv.helm(R.g);
-    T rv[M];
-    ldr<M>((const V*)F.r + R.rc, R.lane, R.L, rv);
+    const V* rrow = (const V*)F.r + R.rc;
     RowSolver<T, M> rs;
+    // r: the whole row, or (streamed stencil) the current column pair
+    T rv[stream_stencil<T, M>() ? 1 : M], r0, r1;
+    if constexpr (!stream_stencil<T, M>()) ldr<M>(rrow, R.lane, R.L, rv);
     auto emit = [&](int k, T, T rest, T xc, T axe, T axw, T ayn, T ays) {
+      T rk;
+      if constexpr (stream_stencil<T, M>()) {
+        if ((k & 1) == 0) ld_pair<V, T>(rrow, R.nx, R.lane, k, R.L, r0, r1);
+        rk = (k & 1) ? r1 : r0;
+      } else {
+        rk = rv[k];
+      }
       const T eta = qdiv((T)1, ayn + ays);
       T lo, di, up;
       row_system(eta, axe, axw, helm, lo, di, up);
-      rs.push(k, lo, di, up, xc + eta * (rest - rv[k]));
+      rs.push(k, lo, di, up, xc + eta * (rest - rk));
     };
     using Q = typename P::Q;
     if constexpr (std::is_same<Q, __half>::value) {
@@ -1149,7 +1301,7 @@ __device__ __forceinline__ void row_residual(const Fields& F, const RowCtx& R, c
   else ldr<M>(F.rhs + R.rc, l, L, b);
   double acc0 = 0.0, acc1 = 0.0;
   auto body = [&](const auto& X) {
-    stencil_row<double, M>(R, cv, X, [&](int k, double zon, double rest, double xc, double, double, double, double) {
+    stencil_row<double, M, true>(R, cv, X, [&](int k, double zon, double rest, double xc, double, double, double, double) {
       rr[k] = zon + rest - helm * xc - b[k];
       acc0 += rr[k] * rr[k];
       xk[k] = xc;
@@ -1234,6 +1386,15 @@ struct SumReader {
     ldr<M>(b + start, l, L, y);
 #pragma unroll
     for (int k = 0; k < M; ++k) v[k] = (double)x[k] + (double)y[k];
+  }
+  template <int M>
+  __device__ __forceinline__ void pair(long long start, int n, int ln, int k, int L, int /*row_g*/, double& u,
+                                       double& v) const {
+    float x0, x1, y0, y1;
+    ld_pair<float, float>(a + start, n, ln, k, L, x0, x1);
+    ld_pair<float, float>(b + start, n, ln, k, L, y0, y1);
+    u = (double)x0 + (double)y0;
+    v = (double)x1 + (double)y1;
   }
 };
 
@@ -1354,7 +1515,7 @@ __device__ __forceinline__ void kb_residual_split(const Fields& F, SplitArgs S, 
   if (R.j < G.polar || R.j >= G.ny - G.polar) {   // float64 polar bands
     const CoefFly<double> cv{F.fly64};
     const double helm = cv.helm(R.g);
-    stencil_row<double, M>(R, cv, SumReader{S.hat, S.tilde},
+    stencil_row<double, M, true>(R, cv, SumReader{S.hat, S.tilde},
                            [&](int k, double zon, double rest, double xc, double, double, double, double) {
                              out[k] = zon + rest - helm * xc - b[k];
                            });
