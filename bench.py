@@ -14,7 +14,10 @@ products, float64 solution and float64 residual replacement at every
 restart).  Timed beside it: the float64 form, and the mixed form with the
 learned preconditioner (semi-implicit Richardson plus a trained bf16
 convolution network correction, weights from
-paper_2103_16120_amd/weights/learned_512x256.bin).
+paper_2103_16120_amd/weights/learned_512x256.bin).  After them, the
+semi-implicit model step around the solve (gcr_si_step) on the same batch
+size over synthetic mountains (`si_step`: its time, the explicit kernels'
+algorithmic bandwidth, and the oracle's step on one member beside it).
 
 Prints one JSON line (rank 0).  Inputs are resident in HBM before the timed
 region starts.  --gpus above 1 is refused: this build measures one GPU.
@@ -165,6 +168,8 @@ def parse():
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel event timing")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner leg")
     ap.add_argument("--graph", action="store_true", help="replay iterations and cycle ends from HIP graphs")
+    ap.add_argument("--no-si-step", action="store_true", help="skip the semi-implicit model-step leg")
+    ap.add_argument("--si-dt", type=float, default=200.0, help="time step of the model-step leg (s)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (reference for HBM counters)")
     return ap.parse_args()
@@ -347,6 +352,87 @@ def cpu_baseline(args, probs, budget_s, runs=5):
                       f"iterations {min(its)}-{max(its)}; one thread"}
 
 
+# algorithmic bytes per point of the model step's explicit kernels (float64
+# fields read and written once: forcings and Courant numbers 10, donor cell
+# 8 + 12, antidiffusive velocities 11, implicit inversion 12, right-hand side
+# 6, recovery 6; H0 read by three of them)
+SI_BYTES_PER_POINT = 8 * (65 + 3)
+
+
+def model_states(args):
+    from workloads import model_state
+    return [model_state(args.nx, args.ny, m) for m in range(args.batch)]
+
+
+def si_step_leg(args, torch, lib, states):
+    """One semi-implicit step of every member (gcr_si_step) over synthetic
+    mountains, in the headline precision form: the step's time, and the
+    explicit kernels' algorithmic bandwidth from HIP events."""
+    nx, ny, count, dt = args.nx, args.ny, args.batch, args.si_dt
+    absorber = 1.0 / (200.0 * dt)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    cur = [tuple(dev(st[k]) for k in ("phi", "qx", "qy")) for st in states]
+    oro = [dev(st["orography"]) for st in states]
+    new = [tuple(torch.empty_like(f) for f in c) for c in cur]
+    s = lib.Solver([(nx, ny)] * count, precision=lib.MIXED_HALF_PC, rtol=args.rtol, max_iters=200)
+    step = lambda: s.si_step(cur, cur, new, [dt] * count, orographies=oro, absorber=absorber)
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        reps = step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    s.set_kernel_timing(True)
+    step()
+    kt = s.kernel_times()
+    s.set_kernel_timing(False)
+    s.close()
+    n_si, ms_si = kt["si_step"]
+    achieved = count * nx * ny * SI_BYTES_PER_POINT / (ms_si * 1e-3) / 1e9
+    return {"workload": f"{count} members of {nx}x{ny} over synthetic mountains, dt {dt:g} s, "
+                        f"absorber 1/(200 dt), mixed half-precision-preconditioner solve, rtol {args.rtol:g}",
+            "ms_per_step": round(ms, 3), "member_steps_per_s": round(count * 1e3 / ms, 1),
+            "gcr_iters_mean": float(np.mean([r.iterations for r in reps])),
+            "statuses": sorted(set(r.status for r in reps)),
+            "explicit_kernels": {"bound": "hbm", "launches": n_si, "ms": round(ms_si, 4),
+                                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                 "alg_bytes_per_point": SI_BYTES_PER_POINT},
+            "solver_kernels_ms": round(sum(v[1] for k, v in kt.items() if k != "si_step"), 4)}
+
+
+def cpu_si_baseline(args, states, runs=3):
+    """The oracle's step (float64 explicit part, its GCR to the same rtol),
+    single-threaded, on the first member: one warm-up step, then the median
+    of `runs` timed steps."""
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(1)
+    except Exception:
+        limiter = None
+    from oracle import si_step as si
+    from oracle.gcr import gcr
+    st = states[0]
+    z = np.zeros((args.ny, args.nx))
+    s0 = si.State(st["phi"], st["qx"], st["qy"])
+    p = si.Params(dt=args.si_dt, absorber=1.0 / (200.0 * args.si_dt))
+    solve = lambda op, rhs, x0: gcr(op, rhs, x0, rtol=args.rtol).x
+    times = []
+    for i in range(runs + 1):
+        t0 = time.perf_counter()
+        si.si_step(args.nx, args.ny, s0, s0, st["orography"], (z, z), p, solve)
+        if i:
+            times.append(time.perf_counter() - t0)
+    if limiter is not None and hasattr(limiter, "unregister"):
+        limiter.unregister()
+    med = float(np.median(times))
+    return {"value": round(1.0 / med, 4), "unit": "member steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"median of {runs} steps of one {args.nx}x{args.ny} member after one warm-up step; "
+                      f"step times {min(times):.2f}-{max(times):.2f} s; one thread"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -470,8 +556,15 @@ def main():
             out["learned"]["kernel_ms_per_step"] = {k: round(v[1] / len(kitl), 4) for k, v in ktl.items() if v[0]}
         lrn.solver.close()
 
+    states = None
+    if not args.no_si_step:
+        states = model_states(args)
+        out["si_step"] = si_step_leg(args, torch, lib, states)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, probs, args.cpu_seconds)
+        if states is not None:
+            out["si_step"]["cpu_baseline"] = cpu_si_baseline(args, states)
     print(json.dumps(out), flush=True)
 
 

@@ -76,9 +76,13 @@ __device__ __forceinline__ bf16x8 ld8(const __bf16* p) {
 // OUT: 0 = bf16 NHWC (32 channels written, the upper 16 zero when NT == 1),
 //      1 = float32 channel 0 only.
 // A workgroup covers CONV_SPW groups of four consecutive 64-pixel strips, one
-// strip per wave at a time; a wave computes its strip two 16-pixel tiles at a
-// time (the 18 input fragments of a tile pair are loaded before the MFMAs
-// that use them, which keeps loads in flight while the matrix cores work).
+// strip per wave at a time.  A wave first stages its strip's input -- the
+// three rows j-1, j, j+1 (across a pole: the polar row shifted by NX/2) over
+// pixels i0-1 .. i0+64, all stored channels -- in an LDS tile of its own, 16
+// bytes a lane per load, so each input pixel is fetched from the caches once
+// per row instead of once per tap; it then computes the strip two 16-pixel
+// tiles at a time from the tile (the 18 input fragments of a tile pair are
+// read before the MFMAs that use them).
 // The four waves share the weight fragments staged in LDS once per workgroup;
 // each [tap][out channel] row of 32 input channels is padded to 40 elements so
 // that the 16 lanes reading one 16-byte column hit distinct banks.  When the
@@ -92,6 +96,7 @@ __device__ __forceinline__ bf16x8 ld8(const __bf16* p) {
 constexpr int WROW = CH + 8;
 constexpr int CONV_SPW = 4;              // strip groups per workgroup
 constexpr int OROW = CH + 8;             // padded pixel row of the output tile
+constexpr int SPX = 64 + 2;              // staged pixels per row: the strip and one on each side
 
 // CIN: channels stored per input pixel (8 for the first layer's packed input,
 // whose channels beyond are zero and not stored; else CH).
@@ -99,6 +104,7 @@ template <int NT, int OUT, int CIN>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs A) {
   __shared__ __attribute__((aligned(16))) __bf16 sw[TAPS * CH * WROW];
   __shared__ __attribute__((aligned(16))) __bf16 so[WG_WAVES][16 * OROW];
+  __shared__ __attribute__((aligned(16))) __bf16 si[WG_WAVES][3 * SPX * CIN];   // [row][pixel][channel]
   if (A.active && !A.active[blockIdx.y]) return;   // the whole workgroup: one image
   const int tid = threadIdx.x;
   const int npix = A.nx * A.ny;
@@ -122,12 +128,50 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs A) {
   const bool kin = CIN == CH || kq < CIN;  // this lane's input channels are stored
   const int ml = lane & 15;
   __bf16* tile = so[wave];
+  __bf16* stage = si[wave];
+  constexpr int CPP = CIN / 8;             // 16-byte chunks per staged pixel
+  constexpr int NCH = 3 * SPX * CPP, NLD = (NCH + 63) / 64;
+  // the staged input of a strip: rows j-1 .. j+1, pixels i0-1 .. i0+64; the
+  // loads of the next strip are issued before the current strip's MFMAs and
+  // written to the tile after them (one tile per wave, two syncs per strip)
+  bf16x8 buf[NLD];
+  auto fetch = [&](long long strip) {
+    const int p0 = (int)(strip * 64);
+    const int j = p0 >> A.log2nx, i0 = p0 & (A.nx - 1);
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+      const int c = lane + 64 * u;
+      if (c < NCH) {
+        const int r = c / (SPX * CPP), rem = c - r * (SPX * CPP);
+        const int px = rem / CPP, q = rem - px * CPP;
+        int jj, ii;
+        bool ghost;
+        sphere_src(j, i0 - 1 + px, r - 1, 0, A.nx, A.ny, jj, ii, ghost);
+        buf[u] = ld8(img + ((long long)jj * A.nx + ii) * CIN + 8 * q);
+      }
+    }
+  };
+  auto put = [&]() {
+    wave_sync_lds();   // the previous strip's reads of the tile come first
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+      const int c = lane + 64 * u;
+      if (c < NCH) *(bf16x8*)&stage[c * 8] = buf[u];   // chunk c = (row, pixel, 16-byte channel block)
+    }
+    wave_sync_lds();
+  };
+  if (s_first + wave < s_end) {
+    fetch(s_first + wave);
+    put();
+  }
 #pragma unroll 1
   for (int g = 0; g < CONV_SPW; ++g) {
     const long long strip = s_first + g * WG_WAVES + wave;
     if (strip >= s_end) break;
     const int p0 = (int)(strip * 64);
-    const int j = p0 >> A.log2nx, i0 = p0 & (A.nx - 1);
+    const long long next = strip + WG_WAVES;
+    const bool more = g + 1 < CONV_SPW && next < s_end;
+    if (more) fetch(next);
 #pragma unroll 1
     for (int mt = 0; mt < CONV_MT; mt += 2) {
       bf16x8 a[2][TAPS];
@@ -136,10 +180,8 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs A) {
         const int dy = t / 3 - 1, dx = t % 3 - 1;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          int jj, ii;
-          bool ghost;
-          sphere_src(j, i0 + 16 * (mt + h) + ml, dy, dx, A.nx, A.ny, jj, ii, ghost);
-          a[h][t] = kin ? ld8(img + ((long long)jj * A.nx + ii) * CIN + kq) : bf16x8{};
+          const int px = 16 * (mt + h) + ml + dx + 1;
+          a[h][t] = kin ? *(const bf16x8*)&stage[((dy + 1) * SPX + px) * CIN + kq] : bf16x8{};
         }
       }
       f32x4 acc[2][NT];
@@ -203,6 +245,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs A) {
         }
       }
     }
+    if (more) put();
   }
 }
 
