@@ -491,7 +491,8 @@ typedef struct {
  * solve's reports).  The step's work fields (20 per member, ~ 8 * 20 * NX *
  * (NY+1) bytes) are allocated by the first call and kept.  Returns the
  * solve's worst soft status, or a hard error.  Synchronous.  Errors:
- * GCR_EINVAL (NULL fields, aliasing of new and old state, dt / g / radius
+ * GCR_EINVAL (NULL fields, a new field equal to another new field or to an
+ * input field (fields must not overlap at all), dt / g / radius
  * not > 0, absorber < 0, and every error of gcr_set_operators / gcr_solve,
  * e.g. a non-positive Phi*), GCR_ENOMEM, GCR_EHIP. */
 int gcr_si_step(gcr_solver* s, const gcr_si_member* members, gcr_report* reports);

@@ -83,6 +83,20 @@ __device__ __forceinline__ double* wf(const SiArgs& A, const SiMember& M, int k)
   for (int p_ = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; p_ < n_;         \
        p_ += gridDim.x * blockDim.x)
 
+// One thread per column i and band of SI_BAND consecutive rows j0 .. j1-1 of
+// member blockIdx.y: a stencil's neighbour rows are loaded once per band
+// row and rolled down in registers instead of loaded once per point.  Bands
+// are numbered row-major over (band, column), with the same XCD mapping as
+// SI_POINTS.
+constexpr int SI_BAND = 4;
+#define SI_BANDS(A, M)                                                                        \
+  const SiMember M = (A).tab[blockIdx.y];                                                     \
+  const int nb_ = ((M.ny + SI_BAND - 1) / SI_BAND) * M.nx;                                    \
+  for (int t_ = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; t_ < nb_;        \
+       t_ += gridDim.x * blockDim.x)                                                          \
+    for (int i_ = t_ & (M.nx - 1), j0_ = (t_ >> M.log2nx) * SI_BAND, j1_ = min(j0_ + SI_BAND, M.ny), once_ = 1; \
+         once_; once_ = 0)
+
 // the latitude table of every member
 __global__ void k_si_lat(SiArgs A) {
   const SiMember M = A.tab[blockIdx.y];
@@ -105,27 +119,16 @@ __device__ __forceinline__ void vel(const double* phi, const double* qx, const d
 
 // 1-2: forcings, Q~ = Q + dt/2 R^n, and the face Courant numbers at n + 1/2
 __global__ void k_si_prepare(SiArgs A) {
-  SI_POINTS(A, M) {
-    const int j = p_ >> M.log2nx, i = p_ & (M.nx - 1), nx = M.nx, ny = M.ny;
-    const long long k = (long long)j * nx + i;
+  SI_BANDS(A, M) {
+    const int nx = M.nx, ny = M.ny;
     const double* lt = wf(A, M, W_LAT);
-    const double cs = lt[LT_N * j + LT_COS], sn = lt[LT_N * j + LT_SIN];
     const double a = M.radius, d = 0.5 * M.dt;
     const double dlam = 2.0 * kPi / nx, dphi = kPi / ny;
-    // gradient of Phi + H0 (central differences, across-pole rows)
+    // Phi + H0 (across-pole rows as in the operator)
     auto hs = [&](int jj, int ii) {
       return at(M.phi, jj, ii, nx, ny, 1.0) + (M.oro ? at(M.oro, jj, ii, nx, ny, 1.0) : 0.0);
     };
-    const double hx = (hs(j, i + 1) - hs(j, i - 1)) / (2.0 * dlam);
-    const double hy = (hs(j + 1, i) - hs(j - 1, i)) / (2.0 * dphi);
-    const double ph = M.phi[k], qx = M.qx[k], qy = M.qy[k];
-    const double f = 2.0 * M.omega * sn, al = lt[LT_N * j + LT_ALPHA], t = sn / cs;
-    const double qbx = M.qbx ? M.qbx[k] : 0.0, qby = M.qby ? M.qby[k] : 0.0;
-    const double rx = -M.g / (a * cs) * ph * hx + f * qy + t * qx * qy / (a * ph) - al * (qx - qbx);
-    const double ry = -M.g / a * ph * hy - f * qx - t * qx * qx / (a * ph) - al * (qy - qby);
-    wf(A, M, W_QTX)[k] = qx + d * rx;
-    wf(A, M, W_QTY)[k] = qy + d * ry;
-    // advective velocity at n + 1/2 = 1.5 v^n - 0.5 v^{n-1}, at the east and north faces
+    // advective velocity at n + 1/2 = 1.5 v^n - 0.5 v^{n-1} at a cell
     auto vext = [&](int jj, int ii, double& vx, double& vy) {
       const long long kk = (long long)jj * nx + (ii & (nx - 1));
       const double c = lt[LT_N * jj + LT_COS];
@@ -135,44 +138,110 @@ __global__ void k_si_prepare(SiArgs A) {
       vx = 1.5 * x1 - 0.5 * x0;
       vy = 1.5 * y1 - 0.5 * y0;
     };
-    double vx, vy, vxe, vye;
-    vext(j, i, vx, vy);
-    vext(j, i + 1, vxe, vye);
-    wf(A, M, W_CX)[k] = 0.5 * (vx + vxe) * M.dt / dlam;
-    double cyn = 0.0;
-    if (j < ny - 1) {
-      double vxn, vyn;
-      vext(j + 1, i, vxn, vyn);
-      cyn = 0.5 * (vy + vyn) * M.dt / dphi;
+    // column i rolled down the band: Phi + H0 at rows j-1, j; v at row j
+    double hs_m = hs(j0_ - 1, i_), hs_c = hs(j0_, i_);
+    double vx, vy;
+    vext(j0_, i_, vx, vy);
+    double* __restrict__ qtx = wf(A, M, W_QTX);
+    double* __restrict__ qty = wf(A, M, W_QTY);
+    double* __restrict__ ocx = wf(A, M, W_CX);
+    double* __restrict__ ocy = wf(A, M, W_CY);
+#pragma unroll
+    for (int r = 0; r < SI_BAND; ++r) {
+      const int j = j0_ + r;
+      if (j >= j1_) break;
+      const long long k = (long long)j * nx + i_;
+      const double cs = lt[LT_N * j + LT_COS], sn = lt[LT_N * j + LT_SIN];
+      const double hs_n = hs(j + 1, i_);
+      // gradient of Phi + H0 (central differences)
+      const double hx = (hs(j, i_ + 1) - hs(j, i_ - 1)) / (2.0 * dlam);
+      const double hy = (hs_n - hs_m) / (2.0 * dphi);
+      const double ph = M.phi[k], qx = M.qx[k], qy = M.qy[k];
+      const double f = 2.0 * M.omega * sn, al = lt[LT_N * j + LT_ALPHA], t = sn / cs;
+      const double qbx = M.qbx ? M.qbx[k] : 0.0, qby = M.qby ? M.qby[k] : 0.0;
+      const double rx = -M.g / (a * cs) * ph * hx + f * qy + t * qx * qy / (a * ph) - al * (qx - qbx);
+      const double ry = -M.g / a * ph * hy - f * qx - t * qx * qx / (a * ph) - al * (qy - qby);
+      qtx[k] = qx + d * rx;
+      qty[k] = qy + d * ry;
+      // Courant numbers at the east face and the north face j + 1/2 (zero at the north pole)
+      double vxe, vye;
+      vext(j, i_ + 1, vxe, vye);
+      ocx[k] = 0.5 * (vx + vxe) * M.dt / dlam;
+      double cyn = 0.0, vxn = 0.0, vyn = 0.0;
+      if (j < ny - 1) {
+        vext(j + 1, i_, vxn, vyn);
+        cyn = 0.5 * (vy + vyn) * M.dt / dphi;
+      }
+      ocy[k] = cyn;
+      hs_m = hs_c;
+      hs_c = hs_n;
+      vx = vxn;
+      vy = vyn;
     }
-    wf(A, M, W_CY)[k] = cyn;   // face j + 1/2 (zero at the north pole)
   }
 }
 
 // donor-cell pass of the three advected fields: out = in - (div of upwind
 // fluxes) / cos(lat); `ax*` / `ay*`: the Courant numbers of each field
 struct UpwindSet {
-  int in[3], out[3], cx[3], cy[3];
-  int from_state;                      // pass 1 reads Phi^n and Q~ (in[0] < 0: Phi^n)
+  int in[3], out[3], cx[3], cy[3];     // work fields; in[0] < 0: Phi^n (the first pass)
 };
 
+// SHARED: the three fields move with the same Courant numbers (the first
+// pass), which are then read once per point
+template <bool SHARED>
 __global__ void k_si_upwind(SiArgs A, UpwindSet U) {
-  SI_POINTS(A, M) {
-    const int j = p_ >> M.log2nx, i = p_ & (M.nx - 1), nx = M.nx, ny = M.ny;
-    const long long k = (long long)j * nx + i;
-    const double g = wf(A, M, W_LAT)[LT_N * j + LT_COS];
-    const int ie = (i + 1) & (nx - 1), iw = (i - 1) & (nx - 1);
-    for (int fdx = 0; fdx < 3; ++fdx) {
-      const double* psi = U.in[fdx] < 0 ? M.phi : wf(A, M, U.in[fdx]);
-      const double* cxa = wf(A, M, U.cx[fdx]);
-      const double* cya = wf(A, M, U.cy[fdx]);
-      const long long row = (long long)j * nx;
-      auto flux = [](double c, double l, double r) { return fmax(c, 0.0) * l + fmin(c, 0.0) * r; };
-      const double fe = flux(cxa[k], psi[k], psi[row + ie]);
-      const double fw = flux(cxa[row + iw], psi[row + iw], psi[k]);
-      const double fn = j < ny - 1 ? flux(cya[k], psi[k], psi[k + nx]) : 0.0;
-      const double fs = j > 0 ? flux(cya[k - nx], psi[k - nx], psi[k]) : 0.0;
-      wf(A, M, U.out[fdx])[k] = psi[k] - ((fe - fw) + (fn - fs)) / g;
+  SI_BANDS(A, M) {
+    const int nx = M.nx, ny = M.ny;
+    const double* lt = wf(A, M, W_LAT);
+    const int ie = (i_ + 1) & (nx - 1), iw = (i_ - 1) & (nx - 1);
+    auto flux = [](double c, double l, double r) { return fmax(c, 0.0) * l + fmin(c, 0.0) * r; };
+    const double* psi[3];
+    const double* cxa[3];
+    const double* cya[3];
+    // the outputs are never read by this pass (restrict lets the next rows'
+    // loads be issued before this row's stores)
+    double* __restrict__ out[3];
+    for (int f = 0; f < 3; ++f) {
+      psi[f] = U.in[f] < 0 ? M.phi : wf(A, M, U.in[f]);
+      cxa[f] = wf(A, M, U.cx[SHARED ? 0 : f]);
+      cya[f] = wf(A, M, U.cy[SHARED ? 0 : f]);
+      out[f] = wf(A, M, U.out[f]);
+    }
+    // column i rolled down the band: psi at rows j-1, j and C^y at face j-1/2
+    const long long k0 = (long long)j0_ * nx + i_;
+    double ps_m[3], ps_c[3], cy_s[3];
+    for (int f = 0; f < 3; ++f) {
+      ps_m[f] = j0_ > 0 ? psi[f][k0 - nx] : 0.0;
+      ps_c[f] = psi[f][k0];
+      cy_s[f] = (j0_ > 0 && (!SHARED || f == 0)) ? cya[f][k0 - nx] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < SI_BAND; ++r) {
+      const int j = j0_ + r;
+      if (j >= j1_) break;
+      const long long row = (long long)j * nx, k = row + i_;
+      const double g = lt[LT_N * j + LT_COS];
+      double ce = 0.0, cw = 0.0, cn = 0.0;
+      const double cs0 = cy_s[0];   // face j-1/2 of the shared Courant numbers
+#pragma unroll
+      for (int f = 0; f < 3; ++f) {
+        if (!SHARED || f == 0) {
+          ce = cxa[f][k];
+          cw = cxa[f][row + iw];
+          cn = j < ny - 1 ? cya[f][k] : 0.0;
+        }
+        const double cs = SHARED ? cs0 : cy_s[f];
+        const double ps_n = j < ny - 1 ? psi[f][k + nx] : 0.0;
+        const double fe = flux(ce, ps_c[f], psi[f][row + ie]);
+        const double fw = flux(cw, psi[f][row + iw], ps_c[f]);
+        const double fn = j < ny - 1 ? flux(cn, ps_c[f], ps_n) : 0.0;
+        const double fs = j > 0 ? flux(cs, ps_m[f], ps_c[f]) : 0.0;
+        out[f][k] = ps_c[f] - ((fe - fw) + (fn - fs)) / g;
+        ps_m[f] = ps_c[f];
+        ps_c[f] = ps_n;
+        if (!SHARED || f == 0) cy_s[f] = cn;
+      }
     }
   }
 }
@@ -180,53 +249,93 @@ __global__ void k_si_upwind(SiArgs A, UpwindSet U) {
 // antidiffusive Courant numbers of the corrective pass for the three fields
 // (|psi| in the ratios; momenta change sign across a pole)
 __global__ void k_si_antidiff(SiArgs A) {
-  SI_POINTS(A, M) {
-    const int j = p_ >> M.log2nx, i = p_ & (M.nx - 1), nx = M.nx, ny = M.ny;
-    const long long k = (long long)j * nx + i;
+  SI_BANDS(A, M) {
+    const int nx = M.nx, ny = M.ny;
     const double* lt = wf(A, M, W_LAT);
-    const double gx = lt[LT_N * j + LT_COS];
     const double* cx = wf(A, M, W_CX);
     const double* cy = wf(A, M, W_CY);
     const int ins[3] = {W_P1, W_Q1X, W_Q1Y};
     const int oxs[3] = {W_AXP, W_AXQX, W_AXQY};
     const int oys[3] = {W_AYP, W_AYQX, W_AYQY};
     const double tiny = 1e-300;
-    // y-face Courant numbers around the east face (i+1/2, j): faces j+1/2 and
-    // j-1/2 of columns i and i+1 (pole faces carry zero)
-    auto cyf = [&](int jj, int ii) {   // face jj + 1/2
-      return (jj < 0 || jj >= ny - 1) ? 0.0 : cy[(long long)jj * nx + (ii & (nx - 1))];
-    };
-    const double cyb = 0.25 * (cyf(j, i) + cyf(j, i + 1) + cyf(j - 1, i) + cyf(j - 1, i + 1));
-    const double c = cx[k];
-    double cxb = 0.0;
-    if (j < ny - 1) {
-      auto cxf = [&](int jj, int ii) { return cx[(long long)jj * nx + (ii & (nx - 1))]; };
-      cxb = 0.25 * (cxf(j, i) + cxf(j, i - 1) + cxf(j + 1, i) + cxf(j + 1, i - 1));
-    }
-    const double cyn = j < ny - 1 ? cy[k] : 0.0;
-    const double gy = lt[LT_N * j + LT_COSN];
-    for (int fdx = 0; fdx < 3; ++fdx) {
+    // |psi| of the three fields at rows j-1 .. j+1, columns i-1 .. i+1 (the
+    // rows beyond a pole seen across it; the momenta change sign there, which
+    // |psi| does not see), rolled down the band
+    double w[3][3][3];   // [field][row j-1, j, j+1][column i-1, i, i+1]
+    auto load_row = [&](int fdx, int jj, double (&r)[3]) {
       const double* psi = wf(A, M, ins[fdx]);
       const double sg = fdx == 0 ? 1.0 : -1.0;
-      auto v = [&](int jj, int ii) { return fabs(at(psi, jj, ii, nx, ny, sg)); };
-      // east face
-      const double pc = v(j, i), pe = v(j, i + 1);
-      const double axr = (pe - pc) / (pe + pc + tiny);
-      const double num = (v(j + 1, i + 1) + v(j + 1, i)) - (v(j - 1, i + 1) + v(j - 1, i));
-      const double den = (v(j + 1, i + 1) + v(j + 1, i)) + (v(j - 1, i + 1) + v(j - 1, i));
-      const double bxr = 0.5 * num / (den + tiny);
-      wf(A, M, oxs[fdx])[k] = (fabs(c) - c * c / gx) * axr - c * cyb / gx * bxr;
-      // north face (interior faces only)
-      double ay = 0.0;
-      if (j < ny - 1) {
-        const double pn = v(j + 1, i);
-        const double ayr = (pn - pc) / (pn + pc + tiny);
-        const double nm = (v(j + 1, i + 1) + v(j, i + 1)) - (v(j + 1, i - 1) + v(j, i - 1));
-        const double dn = (v(j + 1, i + 1) + v(j, i + 1)) + (v(j + 1, i - 1) + v(j, i - 1));
-        const double byr = 0.5 * nm / (dn + tiny);
-        ay = (fabs(cyn) - cyn * cyn / gy) * ayr - cyn * cxb / gy * byr;
+      r[0] = fabs(at(psi, jj, i_ - 1, nx, ny, sg));
+      r[1] = fabs(at(psi, jj, i_, nx, ny, sg));
+      r[2] = fabs(at(psi, jj, i_ + 1, nx, ny, sg));
+    };
+    // face Courant numbers: C^x at columns i-1, i of rows j, j+1; C^y (face
+    // jj + 1/2, zero at the poles) at columns i, i+1 of rows j-1, j
+    auto cxr = [&](int jj, double (&r)[2]) {
+      r[0] = cx[(long long)jj * nx + ((i_ - 1) & (nx - 1))];
+      r[1] = cx[(long long)jj * nx + i_];
+    };
+    auto cyr = [&](int jj, double (&r)[2]) {
+      const bool in = jj >= 0 && jj < ny - 1;
+      r[0] = in ? cy[(long long)jj * nx + i_] : 0.0;
+      r[1] = in ? cy[(long long)jj * nx + ((i_ + 1) & (nx - 1))] : 0.0;
+    };
+    for (int fdx = 0; fdx < 3; ++fdx) {
+      load_row(fdx, j0_ - 1, w[fdx][0]);
+      load_row(fdx, j0_, w[fdx][1]);
+    }
+    double cxw[2][2], cyw[2][2];   // C^x rows j, j+1; C^y rows j-1, j
+    cxr(j0_, cxw[0]);
+    cyr(j0_ - 1, cyw[0]);
+    cyr(j0_, cyw[1]);
+    // the six outputs are written through restrict pointers: the next rows'
+    // loads may be issued before this row's stores
+    double* __restrict__ ox[3] = {wf(A, M, oxs[0]), wf(A, M, oxs[1]), wf(A, M, oxs[2])};
+    double* __restrict__ oy[3] = {wf(A, M, oys[0]), wf(A, M, oys[1]), wf(A, M, oys[2])};
+#pragma unroll
+    for (int r = 0; r < SI_BAND; ++r) {
+      const int j = j0_ + r;
+      if (j >= j1_) break;
+      const long long k = (long long)j * nx + i_;
+      for (int fdx = 0; fdx < 3; ++fdx) load_row(fdx, j + 1, w[fdx][2]);
+      if (j < ny - 1) cxr(j + 1, cxw[1]);
+      const double gx = lt[LT_N * j + LT_COS];
+      const double cyb = 0.25 * (cyw[1][0] + cyw[1][1] + cyw[0][0] + cyw[0][1]);
+      const double c = cxw[0][1];
+      double cxb = 0.0;
+      if (j < ny - 1) cxb = 0.25 * (cxw[0][1] + cxw[0][0] + cxw[1][1] + cxw[1][0]);
+      const double cyn = cyw[1][0];
+      const double gy = lt[LT_N * j + LT_COSN];
+      for (int fdx = 0; fdx < 3; ++fdx) {
+        const double(&u)[3][3] = w[fdx];   // u[row][column]: rows j-1, j, j+1; columns i-1, i, i+1
+        // east face
+        const double pc = u[1][1], pe = u[1][2];
+        const double axr = (pe - pc) / (pe + pc + tiny);
+        const double num = (u[2][2] + u[2][1]) - (u[0][2] + u[0][1]);
+        const double den = (u[2][2] + u[2][1]) + (u[0][2] + u[0][1]);
+        const double bxr = 0.5 * num / (den + tiny);
+        ox[fdx][k] = (fabs(c) - c * c / gx) * axr - c * cyb / gx * bxr;
+        // north face (interior faces only)
+        double ay = 0.0;
+        if (j < ny - 1) {
+          const double pn = u[2][1];
+          const double ayr = (pn - pc) / (pn + pc + tiny);
+          const double nm = (u[2][2] + u[1][2]) - (u[2][0] + u[1][0]);
+          const double dn = (u[2][2] + u[1][2]) + (u[2][0] + u[1][0]);
+          const double byr = 0.5 * nm / (dn + tiny);
+          ay = (fabs(cyn) - cyn * cyn / gy) * ayr - cyn * cxb / gy * byr;
+        }
+        oy[fdx][k] = ay;
       }
-      wf(A, M, oys[fdx])[k] = ay;
+      // roll the windows down one row
+      for (int fdx = 0; fdx < 3; ++fdx)
+        for (int r = 0; r < 2; ++r)
+          for (int q = 0; q < 3; ++q) w[fdx][r][q] = w[fdx][r + 1][q];
+      cxw[0][0] = cxw[1][0];
+      cxw[0][1] = cxw[1][1];
+      cyw[0][0] = cyw[1][0];
+      cyw[0][1] = cyw[1][1];
+      cyr(j + 1, cyw[1]);
     }
   }
 }
@@ -262,49 +371,76 @@ __global__ void k_si_qhh(SiArgs A) {
 // 5: R = D(F^n) + D(Fhathat) - C Phi^n, F = (a Q_x, a cos Q_y) at the faces
 // (means of the two cells; no flux through the poles)
 __global__ void k_si_rhs(SiArgs A) {
-  SI_POINTS(A, M) {
-    const int j = p_ >> M.log2nx, i = p_ & (M.nx - 1), nx = M.nx, ny = M.ny;
-    const long long k = (long long)j * nx + i;
+  SI_BANDS(A, M) {
+    const int nx = M.nx, ny = M.ny;
     const double a = M.radius;
     const double dlam = 2.0 * kPi / nx, dphi = kPi / ny;
+    const double* lt = wf(A, M, W_LAT);
     const double* hx = wf(A, M, W_QHHX);
     const double* hy = wf(A, M, W_QHHY);
-    const long long row = (long long)j * nx;
-    const int ie = (i + 1) & (nx - 1), iw = (i - 1) & (nx - 1);
+    double* __restrict__ out = wf(A, M, W_RHS);
+    const int ie = (i_ + 1) & (nx - 1), iw = (i_ - 1) & (nx - 1);
     auto qsx = [&](long long kk) { return M.qx[kk] + hx[kk]; };
     auto qsy = [&](long long kk) { return M.qy[kk] + hy[kk]; };
-    const double fe = a * 0.5 * (qsx(k) + qsx(row + ie)), fw = a * 0.5 * (qsx(row + iw) + qsx(k));
-    const double* lt = wf(A, M, W_LAT);
-    const double cn = lt[LT_N * j + LT_COSN], csf = j > 0 ? lt[LT_N * (j - 1) + LT_COSN] : 0.0;
-    const double fn = j < ny - 1 ? a * cn * 0.5 * (qsy(k) + qsy(k + nx)) : 0.0;
-    const double fs = j > 0 ? a * csf * 0.5 * (qsy(k - nx) + qsy(k)) : 0.0;
-    const double C = 2.0 * a * a * lt[LT_N * j + LT_COS] / M.dt;
-    wf(A, M, W_RHS)[k] = (fe - fw) / dlam + (fn - fs) / dphi - C * M.phi[k];
+    // column i rolled down the band: Q_y + Qhathat_y at rows j-1, j
+    const long long k0 = (long long)j0_ * nx + i_;
+    double ys_m = j0_ > 0 ? qsy(k0 - nx) : 0.0, ys_c = qsy(k0);
+#pragma unroll
+    for (int r = 0; r < SI_BAND; ++r) {
+      const int j = j0_ + r;
+      if (j >= j1_) break;
+      const long long row = (long long)j * nx, k = row + i_;
+      const double ys_n = j < ny - 1 ? qsy(k + nx) : 0.0;
+      const double xs_c = qsx(k);
+      const double fe = a * 0.5 * (xs_c + qsx(row + ie)), fw = a * 0.5 * (qsx(row + iw) + xs_c);
+      const double cn = lt[LT_N * j + LT_COSN], csf = j > 0 ? lt[LT_N * (j - 1) + LT_COSN] : 0.0;
+      const double fn = j < ny - 1 ? a * cn * 0.5 * (ys_c + ys_n) : 0.0;
+      const double fs = j > 0 ? a * csf * 0.5 * (ys_m + ys_c) : 0.0;
+      const double C = 2.0 * a * a * lt[LT_N * j + LT_COS] / M.dt;
+      out[k] = (fe - fw) / dlam + (fn - fs) / dphi - C * M.phi[k];
+      ys_m = ys_c;
+      ys_c = ys_n;
+    }
   }
 }
 
 // 6: Q^{n+1} = Qhathat + A grad Phi^{n+1} + B Phi^{n+1}
 __global__ void k_si_recover(SiArgs A) {
-  SI_POINTS(A, M) {
-    const int j = p_ >> M.log2nx, i = p_ & (M.nx - 1), nx = M.nx, ny = M.ny;
-    const long long k = (long long)j * nx + i;
+  SI_BANDS(A, M) {
+    const int nx = M.nx, ny = M.ny;
     const double* lt = wf(A, M, W_LAT);
-    const double cs = lt[LT_N * j + LT_COS], sn = lt[LT_N * j + LT_SIN];
     const double a = M.radius, d = 0.5 * M.dt;
     const double dlam = 2.0 * kPi / nx, dphi = kPi / ny;
-    const double al = lt[LT_N * j + LT_ALPHA], gam = 1.0 + d * al, b = d * 2.0 * M.omega * sn;
-    const double D = gam * gam + b * b;
     const double* ps = wf(A, M, W_PHIS);
-    auto hs = [&](int jj, int ii) { return at(ps, jj, ii, nx, ny, 1.0) + (M.oro ? at(M.oro, jj, ii, nx, ny, 1.0) : 0.0); };
     const double* p1 = M.phi1;
-    const double px = (at(p1, j, i + 1, nx, ny, 1.0) - at(p1, j, i - 1, nx, ny, 1.0)) / (2.0 * dlam);
-    const double py = (at(p1, j + 1, i, nx, ny, 1.0) - at(p1, j - 1, i, nx, ny, 1.0)) / (2.0 * dphi);
-    const double hx = (hs(j, i + 1) - hs(j, i - 1)) / (2.0 * dlam);
-    const double hy = (hs(j + 1, i) - hs(j - 1, i)) / (2.0 * dphi);
-    const double ux = -d * M.g / (a * cs) * 0.5 * (p1[k] * hx + ps[k] * px);
-    const double uy = -d * M.g / a * 0.5 * (p1[k] * hy + ps[k] * py);
-    M.qx1[k] = wf(A, M, W_QHHX)[k] + (gam * ux + b * uy) / D;
-    M.qy1[k] = wf(A, M, W_QHHY)[k] + (-b * ux + gam * uy) / D;
+    auto hs = [&](int jj, int ii) { return at(ps, jj, ii, nx, ny, 1.0) + (M.oro ? at(M.oro, jj, ii, nx, ny, 1.0) : 0.0); };
+    // column i rolled down the band: Phi^{n+1} and Phi* + H0 at rows j-1, j
+    double p1_m = at(p1, j0_ - 1, i_, nx, ny, 1.0), p1_c = at(p1, j0_, i_, nx, ny, 1.0);
+    double hs_m = hs(j0_ - 1, i_), hs_c = hs(j0_, i_);
+    double* __restrict__ qx1 = M.qx1;
+    double* __restrict__ qy1 = M.qy1;
+#pragma unroll
+    for (int r = 0; r < SI_BAND; ++r) {
+      const int j = j0_ + r;
+      if (j >= j1_) break;
+      const long long k = (long long)j * nx + i_;
+      const double cs = lt[LT_N * j + LT_COS], sn = lt[LT_N * j + LT_SIN];
+      const double al = lt[LT_N * j + LT_ALPHA], gam = 1.0 + d * al, b = d * 2.0 * M.omega * sn;
+      const double D = gam * gam + b * b;
+      const double p1_n = at(p1, j + 1, i_, nx, ny, 1.0), hs_n = hs(j + 1, i_);
+      const double px = (at(p1, j, i_ + 1, nx, ny, 1.0) - at(p1, j, i_ - 1, nx, ny, 1.0)) / (2.0 * dlam);
+      const double py = (p1_n - p1_m) / (2.0 * dphi);
+      const double hx = (hs(j, i_ + 1) - hs(j, i_ - 1)) / (2.0 * dlam);
+      const double hy = (hs_n - hs_m) / (2.0 * dphi);
+      const double ux = -d * M.g / (a * cs) * 0.5 * (p1_c * hx + ps[k] * px);
+      const double uy = -d * M.g / a * 0.5 * (p1_c * hy + ps[k] * py);
+      qx1[k] = wf(A, M, W_QHHX)[k] + (gam * ux + b * uy) / D;
+      qy1[k] = wf(A, M, W_QHHY)[k] + (-b * ux + gam * uy) / D;
+      p1_m = p1_c;
+      p1_c = p1_n;
+      hs_m = hs_c;
+      hs_c = hs_n;
+    }
   }
 }
 
@@ -321,8 +457,16 @@ extern "C" int gcr_si_step(gcr_solver* s, const gcr_si_member* members, gcr_repo
       return fail(s, GCR_EINVAL, "member %d: NULL state field", m);
     if (!(q.dt > 0.0) || !(q.g > 0.0) || !(q.radius > 0.0) || !std::isfinite(q.omega) || !(q.absorber >= 0.0))
       return fail(s, GCR_EINVAL, "member %d: dt, g, radius must be > 0, absorber >= 0", m);
-    if (q.phi_new == q.phi || q.qx_new == q.qx || q.qy_new == q.qy)
-      return fail(s, GCR_EINVAL, "member %d: the new state must not alias the state at n", m);
+    {   // the new fields are written while every other field is read
+      const void* outs[3] = {q.phi_new, q.qx_new, q.qy_new};
+      const void* ins[9] = {q.phi, q.qx, q.qy, q.phi_old, q.qx_old, q.qy_old, q.orography, q.qbar_x, q.qbar_y};
+      for (int a = 0; a < 3; ++a) {
+        for (int b = a + 1; b < 3; ++b)
+          if (outs[a] == outs[b]) return fail(s, GCR_EINVAL, "member %d: the new fields must be distinct", m);
+        for (const void* in : ins)
+          if (outs[a] == in) return fail(s, GCR_EINVAL, "member %d: the new state must not alias an input field", m);
+      }
+    }
     wpts = std::max(wpts, (long long)s->nx[m] * (s->ny[m] + 1));
   }
   wpts = (wpts + 63) / 64 * 64;
@@ -345,7 +489,7 @@ extern "C" int gcr_si_step(gcr_solver* s, const gcr_si_member* members, gcr_repo
   // the staged table may still feed the previous upload
   HIPCHK(s, hipStreamSynchronize(s->stream));
   SiMember* tab_h = (SiMember*)s->si_stage;
-  int nymax = 0, nptmax = 0;
+  int nymax = 0, nptmax = 0, nbandmax = 0;
   for (int m = 0; m < B; ++m) {
     const gcr_si_member& q = members[m];
     SiMember& t = tab_h[m];
@@ -372,20 +516,23 @@ extern "C" int gcr_si_step(gcr_solver* s, const gcr_si_member* members, gcr_repo
     t.w = (long long)m * W_COUNT * wpts;
     nymax = std::max(nymax, t.ny);
     nptmax = std::max(nptmax, t.nx * t.ny);
+    nbandmax = std::max(nbandmax, t.nx * ((t.ny + SI_BAND - 1) / SI_BAND));
   }
   HIPCHK(s, hipMemcpyAsync(s->si_tab, tab_h, (size_t)B * sizeof(SiMember), hipMemcpyHostToDevice, s->stream));
   SiArgs A{(const SiMember*)s->si_tab, s->si_work, wpts};
   const int nblk = (std::min((nptmax + 255) / 256, 4096) + NXCD - 1) / NXCD * NXCD;
   const dim3 grid((unsigned)nblk, (unsigned)B), blk(256);
+  const int nblk_b = (std::min((nbandmax + 255) / 256, 4096) + NXCD - 1) / NXCD * NXCD;
+  const dim3 grid_b((unsigned)nblk_b, (unsigned)B);   // the band kernels
   KLAUNCH(s, KT_SI_STEP, k_si_lat, dim3((unsigned)((nymax + 255) / 256), (unsigned)B), blk, 0, s->stream, A);
-  KLAUNCH(s, KT_SI_STEP, k_si_prepare, grid, blk, 0, s->stream, A);
-  UpwindSet U1{{-1, W_QTX, W_QTY}, {W_P1, W_Q1X, W_Q1Y}, {W_CX, W_CX, W_CX}, {W_CY, W_CY, W_CY}, 1};
-  KLAUNCH(s, KT_SI_STEP, k_si_upwind, grid, blk, 0, s->stream, A, U1);
-  KLAUNCH(s, KT_SI_STEP, k_si_antidiff, grid, blk, 0, s->stream, A);
-  UpwindSet U2{{W_P1, W_Q1X, W_Q1Y}, {W_PHIS, W_QHX, W_QHY}, {W_AXP, W_AXQX, W_AXQY}, {W_AYP, W_AYQX, W_AYQY}, 0};
-  KLAUNCH(s, KT_SI_STEP, k_si_upwind, grid, blk, 0, s->stream, A, U2);
+  KLAUNCH(s, KT_SI_STEP, k_si_prepare, grid_b, blk, 0, s->stream, A);
+  UpwindSet U1{{-1, W_QTX, W_QTY}, {W_P1, W_Q1X, W_Q1Y}, {W_CX, W_CX, W_CX}, {W_CY, W_CY, W_CY}};
+  KLAUNCH(s, KT_SI_STEP, k_si_upwind<true>, grid_b, blk, 0, s->stream, A, U1);
+  KLAUNCH(s, KT_SI_STEP, k_si_antidiff, grid_b, blk, 0, s->stream, A);
+  UpwindSet U2{{W_P1, W_Q1X, W_Q1Y}, {W_PHIS, W_QHX, W_QHY}, {W_AXP, W_AXQX, W_AXQY}, {W_AYP, W_AYQX, W_AYQY}};
+  KLAUNCH(s, KT_SI_STEP, k_si_upwind<false>, grid_b, blk, 0, s->stream, A, U2);
   KLAUNCH(s, KT_SI_STEP, k_si_qhh, grid, blk, 0, s->stream, A);
-  KLAUNCH(s, KT_SI_STEP, k_si_rhs, grid, blk, 0, s->stream, A);
+  KLAUNCH(s, KT_SI_STEP, k_si_rhs, grid_b, blk, 0, s->stream, A);
   HIPCHK(s, hipGetLastError());
   // the elliptic problem: the operator from Phi* and H0, solved from Phi^n
   std::vector<gcr_operator> ops(B);
@@ -412,7 +559,7 @@ extern "C" int gcr_si_step(gcr_solver* s, const gcr_si_member* members, gcr_repo
   if (rc < 0) return rc;
   const int st = gcr_solve(s, rhs.data(), xs.data(), reports);
   if (st < 0) return st;
-  KLAUNCH(s, KT_SI_STEP, k_si_recover, grid, blk, 0, s->stream, A);
+  KLAUNCH(s, KT_SI_STEP, k_si_recover, grid_b, blk, 0, s->stream, A);
   HIPCHK(s, hipGetLastError());
   HIPCHK(s, hipStreamSynchronize(s->stream));
   return st;

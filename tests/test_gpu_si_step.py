@@ -149,3 +149,26 @@ def test_si_step_rejects_aliasing(gpu_lib):
     new = tuple(torch.empty_like(f) for f in st)
     with pytest.raises(gpu_lib.GcrError):
         solver.si_step([st], [st], [new], [-1.0])
+
+
+def test_si_step_full_size_batch_sampled(gpu_lib):
+    # the model-step workload at full size (64 members of 512x256 over
+    # synthetic mountains, dt 200 s, absorbers 1/(200 dt)), in one batch as
+    # the bench runs it; members 0 and 63 against the oracle's step
+    from workloads import model_state
+    nx, ny, count, dt = 512, 256, 64, 200.0
+    absorber = 1.0 / (200.0 * dt)
+    states = [model_state(nx, ny, m) for m in range(count)]
+    cur = [tuple(dev(st[k]) for k in ("phi", "qx", "qy")) for st in states]
+    oro = [dev(st["orography"]) for st in states]
+    new = [tuple(torch.empty_like(f) for f in c) for c in cur]
+    solver = gpu_lib.Solver([(nx, ny)] * count, rtol=1e-12, max_iters=500)
+    reps = solver.si_step(cur, cur, new, [dt] * count, orographies=oro, absorber=absorber)
+    assert all(r.status == 0 for r in reps)
+    z = np.zeros((ny, nx))
+    p = si.Params(dt=dt, absorber=absorber)
+    for m in (0, count - 1):
+        st = states[m]
+        s0 = si.State(st["phi"], st["qx"], st["qy"])
+        ref, _ = si.si_step(nx, ny, s0, s0, st["orography"], (z, z), p, iterative)
+        _check(tuple(host(f) for f in new[m]), ref)
