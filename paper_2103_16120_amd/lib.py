@@ -163,8 +163,14 @@ class Solver:
 
     def __init__(self, sizes, k=3, precision=FP64, precond=PC_SEMI_IMPLICIT, richardson_iters=2,
                  polar_rows=-1, min_iters=-1, max_iters=200, rtol=1e-8, stream=None, flags=0, one_stream=False,
-                 linf_exit=False, record_history=False, graph=False):
+                 linf_exit=False, record_history=False, graph=False, tuned=False):
+        """tuned: take one_stream / graph from the autotuner's table for this
+        workload (paper_2103_16120_amd.tune), overriding the arguments."""
         self.sizes = [(int(nx), int(ny)) for nx, ny in sizes]
+        if tuned:
+            from .tune import tuned_options
+            opt = tuned_options(self.sizes, precision)
+            one_stream, graph = opt["one_stream"], opt["graph"]
         b = len(self.sizes)
         self._nx = (C.c_int32 * b)(*[s[0] for s in self.sizes])
         self._ny = (C.c_int32 * b)(*[s[1] for s in self.sizes])
