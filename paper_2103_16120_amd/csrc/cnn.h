@@ -14,13 +14,14 @@
 // input channels, N = 16 output channels.
 #pragma once
 
+#include <type_traits>
+
 #include "device.h"
 
 namespace mpgcr {
 
 constexpr int CNN_LAYERS = 5;
 constexpr int TAPS = 9;             // tap t = (dy+1)*3 + (dx+1)
-constexpr int CONV_MT = 4;          // 16-pixel M tiles per wave (64 pixels)
 constexpr int WG_WAVES = 4;
 
 struct ConvArgs {
@@ -36,8 +37,8 @@ struct ConvArgs {
   int pole_row;            // -1: taps use `w`, across-pole taps `wpole` only if wpole == w (forward);
                            // 0 or ny-1: the launch covers that polar row alone and its
                            // across-pole taps use `wpole`
+  int nr;                  // rows per wave (a band of one 64-pixel column strip)
   int nx, ny, log2nx, batch;
-  int relu;
 };
 
 // source pixel (row, column) read by output pixel (j, i) through tap (dy, dx)
@@ -73,179 +74,336 @@ __device__ __forceinline__ bf16x8 ld8(const __bf16* p) {
 
 // ---------------------------------------------------------------------------
 // 3x3 convolution, 32 input channels, NT*16 output channels.
-// OUT: 0 = bf16 NHWC (32 channels written, the upper 16 zero when NT == 1),
-//      1 = float32 channel 0 only.
-// A workgroup covers CONV_SPW groups of four consecutive 64-pixel strips, one
-// strip per wave at a time.  A wave first stages its strip's input -- the
-// three rows j-1, j, j+1 (across a pole: the polar row shifted by NX/2) over
-// pixels i0-1 .. i0+64, all stored channels -- in an LDS tile of its own, 16
-// bytes a lane per load, so each input pixel is fetched from the caches once
-// per row instead of once per tap; it then computes the strip two 16-pixel
-// tiles at a time from the tile (the 18 input fragments of a tile pair are
-// read before the MFMAs that use them).
-// The four waves share the weight fragments staged in LDS once per workgroup;
-// each [tap][out channel] row of 32 input channels is padded to 40 elements so
-// that the 16 lanes reading one 16-byte column hit distinct banks.  When the
-// taps that read across a pole need other weights than the rest (the adjoint
-// in the backward pass), the two polar rows are computed by launches of their
-// own (`pole_row`) whose staged set takes those taps from `wpole`, so the LDS
-// holds one set of nine taps.  bf16 outputs go through a per-wave
-// LDS tile so that each lane stores 16 contiguous bytes (8 channels of one
-// pixel); the backward ReLU mask is applied there, 8 channels at a time.
+// OUT: 0 = bf16 NHWC (32 channels written), 1 = float32 channel 0 only.
+//
+// A wave owns a 64-pixel column strip over a band of `nr` consecutive rows
+// and walks down it with the input rows held in registers: entering output
+// row r it holds input rows r-1, r, r+1 (across a pole: the polar row
+// shifted by NX/2), and once the taps on row r-1 are issued it loads row r+2
+// into that row's registers, so each input pixel is fetched from the caches
+// once per wave rather than once per tap.  A row is held as four
+// 16-pixel fragments in the matrix-core operand layout plus one halo fragment
+// (pixel i0-1 in the lanes of fragment pixel 0, pixel i0+64 in the lanes of
+// fragment pixel 15).  The taps dx = -1 and +1 take the fragments shifted by
+// one pixel across lanes (DPP row shifts within each 16-lane row; the lane
+// that falls off a fragment takes its neighbour fragment's edge pixel
+// through a row rotation, or the halo), so no tap is re-read.
+//
+// The matrix-core product is C[out channel][pixel] = W[out][in] X[in][pixel]:
+// the weights are the A operand (16 output channels x 32 input channels,
+// staged in LDS once per workgroup; each [tap][out channel] row is padded to
+// 40 elements so the 16 lanes reading one 16-byte column hit distinct banks)
+// and the input fragment the B operand, so a lane's result is four
+// consecutive output channels of one pixel.  Accumulation starts from the
+// bias and takes the taps in the order t = 0..8 for every output.  When the taps that read across a pole need
+// other weights than the rest (the adjoint in the backward pass), the two
+// polar rows are computed by launches of their own (`pole_row`) whose staged
+// set takes those taps from `wpole`.  Outputs are stored by conv_store.
 // ---------------------------------------------------------------------------
+constexpr int CONV_NR = 16;             // rows per wave: a band of one 64-pixel column strip
 constexpr int WROW = CH + 8;
-constexpr int CONV_SPW = 4;              // strip groups per workgroup
 constexpr int OROW = CH + 8;             // padded pixel row of the output tile
-constexpr int SPX = 64 + 2;              // staged pixels per row: the strip and one on each side
+
+// DPP controls (16-lane rows): dst[i] = src[i-1] / src[i+1] within the row
+// (the lane beyond the row keeps the `old` operand), and rotations by one
+// lane either way
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHL1 = 0x101, DPP_ROW_ROR1 = 0x121, DPP_ROW_ROR15 = 0x12F;
+
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+template <int CTRL>
+__device__ __forceinline__ bf16x8 dpp_upd(bf16x8 old, bf16x8 src) {
+  const u32x4 o = __builtin_bit_cast(u32x4, old), s = __builtin_bit_cast(u32x4, src);
+  u32x4 r;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r[k] = (unsigned)__builtin_amdgcn_update_dpp((int)o[k], (int)s[k], CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(bf16x8, r);
+}
+
+template <int CTRL>
+__device__ __forceinline__ bf16x8 dpp_mov(bf16x8 src) {
+  const u32x4 s = __builtin_bit_cast(u32x4, src);
+  u32x4 r;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r[k] = (unsigned)__builtin_amdgcn_mov_dpp((int)s[k], CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(bf16x8, r);
+}
+
+struct ConvRow {
+  bf16x8 v[4];   // pixels i0 + 16b + (lane % 16), channels 8*(lane/16) .. +7
+  bf16x8 h;      // halo: pixel i0-1 in lanes with lane % 16 == 0, i0+64 with lane % 16 == 15
+};
+
+// fragment f of a row shifted by dx pixels: lane (m, k) = pixel 16f + m + dx
+template <int DX>
+__device__ __forceinline__ bf16x8 conv_shift(const ConvRow& x, int f) {
+  if constexpr (DX == 0) return x.v[f];
+  else if constexpr (DX < 0) return dpp_upd<DPP_ROW_SHR1>(f == 0 ? x.h : dpp_mov<DPP_ROW_ROR1>(x.v[f - 1]), x.v[f]);
+  else return dpp_upd<DPP_ROW_SHL1>(f == 3 ? x.h : dpp_mov<DPP_ROW_ROR15>(x.v[f + 1]), x.v[f]);
+}
 
 // CIN: channels stored per input pixel (8 for the first layer's packed input,
 // whose channels beyond are zero and not stored; else CH).
-template <int NT, int OUT, int CIN>
-__global__ __launch_bounds__(256) void k_conv(ConvArgs A) {
-  __shared__ __attribute__((aligned(16))) __bf16 sw[TAPS * CH * WROW];
-  __shared__ __attribute__((aligned(16))) __bf16 so[WG_WAVES][16 * OROW];
-  __shared__ __attribute__((aligned(16))) __bf16 si[WG_WAVES][3 * SPX * CIN];   // [row][pixel][channel]
+// stores a wave's output row strip.  acc[n][f]: lane holds output channels
+// 16n + 4*(lane/16) .. +3 of pixel 16f + lane%16 (bias included); prow: the
+// strip's first pixel.  OUT == 1: float32 channel 0; else bf16 NHWC through
+// the wave's LDS tile (8-byte writes of four channels, 16-byte reads and
+// stores of eight), with ReLU (forward hidden layers) or the mask mk (the
+// tile reads' pixels 16u + lane/4, channels 8*(lane%4) .. +7).  The stores
+// are nontemporal: a layer's output is read back by the next layer's pass
+// over the whole batch, far beyond what the caches hold, and streaming
+// stores measured 8% faster per forward pass.
+template <int NT, int OUT, bool MASK>
+__device__ __forceinline__ void conv_store(const ConvArgs& A, const f32x4 (&acc)[NT][4], __bf16* tile, long long prow,
+                                           int lane, const bf16x8* mk) {
+  static_assert(OUT == 1 || NT == 2, "bf16 outputs carry 32 channels");
+  constexpr bool RELU = OUT == 0 && !MASK;
+  const int ml = lane & 15;
+  if constexpr (OUT == 1) {
+    if (lane < 16) {
+#pragma unroll
+      for (int f = 0; f < 4; ++f) __builtin_nontemporal_store(acc[0][f][0], A.out32 + prow + 16 * f + ml);
+    }
+  } else {
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+      const int c0 = 16 * n + 4 * (lane >> 4);
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        bf16x4 o;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float v = acc[n][f][q];
+          if (RELU) v = fmaxf(v, 0.f);
+          o[q] = (__bf16)v;
+        }
+        *(bf16x4*)&tile[(16 * f + ml) * OROW + c0] = o;
+      }
+    }
+    wave_sync_lds();
+    const int c8 = 8 * (lane & 3);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int px = 16 * u + (lane >> 2);
+      bf16x8 v = *(const bf16x8*)&tile[px * OROW + c8];
+      if constexpr (MASK) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          if (!((float)mk[u][c] > 0.f)) v[c] = (__bf16)0.f;
+      }
+      __builtin_nontemporal_store(v, (bf16x8*)(A.out + (prow + px) * CH + c8));
+    }
+    wave_sync_lds();   // the tile is rewritten by the next row's epilogue
+  }
+}
+
+// MASK: the output is multiplied by (mask > 0) (A.mask: the backward pass's
+// input gradients).  ReLU follows the hidden layers of the forward pass
+// (bf16 output without a mask) and no other convolution.
+template <int NT, int OUT, int CIN, bool MASK>
+__global__ __launch_bounds__(256, 3) void k_conv(ConvArgs A) {
+  __shared__ __attribute__((aligned(16))) __bf16 sw[TAPS * NT * 16 * WROW];
+  __shared__ __attribute__((aligned(16))) __bf16 so[OUT == 0 ? WG_WAVES : 1][OUT == 0 ? 64 * OROW : 8];
   if (A.active && !A.active[blockIdx.y]) return;   // the whole workgroup: one image
   const int tid = threadIdx.x;
-  const int npix = A.nx * A.ny;
-  const int spr = A.nx >> 6;                       // 64-pixel strips per row
-  const long long s_first = (long long)A.row_begin * spr + (long long)blockIdx.x * CONV_SPW * WG_WAVES;
-  const long long s_end = (long long)A.row_end * spr;
-  // stage the weights, 16 bytes a thread; in a polar-row launch the taps that
-  // read across the pole come from the across-pole set
-  for (int k = tid; k < TAPS * CH * 4; k += 256) {
-    const int row = k >> 2, q = 8 * (k & 3);
-    const int dy = (row >> 5) / 3 - 1;             // row = tap * CH + out channel
+  // stage the weights of the NT*16 output channels, 16 bytes a thread; in a
+  // polar-row launch the taps that read across the pole come from the
+  // across-pole set
+  for (int k = tid; k < TAPS * NT * 16 * 4; k += 256) {
+    const int row = k >> 2, q = 8 * (k & 3);       // row = tap * (NT*16) + out channel
+    const int t = row / (NT * 16), co = row - t * (NT * 16);
+    const int dy = t / 3 - 1;
     const bool across = A.pole_row >= 0 && ((dy < 0 && A.pole_row == 0) || (dy > 0 && A.pole_row == A.ny - 1));
-    *(bf16x8*)&sw[row * WROW + q] = ld8((across ? A.wpole : A.w) + row * CH + q);
+    *(bf16x8*)&sw[row * WROW + q] = ld8((across ? A.wpole : A.w) + (t * CH + co) * CH + q);
   }
   __syncthreads();
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int spr = A.nx >> 6;                       // 64-pixel strips per row
+  const int w = blockIdx.x * WG_WAVES + wave;      // wave within the image: strip w % spr, band w / spr
+  const int r0 = A.row_begin + (w / spr) * A.nr;
+  if (r0 >= A.row_end) return;
+  const int r1 = min(r0 + A.nr, A.row_end);
+  const int i0 = (w % spr) * 64;
   const int b = blockIdx.y;
+  const long long npix = (long long)A.nx * A.ny;
   const __bf16* img = A.in + (long long)b * npix * CIN;
-  const int kq = 8 * (lane >> 4);          // channel block of this lane (A and B operands)
+  const int kq = 8 * (lane >> 4);          // channel block of this lane (B operand)
   const bool kin = CIN == CH || kq < CIN;  // this lane's input channels are stored
   const int ml = lane & 15;
-  __bf16* tile = so[wave];
-  __bf16* stage = si[wave];
-  constexpr int CPP = CIN / 8;             // 16-byte chunks per staged pixel
-  constexpr int NCH = 3 * SPX * CPP, NLD = (NCH + 63) / 64;
-  // the staged input of a strip: rows j-1 .. j+1, pixels i0-1 .. i0+64; the
-  // loads of the next strip are issued before the current strip's MFMAs and
-  // written to the tile after them (one tile per wave, two syncs per strip)
-  bf16x8 buf[NLD];
-  auto fetch = [&](long long strip) {
-    const int p0 = (int)(strip * 64);
-    const int j = p0 >> A.log2nx, i0 = p0 & (A.nx - 1);
-#pragma unroll
-    for (int u = 0; u < NLD; ++u) {
-      const int c = lane + 64 * u;
-      if (c < NCH) {
-        const int r = c / (SPX * CPP), rem = c - r * (SPX * CPP);
-        const int px = rem / CPP, q = rem - px * CPP;
-        int jj, ii;
-        bool ghost;
-        sphere_src(j, i0 - 1 + px, r - 1, 0, A.nx, A.ny, jj, ii, ghost);
-        buf[u] = ld8(img + ((long long)jj * A.nx + ii) * CIN + 8 * q);
-      }
+  const int hx = ml == 0 ? i0 - 1 : (ml == 15 ? i0 + 64 : i0 + ml);   // halo pixel of this lane
+  auto load_row = [&](int rr, ConvRow& x) {
+    int jj = rr, sh = 0;
+    if (rr < 0) {
+      jj = 0;
+      sh = A.nx >> 1;
+    } else if (rr >= A.ny) {
+      jj = A.ny - 1;
+      sh = A.nx >> 1;
     }
-  };
-  auto put = [&]() {
-    wave_sync_lds();   // the previous strip's reads of the tile come first
+    const __bf16* row = img + (long long)jj * A.nx * CIN + kq;
 #pragma unroll
-    for (int u = 0; u < NLD; ++u) {
-      const int c = lane + 64 * u;
-      if (c < NCH) *(bf16x8*)&stage[c * 8] = buf[u];   // chunk c = (row, pixel, 16-byte channel block)
-    }
-    wave_sync_lds();
+    for (int f = 0; f < 4; ++f)
+      x.v[f] = kin ? ld8(row + ((i0 + 16 * f + ml + sh) & (A.nx - 1)) * CIN) : bf16x8{};
+    x.h = kin ? ld8(row + ((hx + sh) & (A.nx - 1)) * CIN) : bf16x8{};
   };
-  if (s_first + wave < s_end) {
-    fetch(s_first + wave);
-    put();
+  __bf16* tile = so[OUT == 0 ? wave : 0];
+  // this lane's biases: output channels 16n + 4*(lane/16) .. +3 (OUT == 1: channel 0)
+  float bias[NT][4];
+#pragma unroll
+  for (int n = 0; n < NT; ++n)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int co = OUT == 1 ? 0 : 16 * n + 4 * (lane >> 4) + q;
+      bias[n][q] = A.bias ? A.bias[co] : 0.f;
+    }
+  const int c8 = 8 * (lane & 3);   // output tile reads: pixels 16u + lane/4, channels c8 .. c8+7
+  // output row r from input rows xs (r-1), xc (r), xn (r+1); once the taps
+  // of xs are issued, xs receives row `next` (when `load`)
+  auto compute = [&](int r, ConvRow& xs, const ConvRow& xc, const ConvRow& xn, int next, bool load) {
+    f32x4 acc[NT][4];   // the bias, then taps t = 0..8
+#pragma unroll
+    for (int n = 0; n < NT; ++n)
+#pragma unroll
+      for (int f = 0; f < 4; ++f) acc[n][f] = f32x4{bias[n][0], bias[n][1], bias[n][2], bias[n][3]};
+    const long long prow = (long long)b * npix + (long long)r * A.nx + i0;   // first pixel of the strip
+    // the mask of the row's outputs, loaded ahead of the next row's loads so
+    // that waiting for it does not wait for those
+    bf16x8 mk[MASK ? 4 : 1];
+    if constexpr (MASK) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) mk[u] = ld8(A.mask + (prow + 16 * u + (lane >> 2)) * CH + c8);
+    }
+    auto taps = [&](auto DY, const ConvRow& x) {
+      constexpr int dy = decltype(DY)::value;
+      auto tap = [&](auto DX) {
+        constexpr int dx = decltype(DX)::value;
+        constexpr int t = (dy + 1) * 3 + (dx + 1);
+        bf16x8 wf[NT];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) wf[n] = *(const bf16x8*)&sw[(t * NT * 16 + 16 * n + ml) * WROW + kq];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          const bf16x8 fr = conv_shift<dx>(x, f);
+#pragma unroll
+          for (int n = 0; n < NT; ++n) acc[n][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[n], fr, acc[n][f], 0, 0, 0);
+        }
+      };
+      tap(std::integral_constant<int, -1>{});
+      tap(std::integral_constant<int, 0>{});
+      tap(std::integral_constant<int, 1>{});
+    };
+    taps(std::integral_constant<int, -1>{}, xs);
+    if (load) load_row(next, xs);
+    taps(std::integral_constant<int, 0>{}, xc);
+    taps(std::integral_constant<int, 1>{}, xn);
+    conv_store<NT, OUT, MASK>(A, acc, tile, prow, lane, mk);
+  };
+  // three row buffers in rotation: output row r reads (r-1, r, r+1), and the
+  // buffer of row r-1 receives row r+2 once row r's taps on it are issued
+  ConvRow x0, x1, x2;
+  load_row(r0 - 1, x0);
+  load_row(r0, x1);
+  load_row(r0 + 1, x2);
+#pragma unroll 1
+  for (int r = r0; r < r1; r += 3) {
+    compute(r, x0, x1, x2, r + 2, r + 1 < r1);
+    if (r + 1 >= r1) break;
+    compute(r + 1, x1, x2, x0, r + 3, r + 2 < r1);
+    if (r + 2 >= r1) break;
+    compute(r + 2, x2, x0, x1, r + 4, r + 3 < r1);
   }
-#pragma unroll 1
-  for (int g = 0; g < CONV_SPW; ++g) {
-    const long long strip = s_first + g * WG_WAVES + wave;
-    if (strip >= s_end) break;
-    const int p0 = (int)(strip * 64);
-    const long long next = strip + WG_WAVES;
-    const bool more = g + 1 < CONV_SPW && next < s_end;
-    if (more) fetch(next);
-#pragma unroll 1
-    for (int mt = 0; mt < CONV_MT; mt += 2) {
-      bf16x8 a[2][TAPS];
+}
+
+// The first layer's packed input stores 8 channels per pixel, so four taps
+// share one K = 32 matrix-core step: lane row s (lanes 16s .. 16s+15) of the
+// input operand holds tap t = 4g + s of tap group g (t = 9..11 are zero),
+// loaded directly at the tap's source pixel, and the staged weights hold
+// W[4g+s][out][0..7] at k = 8s .. 8s+7.  Three groups replace nine taps, and
+// no operand is shifted across lanes.  A wave walks down its column strip as
+// in k_conv, loading row r+1's operands while row r is computed.  Forward
+// only (one weight set).
+constexpr int TGROUPS = 3;
+
+__global__ __launch_bounds__(256, 2) void k_conv_in8(ConvArgs A) {
+  constexpr int CIN = 8;
+  __shared__ __attribute__((aligned(16))) __bf16 sw[TGROUPS * CH * WROW];
+  __shared__ __attribute__((aligned(16))) __bf16 so[WG_WAVES][64 * OROW];
+  if (A.active && !A.active[blockIdx.y]) return;   // the whole workgroup: one image
+  const int tid = threadIdx.x;
+  for (int k = tid; k < TGROUPS * CH * 4; k += 256) {
+    const int row = k >> 2, sl = k & 3;            // row = group * CH + out channel, sl = tap slot
+    const int g = row / CH, co = row - g * CH, t = 4 * g + sl;
+    *(bf16x8*)&sw[row * WROW + 8 * sl] = t < TAPS ? ld8(A.w + (t * CH + co) * CH) : bf16x8{};
+  }
+  __syncthreads();
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int spr = A.nx >> 6;
+  const int w = blockIdx.x * WG_WAVES + wave;      // wave within the image: strip w % spr, band w / spr
+  const int r0 = A.row_begin + (w / spr) * A.nr;
+  if (r0 >= A.row_end) return;
+  const int r1 = min(r0 + A.nr, A.row_end);
+  const int i0 = (w % spr) * 64;
+  const int b = blockIdx.y;
+  const long long npix = (long long)A.nx * A.ny;
+  const __bf16* img = A.in + (long long)b * npix * CIN;
+  const int sl = lane >> 4, ml = lane & 15;
+  __bf16* tile = so[wave];
+  float bias[2][4];
 #pragma unroll
-      for (int t = 0; t < TAPS; ++t) {
-        const int dy = t / 3 - 1, dx = t % 3 - 1;
+  for (int n = 0; n < 2; ++n)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int px = 16 * (mt + h) + ml + dx + 1;
-          a[h][t] = kin ? *(const bf16x8*)&stage[((dy + 1) * SPX + px) * CIN + kq] : bf16x8{};
-        }
+    for (int q = 0; q < 4; ++q) bias[n][q] = A.bias ? A.bias[16 * n + 4 * sl + q] : 0.f;
+  // operands of output row r: x[g][f] = tap 4g + sl at pixels 16f + ml of the strip
+  auto load = [&](int r, bf16x8 (&x)[TGROUPS][4]) {
+#pragma unroll
+    for (int g = 0; g < TGROUPS; ++g) {
+      const int t = 4 * g + sl;
+      const int dy = t / 3 - 1, dx = t % 3 - 1;
+      int jj = r + dy, sh = 0;
+      if (jj < 0) {
+        jj = 0;
+        sh = A.nx >> 1;
+      } else if (jj >= A.ny) {
+        jj = A.ny - 1;
+        sh = A.nx >> 1;
       }
-      f32x4 acc[2][NT];
+      const __bf16* row = img + (long long)jj * A.nx * CIN;
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int n = 0; n < NT; ++n) acc[h][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int t = 0; t < TAPS; ++t) {
-#pragma unroll
-        for (int n = 0; n < NT; ++n) {
-          const bf16x8 bw = *(const bf16x8*)&sw[(t * CH + 16 * n + ml) * WROW + kq];
-#pragma unroll
-          for (int h = 0; h < 2; ++h)
-            acc[h][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[h][t], bw, acc[h][n], 0, 0, 0);
-        }
-      }
-      // epilogue: lane holds output channel co = 16n + ml of pixels 4*(lane/16) .. +3 of each tile
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const long long pt = (long long)b * npix + p0 + 16 * (mt + h);   // first pixel of the tile
-        if (OUT == 1) {
-          if (ml == 0) {
-            const float bias = A.bias ? A.bias[0] : 0.f;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              float v = acc[h][0][r] + bias;
-              if (A.relu) v = fmaxf(v, 0.f);
-              A.out32[pt + 4 * (lane >> 4) + r] = v;
-            }
-          }
-        } else {
-#pragma unroll
-          for (int n = 0; n < NT; ++n) {
-            const int co = 16 * n + ml;
-            const float bias = A.bias ? A.bias[co] : 0.f;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              float v = acc[h][n][r] + bias;
-              if (A.relu) v = fmaxf(v, 0.f);
-              tile[(4 * (lane >> 4) + r) * OROW + co] = (__bf16)v;
-            }
-          }
-          if (NT == 1) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) tile[(4 * (lane >> 4) + r) * OROW + 16 + ml] = (__bf16)0.f;
-          }
-          wave_sync_lds();
-          // lane: pixel lane/4 of the tile, channels 8*(lane%4) .. +7
-          const int px = lane >> 2, c8 = 8 * (lane & 3);
-          bf16x8 v = *(const bf16x8*)&tile[px * OROW + c8];
-          const long long o = (pt + px) * CH + c8;
-          if (A.mask) {
-            const bf16x8 mk = ld8(A.mask + o);
-#pragma unroll
-            for (int c = 0; c < 8; ++c)
-              if (!((float)mk[c] > 0.f)) v[c] = (__bf16)0.f;
-          }
-          *(bf16x8*)(A.out + o) = v;
-          wave_sync_lds();   // the tile is rewritten by the next tile's epilogue
-        }
-      }
+      for (int f = 0; f < 4; ++f)
+        x[g][f] = t < TAPS ? ld8(row + ((i0 + 16 * f + ml + dx + sh) & (A.nx - 1)) * CIN) : bf16x8{};
     }
-    if (more) put();
+  };
+  auto compute = [&](int r, const bf16x8 (&x)[TGROUPS][4]) {
+    f32x4 acc[2][4];   // the bias, then tap groups 0..2
+#pragma unroll
+    for (int n = 0; n < 2; ++n)
+#pragma unroll
+      for (int f = 0; f < 4; ++f) acc[n][f] = f32x4{bias[n][0], bias[n][1], bias[n][2], bias[n][3]};
+#pragma unroll
+    for (int g = 0; g < TGROUPS; ++g) {
+      bf16x8 wf[2];
+#pragma unroll
+      for (int n = 0; n < 2; ++n) wf[n] = *(const bf16x8*)&sw[(g * CH + 16 * n + ml) * WROW + 8 * sl];
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) acc[n][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[n], x[g][f], acc[n][f], 0, 0, 0);
+    }
+    const long long prow = (long long)b * npix + (long long)r * A.nx + i0;
+    conv_store<2, 0, false>(A, acc, tile, prow, lane, nullptr);
+  };
+  bf16x8 xa[TGROUPS][4], xb[TGROUPS][4];
+  load(r0, xa);
+#pragma unroll 1
+  for (int r = r0; r < r1; r += 2) {
+    if (r + 1 < r1) load(r + 1, xb);
+    compute(r, xa);
+    if (r + 1 >= r1) break;
+    if (r + 2 < r1) load(r + 2, xa);
+    compute(r + 1, xb);
   }
 }
 

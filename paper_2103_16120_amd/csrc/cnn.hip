@@ -312,36 +312,42 @@ static ConvArgs conv_args(const cnn_net* n, int batch) {
   A.row_begin = 0;
   A.row_end = n->ny;
   A.pole_row = -1;
+  A.nr = CONV_NR;
   return A;
 }
 
-static dim3 conv_grid(const cnn_net* n, int batch, int rows) {
-  const long long strips = (long long)(n->nx / 64) * rows;
-  const long long per_wg = (long long)WG_WAVES * CONV_SPW;
-  return dim3((unsigned)((strips + per_wg - 1) / per_wg), batch);
+static dim3 conv_grid(const cnn_net* n, int batch, int rows, int nr) {
+  const long long waves = (long long)(n->nx / 64) * ((rows + nr - 1) / nr);
+  return dim3((unsigned)((waves + WG_WAVES - 1) / WG_WAVES), batch);
 }
 
 // A over all rows; when the across-pole taps need their own weights
 // (A.wpole != A.w), the interior rows and each polar row are separate launches
-template <int NT, int OUT, int CIN = CH>
-static void launch_conv(const cnn_net* n, int batch, ConvArgs A, hipStream_t st) {
+template <int NT, int OUT, int CIN, bool MASK>
+static void launch_conv_m(const cnn_net* n, int batch, ConvArgs A, hipStream_t st) {
   if (A.wpole == A.w) {
-    hipLaunchKernelGGL((k_conv<NT, OUT, CIN>), conv_grid(n, batch, n->ny), dim3(256), 0, st, A);
+    hipLaunchKernelGGL((k_conv<NT, OUT, CIN, MASK>), conv_grid(n, batch, n->ny, A.nr), dim3(256), 0, st, A);
     return;
   }
   if (n->ny > 2) {
     ConvArgs I = A;
     I.row_begin = 1;
     I.row_end = n->ny - 1;
-    hipLaunchKernelGGL((k_conv<NT, OUT, CIN>), conv_grid(n, batch, n->ny - 2), dim3(256), 0, st, I);
+    hipLaunchKernelGGL((k_conv<NT, OUT, CIN, MASK>), conv_grid(n, batch, n->ny - 2, I.nr), dim3(256), 0, st, I);
   }
   for (int pr : {0, n->ny - 1}) {
     ConvArgs P = A;
     P.row_begin = pr;
     P.row_end = pr + 1;
     P.pole_row = pr;
-    hipLaunchKernelGGL((k_conv<NT, OUT, CIN>), conv_grid(n, batch, 1), dim3(256), 0, st, P);
+    hipLaunchKernelGGL((k_conv<NT, OUT, CIN, MASK>), conv_grid(n, batch, 1, P.nr), dim3(256), 0, st, P);
   }
+}
+
+// the forward layers (no mask)
+template <int NT, int OUT, int CIN = CH>
+static void launch_conv(const cnn_net* n, int batch, ConvArgs A, hipStream_t st) {
+  launch_conv_m<NT, OUT, CIN, false>(n, batch, A, st);
 }
 
 // forward from act[0] (already packed) to y (float32 [B][npix])
@@ -355,12 +361,12 @@ int cnn_forward_packed(cnn_net* n, int batch, float* y, hipStream_t st, const in
     A.bias = n->bias + l * CH;
     if (l < CNN_LAYERS - 1) {
       A.out = n->act[l + 1];
-      A.relu = 1;
-      if (l == 0 && n->in_stride == 8) launch_conv<2, 0, 8>(n, batch, A, st);
-      else launch_conv<2, 0>(n, batch, A, st);
+      if (l == 0 && n->in_stride == 8)
+        hipLaunchKernelGGL(k_conv_in8, conv_grid(n, batch, n->ny, A.nr), dim3(256), 0, st, A);
+      else
+        launch_conv<2, 0>(n, batch, A, st);
     } else {
       A.out32 = y;
-      A.relu = 0;
       launch_conv<1, 1>(n, batch, A, st);
     }
   }
@@ -432,8 +438,7 @@ static int backward(cnn_net* n, int batch, const float* dyv) {
     A.bias = nullptr;
     A.out = n->dbuf[cur ^ 1];
     A.mask = n->act[l];
-    A.relu = 0;
-    launch_conv<2, 0>(n, batch, A, n->stream);
+    launch_conv_m<2, 0, CH, true>(n, batch, A, n->stream);
     cur ^= 1;
   }
   CHK(n, hipGetLastError());
