@@ -148,8 +148,9 @@ struct RowIO<float> {
   static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
   }
+  template <int AUX>
   static __device__ __forceinline__ void st(float v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, AUX);
   }
 };
 template <>
@@ -158,8 +159,9 @@ struct RowIO<double> {
   static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
   }
+  template <int AUX>
   static __device__ __forceinline__ void st(double v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B, v), r, vo, so, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B, v), r, vo, so, AUX);
   }
 };
 template <>
@@ -167,8 +169,9 @@ struct RowIO<__half> {
   static __device__ __forceinline__ __half ld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
     return __builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0));
   }
+  template <int AUX>
   static __device__ __forceinline__ void st(__half v, __amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, vo, so, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, vo, so, AUX);
   }
 };
 
@@ -192,12 +195,22 @@ __device__ __forceinline__ void ldr(const S* row, int l, int L, T (&v)[M]) {
 #pragma unroll
   for (int k = 0; k < M; ++k) v[k] = from_store<S, T>(RowIO<S>::ld(r, vo, (unsigned)(k * L) * sizeof(S)));
 }
+// Row stores are nontemporal (cache policy bit NT) where the rows stream
+// through HBM rather than stay in the 256 MB memory-side cache: float64 rows,
+// and every row of 1024-point rows (16 points per lane).  Measured on the
+// float64 form at 64 x 512x256 (+4%) and at 64 x 1024x512 (+2% in both forms);
+// for float32 and float16 rows of the 512-point class, which the next kernel
+// reads back from that cache, they measured no gain.
+template <int M, int BYTES>
+constexpr int row_store_aux() { return (BYTES == 8 || M >= 16) ? 2 : 0; }
+
 template <int M, typename S, typename T>
 __device__ __forceinline__ void str(S* row, int l, int L, const T (&v)[M]) {
   const __amdgpu_buffer_rsrc_t r = row_rsrc(row, (unsigned)(M * L) * sizeof(S));
   const unsigned vo = (unsigned)l * sizeof(S);
 #pragma unroll
-  for (int k = 0; k < M; ++k) RowIO<S>::st(to_store<S, T>(v[k]), r, vo, (unsigned)(k * L) * sizeof(S));
+  for (int k = 0; k < M; ++k)
+    RowIO<S>::template st<row_store_aux<M, (int)sizeof(S)>()>(to_store<S, T>(v[k]), r, vo, (unsigned)(k * L) * sizeof(S));
 }
 
 // float16 rows pair their elements: (k, k+1) of lane l (k even) share the
@@ -226,7 +239,7 @@ __device__ __forceinline__ void str(__half* row, int l, int L, const T (&v)[M]) 
   for (int j = 0; j < M / 2; ++j) {
     const unsigned lo16 = __builtin_bit_cast(unsigned short, __float2half_rn((float)v[2 * j]));
     const unsigned hi16 = __builtin_bit_cast(unsigned short, __float2half_rn((float)v[2 * j + 1]));
-    __builtin_amdgcn_raw_buffer_store_b32(lo16 | (hi16 << 16), r, vo, (unsigned)(j * L) * 4u, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(lo16 | (hi16 << 16), r, vo, (unsigned)(j * L) * 4u, row_store_aux<M, 2>());
   }
 }
 
