@@ -98,6 +98,10 @@ constexpr int SI_BAND = 4;
          once_; once_ = 0)
 
 // the latitude table of every member
+// Field stores are nontemporal: a step's work fields (20 float64 fields per
+// point over the batch) stream through HBM, far beyond the memory-side cache.
+__device__ __forceinline__ void nts(double* p, double v) { __builtin_nontemporal_store(v, p); }
+
 __global__ void k_si_lat(SiArgs A) {
   const SiMember M = A.tab[blockIdx.y];
   double* t = wf(A, M, W_LAT);
@@ -161,18 +165,18 @@ __global__ void k_si_prepare(SiArgs A) {
       const double qbx = M.qbx ? M.qbx[k] : 0.0, qby = M.qby ? M.qby[k] : 0.0;
       const double rx = -M.g / (a * cs) * ph * hx + f * qy + t * qx * qy / (a * ph) - al * (qx - qbx);
       const double ry = -M.g / a * ph * hy - f * qx - t * qx * qx / (a * ph) - al * (qy - qby);
-      qtx[k] = qx + d * rx;
-      qty[k] = qy + d * ry;
+      nts(qtx + k, qx + d * rx);
+      nts(qty + k, qy + d * ry);
       // Courant numbers at the east face and the north face j + 1/2 (zero at the north pole)
       double vxe, vye;
       vext(j, i_ + 1, vxe, vye);
-      ocx[k] = 0.5 * (vx + vxe) * M.dt / dlam;
+      nts(ocx + k, 0.5 * (vx + vxe) * M.dt / dlam);
       double cyn = 0.0, vxn = 0.0, vyn = 0.0;
       if (j < ny - 1) {
         vext(j + 1, i_, vxn, vyn);
         cyn = 0.5 * (vy + vyn) * M.dt / dphi;
       }
-      ocy[k] = cyn;
+      nts(ocy + k, cyn);
       hs_m = hs_c;
       hs_c = hs_n;
       vx = vxn;
@@ -237,7 +241,7 @@ __global__ void k_si_upwind(SiArgs A, UpwindSet U) {
         const double fw = flux(cw, psi[f][row + iw], ps_c[f]);
         const double fn = j < ny - 1 ? flux(cn, ps_c[f], ps_n) : 0.0;
         const double fs = j > 0 ? flux(cs, ps_m[f], ps_c[f]) : 0.0;
-        out[f][k] = ps_c[f] - ((fe - fw) + (fn - fs)) / g;
+        nts(out[f] + k, ps_c[f] - ((fe - fw) + (fn - fs)) / g);
         ps_m[f] = ps_c[f];
         ps_c[f] = ps_n;
         if (!SHARED || f == 0) cy_s[f] = cn;
@@ -314,7 +318,7 @@ __global__ void k_si_antidiff(SiArgs A) {
         const double num = (u[2][2] + u[2][1]) - (u[0][2] + u[0][1]);
         const double den = (u[2][2] + u[2][1]) + (u[0][2] + u[0][1]);
         const double bxr = 0.5 * num / (den + tiny);
-        ox[fdx][k] = (fabs(c) - c * c / gx) * axr - c * cyb / gx * bxr;
+        nts(ox[fdx] + k, (fabs(c) - c * c / gx) * axr - c * cyb / gx * bxr);
         // north face (interior faces only)
         double ay = 0.0;
         if (j < ny - 1) {
@@ -325,7 +329,7 @@ __global__ void k_si_antidiff(SiArgs A) {
           const double byr = 0.5 * nm / (dn + tiny);
           ay = (fabs(cyn) - cyn * cyn / gy) * ayr - cyn * cxb / gy * byr;
         }
-        oy[fdx][k] = ay;
+        nts(oy[fdx] + k, ay);
       }
       // roll the windows down one row
       for (int fdx = 0; fdx < 3; ++fdx)
@@ -362,9 +366,9 @@ __global__ void k_si_qhh(SiArgs A) {
     const double ps = wf(A, M, W_PHIS)[k];
     const double ex = wf(A, M, W_QHX)[k] + d * (al * qbx + 2.0 * mx - mx0) - d * M.g / (a * cs) * 0.5 * ps * h0x;
     const double ey = wf(A, M, W_QHY)[k] + d * (al * qby + 2.0 * my - my0) - d * M.g / a * 0.5 * ps * h0y;
-    wf(A, M, W_QHHX)[k] = (gam * ex + b * ey) / D;
-    wf(A, M, W_QHHY)[k] = (-b * ex + gam * ey) / D;
-    M.phi1[k] = M.phi[k];
+    nts(wf(A, M, W_QHHX) + k, (gam * ex + b * ey) / D);
+    nts(wf(A, M, W_QHHY) + k, (-b * ex + gam * ey) / D);
+    nts(M.phi1 + k, M.phi[k]);
   }
 }
 
@@ -397,7 +401,7 @@ __global__ void k_si_rhs(SiArgs A) {
       const double fn = j < ny - 1 ? a * cn * 0.5 * (ys_c + ys_n) : 0.0;
       const double fs = j > 0 ? a * csf * 0.5 * (ys_m + ys_c) : 0.0;
       const double C = 2.0 * a * a * lt[LT_N * j + LT_COS] / M.dt;
-      out[k] = (fe - fw) / dlam + (fn - fs) / dphi - C * M.phi[k];
+      nts(out + k, (fe - fw) / dlam + (fn - fs) / dphi - C * M.phi[k]);
       ys_m = ys_c;
       ys_c = ys_n;
     }
@@ -434,8 +438,8 @@ __global__ void k_si_recover(SiArgs A) {
       const double hy = (hs_n - hs_m) / (2.0 * dphi);
       const double ux = -d * M.g / (a * cs) * 0.5 * (p1_c * hx + ps[k] * px);
       const double uy = -d * M.g / a * 0.5 * (p1_c * hy + ps[k] * py);
-      qx1[k] = wf(A, M, W_QHHX)[k] + (gam * ux + b * uy) / D;
-      qy1[k] = wf(A, M, W_QHHY)[k] + (-b * ux + gam * uy) / D;
+      nts(qx1 + k, wf(A, M, W_QHHX)[k] + (gam * ux + b * uy) / D);
+      nts(qy1 + k, wf(A, M, W_QHHY)[k] + (-b * ux + gam * uy) / D);
       p1_m = p1_c;
       p1_c = p1_n;
       hs_m = hs_c;
