@@ -407,6 +407,181 @@ __global__ __launch_bounds__(256, 2) void k_conv_in8(ConvArgs A) {
   }
 }
 
+// The first two layers fused (inference: the first layer's output is not
+// kept).  A wave walks down its column strip as in k_conv; entering output
+// row r of the second layer it holds the first layer's outputs for rows r-1
+// and r in registers and computes row r+1 of them in between: the first
+// layer's taps are packed four to a K = 32 step as in k_conv_in8, for the
+// strip's four 16-pixel fragments and a fifth whose lanes 0 and 15 of each
+// lane row compute pixels i0-1 and i0+64 -- the halo the second layer's dx
+// taps need, computed rather than fetched.  The first layer's result lane
+// (pixel m, lane row g) holds its output channels 4g..4g+3 and 16+4g..16+4g+3,
+// which is the second layer's input operand once the second layer's weights
+// take their input channels in that order (k = 8g + j -> channel 4g + j for
+// j < 4, 16 + 4g + j - 4 else).  Beyond a pole the first layer's output row is
+// its polar row seen across the pole: the polar row computed at columns
+// shifted by NX/2.  The intermediate activation never leaves the chip: the
+// pass reads the packed input (16 B a pixel) and writes the second layer's
+// output (64 B), against 16 + 64 + 64 + 64 B for the two layers apart.
+__global__ __launch_bounds__(256, 2) void k_conv12(ConvArgs A, const __bf16* w2, const float* bias2) {
+  constexpr int CIN = 8;
+  __shared__ __attribute__((aligned(16))) __bf16 sw1[TGROUPS * CH * WROW];
+  __shared__ __attribute__((aligned(16))) __bf16 sw2[TAPS * CH * WROW];
+  __shared__ __attribute__((aligned(16))) __bf16 so[WG_WAVES][64 * OROW];
+  if (A.active && !A.active[blockIdx.y]) return;   // the whole workgroup: one image
+  const int tid = threadIdx.x;
+  for (int k = tid; k < TGROUPS * CH * 4; k += 256) {
+    const int row = k >> 2, sl = k & 3;            // row = group * CH + out channel, sl = tap slot
+    const int g = row / CH, co = row - g * CH, t = 4 * g + sl;
+    *(bf16x8*)&sw1[row * WROW + 8 * sl] = t < TAPS ? ld8(A.w + (t * CH + co) * CH) : bf16x8{};
+  }
+  for (int k = tid; k < TAPS * CH * CH; k += 256) {   // [tap][out][k]: input channel order of the fused operand
+    const int row = k / CH, kk = k - row * CH;        // row = tap * CH + out channel
+    const int g = kk >> 3, j = kk & 7;
+    const int ci = j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4);
+    sw2[row * WROW + kk] = w2[row * CH + ci];
+  }
+  __syncthreads();
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int spr = A.nx >> 6;
+  const int w = blockIdx.x * WG_WAVES + wave;      // wave within the image: strip w % spr, band w / spr
+  const int r0 = A.row_begin + (w / spr) * A.nr;
+  if (r0 >= A.row_end) return;
+  const int r1 = min(r0 + A.nr, A.row_end);
+  const int i0 = (w % spr) * 64;
+  const int b = blockIdx.y;
+  const long long npix = (long long)A.nx * A.ny;
+  const __bf16* img = A.in + (long long)b * npix * CIN;
+  const int sl = lane >> 4, ml = lane & 15;
+  const int hx = ml == 0 ? i0 - 1 : (ml == 15 ? i0 + 64 : i0 + ml);   // halo fragment pixel of this lane
+  __bf16* tile = so[wave];
+  float bias1[2][4], bias2v[2][4];
+#pragma unroll
+  for (int n = 0; n < 2; ++n)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      bias1[n][q] = A.bias ? A.bias[16 * n + 4 * sl + q] : 0.f;
+      bias2v[n][q] = bias2 ? bias2[16 * n + 4 * sl + q] : 0.f;
+    }
+  // first-layer operands of fragment f (4: the halo fragment) of row q, the
+  // columns shifted by cs (NX/2 for a row beyond a pole)
+  auto l1_load = [&](int q, int cs, int f, bf16x8 (&x)[TGROUPS]) {
+    const int px = (f < 4 ? i0 + 16 * f + ml : hx) + cs;
+#pragma unroll
+    for (int g = 0; g < TGROUPS; ++g) {
+      const int t = 4 * g + sl;
+      const int dy = t / 3 - 1, dx = t % 3 - 1;
+      int jj = q + dy, sh = 0;
+      if (jj < 0) {
+        jj = 0;
+        sh = A.nx >> 1;
+      } else if (jj >= A.ny) {
+        jj = A.ny - 1;
+        sh = A.nx >> 1;
+      }
+      x[g] = t < TAPS ? ld8(img + ((long long)jj * A.nx + ((px + dx + sh) & (A.nx - 1))) * CIN) : bf16x8{};
+    }
+  };
+  // the first layer's output row q (q = -1 and ny: across the pole) as the
+  // second layer's input row; l1_start issues the loads of its first
+  // fragment into xa, layer1 computes it
+  auto l1_row = [&](int& q, int& cs) {
+    cs = 0;
+    if (q < 0) {
+      q = 0;
+      cs = A.nx >> 1;
+    } else if (q >= A.ny) {
+      q = A.ny - 1;
+      cs = A.nx >> 1;
+    }
+  };
+  auto l1_start = [&](int q, bf16x8 (&xa)[TGROUPS]) {
+    int cs;
+    l1_row(q, cs);
+    l1_load(q, cs, 0, xa);
+  };
+  auto layer1 = [&](int q, bf16x8 (&xa)[TGROUPS], ConvRow& out) {
+    int cs;
+    l1_row(q, cs);
+    bf16x8 xb[TGROUPS];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      bf16x8 (&x)[TGROUPS] = (f & 1) ? xb : xa;
+      if (f + 1 < 5) l1_load(q, cs, f + 1, (f & 1) ? xa : xb);
+      f32x4 acc[2];
+#pragma unroll
+      for (int n = 0; n < 2; ++n) acc[n] = f32x4{bias1[n][0], bias1[n][1], bias1[n][2], bias1[n][3]};
+#pragma unroll
+      for (int g = 0; g < TGROUPS; ++g)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+          const bf16x8 wf = *(const bf16x8*)&sw1[(g * CH + 16 * n + ml) * WROW + 8 * sl];
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf, x[g], acc[n], 0, 0, 0);
+        }
+      bf16x8 o;
+#pragma unroll
+      for (int n = 0; n < 2; ++n)
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) o[4 * n + qq] = (__bf16)fmaxf(acc[n][qq], 0.f);
+      if (f < 4) out.v[f] = o;
+      else out.h = o;
+    }
+  };
+  // second-layer output row r from first-layer rows xs (r-1) and xc (r);
+  // row r+1 is computed into xn after the taps on xs and xc are issued
+  auto compute = [&](int r, const ConvRow& xs, const ConvRow& xc, ConvRow& xn) {
+    f32x4 acc[2][4];
+#pragma unroll
+    for (int n = 0; n < 2; ++n)
+#pragma unroll
+      for (int f = 0; f < 4; ++f) acc[n][f] = f32x4{bias2v[n][0], bias2v[n][1], bias2v[n][2], bias2v[n][3]};
+    auto taps = [&](auto DY, const ConvRow& x) {
+      constexpr int dy = decltype(DY)::value;
+      auto tap = [&](auto DX) {
+        constexpr int dx = decltype(DX)::value;
+        constexpr int t = (dy + 1) * 3 + (dx + 1);
+        bf16x8 wf[2];
+#pragma unroll
+        for (int n = 0; n < 2; ++n) wf[n] = *(const bf16x8*)&sw2[(t * CH + 16 * n + ml) * WROW + 8 * sl];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          const bf16x8 fr = conv_shift<dx>(x, f);
+#pragma unroll
+          for (int n = 0; n < 2; ++n) acc[n][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[n], fr, acc[n][f], 0, 0, 0);
+        }
+      };
+      tap(std::integral_constant<int, -1>{});
+      tap(std::integral_constant<int, 0>{});
+      tap(std::integral_constant<int, 1>{});
+    };
+    bf16x8 xa[TGROUPS];
+    l1_start(r + 1, xa);
+    taps(std::integral_constant<int, -1>{}, xs);
+    taps(std::integral_constant<int, 0>{}, xc);
+    layer1(r + 1, xa, xn);
+    taps(std::integral_constant<int, 1>{}, xn);
+    const long long prow = (long long)b * npix + (long long)r * A.nx + i0;
+    conv_store<2, 0, false>(A, acc, tile, prow, lane, nullptr);
+  };
+  ConvRow x0, x1, x2;
+  {
+    bf16x8 xa[TGROUPS];
+    l1_start(r0 - 1, xa);
+    layer1(r0 - 1, xa, x0);
+    l1_start(r0, xa);
+    layer1(r0, xa, x1);
+  }
+#pragma unroll 1
+  for (int r = r0; r < r1; r += 3) {
+    compute(r, x0, x1, x2);
+    if (r + 1 >= r1) break;
+    compute(r + 1, x1, x2, x0);
+    if (r + 2 >= r1) break;
+    compute(r + 2, x2, x0, x1);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Weight and bias gradients of a 3x3 convolution:
 //   dW[t][co][ci] = sum_q dpre[q][co] * in[src_t(q)][ci],  db[co] = sum_q dpre[q][co]

@@ -350,8 +350,10 @@ static void launch_conv(const cnn_net* n, int batch, ConvArgs A, hipStream_t st)
   launch_conv_m<NT, OUT, CIN, false>(n, batch, A, st);
 }
 
-// forward from act[0] (already packed) to y (float32 [B][npix])
-int cnn_forward_packed(cnn_net* n, int batch, float* y, hipStream_t st, const int* active) {
+// forward from act[0] (already packed) to y (float32 [B][npix]); `keep`:
+// every activation is written (training); else the first two layers run
+// fused when the input is packed 8 channels a pixel, and act[1] is not written
+int cnn_forward_packed(cnn_net* n, int batch, float* y, hipStream_t st, const int* active, bool keep) {
   for (int l = 0; l < CNN_LAYERS; ++l) {
     ConvArgs A = conv_args(n, batch);
     A.active = active;
@@ -361,10 +363,16 @@ int cnn_forward_packed(cnn_net* n, int batch, float* y, hipStream_t st, const in
     A.bias = n->bias + l * CH;
     if (l < CNN_LAYERS - 1) {
       A.out = n->act[l + 1];
-      if (l == 0 && n->in_stride == 8)
+      if (l == 0 && n->in_stride == 8 && !keep) {
+        A.out = n->act[2];
+        hipLaunchKernelGGL(k_conv12, conv_grid(n, batch, n->ny, A.nr), dim3(256), 0, st, A,
+                           (const __bf16*)(n->wf + (size_t)TAPS * CH * CH), (const float*)(n->bias + CH));
+        ++l;
+      } else if (l == 0 && n->in_stride == 8) {
         hipLaunchKernelGGL(k_conv_in8, conv_grid(n, batch, n->ny, A.nr), dim3(256), 0, st, A);
-      else
+      } else {
         launch_conv<2, 0>(n, batch, A, st);
+      }
     } else {
       A.out32 = y;
       launch_conv<1, 1>(n, batch, A, st);
@@ -387,7 +395,15 @@ extern "C" int cnn_forward(cnn_net* n, int32_t batch, const float* in, float* ou
   const long long npix = (long long)n->nx * n->ny;
   hipLaunchKernelGGL(k_pack_input, dim3((unsigned)((npix * batch + 255) / 256)), dim3(256), 0, n->stream, in,
                      n->act[0], n->c_in, npix, batch, n->in_stride);
-  return cnn_forward_packed(n, batch, out, n->stream);
+  return cnn_forward_packed(n, batch, out, n->stream, nullptr, false);
+}
+
+// the forward pass of training: every activation kept for the backward pass
+static int forward_keep(cnn_net* n, int batch, const float* in, float* out) {
+  const long long npix = (long long)n->nx * n->ny;
+  hipLaunchKernelGGL(k_pack_input, dim3((unsigned)((npix * batch + 255) / 256)), dim3(256), 0, n->stream, in,
+                     n->act[0], n->c_in, npix, batch, n->in_stride);
+  return cnn_forward_packed(n, batch, out, n->stream, nullptr, true);
 }
 
 // gradients of sum(dyv * net) w.r.t. all parameters into n->grads (reference layout)
@@ -449,7 +465,7 @@ extern "C" int cnn_gradients(cnn_net* n, int32_t batch, const float* in, const f
   int rc = check_batch(n, batch);
   if (rc != GCR_OK) return rc;
   if (!in || !dy || !grads_host) return cfail(n, GCR_EINVAL, "NULL tensor");
-  if ((rc = cnn_forward(n, batch, in, n->y)) != GCR_OK) return rc;
+  if ((rc = forward_keep(n, batch, in, n->y)) != GCR_OK) return rc;
   if ((rc = backward(n, batch, dy)) != GCR_OK) return rc;
   CHK(n, hipMemcpyAsync(grads_host, n->grads, n->nparams * sizeof(float), hipMemcpyDeviceToHost, n->stream));
   CHK(n, hipStreamSynchronize(n->stream));
@@ -462,7 +478,7 @@ extern "C" int cnn_train_step(cnn_net* n, int32_t batch, const float* in, const 
   if (rc != GCR_OK) return rc;
   if (!in || !target) return cfail(n, GCR_EINVAL, "NULL tensor");
   if (!(lr > 0.f) || !std::isfinite(lr)) return cfail(n, GCR_EINVAL, "lr must be finite and > 0");
-  if ((rc = cnn_forward(n, batch, in, n->y)) != GCR_OK) return rc;
+  if ((rc = forward_keep(n, batch, in, n->y)) != GCR_OK) return rc;
   const long long tot = (long long)n->nx * n->ny * batch;
   const int lb = 256;
   hipLaunchKernelGGL(k_mse, dim3(lb), dim3(256), 0, n->stream, (const float*)n->y, target, n->dy, n->loss_part, tot);

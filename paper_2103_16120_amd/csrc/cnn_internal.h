@@ -46,5 +46,7 @@ struct cnn_net {
 };
 
 // forward pass from the packed input act[0] to `y` on stream `st`; images b
-// with active[b] == 0 are skipped (active: device array [batch], or null)
-int cnn_forward_packed(cnn_net* n, int batch, float* y, hipStream_t st, const int* active = nullptr);
+// with active[b] == 0 are skipped (active: device array [batch], or null);
+// keep: write every layer's activation (the backward pass reads them)
+int cnn_forward_packed(cnn_net* n, int batch, float* y, hipStream_t st, const int* active = nullptr,
+                       bool keep = false);

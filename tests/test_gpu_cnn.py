@@ -54,6 +54,8 @@ def random_params(c_in, seed, last_scale=1.0, bias_scale=0.1):
 
 
 GRIDS = [(64, 16, 2), (128, 9, 1), (256, 6, 3)]
+# several 16-row bands per column strip with a ragged last band, and 16 strips per row
+BAND_GRIDS = [(128, 37, 2), (1024, 20, 1)]
 
 
 def assert_bf16_close(got, ref, what=""):
@@ -101,7 +103,7 @@ def exact_case(nx, ny, batch, seed, c_in=3):
     raise AssertionError("no rounding-free test data found")
 
 
-@pytest.mark.parametrize("nx,ny,batch", GRIDS)
+@pytest.mark.parametrize("nx,ny,batch", GRIDS + BAND_GRIDS)
 def test_forward_exact(gpu_lib, nx, ny, batch):
     params, x, _, yref, _ = exact_case(nx, ny, batch, seed=nx + ny)
     net = gpu_lib.Network(nx, ny, batch, 3)
@@ -140,7 +142,7 @@ def test_gradient_exact(gpu_lib, nx, ny, batch):
     net.close()
 
 
-@pytest.mark.parametrize("nx,ny,batch", GRIDS)
+@pytest.mark.parametrize("nx,ny,batch", GRIDS + BAND_GRIDS)
 def test_forward_parity(gpu_lib, nx, ny, batch):
     c_in = 3
     params = random_params(c_in, 10 + nx)
@@ -176,7 +178,7 @@ def test_forward_pole_rows_sensitive(gpu_lib):
     net.close()
 
 
-@pytest.mark.parametrize("nx,ny,batch", GRIDS)
+@pytest.mark.parametrize("nx,ny,batch", GRIDS + BAND_GRIDS[:1])
 def test_gradient_parity(gpu_lib, nx, ny, batch):
     c_in = 3
     params = random_params(c_in, 20 + nx)
