@@ -582,6 +582,202 @@ __global__ __launch_bounds__(256, 2) void k_conv12(ConvArgs A, const __bf16* w2,
   }
 }
 
+// The last two layers fused (inference: the fourth layer's output is not
+// kept).  A wave walks down its column strip holding the fourth layer's input
+// rows (ConvRow plus a second halo: pixels i0-2 and i0+65 in the lanes of
+// fragment pixels 0 and 15) and the fourth layer's output rows r-1, r, r+1.
+// The fourth layer computes its output for the strip's four fragments by the
+// DPP-shifted taps of k_conv and for a fifth fragment whose lanes 0 and 15
+// compute pixels i0-1 and i0+64 (their dx taps read i0-2, i0-1, i0 and i0+63,
+// i0+64, i0+65, all held), so the last layer's halo is computed rather than
+// fetched.  Its result lane (pixel m, lane row g) holds channels 4g..4g+3 and
+// 16+4g..16+4g+3, the last layer's input operand once the last layer's
+// weights take their input channels in that order.  Beyond a pole the fourth
+// layer's output row is its polar row computed at columns shifted by NX/2.
+// The pass reads the fourth layer's input (64 B a pixel) and writes the
+// float32 output (4 B), against 64 + 64 + 64 + 4 B for the two layers apart.
+struct ConvRow2 {
+  ConvRow x;
+  bf16x8 h2;     // pixel i0-2 in lanes with lane % 16 == 0, i0+65 with lane % 16 == 15
+};
+
+__global__ __launch_bounds__(256, 2) void k_conv45(ConvArgs A, const __bf16* w5, const float* bias5) {
+  __shared__ __attribute__((aligned(16))) __bf16 sw4[TAPS * CH * WROW];
+  __shared__ __attribute__((aligned(16))) __bf16 sw5[TAPS * 16 * WROW];
+  if (A.active && !A.active[blockIdx.y]) return;   // the whole workgroup: one image
+  const int tid = threadIdx.x;
+  for (int k = tid; k < TAPS * CH * 4; k += 256) {
+    const int row = k >> 2, q = 8 * (k & 3);       // row = tap * CH + out channel
+    *(bf16x8*)&sw4[row * WROW + q] = ld8(A.w + row * CH + q);
+  }
+  for (int k = tid; k < TAPS * 16 * CH; k += 256) {   // [tap][out][k]: input channel order of the fused operand
+    const int row = k / CH, kk = k - row * CH;        // row = tap * 16 + out channel
+    const int t = row >> 4, co = row & 15;
+    const int g = kk >> 3, j = kk & 7;
+    const int ci = j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4);
+    sw5[row * WROW + kk] = w5[(t * CH + co) * CH + ci];
+  }
+  __syncthreads();
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int spr = A.nx >> 6;
+  const int w = blockIdx.x * WG_WAVES + wave;      // wave within the image: strip w % spr, band w / spr
+  const int r0 = A.row_begin + (w / spr) * A.nr;
+  if (r0 >= A.row_end) return;
+  const int r1 = min(r0 + A.nr, A.row_end);
+  const int i0 = (w % spr) * 64;
+  const int b = blockIdx.y;
+  const long long npix = (long long)A.nx * A.ny;
+  const __bf16* img = A.in + (long long)b * npix * CH;
+  const int kq = 8 * (lane >> 4), sl = lane >> 4, ml = lane & 15;
+  const int hx = ml == 0 ? i0 - 1 : (ml == 15 ? i0 + 64 : i0 + ml);
+  const int hx2 = ml == 0 ? i0 - 2 : (ml == 15 ? i0 + 65 : i0 + ml);
+  float bias4[2][4], b5 = bias5 ? bias5[0] : 0.f;
+#pragma unroll
+  for (int n = 0; n < 2; ++n)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) bias4[n][q] = A.bias ? A.bias[16 * n + 4 * sl + q] : 0.f;
+  // the fourth layer's input row rr, columns shifted by cs
+  auto load_row = [&](int rr, int cs, ConvRow2& x) {
+    int jj = rr, sh = cs;
+    if (rr < 0) {
+      jj = 0;
+      sh += A.nx >> 1;
+    } else if (rr >= A.ny) {
+      jj = A.ny - 1;
+      sh += A.nx >> 1;
+    }
+    const __bf16* row = img + (long long)jj * A.nx * CH + kq;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) x.x.v[f] = ld8(row + ((i0 + 16 * f + ml + sh) & (A.nx - 1)) * CH);
+    x.x.h = ld8(row + ((hx + sh) & (A.nx - 1)) * CH);
+    x.h2 = ld8(row + ((hx2 + sh) & (A.nx - 1)) * CH);
+  };
+  // the fourth layer's output row from its input rows xs, xc, xn, as the last
+  // layer's input row
+  auto layer4 = [&](const ConvRow2& xs, const ConvRow2& xc, const ConvRow2& xn, ConvRow& out) {
+    // fragments F0 .. F0+NF-1 at a time (fewer accumulators live; the taps'
+    // weights are read once per group)
+    auto group = [&](auto F0_, auto NF_) {
+      constexpr int F0 = decltype(F0_)::value, NF = decltype(NF_)::value;
+      f32x4 acc[2][NF];
+#pragma unroll
+      for (int n = 0; n < 2; ++n)
+#pragma unroll
+        for (int f = 0; f < NF; ++f) acc[n][f] = f32x4{bias4[n][0], bias4[n][1], bias4[n][2], bias4[n][3]};
+      auto taps = [&](auto DY, const ConvRow2& x) {
+        constexpr int dy = decltype(DY)::value;
+        auto tap = [&](auto DX) {
+          constexpr int dx = decltype(DX)::value;
+          constexpr int t = (dy + 1) * 3 + (dx + 1);
+          bf16x8 wf[2];
+#pragma unroll
+          for (int n = 0; n < 2; ++n) wf[n] = *(const bf16x8*)&sw4[(t * CH + 16 * n + ml) * WROW + kq];
+#pragma unroll
+          for (int i = 0; i < NF; ++i) {
+            const int f = F0 + i;
+            bf16x8 fr;
+            if (f < 4) fr = conv_shift<dx>(x.x, f);
+            else if (dx == 0) fr = x.x.h;
+            else if (dx < 0) fr = ml == 0 ? x.h2 : x.x.v[3];   // lane 0: i0-2; lane 15: i0+63
+            else fr = ml == 15 ? x.h2 : x.x.v[0];                 // lane 0: i0; lane 15: i0+65
+#pragma unroll
+            for (int n = 0; n < 2; ++n) acc[n][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[n], fr, acc[n][i], 0, 0, 0);
+          }
+        };
+        tap(std::integral_constant<int, -1>{});
+        tap(std::integral_constant<int, 0>{});
+        tap(std::integral_constant<int, 1>{});
+      };
+      taps(std::integral_constant<int, -1>{}, xs);
+      taps(std::integral_constant<int, 0>{}, xc);
+      taps(std::integral_constant<int, 1>{}, xn);
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+        bf16x8 o;
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) o[4 * n + q] = (__bf16)fmaxf(acc[n][i][q], 0.f);
+        if (F0 + i < 4) out.v[F0 + i] = o;
+        else out.h = o;
+      }
+    };
+    group(std::integral_constant<int, 0>{}, std::integral_constant<int, 3>{});
+    __builtin_amdgcn_sched_barrier(0);   // keeps the groups' weight reads from being hoisted together
+    group(std::integral_constant<int, 3>{}, std::integral_constant<int, 2>{});
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  // the fourth layer's output row q = -1 or ny (across the pole: the polar
+  // row at columns shifted by NX/2), its input rows loaded into ys, yc, yn
+  auto layer4_pole = [&](int q, ConvRow2& ys, ConvRow2& yc, ConvRow2& yn, ConvRow& out) {
+    const int qp = q < 0 ? 0 : A.ny - 1, cs = A.nx >> 1;
+    load_row(qp - 1, cs, ys);
+    load_row(qp, cs, yc);
+    load_row(qp + 1, cs, yn);
+    layer4(ys, yc, yn, out);
+  };
+  // last layer, output row r from the fourth layer's rows as, ac, an
+  auto layer5 = [&](int r, const ConvRow& as, const ConvRow& ac, const ConvRow& an) {
+    f32x4 acc[1][4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) acc[0][f] = f32x4{b5, b5, b5, b5};
+    auto taps = [&](auto DY, const ConvRow& x) {
+      constexpr int dy = decltype(DY)::value;
+      auto tap = [&](auto DX) {
+        constexpr int dx = decltype(DX)::value;
+        constexpr int t = (dy + 1) * 3 + (dx + 1);
+        const bf16x8 wf = *(const bf16x8*)&sw5[(t * 16 + ml) * WROW + kq];
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+          acc[0][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf, conv_shift<dx>(x, f), acc[0][f], 0, 0, 0);
+      };
+      tap(std::integral_constant<int, -1>{});
+      tap(std::integral_constant<int, 0>{});
+      tap(std::integral_constant<int, 1>{});
+    };
+    taps(std::integral_constant<int, -1>{}, as);
+    taps(std::integral_constant<int, 0>{}, ac);
+    taps(std::integral_constant<int, 1>{}, an);
+    const long long prow = (long long)b * npix + (long long)r * A.nx + i0;
+    conv_store<1, 1, false>(A, acc, nullptr, prow, lane, nullptr);
+  };
+  // fourth-layer output rows r-1, r (a0, a1) and input rows r, r+1 (x1, x2)
+  ConvRow a0, a1, a2;
+  ConvRow2 x0, x1, x2;
+  if (r0 == 0) layer4_pole(-1, x0, x1, x2, a0);
+  else {
+    load_row(r0 - 2, 0, x0);
+    load_row(r0 - 1, 0, x1);
+    load_row(r0, 0, x2);
+    layer4(x0, x1, x2, a0);
+  }
+  load_row(r0 - 1, 0, x0);
+  load_row(r0, 0, x1);
+  load_row(r0 + 1, 0, x2);
+  layer4(x0, x1, x2, a1);
+  // step r: input row r+2 into the buffer of row r-1, the fourth layer's row
+  // r+1 into the buffer of row r-2, then the last layer's row r
+  // (at the south pole the row r+1 beyond it; the input buffers are free then)
+  auto step = [&](int r, ConvRow2& xs, ConvRow2& xc, ConvRow2& xn, const ConvRow& as, const ConvRow& ac, ConvRow& an) {
+    if (r + 1 < A.ny) {
+      load_row(r + 2, 0, xs);
+      layer4(xc, xn, xs, an);
+    } else {
+      layer4_pole(r + 1, xs, xc, xn, an);
+    }
+    layer5(r, as, ac, an);
+  };
+#pragma unroll 1
+  for (int r = r0; r < r1; r += 3) {
+    step(r, x0, x1, x2, a0, a1, a2);
+    if (r + 1 >= r1) break;
+    step(r + 1, x1, x2, x0, a1, a2, a0);
+    if (r + 2 >= r1) break;
+    step(r + 2, x2, x0, x1, a2, a0, a1);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Weight and bias gradients of a 3x3 convolution:
 //   dW[t][co][ci] = sum_q dpre[q][co] * in[src_t(q)][ci],  db[co] = sum_q dpre[q][co]

@@ -352,7 +352,8 @@ static void launch_conv(const cnn_net* n, int batch, ConvArgs A, hipStream_t st)
 
 // forward from act[0] (already packed) to y (float32 [B][npix]); `keep`:
 // every activation is written (training); else the first two layers run
-// fused when the input is packed 8 channels a pixel, and act[1] is not written
+// fused when the input is packed 8 channels a pixel (act[1] is not written)
+// and the last two run fused (act[4] is not written)
 int cnn_forward_packed(cnn_net* n, int batch, float* y, hipStream_t st, const int* active, bool keep) {
   for (int l = 0; l < CNN_LAYERS; ++l) {
     ConvArgs A = conv_args(n, batch);
@@ -370,6 +371,12 @@ int cnn_forward_packed(cnn_net* n, int batch, float* y, hipStream_t st, const in
         ++l;
       } else if (l == 0 && n->in_stride == 8) {
         hipLaunchKernelGGL(k_conv_in8, conv_grid(n, batch, n->ny, A.nr), dim3(256), 0, st, A);
+      } else if (l == CNN_LAYERS - 2 && !keep) {   // the last two layers fused
+        A.out32 = y;
+        hipLaunchKernelGGL(k_conv45, conv_grid(n, batch, n->ny, A.nr), dim3(256), 0, st, A,
+                           (const __bf16*)(n->wf + (size_t)(CNN_LAYERS - 1) * TAPS * CH * CH),
+                           (const float*)(n->bias + (CNN_LAYERS - 1) * CH));
+        break;
       } else {
         launch_conv<2, 0>(n, batch, A, st);
       }
