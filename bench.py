@@ -354,9 +354,9 @@ def cpu_baseline(args, probs, budget_s, runs=5):
 
 # algorithmic bytes per point of the model step's explicit kernels (float64
 # fields read and written once: forcings and Courant numbers 10, donor cell
-# 8 + 12, antidiffusive velocities 11, implicit inversion 12, right-hand side
-# 6, recovery 6; H0 read by three of them)
-SI_BYTES_PER_POINT = 8 * (65 + 3)
+# 8, antidiffusive velocities 11, corrective pass with the implicit inversion
+# 19, right-hand side 6, recovery 6; H0 read by three of them)
+SI_BYTES_PER_POINT = 8 * (60 + 3)
 
 
 def model_states(args):

@@ -488,7 +488,7 @@ typedef struct {
  *   (replacing each member's operator) and solved by gcr_solve from Phi^n;
  *   then Q^{n+1} from eq. Qexpr.
  * members: host array [batch].  reports: host array [batch] or NULL (the
- * solve's reports).  The step's work fields (20 per member, ~ 8 * 20 * NX *
+ * solve's reports).  The step's work fields (18 per member, ~ 8 * 18 * NX *
  * (NY+1) bytes) are allocated by the first call and kept.  Returns the
  * solve's worst soft status, or a hard error.  Synchronous.  Errors:
  * GCR_EINVAL (NULL fields, a new field equal to another new field or to an

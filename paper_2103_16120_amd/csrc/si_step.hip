@@ -7,15 +7,16 @@
 //   3. MPDATA (donor cell + one corrective pass) of Phi^n, Q~_x, Q~_y:
 //      Phi* and Qhat;
 //   4. the implicit momentum inverted pointwise (eq. Qexpr): Qhathat, the
-//      part of Q^{n+1} known before the solve;
+//      part of Q^{n+1} known before the solve (inside the corrective pass
+//      of 3, from its Phi* and Qhat in registers);
 //   5. the right-hand side R = D(F^n) + D(Fhathat) - C Phi^n of the elliptic
 //      problem L(Phi^{n+1}) = R, with the operator assembled from Phi* and
 //      H0 and solved by the solver's own precision form, warm-started from
 //      Phi^n;
 //   6. Q^{n+1} = Qhathat + A grad Phi^{n+1} + B Phi^{n+1} (eq. Qexpr).
 // Fields are natural [NY][NX] float64 arrays; the kernels take one thread per
-// point and one workgroup row (blockIdx.y) per member.  Work arrays are the
-// solver's, allocated on the first call.
+// column and band of four rows and one workgroup row (blockIdx.y) per member.
+// Work arrays are the solver's, allocated on the first call.
 #include "solver_impl.h"
 
 namespace {
@@ -33,7 +34,7 @@ struct SiMember {
 // work fields per member, each wpts (>= nx * (ny + 1)) values; W_LAT holds
 // the latitude table: per row j, cos(lat_j), sin(lat_j), cos(lat_{j+1/2}),
 // alpha(lat_j)
-enum { W_CX = 0, W_CY, W_P1, W_Q1X, W_Q1Y, W_AXP, W_AYP, W_AXQX, W_AYQX, W_AXQY, W_AYQY, W_PHIS, W_QHX, W_QHY,
+enum { W_CX = 0, W_CY, W_P1, W_Q1X, W_Q1Y, W_AXP, W_AYP, W_AXQX, W_AYQX, W_AXQY, W_AYQY, W_PHIS,
        W_QTX, W_QTY, W_QHHX, W_QHHY, W_RHS, W_LAT, W_COUNT };
 enum { LT_COS = 0, LT_SIN, LT_COSN, LT_ALPHA, LT_N };
 
@@ -73,21 +74,13 @@ __device__ __forceinline__ double* wf(const SiArgs& A, const SiMember& M, int k)
   return A.work + M.w + (long long)k * A.wpts;
 }
 
-// One thread per point of member blockIdx.y.  gridDim.x is a multiple of the
-// XCD count, so block x of every member runs on XCD x mod 8; xcd_block gives
-// each XCD a contiguous range of rows, and the neighbour rows a stencil reads
-// come from that XCD's own L2.
-#define SI_POINTS(A, M)                                                                      \
-  const SiMember M = (A).tab[blockIdx.y];                                                    \
-  const int n_ = M.nx * M.ny;                                                                \
-  for (int p_ = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; p_ < n_;         \
-       p_ += gridDim.x * blockDim.x)
-
 // One thread per column i and band of SI_BAND consecutive rows j0 .. j1-1 of
 // member blockIdx.y: a stencil's neighbour rows are loaded once per band
 // row and rolled down in registers instead of loaded once per point.  Bands
-// are numbered row-major over (band, column), with the same XCD mapping as
-// SI_POINTS.
+// are numbered row-major over (band, column).  gridDim.x is a multiple of the
+// XCD count, so block x of every member runs on XCD x mod 8; xcd_block gives
+// each XCD a contiguous range of bands, and the neighbour rows a stencil
+// reads come from that XCD's own L2.
 constexpr int SI_BAND = 4;
 #define SI_BANDS(A, M)                                                                        \
   const SiMember M = (A).tab[blockIdx.y];                                                     \
@@ -98,7 +91,7 @@ constexpr int SI_BAND = 4;
          once_; once_ = 0)
 
 // the latitude table of every member
-// Field stores are nontemporal: a step's work fields (20 float64 fields per
+// Field stores are nontemporal: a step's work fields (18 float64 fields per
 // point over the batch) stream through HBM, far beyond the memory-side cache.
 __device__ __forceinline__ void nts(double* p, double v) { __builtin_nontemporal_store(v, p); }
 
@@ -185,15 +178,44 @@ __global__ void k_si_prepare(SiArgs A) {
   }
 }
 
+// 4: Qhathat at point (j, i) from the corrective pass's Phi* (ps) and
+// Qhat (qhx, qhy), and the initial guess of the solve (Phi^n)
+__device__ __forceinline__ void si_qhh_point(const SiArgs& A, const SiMember& M, int j, int i, double ps, double qhx,
+                                             double qhy) {
+  const int nx = M.nx, ny = M.ny;
+  const long long k = (long long)j * nx + i;
+  const double* lt = wf(A, M, W_LAT);
+  const double cs = lt[LT_N * j + LT_COS], sn = lt[LT_N * j + LT_SIN], t = sn / cs;
+  const double a = M.radius, d = 0.5 * M.dt;
+  const double dlam = 2.0 * kPi / nx, dphi = kPi / ny;
+  const double al = lt[LT_N * j + LT_ALPHA], gam = 1.0 + d * al, b = d * 2.0 * M.omega * sn;
+  const double D = gam * gam + b * b;
+  double h0x = 0.0, h0y = 0.0;
+  if (M.oro) {
+    h0x = (at(M.oro, j, i + 1, nx, ny, 1.0) - at(M.oro, j, i - 1, nx, ny, 1.0)) / (2.0 * dlam);
+    h0y = (at(M.oro, j + 1, i, nx, ny, 1.0) - at(M.oro, j - 1, i, nx, ny, 1.0)) / (2.0 * dphi);
+  }
+  const double mx = t * M.qx[k] * M.qy[k] / (a * M.phi[k]), my = -t * M.qx[k] * M.qx[k] / (a * M.phi[k]);
+  const double mx0 = t * M.qx0[k] * M.qy0[k] / (a * M.phi0[k]), my0 = -t * M.qx0[k] * M.qx0[k] / (a * M.phi0[k]);
+  const double qbx = M.qbx ? M.qbx[k] : 0.0, qby = M.qby ? M.qby[k] : 0.0;
+  const double ex = qhx + d * (al * qbx + 2.0 * mx - mx0) - d * M.g / (a * cs) * 0.5 * ps * h0x;
+  const double ey = qhy + d * (al * qby + 2.0 * my - my0) - d * M.g / a * 0.5 * ps * h0y;
+  nts(wf(A, M, W_QHHX) + k, (gam * ex + b * ey) / D);
+  nts(wf(A, M, W_QHHY) + k, (-b * ex + gam * ey) / D);
+  nts(M.phi1 + k, M.phi[k]);
+}
+
 // donor-cell pass of the three advected fields: out = in - (div of upwind
 // fluxes) / cos(lat); `ax*` / `ay*`: the Courant numbers of each field
 struct UpwindSet {
-  int in[3], out[3], cx[3], cy[3];     // work fields; in[0] < 0: Phi^n (the first pass)
+  int in[3], out[3], cx[3], cy[3];     // work fields; in[0] < 0: Phi^n (the first pass); out[f] < 0: not stored
 };
 
 // SHARED: the three fields move with the same Courant numbers (the first
-// pass), which are then read once per point
-template <bool SHARED>
+// pass), which are then read once per point.  QHH (the corrective pass):
+// the implicit inversion of step 4 follows at each point, from the pass's
+// Phi* and Qhat in registers; only Phi* of the three fields is stored.
+template <bool SHARED, bool QHH>
 __global__ void k_si_upwind(SiArgs A, UpwindSet U) {
   SI_BANDS(A, M) {
     const int nx = M.nx, ny = M.ny;
@@ -210,7 +232,7 @@ __global__ void k_si_upwind(SiArgs A, UpwindSet U) {
       psi[f] = U.in[f] < 0 ? M.phi : wf(A, M, U.in[f]);
       cxa[f] = wf(A, M, U.cx[SHARED ? 0 : f]);
       cya[f] = wf(A, M, U.cy[SHARED ? 0 : f]);
-      out[f] = wf(A, M, U.out[f]);
+      out[f] = U.out[f] < 0 ? nullptr : wf(A, M, U.out[f]);   // < 0: not stored (the fused inversion)
     }
     // column i rolled down the band: psi at rows j-1, j and C^y at face j-1/2
     const long long k0 = (long long)j0_ * nx + i_;
@@ -227,6 +249,7 @@ __global__ void k_si_upwind(SiArgs A, UpwindSet U) {
       const long long row = (long long)j * nx, k = row + i_;
       const double g = lt[LT_N * j + LT_COS];
       double ce = 0.0, cw = 0.0, cn = 0.0;
+      double nv[3];
       const double cs0 = cy_s[0];   // face j-1/2 of the shared Courant numbers
 #pragma unroll
       for (int f = 0; f < 3; ++f) {
@@ -241,11 +264,13 @@ __global__ void k_si_upwind(SiArgs A, UpwindSet U) {
         const double fw = flux(cw, psi[f][row + iw], ps_c[f]);
         const double fn = j < ny - 1 ? flux(cn, ps_c[f], ps_n) : 0.0;
         const double fs = j > 0 ? flux(cs, ps_m[f], ps_c[f]) : 0.0;
-        nts(out[f] + k, ps_c[f] - ((fe - fw) + (fn - fs)) / g);
+        nv[f] = ps_c[f] - ((fe - fw) + (fn - fs)) / g;
+        if (!QHH || f == 0) nts(out[f] + k, nv[f]);
         ps_m[f] = ps_c[f];
         ps_c[f] = ps_n;
         if (!SHARED || f == 0) cy_s[f] = cn;
       }
+      if constexpr (QHH) si_qhh_point(A, M, j, i_, nv[0], nv[1], nv[2]);
     }
   }
 }
@@ -341,34 +366,6 @@ __global__ void k_si_antidiff(SiArgs A) {
       cyw[0][1] = cyw[1][1];
       cyr(j + 1, cyw[1]);
     }
-  }
-}
-
-// 4: Qhathat, and the initial guess of the solve (Phi^n)
-__global__ void k_si_qhh(SiArgs A) {
-  SI_POINTS(A, M) {
-    const int j = p_ >> M.log2nx, i = p_ & (M.nx - 1), nx = M.nx, ny = M.ny;
-    const long long k = (long long)j * nx + i;
-    const double* lt = wf(A, M, W_LAT);
-    const double cs = lt[LT_N * j + LT_COS], sn = lt[LT_N * j + LT_SIN], t = sn / cs;
-    const double a = M.radius, d = 0.5 * M.dt;
-    const double dlam = 2.0 * kPi / nx, dphi = kPi / ny;
-    const double al = lt[LT_N * j + LT_ALPHA], gam = 1.0 + d * al, b = d * 2.0 * M.omega * sn;
-    const double D = gam * gam + b * b;
-    double h0x = 0.0, h0y = 0.0;
-    if (M.oro) {
-      h0x = (at(M.oro, j, i + 1, nx, ny, 1.0) - at(M.oro, j, i - 1, nx, ny, 1.0)) / (2.0 * dlam);
-      h0y = (at(M.oro, j + 1, i, nx, ny, 1.0) - at(M.oro, j - 1, i, nx, ny, 1.0)) / (2.0 * dphi);
-    }
-    const double mx = t * M.qx[k] * M.qy[k] / (a * M.phi[k]), my = -t * M.qx[k] * M.qx[k] / (a * M.phi[k]);
-    const double mx0 = t * M.qx0[k] * M.qy0[k] / (a * M.phi0[k]), my0 = -t * M.qx0[k] * M.qx0[k] / (a * M.phi0[k]);
-    const double qbx = M.qbx ? M.qbx[k] : 0.0, qby = M.qby ? M.qby[k] : 0.0;
-    const double ps = wf(A, M, W_PHIS)[k];
-    const double ex = wf(A, M, W_QHX)[k] + d * (al * qbx + 2.0 * mx - mx0) - d * M.g / (a * cs) * 0.5 * ps * h0x;
-    const double ey = wf(A, M, W_QHY)[k] + d * (al * qby + 2.0 * my - my0) - d * M.g / a * 0.5 * ps * h0y;
-    nts(wf(A, M, W_QHHX) + k, (gam * ex + b * ey) / D);
-    nts(wf(A, M, W_QHHY) + k, (-b * ex + gam * ey) / D);
-    nts(M.phi1 + k, M.phi[k]);
   }
 }
 
@@ -493,7 +490,7 @@ extern "C" int gcr_si_step(gcr_solver* s, const gcr_si_member* members, gcr_repo
   // the staged table may still feed the previous upload
   HIPCHK(s, hipStreamSynchronize(s->stream));
   SiMember* tab_h = (SiMember*)s->si_stage;
-  int nymax = 0, nptmax = 0, nbandmax = 0;
+  int nymax = 0, nbandmax = 0;
   for (int m = 0; m < B; ++m) {
     const gcr_si_member& q = members[m];
     SiMember& t = tab_h[m];
@@ -519,23 +516,21 @@ extern "C" int gcr_si_step(gcr_solver* s, const gcr_si_member* members, gcr_repo
     t.log2nx = ilog2(t.nx);
     t.w = (long long)m * W_COUNT * wpts;
     nymax = std::max(nymax, t.ny);
-    nptmax = std::max(nptmax, t.nx * t.ny);
     nbandmax = std::max(nbandmax, t.nx * ((t.ny + SI_BAND - 1) / SI_BAND));
   }
   HIPCHK(s, hipMemcpyAsync(s->si_tab, tab_h, (size_t)B * sizeof(SiMember), hipMemcpyHostToDevice, s->stream));
   SiArgs A{(const SiMember*)s->si_tab, s->si_work, wpts};
-  const int nblk = (std::min((nptmax + 255) / 256, 4096) + NXCD - 1) / NXCD * NXCD;
-  const dim3 grid((unsigned)nblk, (unsigned)B), blk(256);
+  const dim3 blk(256);
   const int nblk_b = (std::min((nbandmax + 255) / 256, 4096) + NXCD - 1) / NXCD * NXCD;
   const dim3 grid_b((unsigned)nblk_b, (unsigned)B);   // the band kernels
   KLAUNCH(s, KT_SI_STEP, k_si_lat, dim3((unsigned)((nymax + 255) / 256), (unsigned)B), blk, 0, s->stream, A);
   KLAUNCH(s, KT_SI_STEP, k_si_prepare, grid_b, blk, 0, s->stream, A);
   UpwindSet U1{{-1, W_QTX, W_QTY}, {W_P1, W_Q1X, W_Q1Y}, {W_CX, W_CX, W_CX}, {W_CY, W_CY, W_CY}};
-  KLAUNCH(s, KT_SI_STEP, k_si_upwind<true>, grid_b, blk, 0, s->stream, A, U1);
+  KLAUNCH(s, KT_SI_STEP, (k_si_upwind<true, false>), grid_b, blk, 0, s->stream, A, U1);
   KLAUNCH(s, KT_SI_STEP, k_si_antidiff, grid_b, blk, 0, s->stream, A);
-  UpwindSet U2{{W_P1, W_Q1X, W_Q1Y}, {W_PHIS, W_QHX, W_QHY}, {W_AXP, W_AXQX, W_AXQY}, {W_AYP, W_AYQX, W_AYQY}};
-  KLAUNCH(s, KT_SI_STEP, k_si_upwind<false>, grid_b, blk, 0, s->stream, A, U2);
-  KLAUNCH(s, KT_SI_STEP, k_si_qhh, grid, blk, 0, s->stream, A);
+  // the corrective pass stores Phi*; its Qhat goes straight into the implicit inversion
+  UpwindSet U2{{W_P1, W_Q1X, W_Q1Y}, {W_PHIS, -1, -1}, {W_AXP, W_AXQX, W_AXQY}, {W_AYP, W_AYQX, W_AYQY}};
+  KLAUNCH(s, KT_SI_STEP, (k_si_upwind<false, true>), grid_b, blk, 0, s->stream, A, U2);
   KLAUNCH(s, KT_SI_STEP, k_si_rhs, grid_b, blk, 0, s->stream, A);
   HIPCHK(s, hipGetLastError());
   // the elliptic problem: the operator from Phi* and H0, solved from Phi^n

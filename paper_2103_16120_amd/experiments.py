@@ -61,7 +61,7 @@ operator assembly from Phi*, the solve (rtol 1e-8) and the momentum recovery
 for the whole batch; the timed steps repeat one step from the same state, so
 every step does the same work.  Reported: time per step, its explicit-part
 share (per-kernel HIP events in a separate pass), the explicit kernels'
-algorithmic bandwidth (544 bytes per point: 68 float64 reads and writes),
+algorithmic bandwidth (504 bytes per point: 63 float64 reads and writes),
 solver iterations, and a five-step trajectory (iterations, mass drift,
 largest velocity).
 """
@@ -403,10 +403,10 @@ def sequence(args):
 def si_bytes_per_point(orography=True, qbar=False):
     """Algorithmic bytes per point of the step's explicit kernels: the float64
     fields each reads and writes once (forcings and Courant numbers 10,
-    donor cell 8 and 12, antidiffusive velocities 11, implicit inversion 12,
-    right-hand side 6, recovery 6), plus H0 in three of them and the two
-    relaxation targets in two."""
-    return 8 * (65 + (3 if orography else 0) + (4 if qbar else 0))
+    donor cell 8, antidiffusive velocities 11, corrective pass with the
+    implicit inversion 19, right-hand side 6, recovery 6), plus H0 in three
+    of them and the two relaxation targets in two."""
+    return 8 * (60 + (3 if orography else 0) + (4 if qbar else 0))
 
 
 def model(args):
