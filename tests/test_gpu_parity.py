@@ -259,6 +259,34 @@ def test_warm_start_batch_all_widths(gpu_lib, precision):
 
 
 @pytest.mark.parametrize("precision", [0, 3])
+@pytest.mark.parametrize("oro", [False, True])
+def test_residual_1024_point_rows(gpu_lib, precision, oro):
+    """Rows of 1024 points take the float64 residual in two halves: the
+    first residual (r_0, from the caller's x and rhs in natural order, poles
+    included) against the oracle's to 1e-12, the final one (pooled x)
+    against the host's recomputation; with orography the kernels read H*."""
+    nx, ny, dt = 1024, 12, 100.0
+    rtol = 1e-10 if precision == 0 else 1e-8
+    pr = problem(2, nx, ny, instance=5, dt=dt)
+    h0 = 1500.0 * np.random.default_rng(3).random((ny, nx)) if oro else None
+    op = EllipticOperator(nx, ny, pr["depth"], dt, orography=h0)
+    rhs = op.apply(pr["x_true"])
+    g = pr["x_true"] + 0.3 * np.std(pr["x_true"]) * np.random.default_rng(4).standard_normal((ny, nx))
+    s = make_solver(gpu_lib, [(nx, ny)], precision=precision, rtol=rtol, max_iters=100)
+    s.set_operator(0, pr["depth"], dt, orography=h0)
+    x = dev(g)
+    rep = s.solve([dev(rhs)], [x])[0]
+    ores = gcr(op, rhs, x0=g, rtol=rtol, max_iters=100)
+    assert rep.r0_norm == pytest.approx(ores.r0_norm, rel=1e-12)
+    xh = host(x)
+    true_res = np.linalg.norm(op.apply(xh) - rhs) / ores.r0_norm
+    assert rep.rel_res_true == pytest.approx(true_res, rel=1e-6, abs=1e-14)
+    assert rep.status == gpu_lib.OK and true_res <= rtol, rep
+    err = np.linalg.norm(xh - ores.x) / np.linalg.norm(ores.x)
+    assert err <= (1e-9 if precision == 0 else 1e-6), err
+
+
+@pytest.mark.parametrize("precision", [0, 3])
 def test_largest_grid_solve(gpu_lib, precision):
     """The largest grid the library takes (1024 x 4096, 4.2 M points, polar
     rows 9.6 m wide): too large for the oracle's GCR, so the GPU solution is
