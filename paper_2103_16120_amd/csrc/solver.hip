@@ -333,8 +333,9 @@ extern "C" int gcr_create(const gcr_params* prm, gcr_solver** out) {
   s->hist_stride = P.max_iters + 1;
   if (P.flags & GCR_F_RECORD_HISTORY)
     s->hist = (double*)track(dalloc<double>((size_t)P.batch * s->hist_stride, herr));
-  s->ptr_rhs = (const double**)track(dalloc<const double*>(P.batch, herr));
-  s->ptr_x = (double**)track(dalloc<double*>(P.batch, herr));
+  // the rhs and x tables in one block, uploaded by one copy
+  s->ptr_rhs = (const double**)track(dalloc<const double*>(2 * (size_t)P.batch, herr));
+  s->ptr_x = s->ptr_rhs ? (double**)(s->ptr_rhs + P.batch) : nullptr;
   if (herr == hipSuccess) herr = hipHostMalloc((void**)&s->ptr_stage, 2 * P.batch * sizeof(void*), 0);
   s->asm_tab = (AsmMember*)track(dalloc<AsmMember>(P.batch, herr));
   if (herr == hipSuccess) herr = hipHostMalloc((void**)&s->state_h, P.batch * sizeof(MemberState), 0);
@@ -416,15 +417,13 @@ extern "C" int gcr_set_operators(gcr_solver* s, int32_t count, const int32_t* me
           return fail(s, GCR_EINVAL, "member %d: depth must be finite and > 0 (point %lld)", member, k);
     }
   }
-  // the staging table (pinned) may still feed the previous upload: wait for
-  // that copy only, not for the whole stream
-  HIPCHK(s, hipEventSynchronize(s->stage_ev[1]));
+  std::vector<AsmMember> tab(count);
   for (int t = 0; t < count; ++t) {
     const int member = members[t];
     const gcr_operator* op = &ops[t];
     const MemberGeom& G = s->geom_h[member];
     const long long n = (long long)G.nx * G.ny;
-    AsmMember& a = s->asm_stage[t];
+    AsmMember& a = tab[t];
     a.member = member;
     a.dt = op->dt;
     a.g = op->g;
@@ -447,8 +446,15 @@ extern "C" int gcr_set_operators(gcr_solver* s, int32_t count, const int32_t* me
     }
     s->scale_h[member] = op->dt / (2.0 * op->radius * op->radius);
   }
-  HIPCHK(s, hipMemcpyAsync(s->asm_tab, s->asm_stage, count * sizeof(AsmMember), hipMemcpyHostToDevice, s->stream));
-  HIPCHK(s, hipEventRecord(s->stage_ev[1], s->stream));
+  if (tab.size() != s->asm_last.size() || std::memcmp(tab.data(), s->asm_last.data(), count * sizeof(AsmMember)) != 0) {
+    // the staging table (pinned) may still feed the previous upload: wait
+    // for that copy only, not for the whole stream
+    HIPCHK(s, hipEventSynchronize(s->stage_ev[1]));
+    std::memcpy(s->asm_stage, tab.data(), count * sizeof(AsmMember));
+    HIPCHK(s, hipMemcpyAsync(s->asm_tab, s->asm_stage, count * sizeof(AsmMember), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipEventRecord(s->stage_ev[1], s->stream));
+    s->asm_last = tab;
+  }
   AssembleArgs A{};
   A.tab = s->asm_tab;
   A.geom = s->geom;
@@ -482,7 +488,7 @@ extern "C" int gcr_set_operators(gcr_solver* s, int32_t count, const int32_t* me
   if (host_inputs) HIPCHK(s, hipStreamSynchronize(s->stream));  // host arrays are read asynchronously
   for (int t = 0; t < count; ++t) {
     s->have_op[members[t]] = 1;
-    s->flat_h[members[t]] = s->asm_stage[t].oro ? 0 : 1;   // as k_assemble sets `flat`
+    s->flat_h[members[t]] = tab[t].oro ? 0 : 1;   // as k_assemble sets `flat`
   }
   refresh_flat(s);
   return GCR_OK;
@@ -542,14 +548,18 @@ extern "C" int gcr_solve(gcr_solver* s, const double* const* rhs, double* const*
   if (s->prm.flags & GCR_F_SPLIT_R0)
     for (int m = 0; m < B; ++m)
       if (!s->have_split[m]) return fail(s, GCR_ESTATE, "member %d has no split base (gcr_set_split_base)", m);
-  HIPCHK(s, hipEventSynchronize(s->stage_ev[0]));  // staging buffer reuse
+  std::vector<const void*> tab(2 * (size_t)B);
   for (int m = 0; m < B; ++m) {
-    s->ptr_stage[m] = rhs[m];
-    s->ptr_stage[B + m] = x[m];
+    tab[m] = rhs[m];
+    tab[B + m] = x[m];
   }
-  HIPCHK(s, hipMemcpyAsync(s->ptr_rhs, s->ptr_stage, B * sizeof(void*), hipMemcpyHostToDevice, s->stream));
-  HIPCHK(s, hipMemcpyAsync(s->ptr_x, s->ptr_stage + B, B * sizeof(void*), hipMemcpyHostToDevice, s->stream));
-  HIPCHK(s, hipEventRecord(s->stage_ev[0], s->stream));
+  if (tab != s->ptr_last) {
+    HIPCHK(s, hipEventSynchronize(s->stage_ev[0]));  // staging buffer reuse
+    std::memcpy(s->ptr_stage, tab.data(), tab.size() * sizeof(void*));
+    HIPCHK(s, hipMemcpyAsync(s->ptr_rhs, s->ptr_stage, tab.size() * sizeof(void*), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipEventRecord(s->stage_ev[0], s->stream));
+    s->ptr_last = tab;
+  }
   // the caller's rhs and x are read in place by the residual kernels (x is
   // copied into the pool by the first one and back by the last one)
   if (s->dx) HIPCHK(s, hipMemsetAsync(s->dx, 0, s->npts * sizeof(float), s->stream));

@@ -158,6 +158,11 @@ struct gcr_solver {
   hipEvent_t cycle_ev[2] = {};       // recorded after each copy
   AsmMember* asm_stage = nullptr;    // pinned staging of the assembly table
   hipEvent_t stage_ev[2] = {};       // recorded after the uploads from ptr_stage / asm_stage
+  // host copies of the tables last uploaded: a call whose tables equal them
+  // (the same caller buffers and operator inputs step after step) uploads
+  // nothing, since the device copies already hold them
+  std::vector<const void*> ptr_last;
+  std::vector<AsmMember> asm_last;
   AsmMember* asm_tab = nullptr;      // device assembly table [batch]
   cnn_net* net = nullptr;            // learned preconditioner (GCR_PC_LEARNED), owned
   int* learn_active = nullptr;       // [batch] images the network runs on in one application
