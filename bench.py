@@ -149,6 +149,10 @@ HBM_PEAK_GBS = 8000.0
 # counter runs (scaled by a plain copy of known size), valid only for the
 # kernel sources it was taken with
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "kernel_traffic_512x256_b64.txt")
+# (batch, nx, ny, dt) -> the counter summary and workload name taken for it
+TRAFFIC_RUNS = {(64, 512, 256, 600.0): (TRAFFIC_FILE, "mixed_half_pc 64x512x256"),
+                (64, 1024, 512, 100.0): (os.path.join(ROOT, "profiles", "kernel_traffic_1024x512_b64.txt"),
+                                         "mixed_half_pc 64x1024x512")}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2103_16120_amd", "csrc", f) for f in ("device.h", "kernels.h")]
 
 
@@ -278,12 +282,12 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, path=TRAFFIC_FILE):
     """HBM bytes per launch of `kernel` (mean over its dispatches) from the
     committed counter summary, or None when it is missing, for another
     workload, or older than the kernel sources."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             recs = [json.loads(l) for l in fh if l.startswith("{")]
     except (OSError, ValueError):
         return None
@@ -490,8 +494,9 @@ def main():
     if not args.no_timing:
         ts = len(kit_mixed)
         out["roofline"], out["roofline_kernels"] = roofline(kt_mixed, kit_mixed, rep_m, pts, "mixed")
-        if out["roofline"] is not None and args.batch == 64 and (args.nx, args.ny) == (512, 256):
-            out["roofline"]["traffic"] = measured_traffic(out["roofline"]["kernel"], "mixed_half_pc 64x512x256")
+        run = TRAFFIC_RUNS.get((args.batch, args.nx, args.ny, float(args.dt)))
+        if out["roofline"] is not None and run is not None:
+            out["roofline"]["traffic"] = measured_traffic(out["roofline"]["kernel"], run[1], run[0])
         out["kernel_ms_per_step"] = {k: round(v[1] / ts, 4) for k, v in kt_mixed.items() if v[0]}
         out["kernel_launches_per_step"] = {k: v[0] / ts for k, v in kt_mixed.items() if v[0]}
     mixed.solver.close()
