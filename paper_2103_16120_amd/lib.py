@@ -11,6 +11,7 @@ import ctypes as C
 import os
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 from .build import lib_path
@@ -158,6 +159,31 @@ def _check_field(t: torch.Tensor, ny: int, nx: int, name: str):
         raise ValueError(f"{name} must be a contiguous float64 tensor of shape ({ny}, {nx})")
 
 
+_F64 = torch.float64
+
+
+def _check_fields(ts, shapes, name: str):
+    """_check_field over a list (shapes: torch.Size (ny, nx) per entry): one
+    pass of cheap attribute tests; the per-entry check only names a failure."""
+    if len(ts) != len(shapes):
+        raise ValueError(f"{name}: {len(shapes)} fields expected, got {len(ts)}")
+    for t, shp in zip(ts, shapes):
+        if not (isinstance(t, torch.Tensor) and t.dtype is _F64 and t.is_cuda and t.shape == shp
+                and t.is_contiguous()):
+            for m, (u, sh) in enumerate(zip(ts, shapes)):
+                _check_field(u, sh[0], sh[1], f"{name}[{m}]")
+            raise ValueError(f"{name}: contiguous float64 CUDA tensors of the members' shapes expected")
+
+
+# numpy views of the operator and report tables (one row per member), so a
+# batch is filled and read column by column instead of field by field
+_OP_DTYPE = np.dtype(GcrOperator)
+_REP_FIELDS = ("status", "iterations", "restarts", "fallback_used", "r0_norm", "rel_res_recursive", "rel_res_true")
+_REP_DTYPE = np.dtype({"names": list(_REP_FIELDS), "formats": ["<i4"] * 4 + ["<f8"] * 3,
+                       "offsets": [getattr(GcrReport, f).offset for f in _REP_FIELDS],
+                       "itemsize": C.sizeof(GcrReport)})
+
+
 class Solver:
     """A batch of independent GCR(k) depth solves sharing one configuration."""
 
@@ -167,6 +193,7 @@ class Solver:
         """tuned: take one_stream / graph from the autotuner's table for this
         workload (paper_2103_16120_amd.tune), overriding the arguments."""
         self.sizes = [(int(nx), int(ny)) for nx, ny in sizes]
+        self._shapes = [torch.Size((ny, nx)) for nx, ny in self.sizes]
         if tuned:
             from .tune import tuned_options
             opt = tuned_options(self.sizes, precision)
@@ -245,18 +272,26 @@ class Solver:
         n = len(members)
         if len(depths) != n or len(dts) != n:
             raise ValueError("one depth and one dt per member")
-        ops = (GcrOperator * n)()
-        for t, m in enumerate(members):
-            nx, ny = self.sizes[m]
-            _check_field(depths[t], ny, nx, f"depth[{t}]")
-            oro = None if orographies is None else orographies[t]
-            if oro is not None:
-                _check_field(oro, ny, nx, f"orography[{t}]")
-            ops[t] = GcrOperator(dt=float(dts[t]), g=g, omega=omega, radius=radius, absorber=absorber,
-                                 depth=depths[t].data_ptr(), orography=None if oro is None else oro.data_ptr(),
-                                 b_terms=1 if b_terms else 0, mem_is_device=1)
-        mem = (C.c_int32 * n)(*members)
-        rc = _lib.gcr_set_operators(self._h, n, mem, ops)
+        mem = np.array(members, dtype=np.int32)
+        if mem.ndim != 1 or (n and (mem.min() < 0 or mem.max() >= len(self.sizes))):
+            raise ValueError(f"members must lie in 0..{len(self.sizes) - 1}")
+        shapes = [self._shapes[m] for m in mem.tolist()]
+        _check_fields(depths, shapes, "depth")
+        ops = np.zeros(n, dtype=_OP_DTYPE)
+        ops["dt"] = dts
+        ops["g"], ops["omega"], ops["radius"], ops["absorber"] = g, omega, radius, absorber
+        ops["depth"] = [t.data_ptr() for t in depths]
+        if orographies is not None:
+            if len(orographies) != n:
+                raise ValueError("one orography (or None) per member")
+            for t, o in enumerate(orographies):
+                if o is not None:
+                    _check_field(o, shapes[t][0], shapes[t][1], f"orography[{t}]")
+            ops["orography"] = [0 if o is None else o.data_ptr() for o in orographies]
+        ops["b_terms"] = 1 if b_terms else 0
+        ops["mem_is_device"] = 1
+        rc = _lib.gcr_set_operators(self._h, n, mem.ctypes.data_as(C.POINTER(C.c_int32)),
+                                    ops.ctypes.data_as(C.POINTER(GcrOperator)))
         if rc < 0:
             raise self._err(rc)
 
@@ -268,9 +303,8 @@ class Solver:
             raise ValueError("one rhs and one x per member")
         if record_history and not (self.params.flags & F_RECORD_HISTORY):
             raise ValueError("record_history needs a solver created with record_history=True")
-        for m, (nx, ny) in enumerate(self.sizes):
-            _check_field(rhs[m], ny, nx, f"rhs[{m}]")
-            _check_field(x[m], ny, nx, f"x[{m}]")
+        _check_fields(rhs, self._shapes, "rhs")
+        _check_fields(x, self._shapes, "x")
         rp = (C.c_void_p * b)(*[t.data_ptr() for t in rhs])
         xp = (C.c_void_p * b)(*[t.data_ptr() for t in x])
         reps = (GcrReport * b)()
@@ -284,13 +318,13 @@ class Solver:
         rc = _lib.gcr_solve(self._h, rp, xp, reps)
         if rc < 0:
             raise self._err(rc)
-        out = []
-        for m in range(b):
-            r = reps[m]
-            hist = list(bufs[m][:r.history_len]) if record_history else []
-            out.append(Report(r.status, r.iterations, r.restarts, r.fallback_used, r.r0_norm,
-                              r.rel_res_recursive, r.rel_res_true, hist))
-        return out
+        tab = np.frombuffer(reps, dtype=_REP_DTYPE)
+        cols = [tab[f].tolist() for f in _REP_FIELDS]
+        if record_history:
+            hists = [list(bufs[m][:reps[m].history_len]) for m in range(b)]
+        else:
+            hists = [[] for _ in range(b)]
+        return [Report(*row, h) for row, h in zip(zip(*cols), hists)]
 
     def si_step(self, states, olds, news, dts, orographies=None, qbars=None, absorber=0.0, g=GRAVITY,
                 omega=OMEGA, radius=RADIUS):
