@@ -217,3 +217,45 @@ def test_si_member_layout_matches_the_header(lib):
     assert C.sizeof(lib.GcrSiMember) == 12 * 8 + 5 * 8
     assert lib.GcrSiMember.dt.offset == 96 and lib.GcrSiMember.absorber.offset == 128
 
+
+
+def test_batch_tables_match_the_c_structs(lib):
+    """The numpy views the binding fills and reads have the C structs' layout:
+    a table filled column by column equals the one built field by field, and
+    the report view reads back what was written through ctypes."""
+    import numpy as np
+    n = 5
+    dts, ptrs = [600.0, 300.5, 100.0, 50.0, 1.0], [4096 + 64 * i for i in range(n)]
+    oro = [None, 77824, None, 5120, None]
+    ref = (lib.GcrOperator * n)()
+    for t in range(n):
+        ref[t] = lib.GcrOperator(dt=dts[t], g=9.8, omega=7.292e-5, radius=6.371e6, absorber=0.25, depth=ptrs[t],
+                                 orography=oro[t], b_terms=1, mem_is_device=1)
+    ops = np.zeros(n, dtype=lib._OP_DTYPE)
+    ops["dt"] = dts
+    ops["g"], ops["omega"], ops["radius"], ops["absorber"] = 9.8, 7.292e-5, 6.371e6, 0.25
+    ops["depth"] = ptrs
+    ops["orography"] = [0 if o is None else o for o in oro]
+    ops["b_terms"], ops["mem_is_device"] = 1, 1
+    assert lib._OP_DTYPE.itemsize == C.sizeof(lib.GcrOperator)
+    assert ops.tobytes() == bytes(ref)
+    reps = (lib.GcrReport * 3)()
+    for m in range(3):
+        r = reps[m]
+        r.status, r.iterations, r.restarts, r.fallback_used = m - 1, 5 + m, m, m % 2
+        r.r0_norm, r.rel_res_recursive, r.rel_res_true, r.history_len = 1.5 * m, 1e-9 * m, 2e-9 * m, 7
+    tab = np.frombuffer(reps, dtype=lib._REP_DTYPE)
+    got = list(zip(*[tab[f].tolist() for f in lib._REP_FIELDS]))
+    assert got == [(r.status, r.iterations, r.restarts, r.fallback_used, r.r0_norm, r.rel_res_recursive,
+                    r.rel_res_true) for r in reps]
+
+
+def test_field_list_checks_name_the_failing_entry(lib):
+    import torch
+    shapes = [torch.Size((4, 8))] * 3
+    with pytest.raises(ValueError, match="3 fields expected"):
+        lib._check_fields([torch.zeros(4, 8, dtype=torch.float64)] * 2, shapes, "rhs")
+    with pytest.raises(TypeError, match=r"rhs\[0\] must be a CUDA tensor"):
+        lib._check_fields([torch.zeros(4, 8, dtype=torch.float64)] * 3, shapes, "rhs")
+    with pytest.raises(TypeError, match=r"x\[0\] must be a CUDA tensor"):
+        lib._check_fields([None, None, None], shapes, "x")

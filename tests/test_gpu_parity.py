@@ -540,6 +540,32 @@ def test_batched_assembly_matches_single(gpu_lib):
         assert torch.equal(a.apply_operator(m, x), b.apply_operator(m, x))
 
 
+def test_binding_names_bad_fields_and_members(gpu_lib):
+    """The binding's one-pass field checks reject a wrong dtype, shape or
+    member index and name the entry; valid calls (orography given for some
+    members only) still assemble and solve."""
+    probs = batch_problems(3, 3, grids=((64, 32),))
+    sizes = [(p["nx"], p["ny"]) for p in probs]
+    s = make_solver(gpu_lib, sizes)
+    depths = [dev(p["depth"]) for p in probs]
+    dts = [p["dt"] for p in probs]
+    with pytest.raises(ValueError, match=r"depth\[2\]"):
+        s.set_operators([0, 1, 2], depths[:2] + [depths[2].float()], dts)
+    with pytest.raises(ValueError, match="members must lie"):
+        s.set_operators([0, 1, 3], depths, dts)
+    with pytest.raises(ValueError, match=r"orography\[1\]"):
+        s.set_operators([0, 1, 2], depths, dts, orographies=[None, depths[1].t(), None])
+    s.set_operators([0, 1, 2], depths, dts, orographies=[None, torch.zeros_like(depths[1]), None])
+    rhs = [s.apply_operator(m, dev(p["x_true"])) for m, p in enumerate(probs)]
+    x = [torch.zeros_like(r) for r in rhs]
+    with pytest.raises(ValueError, match=r"x\[1\]"):
+        s.solve(rhs, [x[0], x[1].t(), x[2]])
+    with pytest.raises(ValueError, match=r"rhs\[0\]"):
+        s.solve([rhs[0][:, :-1]] + rhs[1:], x)
+    reps = s.solve(rhs, x)
+    assert [r.status for r in reps] == [0, 0, 0] and all(r.iterations > 0 for r in reps)
+
+
 # ---------------------------------------------------------------------------
 # full sizes, in the launch configuration the benchmark times
 # ---------------------------------------------------------------------------
