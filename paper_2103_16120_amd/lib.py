@@ -178,6 +178,7 @@ def _check_fields(ts, shapes, name: str):
 # numpy views of the operator and report tables (one row per member), so a
 # batch is filled and read column by column instead of field by field
 _OP_DTYPE = np.dtype(GcrOperator)
+_SI_DTYPE = np.dtype(GcrSiMember)
 _REP_FIELDS = ("status", "iterations", "restarts", "fallback_used", "r0_norm", "rel_res_recursive", "rel_res_true")
 _REP_DTYPE = np.dtype({"names": list(_REP_FIELDS), "formats": ["<i4"] * 4 + ["<f8"] * 3,
                        "offsets": [getattr(GcrReport, f).offset for f in _REP_FIELDS],
@@ -337,7 +338,55 @@ class Solver:
         if len(states) != b or len(olds) != b or len(news) != b:
             raise ValueError("one state, old state and new state per member")
         dts = list(dts) if hasattr(dts, "__len__") else [float(dts)] * b
-        mem = (GcrSiMember * b)()
+        if not self._si_fields_ok(states, olds, news, orographies, qbars):
+            self._si_fields_check(states, olds, news, orographies, qbars)
+            raise ValueError("si_step: contiguous float64 CUDA tensors of the members' shapes expected")
+        tab = np.zeros(b, dtype=_SI_DTYPE)
+        for group, cols in ((states, ("phi", "qx", "qy")), (olds, ("phi_old", "qx_old", "qy_old")),
+                            (news, ("phi_new", "qx_new", "qy_new"))):
+            for i, col in enumerate(cols):
+                tab[col] = [f[i].data_ptr() for f in group]
+        if orographies is not None:
+            tab["orography"] = [0 if o is None else o.data_ptr() for o in orographies]
+        if qbars is not None:
+            tab["qbar_x"] = [0 if q is None else q[0].data_ptr() for q in qbars]
+            tab["qbar_y"] = [0 if q is None else q[1].data_ptr() for q in qbars]
+        tab["dt"] = [float(d) for d in dts]
+        tab["g"], tab["omega"], tab["radius"], tab["absorber"] = float(g), float(omega), float(radius), float(absorber)
+        reps = (GcrReport * b)()
+        rc = _lib.gcr_si_step(self._h, tab.ctypes.data_as(C.POINTER(GcrSiMember)), reps)
+        if rc < 0:
+            raise self._err(rc)
+        rows = zip(*[np.frombuffer(reps, dtype=_REP_DTYPE)[f].tolist() for f in _REP_FIELDS])
+        return [Report(*row, []) for row in rows]
+
+    def _si_fields_ok(self, states, olds, news, orographies, qbars):
+        """One pass of cheap attribute tests over every field of si_step."""
+        if (orographies is not None and len(orographies) != len(self.sizes)) or \
+                (qbars is not None and len(qbars) != len(self.sizes)):
+            return False
+        for m, shp in enumerate(self._shapes):
+            ts = list(states[m]) + list(olds[m]) + list(news[m])
+            if len(ts) != 9 or len(states[m]) != 3 or len(olds[m]) != 3:
+                return False
+            if orographies is not None and orographies[m] is not None:
+                ts.append(orographies[m])
+            if qbars is not None and qbars[m] is not None:
+                if len(qbars[m]) != 2:
+                    return False
+                ts.extend(qbars[m])
+            for t in ts:
+                if not (isinstance(t, torch.Tensor) and t.dtype is _F64 and t.is_cuda and t.shape == shp
+                        and t.is_contiguous()):
+                    return False
+        return True
+
+    def _si_fields_check(self, states, olds, news, orographies, qbars):
+        """The per-field checks of si_step, raising with the failing entry's name."""
+        if orographies is not None and len(orographies) != len(self.sizes):
+            raise ValueError("one orography (or None) per member")
+        if qbars is not None and len(qbars) != len(self.sizes):
+            raise ValueError("one (qbar_x, qbar_y) (or None) per member")
         for m, (nx, ny) in enumerate(self.sizes):
             trip = [("state", states[m]), ("old", olds[m]), ("new", news[m])]
             for what, fields in trip:
@@ -350,22 +399,10 @@ class Solver:
                 _check_field(oro, ny, nx, f"orography[{m}]")
             qb = qbars[m] if qbars is not None else None
             if qb is not None:
+                if len(qb) != 2:
+                    raise ValueError(f"qbar[{m}] must be (qbar_x, qbar_y)")
                 for t in qb:
                     _check_field(t, ny, nx, f"qbar[{m}]")
-            e = mem[m]
-            e.phi, e.qx, e.qy = (t.data_ptr() for t in states[m])
-            e.phi_old, e.qx_old, e.qy_old = (t.data_ptr() for t in olds[m])
-            e.phi_new, e.qx_new, e.qy_new = (t.data_ptr() for t in news[m])
-            e.orography = oro.data_ptr() if oro is not None else None
-            e.qbar_x, e.qbar_y = (qb[0].data_ptr(), qb[1].data_ptr()) if qb is not None else (None, None)
-            e.dt, e.g, e.omega, e.radius, e.absorber = float(dts[m]), float(g), float(omega), float(radius), \
-                float(absorber)
-        reps = (GcrReport * b)()
-        rc = _lib.gcr_si_step(self._h, mem, reps)
-        if rc < 0:
-            raise self._err(rc)
-        return [Report(r.status, r.iterations, r.restarts, r.fallback_used, r.r0_norm, r.rel_res_recursive,
-                       r.rel_res_true, []) for r in reps]
 
     def set_kernel_timing(self, enable=True):
         rc = _lib.gcr_set_kernel_timing(self._h, 1 if enable else 0)

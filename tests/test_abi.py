@@ -259,3 +259,17 @@ def test_field_list_checks_name_the_failing_entry(lib):
         lib._check_fields([torch.zeros(4, 8, dtype=torch.float64)] * 3, shapes, "rhs")
     with pytest.raises(TypeError, match=r"x\[0\] must be a CUDA tensor"):
         lib._check_fields([None, None, None], shapes, "x")
+
+
+def test_si_member_table_matches_the_c_struct(lib):
+    import numpy as np
+    fields = [f for f, _ in lib.GcrSiMember._fields_]
+    ref = (lib.GcrSiMember * 2)()
+    tab = np.zeros(2, dtype=lib._SI_DTYPE)
+    for m in range(2):
+        for i, f in enumerate(fields):
+            v = float(i + 0.5 + 100 * m) if f in ("dt", "g", "omega", "radius", "absorber") else 256 * (i + 1) + m
+            setattr(ref[m], f, v)
+            tab[f][m] = v
+    assert lib._SI_DTYPE.itemsize == C.sizeof(lib.GcrSiMember)
+    assert tab.tobytes() == bytes(ref)

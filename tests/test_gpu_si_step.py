@@ -172,3 +172,24 @@ def test_si_step_full_size_batch_sampled(gpu_lib):
         s0 = si.State(st["phi"], st["qx"], st["qy"])
         ref, _ = si.si_step(nx, ny, s0, s0, st["orography"], (z, z), p, iterative)
         _check(tuple(host(f) for f in new[m]), ref)
+
+
+def test_si_step_binding_names_bad_fields(gpu_lib):
+    """The one-pass field checks of si_step fall back to the per-field check,
+    which names the failing entry; a valid call still steps."""
+    nx, ny = 16, 8
+    m = _member(nx, ny, 96)
+    solver = gpu_lib.Solver([(nx, ny)] * 2, max_iters=500)
+    st = [tuple(dev(f) for f in (m[0].phi, m[0].qx, m[0].qy)) for _ in range(2)]
+    old = [tuple(dev(f) for f in (m[1].phi, m[1].qx, m[1].qy)) for _ in range(2)]
+    new = [tuple(torch.empty_like(f) for f in s) for s in st]
+    oro = [dev(m[2]), dev(m[2])]
+    with pytest.raises(ValueError, match=r"new\[1\]"):
+        solver.si_step(st, old, [new[0], (new[1][0], new[1][1].float(), new[1][2])], [900.0, 900.0])
+    with pytest.raises(ValueError, match=r"old\[0\] must be \(phi, qx, qy\)"):
+        solver.si_step(st, [old[0][:2], old[1]], new, [900.0, 900.0])
+    with pytest.raises(ValueError, match=r"orography\[1\]"):
+        solver.si_step(st, old, new, [900.0, 900.0], orographies=[None, st[0][0].t()])
+    reps = solver.si_step(st, old, new, [900.0, 900.0], orographies=oro)
+    assert [r.status for r in reps] == [0, 0]
+    assert torch.equal(new[0][0], new[1][0])
